@@ -1,0 +1,111 @@
+"""Generators eta(h) and their vector-Jacobian products (FP64).
+
+Test infrastructure (see the package docstring).  h and eta are [N, nsets].
+
+* wegner_graph: the block generator eta = [H_d, H_od] (Eq. block-generator,
+  Sec. 2.1) evaluated as a graph pass over E_eta (Eq. graph-actions, first line):
+  eta_k = s_g * sum_{e in E_eta(k)} c_e (Dh)_{i_e} h_{j_e}, where s_g converts the
+  operator-basis bracket into generator-basis coefficients (+1 for E_pq, whose
+  generator basis is the operator basis; -1 for Majorana strings, whose generator
+  basis is i*Gamma: [Gamma_A, Gamma_B] = -i [iGamma_A, Gamma_B]).
+* g2: normalised Wegner generator for Majorana strings (the reading taken here
+  of a White-type generator built from the diagonal pair energies): with
+  pair energies eps_a = h_{P_a} and the pair-flip set F(S),
+      N_S = -sum_{a in F(S)} c(S, P_a, S^P_a) eps_a h_{S^P_a}
+      Q_S = 4 sum_{a in F(S)} eps_a^2 + delta^2,     eta_S = N_S / Q_S,
+  and eta = 0 on block-diagonal strings.  N is the Wegner generator of the
+  quadratic diagonal part H_0 = sum_a eps_a Gamma_{P_a}; Q_S is the diagonal of
+  ad_{H_0}^2 in the orthonormal string basis, regularised by delta^2.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from .algebra import Graph, MajoranaRegistry, bracket_coeff, _popcount
+
+
+def wegner_graph(g: Graph, h: np.ndarray) -> np.ndarray:
+    ge = g.eta_records()
+    dh = np.where(g.diag[:, None], h, 0.0)       # (Dh)
+    odh = np.where(g.diag[:, None], 0.0, h)      # ((I-D)h)
+    contrib = ge.c[:, None] * dh[ge.i] * odh[ge.j]
+    out = np.zeros_like(h)
+    for s in range(h.shape[1]):
+        out[:, s] = np.bincount(ge.k, weights=contrib[:, s], minlength=g.N)
+    return g.gen_sign * out
+
+
+def wegner_graph_vjp(g: Graph, h: np.ndarray, gbar: np.ndarray) -> np.ndarray:
+    ge = g.eta_records()
+    dmask = g.diag.astype(float)
+    gh = np.zeros_like(h)
+    for s in range(h.shape[1]):
+        w = g.gen_sign * ge.c * gbar[ge.k, s]
+        gh[:, s] += dmask * np.bincount(ge.i, weights=w * (1 - dmask[ge.j]) * h[ge.j, s],
+                                        minlength=g.N)
+        gh[:, s] += (1 - dmask) * np.bincount(ge.j, weights=w * dmask[ge.i] * h[ge.i, s],
+                                              minlength=g.N)
+    return gh
+
+
+class G2:
+    """Per-pair stencil of the normalised Wegner generator (built once per m)."""
+
+    def __init__(self, m: int, delta: float):
+        reg = MajoranaRegistry(m)
+        self.reg = reg
+        self.delta = float(delta)
+        self.stencil = []   # per pair a: (S rows, partner rows, c)
+        for a in range(m // 2):
+            pm = reg.pair_masks[a]
+            flips = _popcount(reg.masks & pm) == 1
+            S = np.nonzero(flips)[0].astype(np.int64)
+            partner_mask = reg.masks[S] ^ pm
+            partner = reg.index_of(partner_mask)
+            assert np.all(partner >= 0)
+            # coefficient of Gamma_S in [i Gamma_{P_a}, Gamma_partner]
+            c = bracket_coeff(np.full(S.size, pm, dtype=np.uint64), partner_mask, m)
+            assert np.all(np.abs(c) == 2.0)
+            self.stencil.append((S, partner, c))
+
+    def _nq(self, h):
+        N = np.zeros_like(h)
+        Qs = np.zeros_like(h)
+        for a, (S, P, c) in enumerate(self.stencil):
+            eps = h[self.reg.pairs[a]][None, :]
+            N[S] += -c[:, None] * eps * h[P]
+            Qs[S] += 4.0 * eps * eps
+        Q = Qs + self.delta ** 2
+        return N, Q
+
+    def __call__(self, h: np.ndarray) -> np.ndarray:
+        N, Q = self._nq(h)
+        eta = N / Q
+        eta[self.reg.diag] = 0.0
+        return eta
+
+    def vjp(self, h: np.ndarray, gbar: np.ndarray) -> np.ndarray:
+        """d/dh of sum(gbar * eta(h)) by the product and quotient rules."""
+        N, Q = self._nq(h)
+        gb = np.where(self.reg.diag[:, None], 0.0, gbar)
+        gh = np.zeros_like(h)
+        for a, (S, P, c) in enumerate(self.stencil):
+            pa = self.reg.pairs[a]
+            eps = h[pa][None, :]
+            w = gb[S] / Q[S]
+            # d eta_S / d h_partner = -c eps / Q
+            np.add.at(gh, P, -c[:, None] * eps * w)
+            # d eta_S / d eps_a = -c h_partner / Q - N_S * 8 eps / Q^2
+            d_eps = -c[:, None] * h[P] * w - gb[S] * N[S] * 8.0 * eps / (Q[S] ** 2)
+            gh[pa] += d_eps.sum(axis=0)
+        return gh
+
+
+def make_generator(g: Graph, kind: str, delta: float = 0.5):
+    """Returns (eta(h), vjp(h, gbar)) for the named generator."""
+    if kind == "wegner_graph":
+        return (lambda h: wegner_graph(g, h)), (lambda h, gb: wegner_graph_vjp(g, h, gb))
+    if kind == "g2":
+        gen = G2(g.size, delta)
+        return gen, gen.vjp
+    raise ValueError(kind)
