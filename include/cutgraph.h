@@ -1,0 +1,225 @@
+/* cutgraph.h -- C ABI of the MI355X compiled-CUT-graph library (libcutgraph.so).
+ *
+ * Method: Peng & Govind, "Compile-once operation graphs for reusable continuous
+ * unitary transformations".  A fixed operator registry and transformation rule
+ * are compiled once into a graph of contribution records (target k, left input
+ * i, right input j, factor c), grouped by target (Sec. 2.2, Eq. graph-actions).
+ * Evaluating the graph on run-time coefficient vectors gives the projected flow
+ * right-hand side dh_k/ds = sum_e c_e eta_{i_e} h_{j_e} for [eta, H] and [eta, X]
+ * (Sec. 2.1, Eq. coflow); the same records, traversed toward their inputs, give
+ * the adjoint action (Sec. 2.4).
+ *
+ * Conventions for every entry point:
+ *  - Status codes are returned; nothing throws across the ABI.  After a non-OK
+ *    status, cut_last_error() returns a thread-local message.
+ *  - Argument and shape validation is synchronous and happens before any launch
+ *    (CUT_E_INVAL).  Kernels run asynchronously on `stream` (a hipStream_t;
+ *    NULL = the null stream).  A device fault surfaces as CUT_E_DEVICE from a
+ *    later call that synchronises.
+ *  - All coefficient pointers are device memory owned by the caller.  Row r of
+ *    an operand starts at base + r*ld (ld counted in elements).
+ *  - Coefficient layout: a state row holds nops*nsets columns, column
+ *    op*nsets + s belongs to operand op (0 = the Hamiltonian) of coefficient set
+ *    s.  A generator row holds nsets columns.  Every operand column of set s is
+ *    paired with generator column s.
+ *  - A graph handle owns all device copies of the graph and a work area that
+ *    grows on demand; calls on one handle must not overlap in time (serialise
+ *    them on one stream).
+ */
+#ifndef CUTGRAPH_H
+#define CUTGRAPH_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct cut_graph_s* cut_graph_t;
+
+typedef enum {
+    CUT_OK = 0,
+    CUT_E_INVAL = 1,        /* bad argument, shape or leading dimension */
+    CUT_E_IO = 2,           /* file cannot be created, read or mapped */
+    CUT_E_FORMAT = 3,       /* bundle header/section/bounds validation failed */
+    CUT_E_CHECKSUM = 4,     /* bundle section checksum mismatch */
+    CUT_E_NOMEM = 5,        /* host or device allocation failed */
+    CUT_E_DEVICE = 6,       /* HIP runtime error or device fault */
+    CUT_E_NUMERIC = 7,      /* non-finite state detected by a flow */
+    CUT_E_UNSUPPORTED = 8   /* valid request outside what this build implements */
+} cut_status;
+
+/* Operator algebras the graph compiler knows. */
+typedef enum {
+    CUT_ALG_EPQ = 1,        /* one-body fermion operators E_pq, size = n orbitals,
+                               registry index p*n+q, [E_pq,E_rs] = d_qr E_ps - d_ps E_rq */
+    CUT_ALG_MAJORANA = 2    /* even Majorana strings of degree 2 and 4 over m = size
+                               modes, registry = 2-subsets then 4-subsets, each
+                               lexicographic; generator basis i*Gamma_S */
+} cut_algebra;
+
+/* Record sets stored in a graph (Eq. graph-actions). */
+typedef enum {
+    CUT_GRAPH_FLOW = 0,     /* E_L: the retained action F_k(h, x) */
+    CUT_GRAPH_GEN = 1       /* E_eta: block-generator records (left input diagonal) */
+} cut_which;
+
+/* Arithmetic of a graph pass. */
+typedef enum {
+    CUT_F64 = 0,            /* double operands, double products and sums */
+    CUT_F32C = 1,           /* float operands and products; compensated sums
+                               (error-free product by FMA + two-sum), double result */
+    CUT_F32X = 2,           /* float operands; products and sums in double (products
+                               of two floats and a small integer factor are exact) */
+    CUT_F32 = 3             /* float operands, products and plain float sums
+                               (precision-study baseline only) */
+} cut_precision;
+
+/* Generators eta(h) (Sec. 2.1, Eq. block-generator). */
+typedef enum {
+    CUT_GEN_WEGNER_GRAPH = 1, /* eta = [H_d, H_od] as a graph pass over E_eta */
+    CUT_GEN_G2 = 2            /* Majorana: Wegner generator of the quadratic diagonal
+                                 part H_0 = sum_a eps_a Gamma_{P_a}, eps_a = h_{P_a},
+                                 divided elementwise by Q_S = sum_t (c_t eps_{a_t})^2
+                                 + delta^2 (the diagonal of ad_{H_0}^2) */
+} cut_generator_kind;
+
+#define CUT_ACCUMULATE   1u   /* apply flags: y += result instead of y = result */
+#define CUT_LOAD_ADJOINT 1u   /* load flags: also build the input-sorted copies */
+#define CUT_LOAD_NO_CHECKSUM 2u /* load flags: skip section checksums (bounds are
+                                   still validated) */
+
+typedef struct {
+    int32_t algebra;        /* cut_algebra */
+    int32_t size;           /* n orbitals or m Majorana modes */
+    int64_t n_ops;          /* registry size N */
+    int64_t n_records;      /* |E_L| */
+    int64_t n_gen_records;  /* |E_eta| */
+    int64_t n_pairs;        /* diagonal quadratic coordinates (pair energies) */
+    uint64_t checksum;      /* combined checksum of the record sections */
+    int64_t file_bytes;     /* bundle size on disk */
+    double build_seconds;   /* compiler wall time (cut_graph_build only) */
+    char identifier[96];    /* algebra, registry, ordering and projection rules */
+} cut_graph_desc;
+
+/* ---------------------------------------------------------------- compile --
+ * cut_graph_build: compile the graph of `algebra` at `size` into a bundle file
+ * (Sec. 2.3).  Two deterministic traversals: the first counts the records of
+ * every target and fixes the exact array sizes, the file is then sized and
+ * mapped, the second traversal writes every record at its final place.  The
+ * bundle holds the registry labels, block mask, pair list, rules identifier,
+ * factor precision (int8), the target-grouped records of E_L and E_eta and one
+ * checksum per section.  Two builds are bitwise identical.
+ * `threads` <= 0 selects the hardware concurrency.  `desc` (nullable) receives
+ * the sizes.  Errors: CUT_E_INVAL (unknown algebra, size out of range: E_pq
+ * 1..64, Majorana even 4..64), CUT_E_IO, CUT_E_NOMEM. */
+cut_status cut_graph_build(int32_t algebra, int32_t size, const char* path, int32_t threads,
+                           cut_graph_desc* desc);
+
+/* ------------------------------------------------------------------- load --
+ * cut_graph_load: map and validate a bundle (magic, version, header checksum,
+ * section table, per-section checksums unless CUT_LOAD_NO_CHECKSUM, offsets
+ * monotone and complete, every index < N, every factor nonzero), then upload
+ * the target-sorted record stream to `hip_device` (Sec. 2.3: validated reload).
+ * With CUT_LOAD_ADJOINT the input-sorted copies used by the adjoint are built
+ * too.  On success *out owns all device memory; release with cut_graph_free.
+ * Errors: CUT_E_IO, CUT_E_FORMAT, CUT_E_CHECKSUM, CUT_E_NOMEM, CUT_E_DEVICE,
+ * CUT_E_UNSUPPORTED (N >= 2^24 or more than 256 distinct factors). */
+cut_status cut_graph_load(const char* path, int32_t hip_device, uint32_t flags, cut_graph_t* out);
+
+cut_status cut_graph_info(cut_graph_t g, cut_graph_desc* desc);
+void cut_graph_free(cut_graph_t g);
+
+/* ------------------------------------------------------------------ apply --
+ * cut_graph_apply: forward graph action (Eq. graph-actions; L(h)x of Sec. 2.4)
+ *   y[k][op*nsets+s] (=|+=) sum_{e in E(k)} c_e * eta[i_e][s] * x[j_e][op*nsets+s]
+ * for 0 <= k < N, 0 <= op < nops, 0 <= s < nsets.  eta and x are double* for
+ * CUT_F64 and float* otherwise; y is always double*.  Requires nsets >= 1,
+ * 1 <= nops <= 8, lde >= nsets, ldx >= nops*nsets, ldy >= nops*nsets.
+ * y must not alias eta or x. */
+cut_status cut_graph_apply(cut_graph_t g, int32_t which, int32_t precision, int64_t nsets,
+                           int64_t nops, const void* eta, int64_t lde, const void* x,
+                           int64_t ldx, double* y, int64_t ldy, uint32_t flags, void* stream);
+
+/* cut_graph_apply_adjoint: the graph-level adjoint (Sec. 2.4): the same factor,
+ * accumulated into the input coordinate (factors are real, so no conjugation):
+ *   g_x[j][op*nsets+s]  (=|+=) sum_{e: j_e=j} c_e * eta[i_e][s] * w[k_e][op*nsets+s]
+ *   g_eta[i][s]         (=|+=) sum_{e: i_e=i} c_e * sum_op w[k_e][op*nsets+s] * x[j_e][op*nsets+s]
+ * Either output may be NULL (then its inputs may be NULL too).  Needs a graph
+ * loaded with CUT_LOAD_ADJOINT (else CUT_E_INVAL).  Types as cut_graph_apply. */
+cut_status cut_graph_apply_adjoint(cut_graph_t g, int32_t which, int32_t precision, int64_t nsets,
+                                   int64_t nops, const void* eta, int64_t lde, const void* x,
+                                   int64_t ldx, const void* w, int64_t ldw, double* g_x,
+                                   int64_t ldgx, double* g_eta, int64_t ldge, uint32_t flags,
+                                   void* stream);
+
+/* -------------------------------------------------------------- generator --
+ * cut_generator: eta[r][s] from h[r][s] (both double, [N][nsets] with leading
+ * dimensions), for CUT_GEN_WEGNER_GRAPH (eta_k = s_g sum_{E_eta(k)} c (Dh)_i
+ * ((I-D)h)_j, s_g = +1 for E_pq and -1 for Majorana strings, whose generator
+ * basis is i*Gamma) or CUT_GEN_G2 (Majorana only; eta = 0 on diagonal strings).
+ * cut_generator_vjp: g_h[r][s] += sum_S gbar[S][s] d eta_S / d h_r. */
+cut_status cut_generator(cut_graph_t g, int32_t kind, double delta, int64_t nsets,
+                         const double* h, int64_t ldh, double* eta, int64_t lde, void* stream);
+cut_status cut_generator_vjp(cut_graph_t g, int32_t kind, double delta, int64_t nsets,
+                             const double* h, int64_t ldh, const double* gbar, int64_t ldg,
+                             double* g_h, int64_t ldgh, void* stream);
+
+/* ------------------------------------------------------------------- flow --
+ * Coflow of H and nops-1 observables (Eq. coflow; Eq. forward-coeff) with the
+ * classic fourth-order Runge-Kutta scheme at fixed step ds.  State z is double
+ * [N][nops][nsets] (row-major, no padding), op 0 = H.  Set s advances while the
+ * global step t satisfies t < n_steps[s], then stays frozen.  The generator,
+ * the RK stage combination and the state are FP64; graph passes use
+ * `precision` (operands are rounded to float once per stage for the float
+ * modes).  Each RK step is one stream-ordered sequence of kernels; with
+ * CUT_FLOW_HIPGRAPH it is captured once as a hipGraph and replayed. */
+#define CUT_FLOW_HIPGRAPH 1u
+
+typedef struct {
+    int32_t generator;      /* cut_generator_kind */
+    int32_t precision;      /* cut_precision of the graph passes */
+    double ds;              /* RK4 step */
+    double delta;           /* G2 regulariser */
+    int32_t ckpt_every;     /* checkpoint period in steps (0 = none) */
+    uint32_t flags;         /* CUT_FLOW_HIPGRAPH */
+    int64_t step_begin;     /* first global step to take (normally 0) */
+    int64_t step_end;       /* one past the last step; < 0 = max(n_steps) */
+} cut_flow_params;
+
+/* cut_flow_integrate: advances z in place over global steps [step_begin,
+ * step_end).  n_steps is a HOST array of nsets int32.  If ckpt is not NULL and
+ * ckpt_every > 0, slot c of ckpt (each N*nops*nsets doubles, device) receives z
+ * at global step c*ckpt_every for every such step in range.  Errors:
+ * CUT_E_INVAL, CUT_E_UNSUPPORTED (G2 on a non-Majorana graph), CUT_E_DEVICE,
+ * CUT_E_NOMEM, CUT_E_NUMERIC (non-finite z after the flow). */
+cut_status cut_flow_integrate(cut_graph_t g, const cut_flow_params* p, int64_t nsets,
+                              int64_t nops, const int32_t* n_steps, double* z, double* ckpt,
+                              void* stream);
+
+/* cut_flow_adjoint: exact adjoint of the discrete RK4 map (reverse-mode
+ * gradient through the flow; graph-level adjoint of Sec. 2.4 plus the induced
+ * generator variation of Eq. directional-derivative).  Needs the checkpoints of
+ * a cut_flow_integrate call from step 0 with the same parameters, and a graph
+ * loaded with CUT_LOAD_ADJOINT.  lambda (device, layout of z): in dL/dz at the
+ * end of the flow, out dL/dz at step 0.  Each checkpoint block is recomputed
+ * forward in FP64 with its stage states kept; all adjoint passes are FP64. */
+cut_status cut_flow_adjoint(cut_graph_t g, const cut_flow_params* p, int64_t nsets,
+                            int64_t nops, const int32_t* n_steps, const double* ckpt,
+                            double* lambda, void* stream);
+
+/* ---------------------------------------------------------------- tuning --
+ * Segment tiling: targets with more than `long_records` records are split over
+ * the four wavefronts of a workgroup (fixed-order combine); shorter targets are
+ * packed four to a workgroup, one per wavefront.  `xcd_remap` != 0 maps
+ * consecutive task ranges onto one XCD (one L2).  Rebuilds the task lists of
+ * every loaded copy.  Errors: CUT_E_INVAL, CUT_E_DEVICE. */
+cut_status cut_graph_set_tiling(cut_graph_t g, int64_t long_records, int32_t xcd_remap);
+
+const char* cut_last_error(void);
+const char* cut_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CUTGRAPH_H */

@@ -1,0 +1,205 @@
+"""ctypes binding of libcutgraph.so: argument marshalling only.
+
+Every function has the name of the C entry point it calls (include/cutgraph.h)
+and takes torch device tensors where the C function takes device pointers.
+No arithmetic of the method happens here, and there is no fallback: if the
+HIP library is missing, importing this module raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libcutgraph.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(
+        f"libcutgraph.so not built at {LIB_PATH}; run `python -c 'import __graft_entry__ as g; g.build()'`")
+
+_L = C.CDLL(LIB_PATH)
+
+# status codes / enums (mirror include/cutgraph.h)
+CUT_OK, CUT_E_INVAL, CUT_E_IO, CUT_E_FORMAT, CUT_E_CHECKSUM = 0, 1, 2, 3, 4
+CUT_E_NOMEM, CUT_E_DEVICE, CUT_E_NUMERIC, CUT_E_UNSUPPORTED = 5, 6, 7, 8
+CUT_ALG_EPQ, CUT_ALG_MAJORANA = 1, 2
+CUT_GRAPH_FLOW, CUT_GRAPH_GEN = 0, 1
+CUT_F64, CUT_F32C, CUT_F32X, CUT_F32 = 0, 1, 2, 3
+CUT_GEN_WEGNER_GRAPH, CUT_GEN_G2 = 1, 2
+CUT_ACCUMULATE = 1
+CUT_LOAD_ADJOINT, CUT_LOAD_NO_CHECKSUM = 1, 2
+CUT_FLOW_HIPGRAPH = 1
+
+STATUS_NAMES = {0: "CUT_OK", 1: "CUT_E_INVAL", 2: "CUT_E_IO", 3: "CUT_E_FORMAT",
+                4: "CUT_E_CHECKSUM", 5: "CUT_E_NOMEM", 6: "CUT_E_DEVICE", 7: "CUT_E_NUMERIC",
+                8: "CUT_E_UNSUPPORTED"}
+
+# symbols declared in include/cutgraph.h
+EXPORTS = ["cut_graph_build", "cut_graph_load", "cut_graph_info", "cut_graph_free",
+           "cut_graph_apply", "cut_graph_apply_adjoint", "cut_generator", "cut_generator_vjp",
+           "cut_flow_integrate", "cut_flow_adjoint", "cut_graph_set_tiling", "cut_last_error",
+           "cut_version"]
+
+
+class CutError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class cut_graph_desc(C.Structure):
+    _fields_ = [("algebra", C.c_int32), ("size", C.c_int32), ("n_ops", C.c_int64),
+                ("n_records", C.c_int64), ("n_gen_records", C.c_int64), ("n_pairs", C.c_int64),
+                ("checksum", C.c_uint64), ("file_bytes", C.c_int64), ("build_seconds", C.c_double),
+                ("identifier", C.c_char * 96)]
+
+    def as_dict(self):
+        d = {k: getattr(self, k) for k, _ in self._fields_}
+        d["identifier"] = self.identifier.decode()
+        return d
+
+
+class cut_flow_params(C.Structure):
+    _fields_ = [("generator", C.c_int32), ("precision", C.c_int32), ("ds", C.c_double),
+                ("delta", C.c_double), ("ckpt_every", C.c_int32), ("flags", C.c_uint32),
+                ("step_begin", C.c_int64), ("step_end", C.c_int64)]
+
+
+_vp, _i32, _i64, _u32, _dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_uint32, C.c_double
+_L.cut_graph_build.argtypes = [_i32, _i32, C.c_char_p, _i32, C.POINTER(cut_graph_desc)]
+_L.cut_graph_load.argtypes = [C.c_char_p, _i32, _u32, C.POINTER(_vp)]
+_L.cut_graph_info.argtypes = [_vp, C.POINTER(cut_graph_desc)]
+_L.cut_graph_free.argtypes = [_vp]
+_L.cut_graph_free.restype = None
+_L.cut_graph_apply.argtypes = [_vp, _i32, _i32, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _i64, _u32, _vp]
+_L.cut_graph_apply_adjoint.argtypes = [_vp, _i32, _i32, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _i64,
+                                       _vp, _i64, _vp, _i64, _u32, _vp]
+_L.cut_generator.argtypes = [_vp, _i32, _dbl, _i64, _vp, _i64, _vp, _i64, _vp]
+_L.cut_generator_vjp.argtypes = [_vp, _i32, _dbl, _i64, _vp, _i64, _vp, _i64, _vp, _i64, _vp]
+_L.cut_flow_integrate.argtypes = [_vp, C.POINTER(cut_flow_params), _i64, _i64, C.POINTER(_i32), _vp, _vp,
+                                  _vp]
+_L.cut_flow_adjoint.argtypes = [_vp, C.POINTER(cut_flow_params), _i64, _i64, C.POINTER(_i32), _vp, _vp, _vp]
+_L.cut_graph_set_tiling.argtypes = [_vp, _i64, _i32]
+_L.cut_last_error.restype = C.c_char_p
+_L.cut_version.restype = C.c_char_p
+for _name in EXPORTS:
+    if _name not in ("cut_graph_free", "cut_last_error", "cut_version"):
+        getattr(_L, _name).restype = C.c_int
+
+
+def lib():
+    return _L
+
+
+def _check(st: int):
+    if st != CUT_OK:
+        raise CutError(st, _L.cut_last_error().decode(errors="replace"))
+
+
+def cut_last_error() -> str:
+    return _L.cut_last_error().decode(errors="replace")
+
+
+def cut_version() -> str:
+    return _L.cut_version().decode()
+
+
+def _ptr(t) -> Optional[int]:
+    if t is None:
+        return None
+    return t.data_ptr()
+
+
+def _ld(t, default: int) -> int:
+    if t is None:
+        return default
+    if t.dim() == 1:
+        return default
+    return t.stride(0)
+
+
+def _stream(stream):
+    if stream is not None:
+        return stream
+    import torch
+    return torch.cuda.current_stream().cuda_stream
+
+
+# ---------------------------------------------------------------- compile --
+def cut_graph_build(algebra: int, size: int, path: str, threads: int = 0) -> dict:
+    d = cut_graph_desc()
+    _check(_L.cut_graph_build(algebra, size, path.encode(), threads, C.byref(d)))
+    return d.as_dict()
+
+
+# ------------------------------------------------------------------- load --
+def cut_graph_load(path: str, device: int = 0, flags: int = 0) -> int:
+    h = _vp()
+    _check(_L.cut_graph_load(path.encode(), device, flags, C.byref(h)))
+    return h.value
+
+
+def cut_graph_info(g: int) -> dict:
+    d = cut_graph_desc()
+    _check(_L.cut_graph_info(g, C.byref(d)))
+    return d.as_dict()
+
+
+def cut_graph_free(g: int) -> None:
+    _L.cut_graph_free(g)
+
+
+def cut_graph_set_tiling(g: int, long_records: int, xcd_remap: int) -> None:
+    _check(_L.cut_graph_set_tiling(g, long_records, xcd_remap))
+
+
+# ------------------------------------------------------------------ apply --
+def cut_graph_apply(g: int, which: int, precision: int, nsets: int, nops: int, eta, x, y,
+                    flags: int = 0, stream=None) -> None:
+    """y[k, op*nsets+s] (=|+=) sum_e c eta[i, s] x[j, op*nsets+s]; 2-D row-major tensors."""
+    _check(_L.cut_graph_apply(g, which, precision, nsets, nops, _ptr(eta), _ld(eta, nsets), _ptr(x),
+                              _ld(x, nops * nsets), _ptr(y), _ld(y, nops * nsets), flags,
+                              _stream(stream)))
+
+
+def cut_graph_apply_adjoint(g: int, which: int, precision: int, nsets: int, nops: int, eta, x, w,
+                            g_x, g_eta, flags: int = 0, stream=None) -> None:
+    _check(_L.cut_graph_apply_adjoint(
+        g, which, precision, nsets, nops, _ptr(eta), _ld(eta, nsets), _ptr(x), _ld(x, nops * nsets),
+        _ptr(w), _ld(w, nops * nsets), _ptr(g_x), _ld(g_x, nops * nsets), _ptr(g_eta),
+        _ld(g_eta, nsets), flags, _stream(stream)))
+
+
+def cut_generator(g: int, kind: int, delta: float, nsets: int, h, eta, stream=None) -> None:
+    _check(_L.cut_generator(g, kind, delta, nsets, _ptr(h), _ld(h, nsets), _ptr(eta), _ld(eta, nsets),
+                            _stream(stream)))
+
+
+def cut_generator_vjp(g: int, kind: int, delta: float, nsets: int, h, gbar, g_h, stream=None) -> None:
+    _check(_L.cut_generator_vjp(g, kind, delta, nsets, _ptr(h), _ld(h, nsets), _ptr(gbar),
+                                _ld(gbar, nsets), _ptr(g_h), _ld(g_h, nsets), _stream(stream)))
+
+
+# ------------------------------------------------------------------- flow --
+def flow_params(generator: int, precision: int, ds: float, delta: float = 0.5, ckpt_every: int = 0,
+                flags: int = CUT_FLOW_HIPGRAPH, step_begin: int = 0, step_end: int = -1):
+    return cut_flow_params(generator, precision, ds, delta, ckpt_every, flags, step_begin, step_end)
+
+
+def _steps_arg(n_steps):
+    arr = (C.c_int32 * len(n_steps))(*[int(v) for v in n_steps])
+    return arr
+
+
+def cut_flow_integrate(g: int, params: cut_flow_params, nsets: int, nops: int, n_steps, z, ckpt=None,
+                       stream=None) -> None:
+    """z: device float64 [N, nops, nsets] contiguous, advanced in place."""
+    _check(_L.cut_flow_integrate(g, C.byref(params), nsets, nops, _steps_arg(n_steps), _ptr(z),
+                                 _ptr(ckpt), _stream(stream)))
+
+
+def cut_flow_adjoint(g: int, params: cut_flow_params, nsets: int, nops: int, n_steps, ckpt, lam,
+                     stream=None) -> None:
+    _check(_L.cut_flow_adjoint(g, C.byref(params), nsets, nops, _steps_arg(n_steps), _ptr(ckpt),
+                               _ptr(lam), _stream(stream)))

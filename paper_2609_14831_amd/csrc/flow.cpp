@@ -1,0 +1,353 @@
+// Flow driver: classic RK4 coflow of H and its observables (Sec. 2.1 Eq. coflow;
+// Sec. 2.4 Eq. forward-coeff) and the exact adjoint of the discrete RK4 map.
+//
+// One RK step = 4 x { generator eta(h) ; graph pass with the fused RK stage
+// epilogue }, then a device step counter is bumped.  Per-set activity
+// (t < n_steps[s]) is read on the device from that counter, so the same
+// kernel sequence serves every step and is captured once as a hipGraph.
+//
+// Work area (grown on demand, kept in the handle):
+//   xsh[2]  next/current stage operand (float or double) [N][nops][nsets]
+//   acc     RK accumulator (double)                     [N][nops][nsets]
+//   hst     FP64 Hamiltonian column of the stage         [N][nsets]
+//   eta     generator in the stage precision              [N][nsets]
+//   nsteps, step, flag (int32)
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "internal.h"
+
+namespace cut {
+
+struct StepGraphCache {
+    hipGraphExec_t exec = nullptr;
+    hipGraph_t graph = nullptr;
+    hipStream_t stream = nullptr;
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    std::vector<uint64_t> key;
+};
+
+void release_step_graphs(Graph& g) {
+    StepGraphCache* c = g.graphs;
+    if (!c) return;
+    if (c->exec) (void)hipGraphExecDestroy(c->exec);
+    if (c->graph) (void)hipGraphDestroy(c->graph);
+    if (c->ev_in) (void)hipEventDestroy(c->ev_in);
+    if (c->ev_out) (void)hipEventDestroy(c->ev_out);
+    if (c->stream) (void)hipStreamDestroy(c->stream);
+    delete c;
+    g.graphs = nullptr;
+}
+
+static size_t al(size_t x) { return (x + 255) & ~size_t(255); }
+
+struct FlowBufs {
+    void* xsh[2];
+    double* acc;
+    double* hst;
+    void* eta;
+    int32_t* nsteps;
+    int32_t* step;
+    int32_t* flag;
+};
+
+static FlowBufs flow_bufs(Graph& g, int64_t nsets, int64_t nops, bool f32, size_t extra, char** extra_ptr) {
+    const int64_t N = g.N, cols = nops * nsets;
+    const size_t tb = f32 ? 4 : 8;
+    size_t o = 0;
+    size_t oxs0 = o;
+    o += al(N * cols * tb);
+    size_t oxs1 = o;
+    o += al(N * cols * tb);
+    size_t oacc = o;
+    o += al(N * cols * 8);
+    size_t ohst = o;
+    o += al(N * nsets * 8);
+    size_t oeta = o;
+    o += al(N * nsets * tb);
+    size_t ons = o;
+    o += al(nsets * 4);
+    size_t ost = o;
+    o += 256;
+    size_t ofl = o;
+    o += 256;
+    size_t oex = o;
+    o += al(extra);
+    char* b = (char*)g.ws.get(o);
+    FlowBufs f;
+    f.xsh[0] = b + oxs0;
+    f.xsh[1] = b + oxs1;
+    f.acc = (double*)(b + oacc);
+    f.hst = (double*)(b + ohst);
+    f.eta = b + oeta;
+    f.nsteps = (int32_t*)(b + ons);
+    f.step = (int32_t*)(b + ost);
+    f.flag = (int32_t*)(b + ofl);
+    if (extra_ptr) *extra_ptr = b + oex;
+    return f;
+}
+
+struct StepPlan {
+    Graph* g;
+    int gen;
+    int prec;
+    double ds, delta;
+    int32_t nsets, nops;
+    FlowBufs fb;
+    double* z;
+    // stage operand pointers: stage s reads xin[s], writes xout[s]
+    void* xin[4];
+    void* xout[4];
+};
+
+// the kernel sequence of one RK step (stream-ordered, capturable)
+static void enqueue_step(const StepPlan& P, hipStream_t s) {
+    Graph& g = *P.g;
+    const bool f32 = P.prec != CUT_F64;
+    const int64_t cols = (int64_t)P.nops * P.nsets;
+    for (int st = 0; st < 4; ++st) {
+        eval_generator(g, P.gen, P.delta, P.nsets, P.fb.hst, P.nsets, P.fb.eta, P.nsets, f32, P.fb.nsteps,
+                       P.fb.step, s);
+        PassArgs p{};
+        p.csr = &g.csr[0][0];
+        p.ftab = g.ftab;
+        p.A = P.fb.eta;
+        p.lda = P.nsets;
+        p.B = P.xin[st];
+        p.ldb = cols;
+        p.nsets = P.nsets;
+        p.nops = P.nops;
+        p.precision = P.prec;
+        p.nsteps = P.fb.nsteps;
+        p.step = P.fb.step;
+        p.stage = st;
+        p.ds = P.ds;
+        p.z = P.z;
+        p.acc = P.fb.acc;
+        p.xout = P.xout[st];
+        p.hst = P.fb.hst;
+        p.ldh = P.nsets;
+        launch_pass(MODE_BCAST, EPI_RK, p, s);
+    }
+    launch_bump(P.fb.step, s);
+}
+
+static void check_flow(Graph& g, const cut_flow_params* p, int64_t nsets, int64_t nops, const int32_t* n_steps) {
+    if (!p || !n_steps) CUT_FAIL(CUT_E_INVAL, "flow: null params or n_steps");
+    check_prec(p->precision);
+    check_shape(nsets, nops);
+    check_generator(g, p->generator);
+    if (!(p->ds > 0.0) || !std::isfinite(p->ds)) CUT_FAIL(CUT_E_INVAL, "flow: ds must be positive");
+    if (p->ckpt_every < 0) CUT_FAIL(CUT_E_INVAL, "flow: ckpt_every < 0");
+    for (int64_t s = 0; s < nsets; ++s)
+        if (n_steps[s] < 0) CUT_FAIL(CUT_E_INVAL, "flow: negative n_steps");
+}
+
+}  // namespace cut
+
+using namespace cut;
+
+extern "C" cut_status cut_flow_integrate(cut_graph_t h, const cut_flow_params* p, int64_t nsets, int64_t nops,
+                                         const int32_t* n_steps, double* z, double* ckpt, void* stream_) {
+    try {
+        Graph& g = checked(h);
+        check_flow(g, p, nsets, nops, n_steps);
+        if (!z) CUT_FAIL(CUT_E_INVAL, "flow: null state");
+        DeviceGuard dg(g.device);
+        hipStream_t stream = (hipStream_t)stream_;
+        int64_t T = 0;
+        for (int64_t s = 0; s < nsets; ++s) T = std::max<int64_t>(T, n_steps[s]);
+        const int64_t t0 = std::max<int64_t>(0, p->step_begin);
+        const int64_t t1 = p->step_end < 0 ? T : std::min<int64_t>(p->step_end, T);
+        const bool f32 = p->precision != CUT_F64;
+        const int64_t cols = nops * nsets, M = g.N * cols;
+        FlowBufs fb = flow_bufs(g, nsets, nops, f32, 0, nullptr);
+        HIP_CHECK(hipMemcpyAsync(fb.nsteps, n_steps, nsets * 4, hipMemcpyHostToDevice, stream));
+        launch_set_scalar(fb.step, (int32_t)t0, stream);
+        launch_set_scalar(fb.flag, 0, stream);
+        launch_prep_state(z, g.N, (int32_t)nops, (int32_t)nsets, fb.xsh[0], f32, fb.hst, stream);
+        StepPlan P{&g, p->generator, p->precision, p->ds, p->delta, (int32_t)nsets, (int32_t)nops, fb, z, {}, {}};
+        for (int st = 0; st < 4; ++st) {
+            P.xin[st] = fb.xsh[st & 1];
+            P.xout[st] = fb.xsh[(st + 1) & 1];
+        }
+        const bool use_graph = (p->flags & CUT_FLOW_HIPGRAPH) && t1 - t0 > 1;
+        StepGraphCache* gc = nullptr;
+        if (use_graph) {
+            std::vector<uint64_t> key = {(uint64_t)(uintptr_t)z, (uint64_t)(uintptr_t)g.ws.ptr, (uint64_t)p->generator,
+                                         (uint64_t)p->precision, (uint64_t)nsets, (uint64_t)nops, 0, 0,
+                                         (uint64_t)g.csr[0][0].ntasks, (uint64_t)(uintptr_t)g.csr[0][0].tasks};
+            std::memcpy(&key[6], &p->ds, 8);
+            std::memcpy(&key[7], &p->delta, 8);
+            if (!g.graphs || g.graphs->key != key) {
+                release_step_graphs(g);
+                gc = new StepGraphCache();
+                g.graphs = gc;
+                HIP_CHECK(hipStreamCreateWithFlags(&gc->stream, hipStreamNonBlocking));
+                HIP_CHECK(hipEventCreateWithFlags(&gc->ev_in, hipEventDisableTiming));
+                HIP_CHECK(hipEventCreateWithFlags(&gc->ev_out, hipEventDisableTiming));
+                HIP_CHECK(hipStreamBeginCapture(gc->stream, hipStreamCaptureModeThreadLocal));
+                enqueue_step(P, gc->stream);
+                HIP_CHECK(hipStreamEndCapture(gc->stream, &gc->graph));
+                HIP_CHECK(hipGraphInstantiate(&gc->exec, gc->graph, nullptr, nullptr, 0));
+                gc->key = key;
+            }
+            gc = g.graphs;
+            HIP_CHECK(hipEventRecord(gc->ev_in, stream));
+            HIP_CHECK(hipStreamWaitEvent(gc->stream, gc->ev_in, 0));
+        }
+        hipStream_t run = use_graph ? gc->stream : stream;
+        for (int64_t t = t0; t < t1; ++t) {
+            if (ckpt && p->ckpt_every > 0 && t % p->ckpt_every == 0)
+                HIP_CHECK(hipMemcpyAsync(ckpt + (t / p->ckpt_every) * M, z, M * 8, hipMemcpyDeviceToDevice, run));
+            if (use_graph) HIP_CHECK(hipGraphLaunch(gc->exec, run));
+            else enqueue_step(P, run);
+        }
+        launch_finite_check(z, M, fb.flag, run);
+        if (use_graph) {
+            HIP_CHECK(hipEventRecord(gc->ev_out, run));
+            HIP_CHECK(hipStreamWaitEvent(stream, gc->ev_out, 0));
+        }
+        HIP_CHECK(hipGetLastError());
+        int32_t flag = 0;
+        HIP_CHECK(hipMemcpyAsync(&flag, fb.flag, 4, hipMemcpyDeviceToHost, stream));
+        HIP_CHECK(hipStreamSynchronize(stream));
+        if (flag) CUT_FAIL(CUT_E_NUMERIC, "flow produced non-finite coefficients");
+        return CUT_OK;
+    } catch (const Fail& f) {
+        return f.st;
+    } catch (const std::bad_alloc&) {
+        set_error("out of host memory");
+        return CUT_E_NOMEM;
+    }
+}
+
+// J(Z)^T mu for f(Z) = L(eta(Z_h)) Z, all FP64:
+//   u      = adjoint-x pass (j-grouped records) with eta(Z_h)
+//   geta   = adjoint-eta pass (i-grouped records) of (mu, Z)
+//   u_h   += eta'(Z_h)^T geta
+static void jt(Graph& g, const cut_flow_params* p, int32_t nsets, int32_t nops, const double* Z, const double* mu,
+               double* u, double* eta, double* geta, double* tmp, const int32_t* nsteps, const int32_t* step,
+               hipStream_t s) {
+    const int64_t cols = (int64_t)nops * nsets;
+    eval_generator(g, p->generator, p->delta, nsets, Z, cols, eta, nsets, false, nsteps, step, s);
+    PassArgs a{};
+    a.ftab = g.ftab;
+    a.nsets = nsets;
+    a.nops = nops;
+    a.precision = CUT_F64;
+    a.nsteps = nsteps;
+    a.step = step;
+    a.scale = 1.0;
+    a.csr = &g.csr[0][1];
+    a.A = eta;
+    a.lda = nsets;
+    a.B = mu;
+    a.ldb = cols;
+    a.y = u;
+    a.ldy = cols;
+    launch_pass(MODE_BCAST, EPI_Y, a, s);
+    a.csr = &g.csr[0][2];
+    a.A = mu;
+    a.lda = cols;
+    a.B = Z;
+    a.ldb = cols;
+    a.y = geta;
+    a.ldy = nsets;
+    launch_pass(MODE_REDOPS, EPI_Y, a, s);
+    eval_generator_vjp(g, p->generator, p->delta, nsets, Z, cols, geta, nsets, u, cols, tmp, s);
+}
+
+extern "C" cut_status cut_flow_adjoint(cut_graph_t h, const cut_flow_params* p, int64_t nsets, int64_t nops,
+                                       const int32_t* n_steps, const double* ckpt, double* lambda, void* stream_) {
+    try {
+        Graph& g = checked(h);
+        check_flow(g, p, nsets, nops, n_steps);
+        if (!g.have_adjoint) CUT_FAIL(CUT_E_INVAL, "flow adjoint needs a graph loaded with CUT_LOAD_ADJOINT");
+        if (!ckpt || !lambda || p->ckpt_every <= 0)
+            CUT_FAIL(CUT_E_INVAL, "flow adjoint needs checkpoints (ckpt_every > 0) and lambda");
+        DeviceGuard dg(g.device);
+        hipStream_t s = (hipStream_t)stream_;
+        int64_t T = 0;
+        for (int64_t q = 0; q < nsets; ++q) T = std::max<int64_t>(T, n_steps[q]);
+        if (T == 0) return CUT_OK;
+        const int64_t cols = nops * nsets, M = g.N * cols;
+        const int C = p->ckpt_every;
+        const int64_t nslot = (int64_t)C * 4 + 1;
+        // extra: stage storage, zr, lam_new, mu, u, eta, geta, vjp scratch
+        const size_t extra = al(nslot * M * 8) + 4 * al(M * 8) + 2 * al(g.N * nsets * 8) + al(2 * g.N * nsets * 8);
+        char* ex = nullptr;
+        FlowBufs fb = flow_bufs(g, nsets, nops, false, extra, &ex);
+        double* St = (double*)ex;
+        ex += al(nslot * M * 8);
+        double* zr = (double*)ex;
+        ex += al(M * 8);
+        double* lam_new = (double*)ex;
+        ex += al(M * 8);
+        double* mu = (double*)ex;
+        ex += al(M * 8);
+        double* u = (double*)ex;
+        ex += al(M * 8);
+        double* eta = (double*)ex;
+        ex += al(g.N * nsets * 8);
+        double* geta = (double*)ex;
+        ex += al(g.N * nsets * 8);
+        double* tmp = (double*)ex;
+        HIP_CHECK(hipMemcpyAsync(fb.nsteps, n_steps, nsets * 4, hipMemcpyHostToDevice, s));
+        const int64_t nblk = (T + C - 1) / C;
+        const double ds = p->ds;
+        for (int64_t b = nblk - 1; b >= 0; --b) {
+            const int64_t t0 = b * C, t1 = std::min<int64_t>(T, t0 + C);
+            // recompute the block forward in FP64, keeping every stage state:
+            // stage st of local step l reads St[4l+st] and writes St[4l+st+1]
+            HIP_CHECK(hipMemcpyAsync(zr, ckpt + b * M, M * 8, hipMemcpyDeviceToDevice, s));
+            launch_prep_state(zr, g.N, (int32_t)nops, (int32_t)nsets, St, false, fb.hst, s);
+            launch_set_scalar(fb.step, (int32_t)t0, s);
+            StepPlan P{&g, p->generator, CUT_F64, ds, p->delta, (int32_t)nsets, (int32_t)nops, fb, zr, {}, {}};
+            for (int64_t t = t0; t < t1; ++t) {
+                const int64_t l = t - t0;
+                for (int st = 0; st < 4; ++st) {
+                    P.xin[st] = St + (4 * l + st) * M;
+                    P.xout[st] = St + (4 * l + st + 1) * M;
+                }
+                enqueue_step(P, s);
+            }
+            for (int64_t t = t1 - 1; t >= t0; --t) {
+                const int64_t l = t - t0;
+                launch_set_scalar(fb.step, (int32_t)t, s);
+                const double* Zs[4] = {St + (4 * l) * M, St + (4 * l + 1) * M, St + (4 * l + 2) * M,
+                                       St + (4 * l + 3) * M};
+                // u4 = J(Z4)^T [ds/6 lam]
+                launch_adj_combine(g.N, (int32_t)cols, (int32_t)nsets, fb.nsteps, fb.step, lambda, nullptr, lam_new,
+                                   mu, ds / 6.0, 0.0, 1, s);
+                jt(g, p, (int32_t)nsets, (int32_t)nops, Zs[3], mu, u, eta, geta, tmp, fb.nsteps, fb.step, s);
+                launch_adj_combine(g.N, (int32_t)cols, (int32_t)nsets, fb.nsteps, fb.step, lambda, u, lam_new, mu,
+                                   ds / 3.0, ds, 0, s);
+                jt(g, p, (int32_t)nsets, (int32_t)nops, Zs[2], mu, u, eta, geta, tmp, fb.nsteps, fb.step, s);
+                launch_adj_combine(g.N, (int32_t)cols, (int32_t)nsets, fb.nsteps, fb.step, lambda, u, lam_new, mu,
+                                   ds / 3.0, 0.5 * ds, 0, s);
+                jt(g, p, (int32_t)nsets, (int32_t)nops, Zs[1], mu, u, eta, geta, tmp, fb.nsteps, fb.step, s);
+                launch_adj_combine(g.N, (int32_t)cols, (int32_t)nsets, fb.nsteps, fb.step, lambda, u, lam_new, mu,
+                                   ds / 6.0, 0.5 * ds, 0, s);
+                jt(g, p, (int32_t)nsets, (int32_t)nops, Zs[0], mu, u, eta, geta, tmp, fb.nsteps, fb.step, s);
+                launch_adj_combine(g.N, (int32_t)cols, (int32_t)nsets, fb.nsteps, fb.step, lambda, u, lam_new,
+                                   nullptr, 0.0, 0.0, 0, s);
+                launch_copy_active(g.N, (int32_t)cols, (int32_t)nsets, fb.nsteps, fb.step, lam_new, lambda, s);
+            }
+        }
+        launch_set_scalar(fb.flag, 0, s);
+        launch_finite_check(lambda, M, fb.flag, s);
+        HIP_CHECK(hipGetLastError());
+        int32_t flag = 0;
+        HIP_CHECK(hipMemcpyAsync(&flag, fb.flag, 4, hipMemcpyDeviceToHost, s));
+        HIP_CHECK(hipStreamSynchronize(s));
+        if (flag) CUT_FAIL(CUT_E_NUMERIC, "adjoint produced non-finite values");
+        return CUT_OK;
+    } catch (const Fail& f) {
+        return f.st;
+    } catch (const std::bad_alloc&) {
+        set_error("out of host memory");
+        return CUT_E_NOMEM;
+    }
+}

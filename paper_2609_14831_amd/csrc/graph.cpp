@@ -1,0 +1,359 @@
+// Graph load: validated reload of a bundle (Sec. 2.3) and the device layout.
+//
+// Device layout per record set (E_L, E_eta):
+//   orientation 0: grouped by target k, records (a=i, b=j) in stored (i, j) order
+//   orientation 1: grouped by right input j, records (a=i, b=k), ordered (k, i)
+//   orientation 2: grouped by left input i, records (a=k, b=j), ordered (k, j)
+// Orientations 1 and 2 are the reverse traversals of the same records used by
+// the adjoint (Sec. 2.4); they are built by a stable counting sort on the host.
+// Each record is 8 bytes: int32 (factor code << 24 | a), int32 b, with the
+// factor looked up in a table of at most 256 distinct values.
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+
+#include "internal.h"
+
+namespace cut {
+
+static thread_local char g_err[512] = "";
+
+void set_error(const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+}
+
+template <class T>
+static T* dev_alloc(size_t n) {
+    void* p = nullptr;
+    if (n == 0) n = 1;
+    hipError_t e = hipMalloc(&p, n * sizeof(T));
+    if (e != hipSuccess) CUT_FAIL(CUT_E_NOMEM, "hipMalloc(%zu bytes): %s", n * sizeof(T), hipGetErrorString(e));
+    return (T*)p;
+}
+
+template <class T>
+static void dev_free(T*& p) {
+    if (p) (void)hipFree((void*)p);
+    p = nullptr;
+}
+
+void DevCSR::release() {
+    dev_free(off);
+    dev_free(rec);
+    dev_free(tasks);
+    off_h.clear();
+    off_h.shrink_to_fit();
+    nseg = nrec = ntasks = per_xcd = 0;
+}
+
+void* Workspace::get(size_t need) {
+    if (need <= bytes) return ptr;
+    if (ptr) {
+        HIP_CHECK(hipDeviceSynchronize());
+        (void)hipFree(ptr);
+        ptr = nullptr;
+        bytes = 0;
+    }
+    size_t nb = std::max(need, bytes + bytes / 2);
+    hipError_t e = hipMalloc(&ptr, nb);
+    if (e != hipSuccess) {
+        ptr = nullptr;
+        CUT_FAIL(CUT_E_NOMEM, "workspace hipMalloc(%zu): %s", nb, hipGetErrorString(e));
+    }
+    bytes = nb;
+    return ptr;
+}
+
+void Workspace::release() {
+    if (ptr) (void)hipFree(ptr);
+    ptr = nullptr;
+    bytes = 0;
+}
+
+void release_step_graphs(Graph& g);
+
+Graph::~Graph() {
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    (void)hipSetDevice(device);
+    release_step_graphs(*this);
+    for (auto& w : csr)
+        for (auto& c : w) c.release();
+    dev_free(ftab);
+    dev_free(diag);
+    dev_free(pairs);
+    dev_free(stencil);
+    dev_free(st_t_off);
+    dev_free(st_t);
+    dev_free(st_p_off);
+    dev_free(st_p);
+    ws.release();
+    ws_small.release();
+    (void)hipSetDevice(cur);
+}
+
+// Tiling plan.  Targets longer than long_records become one task split over the
+// four wavefronts; shorter consecutive targets are packed four per task.  With
+// XCD remapping, the target range is cut into 8 contiguous pieces of equal
+// record count (one per XCD, so neighbouring targets share one L2), each piece
+// lists its long tasks first; shorter lists are padded with empty tasks.
+void build_tasks(Graph& g, DevCSR& c) {
+    dev_free(c.tasks);
+    c.ntasks = c.per_xcd = 0;
+    if (c.nseg == 0) return;
+    const std::vector<int64_t>& off = c.off_h;
+    auto plan = [&](int64_t b, int64_t e, std::vector<Task>& out) {
+        std::vector<Task> shorts;
+        for (int64_t k = b; k < e;) {
+            if (off[k + 1] - off[k] > g.long_records) {
+                out.push_back({(int32_t)k, -1});
+                ++k;
+                continue;
+            }
+            int64_t k0 = k;
+            int n = 0;
+            while (k < e && n < 4 && off[k + 1] - off[k] <= g.long_records) {
+                ++k;
+                ++n;
+            }
+            shorts.push_back({(int32_t)k0, n});
+        }
+        out.insert(out.end(), shorts.begin(), shorts.end());
+    };
+    std::vector<Task> all;
+    if (g.xcd_remap) {
+        std::vector<std::vector<Task>> parts(8);
+        const int64_t total = off[c.nseg] + 64 * c.nseg;  // records + per-target overhead
+        int64_t b = 0;
+        for (int x = 0; x < 8; ++x) {
+            int64_t e = b;
+            const int64_t goal = total * (x + 1) / 8;
+            while (e < c.nseg && (off[e] + 64 * e) < goal) ++e;
+            if (x == 7) e = c.nseg;
+            plan(b, e, parts[x]);
+            b = e;
+        }
+        size_t per = 0;
+        for (auto& p : parts) per = std::max(per, p.size());
+        all.assign(per * 8, Task{0, 0});
+        for (int x = 0; x < 8; ++x) std::copy(parts[x].begin(), parts[x].end(), all.begin() + x * per);
+        c.per_xcd = (int64_t)per;
+    } else {
+        plan(0, c.nseg, all);
+    }
+    c.ntasks = (int64_t)all.size();
+    c.tasks = dev_alloc<Task>(all.size());
+    HIP_CHECK(hipMemcpy(c.tasks, all.data(), all.size() * sizeof(Task), hipMemcpyHostToDevice));
+}
+
+static void upload_csr(Graph& g, DevCSR& c, int64_t nseg, std::vector<int64_t>&& off,
+                       const std::vector<uint2>& rec) {
+    c.nseg = nseg;
+    c.nrec = (int64_t)rec.size();
+    c.max_len = 0;
+    for (int64_t k = 0; k < nseg; ++k) c.max_len = std::max(c.max_len, off[k + 1] - off[k]);
+    c.off = dev_alloc<int64_t>(nseg + 1);
+    HIP_CHECK(hipMemcpy(c.off, off.data(), (nseg + 1) * sizeof(int64_t), hipMemcpyHostToDevice));
+    c.rec = dev_alloc<uint2>(rec.size());
+    if (!rec.empty()) HIP_CHECK(hipMemcpy(c.rec, rec.data(), rec.size() * sizeof(uint2), hipMemcpyHostToDevice));
+    c.off_h = std::move(off);
+    build_tasks(g, c);
+}
+
+// orientation 0 from the bundle; 1 and 2 by stable counting sort
+static void build_copies(Graph& g, const HostGraph& hg, int w, bool adjoint, const uint8_t* code) {
+    const int64_t N = hg.hdr.n_ops;
+    const int64_t E = w == 0 ? hg.hdr.n_records : hg.hdr.n_gen_records;
+    const int64_t* off = hg.off[w];
+    const int32_t* ri = hg.ri[w];
+    const int32_t* rj = hg.rj[w];
+    const int8_t* rc = hg.rc[w];
+    {
+        std::vector<uint2> rec((size_t)E);
+        for (int64_t e = 0; e < E; ++e)
+            rec[e] = make_uint2(((uint32_t)code[(uint8_t)rc[e]] << 24) | (uint32_t)ri[e], (uint32_t)rj[e]);
+        upload_csr(g, g.csr[w][0], N, std::vector<int64_t>(off, off + N + 1), rec);
+    }
+    if (!adjoint) return;
+    for (int o = 1; o <= 2; ++o) {
+        const int32_t* key = o == 1 ? rj : ri;
+        std::vector<int64_t> noff(N + 1, 0);
+        for (int64_t e = 0; e < E; ++e) noff[key[e] + 1]++;
+        for (int64_t k = 0; k < N; ++k) noff[k + 1] += noff[k];
+        std::vector<int64_t> cur(noff.begin(), noff.end() - 1);
+        std::vector<uint2> rec((size_t)E);
+        for (int64_t k = 0; k < N; ++k)
+            for (int64_t e = off[k]; e < off[k + 1]; ++e) {
+                const uint32_t cc = (uint32_t)code[(uint8_t)rc[e]] << 24;
+                if (o == 1) rec[cur[rj[e]]++] = make_uint2(cc | (uint32_t)ri[e], (uint32_t)k);
+                else rec[cur[ri[e]]++] = make_uint2(cc | (uint32_t)k, (uint32_t)rj[e]);
+            }
+        upload_csr(g, g.csr[w][o], N, std::move(noff), rec);
+    }
+}
+
+// G2 stencil: the E_L records of target S whose left input is a pair coordinate
+// P_a (the Wegner terms of the quadratic diagonal part), at most 4 per target.
+static void build_stencil(Graph& g, const HostGraph& hg, const uint8_t* code) {
+    const int64_t N = hg.hdr.n_ops, np = hg.hdr.n_pairs;
+    std::vector<int32_t> pair_of(N, -1);
+    for (int64_t a = 0; a < np; ++a) pair_of[hg.pairs[a]] = (int32_t)a;
+    std::vector<int4> st((size_t)N * 4, make_int4(-1, 0, 0, 0));
+    const int64_t* off = hg.off[0];
+    for (int64_t S = 0; S < N; ++S) {
+        int n = 0;
+        for (int64_t e = off[S]; e < off[S + 1]; ++e) {
+            const int32_t a = pair_of[hg.ri[0][e]];
+            if (a < 0) continue;
+            if (n == 4) return;  // not a pair-flip algebra: no G2 stencil
+            st[S * 4 + n++] = make_int4(hg.rj[0][e], a, code[(uint8_t)hg.rc[0][e]], 0);
+        }
+    }
+    // transposed stencil (by partner row) and per-pair lists, in (S, t) order
+    std::vector<int64_t> toff(N + 1, 0), poff(np + 1, 0);
+    for (int64_t q = 0; q < N * 4; ++q)
+        if (st[q].x >= 0) {
+            toff[st[q].x + 1]++;
+            poff[st[q].y + 1]++;
+        }
+    for (int64_t r = 0; r < N; ++r) toff[r + 1] += toff[r];
+    for (int64_t a = 0; a < np; ++a) poff[a + 1] += poff[a];
+    std::vector<int4> tent(toff[N]), pent(poff[np]);
+    std::vector<int64_t> tc(toff.begin(), toff.end() - 1), pc(poff.begin(), poff.end() - 1);
+    for (int64_t S = 0; S < N; ++S)
+        for (int t = 0; t < 4; ++t) {
+            const int4 e = st[S * 4 + t];
+            if (e.x < 0) break;
+            tent[tc[e.x]++] = make_int4((int32_t)S, e.y, e.z, 0);
+            pent[pc[e.y]++] = make_int4((int32_t)S, e.x, e.z, 0);
+        }
+    g.stencil = dev_alloc<int4>(st.size());
+    HIP_CHECK(hipMemcpy(g.stencil, st.data(), st.size() * sizeof(int4), hipMemcpyHostToDevice));
+    g.st_t_off = dev_alloc<int64_t>(N + 1);
+    HIP_CHECK(hipMemcpy(g.st_t_off, toff.data(), (N + 1) * 8, hipMemcpyHostToDevice));
+    g.st_t = dev_alloc<int4>(tent.size());
+    if (!tent.empty()) HIP_CHECK(hipMemcpy(g.st_t, tent.data(), tent.size() * sizeof(int4), hipMemcpyHostToDevice));
+    g.st_p_off = dev_alloc<int64_t>(np + 1);
+    HIP_CHECK(hipMemcpy(g.st_p_off, poff.data(), (np + 1) * 8, hipMemcpyHostToDevice));
+    g.st_p = dev_alloc<int4>(pent.size());
+    if (!pent.empty()) HIP_CHECK(hipMemcpy(g.st_p, pent.data(), pent.size() * sizeof(int4), hipMemcpyHostToDevice));
+    g.have_stencil = true;
+}
+
+}  // namespace cut
+
+using namespace cut;
+
+extern "C" const char* cut_last_error(void) { return g_err; }
+extern "C" const char* cut_version(void) { return "cutgraph 1.0 gfx950"; }
+
+extern "C" cut_status cut_graph_load(const char* path, int32_t dev, uint32_t flags, cut_graph_t* out) {
+    Graph* g = nullptr;
+    int prev = 0;
+    bool switched = false;
+    try {
+        if (!path || !out) CUT_FAIL(CUT_E_INVAL, "cut_graph_load: null argument");
+        *out = nullptr;
+        HostGraph hg;
+        read_bundle(path, (flags & CUT_LOAD_NO_CHECKSUM) == 0, hg);
+        const int64_t N = hg.hdr.n_ops;
+        if (N >= (1ll << 24)) CUT_FAIL(CUT_E_UNSUPPORTED, "registry of %lld exceeds 2^24 rows", (long long)N);
+        // factor dictionary over both record sets
+        uint8_t code[256];
+        std::memset(code, 0, sizeof code);
+        std::vector<double> ftab;
+        {
+            bool seen[256] = {false};
+            for (int w = 0; w < 2; ++w) {
+                const int64_t E = w == 0 ? hg.hdr.n_records : hg.hdr.n_gen_records;
+                for (int64_t e = 0; e < E; ++e) seen[(uint8_t)hg.rc[w][e]] = true;
+            }
+            for (int v = -128; v < 128; ++v)
+                if (seen[(uint8_t)v]) {
+                    code[(uint8_t)v] = (uint8_t)ftab.size();
+                    ftab.push_back((double)v);
+                }
+        }
+        HIP_CHECK(hipGetDevice(&prev));
+        HIP_CHECK(hipSetDevice(dev));
+        switched = true;
+        g = new Graph();
+        g->device = dev;
+        g->hdr = hg.hdr;
+        g->N = N;
+        g->gen_sign = hg.hdr.gen_sign;
+        g->nfactors = (int)ftab.size();
+        g->ftab = dev_alloc<double>(256);
+        ftab.resize(256, 0.0);
+        HIP_CHECK(hipMemcpy(g->ftab, ftab.data(), 256 * sizeof(double), hipMemcpyHostToDevice));
+        const bool adj = (flags & CUT_LOAD_ADJOINT) != 0;
+        build_copies(*g, hg, 0, adj, code);
+        build_copies(*g, hg, 1, adj, code);
+        g->have_adjoint = adj;
+        g->diag = dev_alloc<uint8_t>(N);
+        HIP_CHECK(hipMemcpy(g->diag, hg.diag, N, hipMemcpyHostToDevice));
+        g->npairs = hg.hdr.n_pairs;
+        g->pairs = dev_alloc<int32_t>(g->npairs);
+        if (g->npairs) HIP_CHECK(hipMemcpy(g->pairs, hg.pairs, g->npairs * 4, hipMemcpyHostToDevice));
+        build_stencil(*g, hg, code);
+        HIP_CHECK(hipDeviceSynchronize());
+        HIP_CHECK(hipSetDevice(prev));
+        *out = (cut_graph_t)g;
+        return CUT_OK;
+    } catch (const Fail& f) {
+        delete g;
+        if (switched) (void)hipSetDevice(prev);
+        return f.st;
+    } catch (const std::bad_alloc&) {
+        delete g;
+        if (switched) (void)hipSetDevice(prev);
+        set_error("cut_graph_load: out of host memory");
+        return CUT_E_NOMEM;
+    }
+}
+
+extern "C" void cut_graph_free(cut_graph_t h) { delete (Graph*)h; }
+
+extern "C" cut_status cut_graph_info(cut_graph_t h, cut_graph_desc* d) {
+    if (!h || !d) {
+        set_error("cut_graph_info: null argument");
+        return CUT_E_INVAL;
+    }
+    const Graph& g = *(const Graph*)h;
+    std::memset(d, 0, sizeof *d);
+    d->algebra = g.hdr.algebra;
+    d->size = g.hdr.size;
+    d->n_ops = g.N;
+    d->n_records = g.hdr.n_records;
+    d->n_gen_records = g.hdr.n_gen_records;
+    d->n_pairs = g.hdr.n_pairs;
+    d->checksum = g.hdr.records_checksum;
+    d->file_bytes = (int64_t)g.hdr.file_bytes;
+    std::strncpy(d->identifier, g.hdr.identifier, sizeof d->identifier - 1);
+    return CUT_OK;
+}
+
+extern "C" cut_status cut_graph_set_tiling(cut_graph_t h, int64_t long_records, int32_t xcd_remap) {
+    try {
+        if (!h || long_records < 1) CUT_FAIL(CUT_E_INVAL, "cut_graph_set_tiling: bad argument");
+        Graph& g = *(Graph*)h;
+        int prev = 0;
+        HIP_CHECK(hipGetDevice(&prev));
+        HIP_CHECK(hipSetDevice(g.device));
+        HIP_CHECK(hipDeviceSynchronize());
+        g.long_records = long_records;
+        g.xcd_remap = xcd_remap ? 1 : 0;
+        for (auto& w : g.csr)
+            for (auto& c : w)
+                if (c.nseg) build_tasks(g, c);
+        HIP_CHECK(hipSetDevice(prev));
+        return CUT_OK;
+    } catch (const Fail& f) {
+        return f.st;
+    }
+}

@@ -1,0 +1,542 @@
+// gfx950 kernels of the compiled-CUT-graph path.
+//
+// k_pass: segmented gather-multiply-reduce over one target-grouped record
+// stream (Sec. 2.2: records that contribute to the same output are stored
+// together and reduced directly into it).  One wavefront owns one output
+// segment (or a quarter of a long one); its 64 lanes are split into R = 64/G
+// record slots x G coefficient sets, so every gather is a contiguous run of G
+// sets of one operand row.  Reductions are fixed-order (butterfly shuffles,
+// then an ordered LDS combine for split segments): results are bitwise
+// reproducible run to run.
+//
+//   MODE_BCAST : out[seg][op][s] = sum_e c_e * A[a_e][s] * B[b_e][op][s]
+//                (forward action with a=i, b=j; adjoint-x with a=i, b=k)
+//   MODE_REDOPS: out[seg][s]     = sum_e c_e * sum_op A[a_e][op][s] * B[b_e][op][s]
+//                (adjoint-eta with a=k, b=j)
+//
+// Epilogues: EPI_Y (store / accumulate a double result, scaled), EPI_ETA
+// (generator graph pass: store eta in the stage precision), EPI_RK (classic RK4
+// stage combination fused into the flow pass, Eq. coflow integrated at fixed ds).
+#include <hip/hip_runtime.h>
+
+#include "internal.h"
+
+namespace cut {
+
+struct KArgs {
+    const Task* tasks;
+    int64_t ntasks;
+    int64_t per_xcd;  // >0: task = (bid % 8) * per_xcd + bid / 8
+    const int64_t* off;
+    const uint2* rec;
+    const double* ftab;
+    const void* A;
+    int64_t lda;
+    const void* B;
+    int64_t ldb;
+    int32_t nsets, nops;
+    const int32_t* nsteps;
+    const int32_t* step;
+    void* y;
+    int64_t ldy;
+    int32_t accumulate;
+    int32_t out_f32;
+    double scale;
+    int32_t stage;
+    double ds;
+    double* z;
+    double* acc;
+    void* xout;
+    double* hst;
+    int64_t ldh;
+};
+
+template <int PREC>
+struct PrecT {
+    using T = float;
+};
+template <>
+struct PrecT<CUT_F64> {
+    using T = double;
+};
+
+// Accumulator of one lane for one operand column.
+template <int PREC>
+struct Acc;
+
+template <>
+struct Acc<CUT_F64> {
+    double v = 0.0;
+    __device__ void add(double t, double b) { v = __builtin_fma(t, b, v); }
+    __device__ double get() const { return v; }
+};
+template <>
+struct Acc<CUT_F32X> {
+    double v = 0.0;
+    __device__ void add(double t, float b) { v = __builtin_fma(t, (double)b, v); }
+    __device__ double get() const { return v; }
+};
+template <>
+struct Acc<CUT_F32> {
+    float v = 0.f;
+    __device__ void add(float t, float b) { v = __builtin_fmaf(t, b, v); }
+    __device__ double get() const { return (double)v; }
+};
+// Compensated: error-free product (FMA) and error-free sum (two-sum); the
+// running error terms are summed in a second float.
+template <>
+struct Acc<CUT_F32C> {
+    float hi = 0.f, lo = 0.f;
+    __device__ void add(float t, float b) {
+        // the error-free transformations need every operation rounded on its
+        // own: no contraction of t*b into the following additions
+#pragma clang fp contract(off)
+        float p = t * b;
+        float pe = __builtin_fmaf(t, b, -p);
+        float s = hi + p;
+        float bb = s - hi;
+        float se = (hi - (s - bb)) + (p - bb);
+        hi = s;
+        lo += se + pe;
+    }
+    __device__ double get() const { return (double)hi + (double)lo; }
+};
+
+// scaled left operand in the accumulation type
+template <int PREC>
+__device__ inline auto left_term(double cf, typename PrecT<PREC>::T av) {
+    if constexpr (PREC == CUT_F64) return cf * av;
+    else if constexpr (PREC == CUT_F32X) return cf * (double)av;
+    else return (float)cf * av;
+}
+
+__device__ inline bool set_active(const KArgs& a, int s) {
+    if (s >= a.nsets) return false;
+    if (a.nsteps == nullptr) return true;
+    return a.nsteps[s] > *a.step;
+}
+
+template <int G, int NOPS, int PREC, int MODE, int EPI>
+__global__ __launch_bounds__(256) void k_pass(KArgs a) {
+    using T = typename PrecT<PREC>::T;
+    constexpr int R = 64 / G;
+    constexpr int NACC = (MODE == MODE_REDOPS) ? 1 : NOPS;
+    __shared__ double red[4][NACC][G];
+
+    int64_t t = blockIdx.x;
+    if (a.per_xcd > 0) {
+        t = (int64_t)(blockIdx.x & 7) * a.per_xcd + (blockIdx.x >> 3);
+        if ((blockIdx.x >> 3) >= a.per_xcd) return;
+    }
+    if (t >= a.ntasks) return;
+    const Task task = a.tasks[t];
+    const int wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int sg = lane % G;
+    const int sub = lane / G;
+    const int s = blockIdx.y * G + sg;
+    const bool act = set_active(a, s);
+    const bool split = task.nseg < 0;
+
+    int64_t seg, e0, e1;
+    if (split) {
+        seg = task.seg;
+        const int64_t b = a.off[seg], n = a.off[seg + 1] - b;
+        e0 = b + (n * wave) / 4;
+        e1 = b + (n * (wave + 1)) / 4;
+    } else {
+        if (wave >= task.nseg) return;  // block-uniform task kind: no barrier below
+        seg = task.seg + wave;
+        e0 = a.off[seg];
+        e1 = a.off[seg + 1];
+    }
+
+    Acc<PREC> acc[NACC];
+    const T* __restrict__ A = (const T*)a.A;
+    const T* __restrict__ B = (const T*)a.B;
+    const int nsets = a.nsets, nops = a.nops;
+    if (act) {
+        for (int64_t e = e0 + sub; e < e1; e += R) {
+            const uint2 r = a.rec[e];
+            const int64_t ia = r.x & 0xFFFFFFu;
+            const int64_t ib = r.y;
+            const double cf = a.ftab[r.x >> 24];
+            if constexpr (MODE == MODE_BCAST) {
+                const auto tl = left_term<PREC>(cf, A[ia * a.lda + s]);
+                const T* brow = B + ib * a.ldb + s;
+#pragma unroll
+                for (int op = 0; op < NOPS; ++op)
+                    if (op < nops) acc[op].add(tl, brow[(int64_t)op * nsets]);
+            } else {
+                const T* arow = A + ia * a.lda + s;
+                const T* brow = B + ib * a.ldb + s;
+                // sum over operand columns first, then one scaled accumulation
+                if constexpr (PREC == CUT_F64 || PREC == CUT_F32X) {
+                    double d = 0.0;
+#pragma unroll
+                    for (int op = 0; op < NOPS; ++op)
+                        if (op < nops) d = __builtin_fma((double)arow[(int64_t)op * nsets],
+                                                         (double)brow[(int64_t)op * nsets], d);
+                    acc[0].v = __builtin_fma(cf, d, acc[0].v);
+                } else {
+                    const float fc = (float)cf;
+#pragma unroll
+                    for (int op = 0; op < NOPS; ++op)
+                        if (op < nops) acc[0].add(fc * arow[(int64_t)op * nsets], brow[(int64_t)op * nsets]);
+                }
+            }
+        }
+    }
+
+    double v[NACC];
+#pragma unroll
+    for (int q = 0; q < NACC; ++q) {
+        v[q] = acc[q].get();
+#pragma unroll
+        for (int o = G; o < 64; o <<= 1) v[q] += __shfl_xor(v[q], o);
+    }
+    if (split) {
+        if (sub == 0) {
+#pragma unroll
+            for (int q = 0; q < NACC; ++q) red[wave][q][sg] = v[q];
+        }
+        __syncthreads();
+        if (wave != 0) return;
+#pragma unroll
+        for (int q = 0; q < NACC; ++q) {
+            if (sub == 0) v[q] = ((red[0][q][sg] + red[1][q][sg]) + red[2][q][sg]) + red[3][q][sg];
+        }
+    }
+    if (sub != 0 || !act) return;
+
+    if constexpr (EPI == EPI_Y) {
+        double* y = (double*)a.y + seg * a.ldy + s;
+        if constexpr (MODE == MODE_REDOPS) {
+            y[0] = a.accumulate ? y[0] + a.scale * v[0] : a.scale * v[0];
+        } else {
+#pragma unroll
+            for (int op = 0; op < NOPS; ++op)
+                if (op < nops) {
+                    double& o = y[(int64_t)op * nsets];
+                    o = a.accumulate ? o + a.scale * v[op] : a.scale * v[op];
+                }
+        }
+    } else if constexpr (EPI == EPI_ETA) {
+        if (a.out_f32) ((float*)a.y)[seg * a.ldy + s] = (float)(a.scale * v[0]);
+        else ((double*)a.y)[seg * a.ldy + s] = a.scale * v[0];
+    } else {  // EPI_RK: stage combination of classic RK4
+        const double ds = a.ds;
+        T* xo = (T*)a.xout;
+#pragma unroll
+        for (int op = 0; op < NOPS; ++op) {
+            if (op >= nops) break;
+            const int64_t idx = seg * a.ldb + (int64_t)op * nsets + s;
+            const double zk = a.z[idx];
+            const double f = v[op];
+            double nxt;
+            if (a.stage == 0) {
+                a.acc[idx] = zk + (ds / 6.0) * f;
+                nxt = zk + 0.5 * ds * f;
+            } else if (a.stage == 1) {
+                a.acc[idx] += (ds / 3.0) * f;
+                nxt = zk + 0.5 * ds * f;
+            } else if (a.stage == 2) {
+                a.acc[idx] += (ds / 3.0) * f;
+                nxt = zk + ds * f;
+            } else {
+                nxt = a.acc[idx] + (ds / 6.0) * f;
+                a.z[idx] = nxt;
+            }
+            xo[idx] = (T)nxt;
+            if (op == 0) a.hst[seg * a.ldh + s] = nxt;
+        }
+    }
+}
+
+// ------------------------------------------------------------- dispatch ----
+template <int G, int NOPS, int MODE, int EPI>
+static void launch_prec(const KArgs& k, int prec, dim3 grid, hipStream_t s) {
+    switch (prec) {
+        case CUT_F64: hipLaunchKernelGGL((k_pass<G, NOPS, CUT_F64, MODE, EPI>), grid, dim3(256), 0, s, k); break;
+        case CUT_F32X: hipLaunchKernelGGL((k_pass<G, NOPS, CUT_F32X, MODE, EPI>), grid, dim3(256), 0, s, k); break;
+        case CUT_F32C: hipLaunchKernelGGL((k_pass<G, NOPS, CUT_F32C, MODE, EPI>), grid, dim3(256), 0, s, k); break;
+        default: hipLaunchKernelGGL((k_pass<G, NOPS, CUT_F32, MODE, EPI>), grid, dim3(256), 0, s, k); break;
+    }
+}
+
+template <int G, int MODE, int EPI>
+static void launch_nops(const KArgs& k, int prec, dim3 grid, hipStream_t s) {
+    if constexpr (EPI == EPI_ETA) {
+        hipLaunchKernelGGL((k_pass<G, 1, CUT_F64, MODE_BCAST, EPI_ETA>), grid, dim3(256), 0, s, k);
+    } else {
+        if (k.nops <= 1) launch_prec<G, 1, MODE, EPI>(k, prec, grid, s);
+        else if (k.nops <= 2) launch_prec<G, 2, MODE, EPI>(k, prec, grid, s);
+        else if (k.nops <= 4) launch_prec<G, 4, MODE, EPI>(k, prec, grid, s);
+        else launch_prec<G, 8, MODE, EPI>(k, prec, grid, s);
+    }
+}
+
+template <int MODE, int EPI>
+static void launch_g(const KArgs& k, int prec, int G, dim3 grid, hipStream_t s) {
+    switch (G) {
+        case 1: launch_nops<1, MODE, EPI>(k, prec, grid, s); break;
+        case 2: launch_nops<2, MODE, EPI>(k, prec, grid, s); break;
+        case 4: launch_nops<4, MODE, EPI>(k, prec, grid, s); break;
+        case 8: launch_nops<8, MODE, EPI>(k, prec, grid, s); break;
+        case 16: launch_nops<16, MODE, EPI>(k, prec, grid, s); break;
+        case 32: launch_nops<32, MODE, EPI>(k, prec, grid, s); break;
+        default: launch_nops<64, MODE, EPI>(k, prec, grid, s); break;
+    }
+}
+
+static int group_width(int nsets) {
+    int g = 1;
+    while (g < nsets && g < 64) g <<= 1;
+    return g;
+}
+
+void launch_pass(int mode, int epi, const PassArgs& p, hipStream_t s) {
+    const DevCSR& c = *p.csr;
+    if (c.nseg == 0) return;
+    KArgs k{};
+    k.tasks = c.tasks;
+    k.ntasks = c.ntasks;
+    k.per_xcd = c.per_xcd;
+    k.off = c.off;
+    k.rec = c.rec;
+    k.ftab = p.ftab;
+    k.A = p.A;
+    k.lda = p.lda;
+    k.B = p.B;
+    k.ldb = p.ldb;
+    k.nsets = p.nsets;
+    k.nops = p.nops;
+    k.nsteps = p.nsteps;
+    k.step = p.step;
+    k.y = p.y;
+    k.ldy = p.ldy;
+    k.accumulate = p.accumulate;
+    k.out_f32 = p.precision != CUT_F64;
+    k.scale = p.scale;
+    k.stage = p.stage;
+    k.ds = p.ds;
+    k.z = p.z;
+    k.acc = p.acc;
+    k.xout = p.xout;
+    k.hst = p.hst;
+    k.ldh = p.ldh;
+    const int G = group_width(p.nsets);
+    const int64_t nblk = c.per_xcd > 0 ? 8 * c.per_xcd : c.ntasks;
+    dim3 grid((unsigned)nblk, (unsigned)((p.nsets + G - 1) / G));
+    if (mode == MODE_BCAST) {
+        if (epi == EPI_Y) launch_g<MODE_BCAST, EPI_Y>(k, p.precision, G, grid, s);
+        else if (epi == EPI_ETA) launch_g<MODE_BCAST, EPI_ETA>(k, p.precision, G, grid, s);
+        else launch_g<MODE_BCAST, EPI_RK>(k, p.precision, G, grid, s);
+    } else {
+        launch_g<MODE_REDOPS, EPI_Y>(k, p.precision, G, grid, s);
+    }
+}
+
+// ------------------------------------------------------------ generator ----
+// G2: eta_S = s_g * sum_t c_t eps_{a_t} h_{p_t} / (sum_t (c_t eps_{a_t})^2 + delta^2)
+// over the stencil rows t of S (the generator records whose left input is a
+// pair coordinate P_a); FP64 arithmetic, eta stored in the stage precision.
+__global__ void k_g2(int64_t N, int32_t nsets, const int4* __restrict__ st,
+                     const int32_t* __restrict__ pairs, const double* __restrict__ ftab,
+                     double gsign, double d2, const double* __restrict__ h, int64_t ldh, void* eta,
+                     int64_t lde, int eta_f32, const int32_t* nsteps, const int32_t* step) {
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t S = gid / nsets;
+    const int s = (int)(gid % nsets);
+    if (S >= N) return;
+    if (nsteps && nsteps[s] <= *step) return;
+    double num = 0.0, q = 0.0;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const int4 e = st[S * 4 + t];
+        if (e.x < 0) break;
+        const double c = ftab[e.z];
+        const double eps = h[(int64_t)pairs[e.y] * ldh + s];
+        num = __builtin_fma(c * eps, h[(int64_t)e.x * ldh + s], num);
+        q = __builtin_fma(c * eps, c * eps, q);
+    }
+    const bool has = st[S * 4].x >= 0;
+    const double v = has ? gsign * num / (q + d2) : 0.0;
+    if (eta_f32) ((float*)eta)[S * lde + s] = (float)v;
+    else ((double*)eta)[S * lde + s] = v;
+}
+
+// VJP stage 1: per stencil target S, w_S = gbar_S / Q_S and u_S = gbar_S * Nsig_S / Q_S^2
+// where Nsig_S = s_g * sum_t c_t eps h_p (so eta_S = Nsig_S / Q_S).
+__global__ void k_g2_vjp_prep(int64_t N, int32_t nsets, const int4* __restrict__ st,
+                              const int32_t* __restrict__ pairs, const double* __restrict__ ftab,
+                              double gsign, double d2, const double* __restrict__ h, int64_t ldh,
+                              const double* __restrict__ gbar, int64_t ldg, double* w, double* u) {
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t S = gid / nsets;
+    const int s = (int)(gid % nsets);
+    if (S >= N) return;
+    double num = 0.0, q = 0.0;
+    for (int t = 0; t < 4; ++t) {
+        const int4 e = st[S * 4 + t];
+        if (e.x < 0) break;
+        const double c = ftab[e.z];
+        const double eps = h[(int64_t)pairs[e.y] * ldh + s];
+        num = __builtin_fma(c * eps, h[(int64_t)e.x * ldh + s], num);
+        q = __builtin_fma(c * eps, c * eps, q);
+    }
+    const bool has = st[S * 4].x >= 0;
+    q += d2;
+    const double gb = has ? gbar[S * ldg + s] : 0.0;
+    w[S * nsets + s] = gb / q;
+    u[S * nsets + s] = gb * (gsign * num) / (q * q);
+}
+
+// VJP stage 2 (gather form, fixed order):
+//  g_h[r] += sum_{(S,t): p_t(S)=r} s_g c_t eps_{a_t} w_S                    (d eta_S / d h_p)
+//  g_h[P_a] += sum_{(S,t): a_t=a} (s_g c_t h_{p_t} w_S - 2 c_t^2 eps_a u_S)  (d eta_S / d eps_a)
+__global__ void k_g2_vjp_partner(int64_t N, int32_t nsets, const int64_t* __restrict__ toff,
+                                 const int4* __restrict__ tent, const int32_t* __restrict__ pairs,
+                                 const double* __restrict__ ftab, double gsign,
+                                 const double* __restrict__ h, int64_t ldh,
+                                 const double* __restrict__ w, double* g_h, int64_t ldgh) {
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t r = gid / nsets;
+    const int s = (int)(gid % nsets);
+    if (r >= N) return;
+    double acc = 0.0;
+    for (int64_t q = toff[r]; q < toff[r + 1]; ++q) {
+        const int4 e = tent[q];
+        const double eps = h[(int64_t)pairs[e.y] * ldh + s];
+        acc = __builtin_fma(gsign * ftab[e.z] * eps, w[(int64_t)e.x * nsets + s], acc);
+    }
+    g_h[r * ldgh + s] += acc;
+}
+
+// one wavefront per (pair a, set s); lanes stride over the pair's list
+__global__ void k_g2_vjp_pairs(int64_t npairs, int32_t nsets, const int64_t* __restrict__ poff,
+                               const int4* __restrict__ pent, const int32_t* __restrict__ pairs,
+                               const double* __restrict__ ftab, double gsign,
+                               const double* __restrict__ h, int64_t ldh,
+                               const double* __restrict__ w, const double* __restrict__ u,
+                               double* g_h, int64_t ldgh) {
+    const int64_t wid = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int lane = threadIdx.x & 63;
+    const int64_t a = wid / nsets;
+    const int s = (int)(wid % nsets);
+    if (a >= npairs) return;
+    const int64_t pa = pairs[a];
+    const double eps = h[pa * ldh + s];
+    double acc = 0.0;
+    for (int64_t q = poff[a] + lane; q < poff[a + 1]; q += 64) {
+        const int4 e = pent[q];
+        const double c = ftab[e.z];
+        acc += gsign * c * h[(int64_t)e.y * ldh + s] * w[(int64_t)e.x * nsets + s] -
+               2.0 * c * c * eps * u[(int64_t)e.x * nsets + s];
+    }
+    for (int o = 1; o < 64; o <<= 1) acc += __shfl_xor(acc, o);
+    if (lane == 0) g_h[pa * ldgh + s] += acc;
+}
+
+void launch_g2(const Graph& g, double delta, int32_t nsets, const double* h, int64_t ldh, void* eta,
+               int64_t lde, bool eta_f32, const int32_t* nsteps, const int32_t* step, hipStream_t s) {
+    const int64_t n = g.N * nsets;
+    hipLaunchKernelGGL(k_g2, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, g.N, nsets, g.stencil,
+                       g.pairs, g.ftab, g.gen_sign, delta * delta, h, ldh, eta, lde, (int)eta_f32,
+                       nsteps, step);
+}
+
+void launch_g2_vjp(const Graph& g, double delta, int32_t nsets, const double* h, int64_t ldh,
+                   const double* gbar, int64_t ldg, double* g_h, int64_t ldgh, double* tmp,
+                   hipStream_t s) {
+    const int64_t n = g.N * nsets;
+    double* w = tmp;
+    double* u = tmp + n;
+    const unsigned nb = (unsigned)((n + 255) / 256);
+    hipLaunchKernelGGL(k_g2_vjp_prep, dim3(nb), dim3(256), 0, s, g.N, nsets, g.stencil, g.pairs, g.ftab,
+                       g.gen_sign, delta * delta, h, ldh, gbar, ldg, w, u);
+    hipLaunchKernelGGL(k_g2_vjp_partner, dim3(nb), dim3(256), 0, s, g.N, nsets, g.st_t_off, g.st_t,
+                       g.pairs, g.ftab, g.gen_sign, h, ldh, w, g_h, ldgh);
+    const int64_t waves = g.npairs * nsets;
+    hipLaunchKernelGGL(k_g2_vjp_pairs, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, s, g.npairs,
+                       nsets, g.st_p_off, g.st_p, g.pairs, g.ftab, g.gen_sign, h, ldh, w, u, g_h, ldgh);
+}
+
+// ---------------------------------------------------------- elementwise ----
+__global__ void k_prep_state(const double* z, int64_t rows, int32_t nops, int32_t nsets, void* xsh,
+                             int f32, double* hst) {
+    const int64_t cols = (int64_t)nops * nsets;
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= rows * cols) return;
+    const double v = z[q];
+    if (f32) ((float*)xsh)[q] = (float)v;
+    else ((double*)xsh)[q] = v;
+    const int64_t r = q / cols, c = q % cols;
+    if (c < nsets) hst[r * nsets + c] = v;
+}
+
+void launch_prep_state(const double* z, int64_t rows, int32_t nops, int32_t nsets, void* xsh, bool f32,
+                       double* hst, hipStream_t s) {
+    const int64_t n = rows * nops * nsets;
+    hipLaunchKernelGGL(k_prep_state, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, z, rows, nops,
+                       nsets, xsh, (int)f32, hst);
+}
+
+__global__ void k_bump(int32_t* step) {
+    if (threadIdx.x == 0) *step += 1;
+}
+__global__ void k_set(int32_t* p, int32_t v) {
+    if (threadIdx.x == 0) *p = v;
+}
+void launch_bump(int32_t* step, hipStream_t s) { hipLaunchKernelGGL(k_bump, dim3(1), dim3(64), 0, s, step); }
+void launch_set_scalar(int32_t* p, int32_t v, hipStream_t s) {
+    hipLaunchKernelGGL(k_set, dim3(1), dim3(64), 0, s, p, v);
+}
+
+// Adjoint RK4 stage combination for active sets:
+//   lam_new (=|+=) u ;  mu = alpha * lam + beta * u
+__global__ void k_adj_combine(int64_t n, int32_t nsets, const int32_t* nsteps, const int32_t* step,
+                              const double* lam, const double* u, double* lam_new, double* mu,
+                              double alpha, double beta, int first) {
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n) return;
+    const int s = (int)(q % nsets);
+    if (nsteps[s] <= *step) return;
+    const double uq = u ? u[q] : 0.0;
+    if (first) lam_new[q] = lam[q] + uq;
+    else lam_new[q] += uq;
+    if (mu) mu[q] = alpha * lam[q] + beta * uq;
+}
+
+void launch_adj_combine(int64_t rows, int32_t ncols, int32_t nsets, const int32_t* nsteps,
+                        const int32_t* step, const double* lam, const double* u, double* lam_new,
+                        double* mu, double alpha, double beta, int first, hipStream_t s) {
+    const int64_t n = rows * ncols;
+    hipLaunchKernelGGL(k_adj_combine, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, nsets, nsteps,
+                       step, lam, u, lam_new, mu, alpha, beta, first);
+}
+
+__global__ void k_copy_active(int64_t n, int32_t nsets, const int32_t* nsteps, const int32_t* step,
+                              const double* src, double* dst) {
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n) return;
+    if (nsteps[q % nsets] <= *step) return;
+    dst[q] = src[q];
+}
+
+void launch_copy_active(int64_t rows, int32_t ncols, int32_t nsets, const int32_t* nsteps,
+                        const int32_t* step, const double* src, double* dst, hipStream_t s) {
+    const int64_t n = rows * ncols;
+    hipLaunchKernelGGL(k_copy_active, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, nsets, nsteps,
+                       step, src, dst);
+}
+
+__global__ void k_finite(const double* z, int64_t n, int32_t* flag) {
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < n && !__builtin_isfinite(z[q])) *flag = 1;
+}
+void launch_finite_check(const double* z, int64_t n, int32_t* flag, hipStream_t s) {
+    hipLaunchKernelGGL(k_finite, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, z, n, flag);
+}
+
+}  // namespace cut

@@ -1,0 +1,39 @@
+"""Test-side reader of the graph bundle file (layout of include/cutgraph.h,
+cut_graph_build): header, section table, then 64-byte aligned sections."""
+from __future__ import annotations
+
+import struct
+
+import numpy as np
+
+HEADER = 256
+SECTION = 32
+NAMES = {1: "labels", 2: "diag", 3: "pairs", 4: "flow_off", 5: "flow_i", 6: "flow_j", 7: "flow_c",
+         8: "gen_off", 9: "gen_i", 10: "gen_j", 11: "gen_c"}
+DT = {1: np.uint64, 2: np.uint8, 3: np.int32, 4: np.int64, 5: np.int32, 6: np.int32, 7: np.int8,
+      8: np.int64, 9: np.int32, 10: np.int32, 11: np.int8}
+
+
+def read(path: str) -> dict:
+    raw = np.fromfile(path, dtype=np.uint8)
+    b = raw.tobytes()
+    assert b[:8] == b"CUTGRPH1"
+    n_sections = struct.unpack_from("<I", b, 64)[0]
+    table = struct.unpack_from("<Q", b, 72)[0]
+    out = {"n_ops": struct.unpack_from("<q", b, 24)[0],
+           "n_records": struct.unpack_from("<q", b, 32)[0],
+           "gen_sign": struct.unpack_from("<i", b, 60)[0],
+           "identifier": b[96:192].split(b"\0")[0].decode()}
+    out["sections"] = {}
+    for s in range(n_sections):
+        sid, eb, off, cnt, ck = struct.unpack_from("<IIQQQ", b, table + s * SECTION)
+        out["sections"][sid] = (off, cnt, eb)
+        out[NAMES[sid]] = np.frombuffer(b, dtype=DT[sid], count=cnt, offset=off)
+    return out
+
+
+def records(d: dict, which: str = "flow"):
+    off = d[f"{which}_off"]
+    k = np.repeat(np.arange(off.size - 1), np.diff(off))
+    return (k.astype(np.int64), d[f"{which}_i"].astype(np.int64), d[f"{which}_j"].astype(np.int64),
+            d[f"{which}_c"].astype(np.float64))

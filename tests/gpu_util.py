@@ -1,0 +1,58 @@
+"""Helpers for the GPU tests: graph build/load cache and error bounds."""
+from __future__ import annotations
+
+import os
+import sys
+import tempfile
+
+import numpy as np
+
+U32 = 2.0 ** -24   # unit roundoff of float32
+U64 = 2.0 ** -53
+
+_cache = {}
+_tmp = tempfile.mkdtemp(prefix="cutgraph_tests_")
+
+
+def dot2_bound(n: int) -> float:
+    """Relative (to sum |terms|) error bound of the compensated dot product."""
+    g = n * U32 / (1 - n * U32)
+    return g * g + 2.0 ** -52
+
+
+def say(msg: str) -> None:
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def graph(L, alg: str, size: int, adjoint: bool = True):
+    key = (alg, size, adjoint)
+    if key not in _cache:
+        path = os.path.join(_tmp, f"{alg}_{size}.cgb")
+        if not os.path.exists(path):
+            L.cut_graph_build(L.CUT_ALG_EPQ if alg == "epq" else L.CUT_ALG_MAJORANA, size, path)
+        _cache[key] = L.cut_graph_load(path, 0, L.CUT_LOAD_ADJOINT if adjoint else 0)
+    return _cache[key]
+
+
+def bundle_path(L, alg: str, size: int) -> str:
+    path = os.path.join(_tmp, f"{alg}_{size}.cgb")
+    if not os.path.exists(path):
+        L.cut_graph_build(L.CUT_ALG_EPQ if alg == "epq" else L.CUT_ALG_MAJORANA, size, path)
+    return path
+
+
+def f32(a: np.ndarray) -> np.ndarray:
+    """FP32 rounding (round to nearest even) of an FP64 array, back in FP64."""
+    return a.astype(np.float32).astype(np.float64)
+
+
+def assert_within(got: np.ndarray, ref: np.ndarray, bound: np.ndarray, what: str) -> float:
+    err = np.abs(got - ref)
+    bad = err > bound
+    if np.any(bad):
+        idx = np.argwhere(bad)[0]
+        raise AssertionError(f"{what}: {int(bad.sum())} elements beyond bound; first {tuple(idx)} "
+                             f"got {got[tuple(idx)]!r} ref {ref[tuple(idx)]!r} bound {bound[tuple(idx)]!r}")
+    scale = np.maximum(bound, 1e-300)
+    return float(np.max(err / scale))

@@ -1,0 +1,139 @@
+"""Host-side tests of the product library (no GPU needed): exported symbols,
+graph compilation bit-exact against the oracle, deterministic rebuilds, and
+bundle validation failures (Sec. 2.3: validated reload)."""
+import ctypes as C
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+import bundle_io
+from oracle import algebra as A
+
+L = pytest.importorskip("paper_2609_14831_amd._lib")
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_library_exports_every_declared_symbol():
+    hdr = open(os.path.join(ROOT, "include", "cutgraph.h")).read()
+    declared = set(re.findall(r"\b(cut_[a-z_]+)\s*\(", hdr))
+    declared -= {"cut_status"}
+    assert declared == set(L.EXPORTS)
+    for name in declared:
+        assert hasattr(L.lib(), name)
+    assert "gfx950" in L.cut_version()
+
+
+@pytest.fixture(scope="module")
+def tmpdir_mod(tmp_path_factory):
+    return tmp_path_factory.mktemp("bundles")
+
+
+def _build(tmpdir, alg, size, threads=0, name=None):
+    p = str(tmpdir / (name or f"g_{alg}_{size}_{threads}.cgb"))
+    L.cut_graph_build(alg, size, p, threads)
+    return p
+
+
+@pytest.mark.parametrize("alg,size", [("epq", 3), ("epq", 8), ("majorana", 4), ("majorana", 8),
+                                      ("majorana", 12), ("majorana", 24)])
+def test_graph_bit_exact_vs_oracle(tmpdir_mod, alg, size):
+    code = L.CUT_ALG_EPQ if alg == "epq" else L.CUT_ALG_MAJORANA
+    d = bundle_io.read(_build(tmpdir_mod, code, size))
+    g = A.graph_for(alg, size)
+    k, i, j, c = bundle_io.records(d, "flow")
+    np.testing.assert_array_equal(k, g.k)
+    np.testing.assert_array_equal(i, g.i)
+    np.testing.assert_array_equal(j, g.j)
+    np.testing.assert_array_equal(c, g.c)
+    ge = g.eta_records()
+    k, i, j, c = bundle_io.records(d, "gen")
+    np.testing.assert_array_equal(k, ge.k)
+    np.testing.assert_array_equal(i, ge.i)
+    np.testing.assert_array_equal(j, ge.j)
+    np.testing.assert_array_equal(c, ge.c)
+    np.testing.assert_array_equal(d["diag"].astype(bool), g.diag)
+    np.testing.assert_array_equal(d["pairs"], g.pairs)
+    assert d["gen_sign"] == g.gen_sign
+    if alg == "majorana":
+        np.testing.assert_array_equal(d["labels"], g.masks)
+
+
+@pytest.mark.parametrize("m", [40])
+def test_graph_sampled_targets_vs_oracle(tmpdir_mod, m):
+    d = bundle_io.read(_build(tmpdir_mod, L.CUT_ALG_MAJORANA, m))
+    reg = A.MajoranaRegistry(m)
+    off = d["flow_off"]
+    nq = math.comb(m, 2)
+    cnt = np.diff(off)
+    assert np.all(cnt[:nq] == 2 * (m - 2) + 2 * math.comb(m - 2, 3))
+    assert np.all(cnt[nq:] == 8 * (m - 4))
+    assert off[-1] == 39_539_760
+    rng = np.random.default_rng(17)
+    sample = np.concatenate([[0, nq - 1, nq, reg.N - 1], rng.integers(0, reg.N, 12)])
+    for t in sample:
+        ii, jj, cc = reg.records_for_target(int(t))
+        sl = slice(off[t], off[t + 1])
+        np.testing.assert_array_equal(d["flow_i"][sl], ii)
+        np.testing.assert_array_equal(d["flow_j"][sl], jj)
+        np.testing.assert_array_equal(d["flow_c"][sl].astype(float), cc)
+
+
+def test_rebuild_is_bitwise_identical_any_thread_count(tmpdir_mod):
+    a = _build(tmpdir_mod, L.CUT_ALG_MAJORANA, 16, threads=1, name="a.cgb")
+    b = _build(tmpdir_mod, L.CUT_ALG_MAJORANA, 16, threads=7, name="b.cgb")
+    assert open(a, "rb").read() == open(b, "rb").read()
+
+
+def _corrupt(src, dst, pos, value=None, truncate=None):
+    data = bytearray(open(src, "rb").read())
+    if truncate is not None:
+        data = data[:truncate]
+    if pos is not None:
+        data[pos] = (data[pos] ^ 0x5A) if value is None else value
+    open(dst, "wb").write(bytes(data))
+    return dst
+
+
+def _load_status(path, flags=0):
+    h = C.c_void_p()
+    return L.lib().cut_graph_load(path.encode(), 0, flags, C.byref(h))
+
+
+def test_load_rejects_corrupt_bundles(tmpdir_mod):
+    """Validation runs on the host before any device call: every case below is
+    rejected without touching a GPU."""
+    src = _build(tmpdir_mod, L.CUT_ALG_MAJORANA, 8, name="v.cgb")
+    d = bundle_io.read(src)
+    off_i, cnt_i, _ = d["sections"][5]
+    off_c, _, _ = d["sections"][7]
+    size = os.path.getsize(src)
+    # flipped record byte -> section checksum
+    assert _load_status(_corrupt(src, str(tmpdir_mod / "c1"), off_i + 5)) == L.CUT_E_CHECKSUM
+    # flipped header byte -> header checksum
+    assert _load_status(_corrupt(src, str(tmpdir_mod / "c2"), 100)) == L.CUT_E_CHECKSUM
+    # wrong magic / truncated / missing file
+    assert _load_status(_corrupt(src, str(tmpdir_mod / "c3"), 0, value=0)) == L.CUT_E_FORMAT
+    assert _load_status(_corrupt(src, str(tmpdir_mod / "c4"), None, truncate=size - 64)) == L.CUT_E_FORMAT
+    assert _load_status(_corrupt(src, str(tmpdir_mod / "c5"), None, truncate=100)) == L.CUT_E_FORMAT
+    assert _load_status(str(tmpdir_mod / "does_not_exist")) == L.CUT_E_IO
+    # out-of-range index / zero factor with checksums skipped -> bounds check
+    bad = _corrupt(src, str(tmpdir_mod / "c6"), off_i + 3, value=0x7F)
+    assert _load_status(bad, L.CUT_LOAD_NO_CHECKSUM) == L.CUT_E_FORMAT
+    bad = _corrupt(src, str(tmpdir_mod / "c7"), off_c + 2, value=0)
+    assert _load_status(bad, L.CUT_LOAD_NO_CHECKSUM) == L.CUT_E_FORMAT
+    assert "section" in L.cut_last_error() or "factor" in L.cut_last_error()
+
+
+def test_build_rejects_bad_arguments(tmpdir_mod):
+    p = str(tmpdir_mod / "x.cgb")
+    for alg, size in ((L.CUT_ALG_MAJORANA, 7), (L.CUT_ALG_MAJORANA, 66), (L.CUT_ALG_EPQ, 0), (9, 8)):
+        with pytest.raises(L.CutError) as e:
+            L.cut_graph_build(alg, size, p)
+        assert e.value.status == L.CUT_E_INVAL
+    with pytest.raises(L.CutError) as e:
+        L.cut_graph_build(L.CUT_ALG_EPQ, 4, "/nonexistent_dir/x.cgb")
+    assert e.value.status == L.CUT_E_IO

@@ -1,0 +1,159 @@
+"""GPU parity of the RK4 coflow and its discrete adjoint (C ABI) vs the oracle."""
+import numpy as np
+import pytest
+
+import gpu_util as U
+import workloads
+from oracle import algebra as A
+from oracle import flow as OF
+from oracle import gen as OG
+from oracle import native
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2609_14831_amd import _lib
+    return _lib
+
+
+def _flow(L, g, z0, ns, gen, prec, ds, ckpt_every=0, flags=None):
+    z = torch.tensor(z0, device=DEV).contiguous()
+    N, nops, nsets = z0.shape
+    T = int(max(ns))
+    ck = None
+    if ckpt_every:
+        ck = torch.zeros(((T + ckpt_every - 1) // ckpt_every, N, nops, nsets), dtype=torch.float64, device=DEV)
+    p = L.flow_params(gen, prec, ds, 0.5, ckpt_every) if flags is None else \
+        L.flow_params(gen, prec, ds, 0.5, ckpt_every, flags=flags)
+    L.cut_flow_integrate(g, p, nsets, nops, list(ns), z, ck)
+    torch.cuda.synchronize()
+    return z.cpu().numpy(), ck
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def test_epq_wegner_flow_full_config(L):
+    """n=8 one-body flow, Wegner generator as a graph pass, ds=1e-3 to s=10
+    (10^4 RK4 steps): FP64 GPU flow vs the oracle with the same RK4."""
+    U.say("[flow] epq n=8 wegner 10000 steps")
+    w = workloads.WORKLOADS[1]
+    inp = workloads.make_inputs(1)
+    g = U.graph(L, "epq", 8)
+    z, _ = _flow(L, g, inp.z0, inp.n_steps, L.CUT_GEN_WEGNER_GRAPH, L.CUT_F64, w.ds)
+    og = A.epq_graph(8)
+    zr, _ = native.Engine(og, "wegner_graph").flow(inp.z0, w.ds, inp.n_steps)
+    assert np.max(np.abs(z - zr)) < 1e-10
+    H0 = inp.z0[:, 0, 0].reshape(8, 8)
+    H = z[:, 0, 0].reshape(8, 8)
+    assert abs(np.linalg.norm(H) - np.linalg.norm(H0)) < 1e-8 * np.linalg.norm(H0)
+    np.testing.assert_allclose(np.linalg.eigvalsh(H), np.linalg.eigvalsh(H0), atol=1e-7)
+
+
+@pytest.mark.parametrize("prec", ["F64", "F32X", "F32C"])
+def test_majorana_flow_ragged(L, prec):
+    U.say(f"[flow] majorana m=12 ragged {prec}")
+    m = 12
+    g = U.graph(L, "majorana", m)
+    og = A.majorana_graph(m)
+    z0 = workloads.small_majorana(m, 5, 3, seed=21)
+    ns = np.array([40, 0, 17, 40, 3], dtype=np.int32)
+    z, _ = _flow(L, g, z0, ns, L.CUT_GEN_G2, getattr(L, "CUT_" + prec), 1e-2)
+    gen, _ = OG.make_generator(og, "g2", 0.5)
+    zr, _ = OF.integrate(og, gen, z0, 1e-2, ns)
+    np.testing.assert_array_equal(z[:, :, 1], z0[:, :, 1])   # zero steps: untouched
+    for s in range(5):
+        for op in range(3):
+            r = _rel(z[:, op, s], zr[:, op, s])
+            assert r < (1e-13 if prec == "F64" else 1e-7), (s, op, r)
+
+
+def test_flow_graph_replay_matches_stream_path(L):
+    m = 10
+    g = U.graph(L, "majorana", m)
+    z0 = workloads.small_majorana(m, 4, 2, seed=8)
+    ns = [25, 10, 25, 1]
+    a, _ = _flow(L, g, z0, ns, L.CUT_GEN_G2, L.CUT_F32C, 1e-2, flags=L.CUT_FLOW_HIPGRAPH)
+    b, _ = _flow(L, g, z0, ns, L.CUT_GEN_G2, L.CUT_F32C, 1e-2, flags=0)
+    c, _ = _flow(L, g, z0, ns, L.CUT_GEN_G2, L.CUT_F32C, 1e-2, flags=L.CUT_FLOW_HIPGRAPH)
+    assert np.array_equal(a, b) and np.array_equal(a, c)
+
+
+def test_config2_short_flow_precision(L):
+    """Majorana m=24 (config-2 graph, 2.56M records), H + 2 quadratic observables,
+    100 RK4 steps: FP64 vs the oracle's C engine, float passes vs FP64."""
+    U.say("[flow] m=24 config-2 inputs, 100 steps")
+    w = workloads.WORKLOADS[2]
+    inp = workloads.make_inputs(2)
+    ns = [100]
+    g = U.graph(L, "majorana", 24)
+    z64, _ = _flow(L, g, inp.z0, ns, L.CUT_GEN_G2, L.CUT_F64, w.ds)
+    og = A.majorana_graph(24)
+    zr, _ = native.Engine(og, "g2", w.delta).flow(inp.z0, w.ds, ns)
+    for op in range(3):
+        assert _rel(z64[:, op, 0], zr[:, op, 0]) < 1e-12
+    for prec, bound in (("F32C", 1e-7), ("F32X", 1e-7)):
+        z, _ = _flow(L, g, inp.z0, ns, L.CUT_GEN_G2, getattr(L, "CUT_" + prec), w.ds)
+        for op in range(3):
+            assert _rel(z[:, op, 0], zr[:, op, 0]) < bound, (prec, op)
+
+
+@pytest.mark.parametrize("alg,size,kind,nops", [("majorana", 10, "g2", 2), ("epq", 5, "wegner_graph", 1)])
+def test_flow_adjoint_vs_oracle(L, alg, size, kind, nops):
+    U.say(f"[adjoint flow] {alg} {size} {kind}")
+    g = U.graph(L, alg, size)
+    og = A.graph_for(alg, size)
+    if alg == "majorana":
+        z0 = workloads.small_majorana(size, 3, nops, seed=13)
+        ns = np.array([23, 9, 0], dtype=np.int32)
+    else:
+        h = workloads.random_dense((size, size), seed=3)
+        z0 = (h + h.T + np.diag(np.arange(size) * 1.0)).reshape(-1, 1, 1)
+        ns = np.array([23], dtype=np.int32)
+    ds, C = 1e-2, 5
+    K = L.CUT_GEN_G2 if kind == "g2" else L.CUT_GEN_WEGNER_GRAPH
+    z, ck = _flow(L, g, z0, ns, K, L.CUT_F64, ds, ckpt_every=C)
+    lam_end = workloads.random_dense(z0.shape, seed=14)
+    lam = torch.tensor(lam_end, device=DEV).contiguous()
+    L.cut_flow_adjoint(g, L.flow_params(K, L.CUT_F64, ds, 0.5, C), z0.shape[2], z0.shape[1], list(ns), ck, lam)
+    torch.cuda.synchronize()
+    gen, vjp = OG.make_generator(og, kind, 0.5)
+    ref = OF.flow_adjoint(og, gen, vjp, z0, ds, ns, lam_end, ckpt_every=C)
+    assert _rel(lam.cpu().numpy(), ref) < 1e-12
+
+
+def test_flow_function_autograd_config5_reduced(L):
+    """Config-5 shape (m=24, 8 sets, H only, checkpoints every 16 steps) over a
+    shortened flow: torch autograd through FlowFn vs the oracle's C-engine
+    discrete adjoint, and vs central differences of FP64 GPU flows."""
+    from paper_2609_14831_amd.flow import flow
+    U.say("[autograd] m=24 8 sets 40 steps")
+    w = workloads.WORKLOADS[5]
+    inp = workloads.make_inputs(5, with_fd=4)
+    g = U.graph(L, "majorana", 24)
+    og = A.majorana_graph(24)
+    ns = [40] * 8
+    z0 = torch.tensor(inp.z0, device=DEV, requires_grad=True)
+    zend = flow(z0, g, ns, L.CUT_GEN_G2, w.ds, w.delta, 16)
+    pairs = torch.tensor(og.pairs, device=DEV)
+    loss = zend[pairs, 0, :].sum()
+    loss.backward()
+    grad = z0.grad.cpu().numpy()
+    lam_end = np.zeros_like(inp.z0)
+    lam_end[og.pairs, 0, :] = 1.0
+    ref = native.Engine(og, "g2", w.delta).flow_adjoint(inp.z0, w.ds, ns, lam_end, ckpt_every=16)
+    assert _rel(grad, ref) < 1e-11
+    with torch.no_grad():
+        for d in inp.fd_dirs:
+            v = torch.tensor(d[:, None, :], device=DEV)
+            eps = 1e-6
+            lp = flow(z0 + eps * v, g, ns, L.CUT_GEN_G2, w.ds, w.delta, 16)[pairs, 0, :].sum()
+            lm = flow(z0 - eps * v, g, ns, L.CUT_GEN_G2, w.ds, w.delta, 16)[pairs, 0, :].sum()
+            fd = float((lp - lm) / (2 * eps))
+            an = float(np.sum(grad[:, 0, :] * d))
+            assert abs(fd - an) <= 1e-6 * max(abs(fd), 1e-3 * np.linalg.norm(grad)), (fd, an)
