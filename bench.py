@@ -1,0 +1,234 @@
+#!/usr/bin/env python3
+"""Benchmark of the compiled-CUT-graph hot path on one MI355X.
+
+Workload: the batched coflow on the 2n = 40 Majorana-string graph (N = 92,170
+strings, E = 39,539,760 records): 64 coefficient sets (mass-scaling sweep) x
+(H + 4 quadratic observables) = 320 operand columns, G2 generator, classic RK4
+at ds = 5e-3, float-operand graph passes with compensated accumulation, FP64 RK
+state, one hipGraph launch per RK step.  A step = one RK4 step of the whole
+batch (4 x {generator, graph pass with the fused stage update}).
+
+Printed (one JSON line): contributions x batch / s over the timed steps; the
+dominant kernel's roofline (HIP-event average of the fused graph pass,
+algorithmic bytes per launch); the plain FP64 one-column flow for the batched /
+plain ratio; and the oracle's CPU rate on a bounded sample (cpu_baseline leg).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import tempfile
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+FP64_VEC_TFLOPS = 78.6
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def pass_bytes(N, E, nsets, nops, prec_bytes):
+    """Algorithmic HBM bytes of one fused graph pass, averaged over the 4 RK stages.
+
+    records 8 B each; offsets; generator [N, nsets] and stage operand [N, cols]
+    read once; per state element the RK epilogue reads z, reads/writes the
+    accumulator (stage 0 write, 1-2 read+write, 3 read + z write: 14 B average)
+    and writes the next stage operand; the FP64 Hamiltonian column is written.
+    """
+    cols = nsets * nops
+    return (E * 8 + (N + 1) * 8 + N * nsets * prec_bytes + N * cols * prec_bytes
+            + N * cols * (8 + 14) + N * cols * prec_bytes + N * nsets * 8)
+
+
+def cpu_baseline(inp, w, nsets, nops, budget_s=15.0):
+    """Oracle (plain-C FP64 engine, all host threads) on a sample of targets."""
+    import numpy as np
+    from oracle import algebra as A
+    from oracle import gen as OG
+    from oracle import native
+
+    reg = A.MajoranaRegistry(w.size)
+    stride = 40
+    targets = np.arange(0, reg.N, stride)
+    ks, is_, js, cs = [], [], [], []
+    for t in targets:
+        ii, jj, cc = reg.records_for_target(int(t))
+        ks.append(np.full(ii.size, t))
+        is_.append(ii)
+        js.append(jj)
+        cs.append(cc)
+    g = A.Graph("majorana", w.size, reg.N, np.concatenate(ks), np.concatenate(is_),
+                np.concatenate(js), np.concatenate(cs), reg.diag, reg.pairs, -1.0, masks=reg.masks)
+    eng = native.Engine(g, "g2", w.delta)
+    eta = OG.G2(w.size, w.delta)(inp.z0[:, 0, :])
+    x = inp.z0
+    eng.apply(eta, x)  # warm
+    reps, t0 = 0, time.perf_counter()
+    while True:
+        eng.apply(eta, x)
+        reps += 1
+        el = time.perf_counter() - t0
+        if el > budget_s or reps >= 200:
+            break
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": g.E * nsets * nops * reps / el, "unit": "contributions*batch/s",
+            "cores": threads, "kind": "oracle",
+            "sample": f"one graph action (all {nsets * nops} columns, FP64) over the records of every "
+                      f"{stride}th target ({targets.size} targets, {g.E} records), {reps} repetitions, "
+                      f"{el:.1f} s; plain-C oracle engine with OpenMP"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--precision", default="f32c", choices=["f32c", "f32x", "f64", "f32"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--minimal", action="store_true", help="timed flow only")
+    ap.add_argument("--profile", action="store_true",
+                    help="counter runs: a 1 GiB device copy (calibration), then the steps in "
+                         "stream order (no hipGraph), nothing else")
+    ap.add_argument("--long-records", type=int, default=1024)
+    ap.add_argument("--xcd-remap", type=int, default=0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the method's batch sharding "
+              "across GPUs is described in DESIGN.md but not built.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import workloads
+    from paper_2609_14831_amd import _lib as L
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    w = workloads.WORKLOADS[3]
+    PREC = {"f32c": L.CUT_F32C, "f32x": L.CUT_F32X, "f64": L.CUT_F64, "f32": L.CUT_F32}[args.precision]
+    pbytes = 8 if PREC == L.CUT_F64 else 4
+
+    tmp = tempfile.mkdtemp(prefix="cutgraph_bench_")
+    path = os.path.join(tmp, "m40.cgb")
+    desc = L.cut_graph_build(L.CUT_ALG_MAJORANA, w.size, path, 0)
+    log(f"compiled m={w.size}: N={desc['n_ops']} E={desc['n_records']} in {desc['build_seconds']:.2f} s")
+    t0 = time.perf_counter()
+    g = L.cut_graph_load(path, 0, 0)
+    load_s = time.perf_counter() - t0
+    L.cut_graph_set_tiling(g, args.long_records, args.xcd_remap)
+    N, E = desc["n_ops"], desc["n_records"]
+
+    inp = workloads.make_inputs(3)
+    nsets, nops = w.nsets, w.nops
+    ns = [int(v) for v in inp.n_steps]
+    z = torch.tensor(inp.z0, device=dev).contiguous()
+    W, K = args.warmup, args.steps
+    assert W + K <= min(ns), "timed steps must keep every set active"
+    if args.profile:
+        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)   # 1 GiB
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        p = L.flow_params(L.CUT_GEN_G2, PREC, w.ds, w.delta, 0, flags=L.CUT_FLOW_TIME_PASSES,
+                          step_begin=0, step_end=W + K)
+        L.cut_flow_integrate(g, p, nsets, nops, ns, z)
+        tm = L.cut_flow_last_timing(g)
+        print(json.dumps({"profile": True, "copy_bytes_each_way": 1 << 30, "steps": W + K,
+                          "pass_avg_ms": tm["pass_ms"] / max(1, tm["pass_launches"]),
+                          "pass_bytes": pass_bytes(N, E, nsets, nops, pbytes)}), flush=True)
+        return
+
+    p = L.flow_params(L.CUT_GEN_G2, PREC, w.ds, w.delta, 0, flags=L.CUT_FLOW_HIPGRAPH,
+                      step_begin=0, step_end=W)
+    L.cut_flow_integrate(g, p, nsets, nops, ns, z)
+    torch.cuda.synchronize()
+    log(f"warmup {W} steps done")
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    p = L.flow_params(L.CUT_GEN_G2, PREC, w.ds, w.delta, 0, flags=L.CUT_FLOW_HIPGRAPH,
+                      step_begin=W, step_end=W + K)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    t0 = time.perf_counter()
+    L.cut_flow_integrate(g, p, nsets, nops, ns, z)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    e1.record(stream)
+    torch.cuda.synchronize()
+    active_cols = sum(nops * sum(1 for n in ns if n > t) for t in range(W, W + K))
+    contributions = 4 * E * active_cols
+    value = contributions / wall
+    log(f"timed {K} steps: {wall * 1e3 / K:.3f} ms/step, {value:.3e} contributions*batch/s")
+    out = {"metric": "graph contributions×batch/s + HBM GB/s; batched FP32 vs plain FP64 flow",
+           "value": value, "unit": "contributions×batch/s", "n_gpus": 1, "steps": K, "warmup": W,
+           "ms_per_step": wall * 1e3 / K, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32" if PREC != L.CUT_F64 else "f64",
+           "data": "synthetic (seeded mass-scaling sweep, no dataset)",
+           "config": {"workload": f"majorana_m40_batched: 2n=40 Majorana strings, N={N}, E={E} records, "
+                                  f"{nsets} sets x {nops} operands = {nsets * nops} columns, ragged "
+                                  f"s_max in [2,20], ds={w.ds}, G2 generator (delta={w.delta}), RK4, "
+                                  f"one hipGraph per step",
+                      "precision": {"f32c": "float operands and products, compensated (two-product + "
+                                            "two-sum) accumulation, FP64 result and RK state",
+                                    "f32x": "float operands, products and sums in FP64, FP64 RK state",
+                                    "f64": "FP64 throughout", "f32": "plain float sums"}[args.precision],
+                      "graph_compile_s": desc["build_seconds"], "graph_load_s": load_s}}
+    if args.minimal:
+        print(json.dumps(out), flush=True)
+        return
+
+    # kernel timing leg: same steps in stream order, HIP events around each pass
+    zt = torch.tensor(inp.z0, device=dev).contiguous()
+    p = L.flow_params(L.CUT_GEN_G2, PREC, w.ds, w.delta, 0, flags=L.CUT_FLOW_TIME_PASSES,
+                      step_begin=0, step_end=W + K)
+    L.cut_flow_integrate(g, p, nsets, nops, ns, zt)
+    tm = L.cut_flow_last_timing(g)
+    pass_ms = tm["pass_ms"] / max(1, tm["pass_launches"])
+    gen_ms = tm["gen_ms"] / max(1, tm["gen_launches"])
+    bytes_per = pass_bytes(N, E, nsets, nops, pbytes)
+    achieved = bytes_per / (pass_ms * 1e-3) / 1e9
+    flops_per = 2.0 * E * nsets * nops
+    log(f"fused pass avg {pass_ms:.4f} ms ({tm['pass_launches']} launches), generator {gen_ms:.4f} ms")
+    out["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                       "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                       "kernel": "k_pass<64,8,prec,MODE_BCAST,EPI_RK> (fused graph pass + RK stage)",
+                       "avg_launch_ms": pass_ms, "algorithmic_bytes_per_launch": bytes_per,
+                       "fp64_equiv_tflops": flops_per / (pass_ms * 1e-3) / 1e12,
+                       "fp64_vector_peak_tflops": FP64_VEC_TFLOPS}
+    out["generator_avg_ms"] = gen_ms
+
+    # plain FP64 flow, one operand column per pass (one set, H only)
+    z1 = torch.tensor(inp.z0[:, :1, :1], device=dev).contiguous()
+    ns1 = [ns[0]]
+    p = L.flow_params(L.CUT_GEN_G2, L.CUT_F64, w.ds, w.delta, 0, flags=L.CUT_FLOW_HIPGRAPH,
+                      step_begin=0, step_end=W)
+    L.cut_flow_integrate(g, p, 1, 1, ns1, z1)
+    p = L.flow_params(L.CUT_GEN_G2, L.CUT_F64, w.ds, w.delta, 0, flags=L.CUT_FLOW_HIPGRAPH,
+                      step_begin=W, step_end=W + K)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    L.cut_flow_integrate(g, p, 1, 1, ns1, z1)
+    torch.cuda.synchronize()
+    plain = 4 * E * K / (time.perf_counter() - t0)
+    out["plain_fp64_flow"] = {"value": plain, "unit": "contributions×batch/s",
+                              "columns": 1, "ratio_batched_over_plain": value / plain}
+    log(f"plain FP64 one-column flow {plain:.3e}/s; batched/plain = {value / plain:.1f}x")
+    L.cut_graph_free(g)
+    os.remove(path)
+
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(inp, w, nsets, nops)
+        log(f"cpu baseline {out['cpu_baseline']['value']:.3e}/s")
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

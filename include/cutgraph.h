@@ -175,6 +175,9 @@ cut_status cut_generator_vjp(cut_graph_t g, int32_t kind, double delta, int64_t 
  * modes).  Each RK step is one stream-ordered sequence of kernels; with
  * CUT_FLOW_HIPGRAPH it is captured once as a hipGraph and replayed. */
 #define CUT_FLOW_HIPGRAPH 1u
+#define CUT_FLOW_TIME_PASSES 2u  /* without CUT_FLOW_HIPGRAPH: bracket every graph
+                                    pass and generator launch with HIP events on
+                                    the launch stream (see cut_flow_last_timing) */
 
 typedef struct {
     int32_t generator;      /* cut_generator_kind */
@@ -215,6 +218,18 @@ cut_status cut_flow_adjoint(cut_graph_t g, const cut_flow_params* p, int64_t nse
  * consecutive task ranges onto one XCD (one L2).  Rebuilds the task lists of
  * every loaded copy.  Errors: CUT_E_INVAL, CUT_E_DEVICE. */
 cut_status cut_graph_set_tiling(cut_graph_t g, int64_t long_records, int32_t xcd_remap);
+
+/* Per-kernel timing of the last cut_flow_integrate call made with
+ * CUT_FLOW_TIME_PASSES: summed HIP-event elapsed milliseconds and launch counts
+ * of the fused graph passes and of the generator launches.  Zeros when the last
+ * flow was not timed.  Errors: CUT_E_INVAL (null argument). */
+typedef struct {
+    double pass_ms;
+    int64_t pass_launches;
+    double gen_ms;
+    int64_t gen_launches;
+} cut_flow_timing;
+cut_status cut_flow_last_timing(cut_graph_t g, cut_flow_timing* t);
 
 const char* cut_last_error(void);
 const char* cut_version(void);

@@ -20,6 +20,67 @@
 #include <stdlib.h>
 #include <string.h>
 
+/* ---------------------------------------------------------------- records --
+ * Majorana records of the given targets, by brute force over the left input:
+ * for target mask K and every registry string A, B = A xor K is kept when B has
+ * degree 2 or 4 (in the registry) and |A & B| is odd (the two anticommute).
+ * Factor of [i Gamma_A, Gamma_B] = c Gamma_K: c = 2 i^e with
+ * e = 1 + t(|A|) + t(|B|) - t(|K|) + 2 inv(A, B), t(d) = d(d-1)/2 and
+ * inv(A, B) = #{(a, b) in A x B : a > b} counted pair by pair.
+ * Records of one target come out in ascending left input (= ascending (i, j)).
+ * counts[t] = number of records of targets[t]; with ri == NULL only counts are
+ * produced, otherwise records of target t are written from offsets[t]. */
+static int popc(uint64_t x) { return __builtin_popcountll(x); }
+
+static int64_t find_mask(const uint64_t* sorted, const int64_t* order, int64_t N, uint64_t q) {
+    int64_t lo = 0, hi = N - 1;
+    while (lo <= hi) {
+        int64_t mid = (lo + hi) / 2;
+        if (sorted[mid] == q) return order[mid];
+        if (sorted[mid] < q) lo = mid + 1;
+        else hi = mid - 1;
+    }
+    return -1;
+}
+
+static double maj_coeff(uint64_t A, uint64_t B, int m) {
+    int inv = 0;
+    for (int a = 0; a < m; ++a)
+        if ((A >> a) & 1)
+            for (int b = 0; b < a; ++b)
+                if ((B >> b) & 1) ++inv;
+    int dA = popc(A), dB = popc(B), dK = popc(A ^ B);
+    int e = 1 + dA * (dA - 1) / 2 + dB * (dB - 1) / 2 - dK * (dK - 1) / 2 + 2 * inv;
+    e = ((e % 4) + 4) % 4;
+    return e == 0 ? 2.0 : -2.0; /* e is even for anticommuting Hermitian strings */
+}
+
+int orc_maj_records(int m, int64_t N, const uint64_t* masks, const uint64_t* sorted, const int64_t* order,
+                    const int64_t* targets, int64_t nt, int64_t* counts, const int64_t* offsets, int32_t* ri,
+                    int32_t* rj, double* rc) {
+    int bad = 0;
+#pragma omp parallel for schedule(dynamic, 8) reduction(| : bad)
+    for (int64_t t = 0; t < nt; ++t) {
+        const uint64_t K = masks[targets[t]];
+        int64_t n = 0;
+        for (int64_t a = 0; a < N; ++a) {
+            const uint64_t A = masks[a], B = A ^ K;
+            const int dB = popc(B);
+            if ((dB != 2 && dB != 4) || (popc(A & B) & 1) == 0) continue;
+            if (ri) {
+                const int64_t j = find_mask(sorted, order, N, B);
+                if (j < 0) bad = 1;
+                ri[offsets[t] + n] = (int32_t)a;
+                rj[offsets[t] + n] = (int32_t)j;
+                rc[offsets[t] + n] = maj_coeff(A, B, m);
+            }
+            ++n;
+        }
+        counts[t] = n;
+    }
+    return bad;
+}
+
 typedef struct {
     int64_t N, nops, nsets;
     const int64_t* off; const int32_t* ri; const int32_t* rj; const double* rc;

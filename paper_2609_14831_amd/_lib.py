@@ -30,6 +30,7 @@ CUT_GEN_WEGNER_GRAPH, CUT_GEN_G2 = 1, 2
 CUT_ACCUMULATE = 1
 CUT_LOAD_ADJOINT, CUT_LOAD_NO_CHECKSUM = 1, 2
 CUT_FLOW_HIPGRAPH = 1
+CUT_FLOW_TIME_PASSES = 2
 
 STATUS_NAMES = {0: "CUT_OK", 1: "CUT_E_INVAL", 2: "CUT_E_IO", 3: "CUT_E_FORMAT",
                 4: "CUT_E_CHECKSUM", 5: "CUT_E_NOMEM", 6: "CUT_E_DEVICE", 7: "CUT_E_NUMERIC",
@@ -38,8 +39,8 @@ STATUS_NAMES = {0: "CUT_OK", 1: "CUT_E_INVAL", 2: "CUT_E_IO", 3: "CUT_E_FORMAT",
 # symbols declared in include/cutgraph.h
 EXPORTS = ["cut_graph_build", "cut_graph_load", "cut_graph_info", "cut_graph_free",
            "cut_graph_apply", "cut_graph_apply_adjoint", "cut_generator", "cut_generator_vjp",
-           "cut_flow_integrate", "cut_flow_adjoint", "cut_graph_set_tiling", "cut_last_error",
-           "cut_version"]
+           "cut_flow_integrate", "cut_flow_adjoint", "cut_graph_set_tiling", "cut_flow_last_timing",
+           "cut_last_error", "cut_version"]
 
 
 class CutError(RuntimeError):
@@ -81,6 +82,14 @@ _L.cut_flow_integrate.argtypes = [_vp, C.POINTER(cut_flow_params), _i64, _i64, C
                                   _vp]
 _L.cut_flow_adjoint.argtypes = [_vp, C.POINTER(cut_flow_params), _i64, _i64, C.POINTER(_i32), _vp, _vp, _vp]
 _L.cut_graph_set_tiling.argtypes = [_vp, _i64, _i32]
+
+
+class cut_flow_timing(C.Structure):
+    _fields_ = [("pass_ms", C.c_double), ("pass_launches", C.c_int64), ("gen_ms", C.c_double),
+                ("gen_launches", C.c_int64)]
+
+
+_L.cut_flow_last_timing.argtypes = [_vp, C.POINTER(cut_flow_timing)]
 _L.cut_last_error.restype = C.c_char_p
 _L.cut_version.restype = C.c_char_p
 for _name in EXPORTS:
@@ -197,6 +206,12 @@ def cut_flow_integrate(g: int, params: cut_flow_params, nsets: int, nops: int, n
     """z: device float64 [N, nops, nsets] contiguous, advanced in place."""
     _check(_L.cut_flow_integrate(g, C.byref(params), nsets, nops, _steps_arg(n_steps), _ptr(z),
                                  _ptr(ckpt), _stream(stream)))
+
+
+def cut_flow_last_timing(g: int) -> dict:
+    t = cut_flow_timing()
+    _check(_L.cut_flow_last_timing(g, C.byref(t)))
+    return {k: getattr(t, k) for k, _ in t._fields_}
 
 
 def cut_flow_adjoint(g: int, params: cut_flow_params, nsets: int, nops: int, n_steps, ckpt, lam,

@@ -101,14 +101,38 @@ struct StepPlan {
     void* xout[4];
 };
 
+// HIP events bracketing launches (kind 0 = graph pass, 1 = generator)
+struct PassTimer {
+    std::vector<hipEvent_t> ev;
+    std::vector<int> kind;
+    size_t used = 0;
+    hipEvent_t next() {
+        if (used == ev.size()) {
+            hipEvent_t e;
+            HIP_CHECK(hipEventCreate(&e));
+            ev.push_back(e);
+        }
+        return ev[used++];
+    }
+    void mark(int k, hipStream_t s) {
+        HIP_CHECK(hipEventRecord(next(), s));
+        if (used % 2 == 1) kind.push_back(k);
+    }
+    ~PassTimer() {
+        for (auto e : ev) (void)hipEventDestroy(e);
+    }
+};
+
 // the kernel sequence of one RK step (stream-ordered, capturable)
-static void enqueue_step(const StepPlan& P, hipStream_t s) {
+static void enqueue_step(const StepPlan& P, hipStream_t s, PassTimer* tm = nullptr) {
     Graph& g = *P.g;
     const bool f32 = P.prec != CUT_F64;
     const int64_t cols = (int64_t)P.nops * P.nsets;
     for (int st = 0; st < 4; ++st) {
+        if (tm) tm->mark(1, s);
         eval_generator(g, P.gen, P.delta, P.nsets, P.fb.hst, P.nsets, P.fb.eta, P.nsets, f32, P.fb.nsteps,
                        P.fb.step, s);
+        if (tm) tm->mark(1, s);
         PassArgs p{};
         p.csr = &g.csr[0][0];
         p.ftab = g.ftab;
@@ -128,7 +152,9 @@ static void enqueue_step(const StepPlan& P, hipStream_t s) {
         p.xout = P.xout[st];
         p.hst = P.fb.hst;
         p.ldh = P.nsets;
+        if (tm) tm->mark(0, s);
         launch_pass(MODE_BCAST, EPI_RK, p, s);
+        if (tm) tm->mark(0, s);
     }
     launch_bump(P.fb.step, s);
 }
@@ -173,6 +199,9 @@ extern "C" cut_status cut_flow_integrate(cut_graph_t h, const cut_flow_params* p
             P.xout[st] = fb.xsh[(st + 1) & 1];
         }
         const bool use_graph = (p->flags & CUT_FLOW_HIPGRAPH) && t1 - t0 > 1;
+        const bool timed = !use_graph && (p->flags & CUT_FLOW_TIME_PASSES);
+        PassTimer timer;
+        g.timing = cut_flow_timing{};
         StepGraphCache* gc = nullptr;
         if (use_graph) {
             std::vector<uint64_t> key = {(uint64_t)(uintptr_t)z, (uint64_t)(uintptr_t)g.ws.ptr, (uint64_t)p->generator,
@@ -202,7 +231,21 @@ extern "C" cut_status cut_flow_integrate(cut_graph_t h, const cut_flow_params* p
             if (ckpt && p->ckpt_every > 0 && t % p->ckpt_every == 0)
                 HIP_CHECK(hipMemcpyAsync(ckpt + (t / p->ckpt_every) * M, z, M * 8, hipMemcpyDeviceToDevice, run));
             if (use_graph) HIP_CHECK(hipGraphLaunch(gc->exec, run));
-            else enqueue_step(P, run);
+            else enqueue_step(P, run, timed ? &timer : nullptr);
+        }
+        if (timed) {
+            HIP_CHECK(hipStreamSynchronize(run));
+            for (size_t q = 0; q + 1 < timer.used; q += 2) {
+                float ms = 0.f;
+                HIP_CHECK(hipEventElapsedTime(&ms, timer.ev[q], timer.ev[q + 1]));
+                if (timer.kind[q / 2] == 0) {
+                    g.timing.pass_ms += ms;
+                    g.timing.pass_launches++;
+                } else {
+                    g.timing.gen_ms += ms;
+                    g.timing.gen_launches++;
+                }
+            }
         }
         launch_finite_check(z, M, fb.flag, run);
         if (use_graph) {
@@ -350,4 +393,13 @@ extern "C" cut_status cut_flow_adjoint(cut_graph_t h, const cut_flow_params* p, 
         set_error("out of host memory");
         return CUT_E_NOMEM;
     }
+}
+
+extern "C" cut_status cut_flow_last_timing(cut_graph_t h, cut_flow_timing* t) {
+    if (!h || !t) {
+        set_error("cut_flow_last_timing: null argument");
+        return CUT_E_INVAL;
+    }
+    *t = ((Graph*)h)->timing;
+    return CUT_OK;
 }

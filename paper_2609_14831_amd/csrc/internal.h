@@ -159,6 +159,7 @@ struct Graph {
     Workspace ws;                    // flow state and stage storage
     Workspace ws_small;              // scratch of single generator-VJP calls
     StepGraphCache* graphs = nullptr;
+    cut_flow_timing timing{};        // last timed flow
     ~Graph();
 };
 

@@ -130,7 +130,8 @@ __global__ __launch_bounds__(256) void k_pass(KArgs a) {
     }
     if (t >= a.ntasks) return;
     const Task task = a.tasks[t];
-    const int wave = threadIdx.x >> 6;
+    // wave index through an SGPR so segment bounds and loop control stay scalar
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int lane = threadIdx.x & 63;
     const int sg = lane % G;
     const int sub = lane / G;
@@ -154,35 +155,83 @@ __global__ __launch_bounds__(256) void k_pass(KArgs a) {
     Acc<PREC> acc[NACC];
     const T* __restrict__ A = (const T*)a.A;
     const T* __restrict__ B = (const T*)a.B;
-    const int nsets = a.nsets, nops = a.nops;
-    if (act) {
-        for (int64_t e = e0 + sub; e < e1; e += R) {
-            const uint2 r = a.rec[e];
-            const int64_t ia = r.x & 0xFFFFFFu;
-            const int64_t ib = r.y;
-            const double cf = a.ftab[r.x >> 24];
-            if constexpr (MODE == MODE_BCAST) {
-                const auto tl = left_term<PREC>(cf, A[ia * a.lda + s]);
-                const T* brow = B + ib * a.ldb + s;
+    const int nsets = a.nsets;
+    // lanes of inactive sets compute on an in-range column and are discarded
+    // at the epilogue; no load is ever predicated
+    const int sl = s < nsets ? s : nsets - 1;
+    int coff[NOPS];
 #pragma unroll
-                for (int op = 0; op < NOPS; ++op)
-                    if (op < nops) acc[op].add(tl, brow[(int64_t)op * nsets]);
-            } else {
-                const T* arow = A + ia * a.lda + s;
-                const T* brow = B + ib * a.ldb + s;
-                // sum over operand columns first, then one scaled accumulation
-                if constexpr (PREC == CUT_F64 || PREC == CUT_F32X) {
+    for (int op = 0; op < NOPS; ++op) coff[op] = sl + op * nsets;
+    // Records are fetched cooperatively, 64 per wavefront load (one per lane),
+    // then handed to the lane groups by cross-lane moves; each group issues the
+    // gathers of U records before any arithmetic, so U dependent load chains are
+    // in flight per wavefront.
+    constexpr int NA = (MODE == MODE_REDOPS) ? NOPS : 1;
+    constexpr int U = (NOPS <= 2) ? 8 : 4;
+    constexpr int CH = (G >= U) ? 1 : U / G;  // 64-record chunks per outer iteration
+    constexpr int SLOTS = CH * G;             // record slots of one lane group per iteration
+    for (int64_t base = e0; base < e1; base += 64 * CH) {
+        uint2 mine[CH];
+#pragma unroll
+        for (int c = 0; c < CH; ++c) {
+            // clamped (always valid) address; slots past e1 are masked by cnt
+            const int64_t idx = base + c * 64 + lane;
+            // records are read once per pass: non-temporal
+            const unsigned long long rv = __builtin_nontemporal_load(
+                (const unsigned long long*)a.rec + (idx < e1 ? idx : e1 - 1));
+            mine[c] = make_uint2((uint32_t)rv, (uint32_t)(rv >> 32));
+        }
+        const int cnt = (int)((e1 - base) < 64 * CH ? (e1 - base) : 64 * CH);
+#pragma unroll
+        for (int t0 = 0; t0 < SLOTS; t0 += U) {
+            if (t0 * R >= cnt) break;
+            uint32_t rx[U], ry[U];
+            bool ok[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int t = t0 + u;
+                const int c = t / G;
+                const int src = (t % G) * R + sub;
+                if constexpr (G == 64) {
+                    rx[u] = (uint32_t)__builtin_amdgcn_readlane((int)mine[c].x, src);
+                    ry[u] = (uint32_t)__builtin_amdgcn_readlane((int)mine[c].y, src);
+                } else {
+                    rx[u] = (uint32_t)__shfl((int)mine[c].x, src);
+                    ry[u] = (uint32_t)__shfl((int)mine[c].y, src);
+                }
+                ok[u] = t * R + sub < cnt;
+            }
+            // slots past the segment end hold the (valid) clamped last record;
+            // their factor is zeroed below
+            T av[U][NA];
+            T bv[U][NOPS];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                // row base (uniform when G == 64) + loop-invariant lane offsets
+                const T* arow = A + (int64_t)(rx[u] & 0xFFFFFFu) * a.lda;
+                const T* brow = B + (int64_t)ry[u] * a.ldb;
+#pragma unroll
+                for (int q = 0; q < NA; ++q) av[u][q] = arow[coff[q]];
+#pragma unroll
+                for (int op = 0; op < NOPS; ++op) bv[u][op] = brow[coff[op]];
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const double cf = ok[u] ? a.ftab[rx[u] >> 24] : 0.0;
+                if constexpr (MODE == MODE_BCAST) {
+                    const auto tl = left_term<PREC>(cf, av[u][0]);
+#pragma unroll
+                    for (int op = 0; op < NOPS; ++op) acc[op].add(tl, bv[u][op]);
+                } else if constexpr (PREC == CUT_F64 || PREC == CUT_F32X) {
+                    // sum over operand columns first, then one scaled accumulation
                     double d = 0.0;
 #pragma unroll
-                    for (int op = 0; op < NOPS; ++op)
-                        if (op < nops) d = __builtin_fma((double)arow[(int64_t)op * nsets],
-                                                         (double)brow[(int64_t)op * nsets], d);
+                    for (int op = 0; op < NOPS; ++op) d = __builtin_fma((double)av[u][op], (double)bv[u][op], d);
                     acc[0].v = __builtin_fma(cf, d, acc[0].v);
                 } else {
                     const float fc = (float)cf;
 #pragma unroll
-                    for (int op = 0; op < NOPS; ++op)
-                        if (op < nops) acc[0].add(fc * arow[(int64_t)op * nsets], brow[(int64_t)op * nsets]);
+                    for (int op = 0; op < NOPS; ++op) acc[0].add(fc * av[u][op], bv[u][op]);
                 }
             }
         }
@@ -215,11 +264,10 @@ __global__ __launch_bounds__(256) void k_pass(KArgs a) {
             y[0] = a.accumulate ? y[0] + a.scale * v[0] : a.scale * v[0];
         } else {
 #pragma unroll
-            for (int op = 0; op < NOPS; ++op)
-                if (op < nops) {
-                    double& o = y[(int64_t)op * nsets];
-                    o = a.accumulate ? o + a.scale * v[op] : a.scale * v[op];
-                }
+            for (int op = 0; op < NOPS; ++op) {
+                double& o = y[(int64_t)op * nsets];
+                o = a.accumulate ? o + a.scale * v[op] : a.scale * v[op];
+            }
         }
     } else if constexpr (EPI == EPI_ETA) {
         if (a.out_f32) ((float*)a.y)[seg * a.ldy + s] = (float)(a.scale * v[0]);
@@ -229,23 +277,24 @@ __global__ __launch_bounds__(256) void k_pass(KArgs a) {
         T* xo = (T*)a.xout;
 #pragma unroll
         for (int op = 0; op < NOPS; ++op) {
-            if (op >= nops) break;
             const int64_t idx = seg * a.ldb + (int64_t)op * nsets + s;
-            const double zk = a.z[idx];
+            // z and the accumulator are touched once per stage: streamed with
+            // non-temporal hints so they do not displace gathered operand rows
+            const double zk = __builtin_nontemporal_load(a.z + idx);
             const double f = v[op];
             double nxt;
             if (a.stage == 0) {
-                a.acc[idx] = zk + (ds / 6.0) * f;
+                __builtin_nontemporal_store(zk + (ds / 6.0) * f, a.acc + idx);
                 nxt = zk + 0.5 * ds * f;
             } else if (a.stage == 1) {
-                a.acc[idx] += (ds / 3.0) * f;
+                __builtin_nontemporal_store(__builtin_nontemporal_load(a.acc + idx) + (ds / 3.0) * f, a.acc + idx);
                 nxt = zk + 0.5 * ds * f;
             } else if (a.stage == 2) {
-                a.acc[idx] += (ds / 3.0) * f;
+                __builtin_nontemporal_store(__builtin_nontemporal_load(a.acc + idx) + (ds / 3.0) * f, a.acc + idx);
                 nxt = zk + ds * f;
             } else {
-                nxt = a.acc[idx] + (ds / 6.0) * f;
-                a.z[idx] = nxt;
+                nxt = __builtin_nontemporal_load(a.acc + idx) + (ds / 6.0) * f;
+                __builtin_nontemporal_store(nxt, a.z + idx);
             }
             xo[idx] = (T)nxt;
             if (op == 0) a.hst[seg * a.ldh + s] = nxt;
@@ -269,10 +318,16 @@ static void launch_nops(const KArgs& k, int prec, dim3 grid, hipStream_t s) {
     if constexpr (EPI == EPI_ETA) {
         hipLaunchKernelGGL((k_pass<G, 1, CUT_F64, MODE_BCAST, EPI_ETA>), grid, dim3(256), 0, s, k);
     } else {
-        if (k.nops <= 1) launch_prec<G, 1, MODE, EPI>(k, prec, grid, s);
-        else if (k.nops <= 2) launch_prec<G, 2, MODE, EPI>(k, prec, grid, s);
-        else if (k.nops <= 4) launch_prec<G, 4, MODE, EPI>(k, prec, grid, s);
-        else launch_prec<G, 8, MODE, EPI>(k, prec, grid, s);
+        switch (k.nops) {
+            case 1: launch_prec<G, 1, MODE, EPI>(k, prec, grid, s); break;
+            case 2: launch_prec<G, 2, MODE, EPI>(k, prec, grid, s); break;
+            case 3: launch_prec<G, 3, MODE, EPI>(k, prec, grid, s); break;
+            case 4: launch_prec<G, 4, MODE, EPI>(k, prec, grid, s); break;
+            case 5: launch_prec<G, 5, MODE, EPI>(k, prec, grid, s); break;
+            case 6: launch_prec<G, 6, MODE, EPI>(k, prec, grid, s); break;
+            case 7: launch_prec<G, 7, MODE, EPI>(k, prec, grid, s); break;
+            default: launch_prec<G, 8, MODE, EPI>(k, prec, grid, s); break;
+        }
     }
 }
 
@@ -280,19 +335,15 @@ template <int MODE, int EPI>
 static void launch_g(const KArgs& k, int prec, int G, dim3 grid, hipStream_t s) {
     switch (G) {
         case 1: launch_nops<1, MODE, EPI>(k, prec, grid, s); break;
-        case 2: launch_nops<2, MODE, EPI>(k, prec, grid, s); break;
         case 4: launch_nops<4, MODE, EPI>(k, prec, grid, s); break;
-        case 8: launch_nops<8, MODE, EPI>(k, prec, grid, s); break;
         case 16: launch_nops<16, MODE, EPI>(k, prec, grid, s); break;
-        case 32: launch_nops<32, MODE, EPI>(k, prec, grid, s); break;
         default: launch_nops<64, MODE, EPI>(k, prec, grid, s); break;
     }
 }
 
+// lanes per record slot: the smallest of 1, 4, 16, 64 holding nsets
 static int group_width(int nsets) {
-    int g = 1;
-    while (g < nsets && g < 64) g <<= 1;
-    return g;
+    return nsets <= 1 ? 1 : nsets <= 4 ? 4 : nsets <= 16 ? 16 : 64;
 }
 
 void launch_pass(int mode, int epi, const PassArgs& p, hipStream_t s) {

@@ -1,0 +1,205 @@
+"""GPU parity at the workloads' full sizes.
+
+* config 3 (m=40, 39.5M records, 64 sets x 5 operands), in the launch
+  configuration bench.py times (G2 generator, compensated float passes, RK4 steps
+  replayed from one hipGraph, default tiling): two whole RK4 steps of every
+  coefficient against the oracle's C engine; sampled single actions per target;
+* config 4 (m=64, 457.7M records, 16 sets): sampled single actions per target,
+  norm conservation over a short flow, float passes vs FP64 passes;
+* config 2: the whole flow to s=10 against the oracle's stored flow;
+* config 5: the whole-flow gradient against the oracle's stored discrete adjoint
+  and central differences of FP64 flows (32 directions).
+
+Tolerances: flowed coefficients within 1e-7 (norm-wise relative, per set and
+operand) for the float passes, 1e-11 for FP64; gradients within 1e-6 of central
+differences.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import gpu_util as U
+import workloads
+from oracle import algebra as A
+from oracle import gen as OG
+from oracle import graph as OGr
+from oracle import native
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2609_14831_amd import _lib
+    return _lib
+
+
+def _rel_cols(a, b):
+    """max over (op, set) of |a - b|_2 / |b|_2 along the registry axis."""
+    num = np.linalg.norm(a - b, axis=0)
+    den = np.linalg.norm(b, axis=0)
+    return float(np.max(num / den))
+
+
+def _flow(L, g, z0, ns, prec, w, steps=None, flags=None):
+    z = torch.tensor(z0, device=DEV).contiguous()
+    N, nops, nsets = z0.shape
+    p = L.flow_params(L.CUT_GEN_G2, prec, w.ds, w.delta, 0,
+                      flags=L.CUT_FLOW_HIPGRAPH if flags is None else flags,
+                      step_begin=0, step_end=-1 if steps is None else steps)
+    L.cut_flow_integrate(g, p, nsets, nops, [int(v) for v in ns], z)
+    torch.cuda.synchronize()
+    return z.cpu().numpy()
+
+
+@pytest.fixture(scope="module")
+def cfg3(L):
+    w = workloads.WORKLOADS[3]
+    U.say("[cfg3] build + load m=40")
+    g = U.graph(L, "majorana", 40, adjoint=False)
+    L.cut_graph_set_tiling(g, 1024, 0)   # bench default
+    return g, w, workloads.make_inputs(3)
+
+
+@pytest.fixture(scope="module")
+def cfg3_oracle():
+    U.say("[cfg3] oracle graph (C engine)")
+    return native.majorana_graph(40)
+
+
+@pytest.mark.timeout(600)
+def test_cfg3_two_rk4_steps_every_coefficient(L, cfg3, cfg3_oracle):
+    g, w, inp = cfg3
+    U.say("[cfg3] oracle 2 RK4 steps on 64 sets x 5 operands")
+    zr, _ = native.Engine(cfg3_oracle, "g2", w.delta).flow(inp.z0, w.ds, [2] * w.nsets)
+    for name, tol in (("F32C", 1e-7), ("F32X", 1e-7), ("F64", 1e-11)):
+        U.say(f"[cfg3] GPU 2 steps {name}")
+        z = _flow(L, g, inp.z0, inp.n_steps, getattr(L, "CUT_" + name), w, steps=2)
+        r = _rel_cols(z - inp.z0, zr - inp.z0)
+        U.say(f"[cfg3] {name}: max relative error of the 2-step increment {r:.3e}")
+        assert _rel_cols(z, zr) < tol
+        assert r < (1e-6 if name != "F64" else 1e-10)
+
+
+@pytest.mark.timeout(300)
+def test_cfg3_sampled_single_actions(L, cfg3):
+    g, w, inp = cfg3
+    reg = A.MajoranaRegistry(40)
+    rows = np.array([0, 1, 779, 780, 781, 40000, reg.N - 1] +
+                    list(np.random.default_rng(5).integers(0, reg.N, 25)))
+    og = A.majorana_graph(40, targets=rows)
+    eta = OG.G2(40, w.delta)(inp.z0[:, 0, :])
+    x = inp.z0
+    ref = OGr.apply_rows(og, eta, x, rows)
+    ga = A.Graph("majorana", 40, og.N, og.k, og.i, og.j, np.abs(og.c), og.diag, og.pairs, 1.0)
+    S = OGr.apply_rows(ga, np.abs(eta), np.abs(x), rows)
+    for name in ("F64", "F32X", "F32C"):
+        P = getattr(L, "CUT_" + name)
+        dt = torch.float64 if P == L.CUT_F64 else torch.float32
+        y = torch.zeros((reg.N, 320), dtype=torch.float64, device=DEV)
+        L.cut_graph_apply(g, 0, P, 64, 5, torch.tensor(eta, device=DEV).to(dt),
+                          torch.tensor(x.reshape(reg.N, 320), device=DEV).to(dt), y)
+        torch.cuda.synchronize()
+        got = y.cpu().numpy().reshape(reg.N, 5, 64)[rows]
+        bound = (64 * U.U64 if name == "F64" else 2 * U.U32 + U.dot2_bound(16948)) * S + 1e-300
+        U.assert_within(got, ref, bound, f"cfg3 sampled {name}")
+
+
+@pytest.mark.timeout(900)
+def test_cfg4_stress_graph(L):
+    w = workloads.WORKLOADS[4]
+    U.say("[cfg4] build m=64 (457.7M records)")
+    path = U.bundle_path(L, "majorana", 64)
+    desc = None
+    g = L.cut_graph_load(path, 0, 0)
+    try:
+        desc = L.cut_graph_info(g)
+        assert desc["n_records"] == 457_720_704 and desc["n_ops"] == 637_392
+        inp = workloads.make_inputs(4)
+        reg = A.MajoranaRegistry(64)
+        rows = np.array([0, 2015, 2016, reg.N // 2, reg.N - 1] +
+                        list(np.random.default_rng(6).integers(0, reg.N, 11)))
+        U.say("[cfg4] oracle sampled targets")
+        og = native.majorana_graph(64, targets=rows)
+        eta = OG.G2(64, w.delta)(inp.z0[:, 0, :])
+        ref = OGr.apply_rows(og, eta, inp.z0, rows)
+        ga = A.Graph("majorana", 64, og.N, og.k, og.i, og.j, np.abs(og.c), og.diag, og.pairs, 1.0)
+        S = OGr.apply_rows(ga, np.abs(eta), np.abs(inp.z0), rows)
+        for name in ("F64", "F32C"):
+            U.say(f"[cfg4] apply {name}")
+            P = getattr(L, "CUT_" + name)
+            dt = torch.float64 if P == L.CUT_F64 else torch.float32
+            y = torch.zeros((reg.N, 16), dtype=torch.float64, device=DEV)
+            L.cut_graph_apply(g, 0, P, 16, 1, torch.tensor(eta, device=DEV).to(dt),
+                              torch.tensor(inp.z0.reshape(reg.N, 16), device=DEV).to(dt), y)
+            torch.cuda.synchronize()
+            got = y.cpu().numpy().reshape(reg.N, 1, 16)[rows]
+            bound = (64 * U.U64 if name == "F64" else 2 * U.U32 + U.dot2_bound(75764)) * S + 1e-300
+            U.assert_within(got, ref, bound, f"cfg4 sampled {name}")
+        U.say("[cfg4] 20-step flows")
+        z64 = _flow(L, g, inp.z0, inp.n_steps, L.CUT_F64, w, steps=20)
+        z32 = _flow(L, g, inp.z0, inp.n_steps, L.CUT_F32C, w, steps=20)
+        assert _rel_cols(z32, z64) < 1e-7
+        n0 = np.linalg.norm(inp.z0, axis=0)
+        assert np.max(np.abs(np.linalg.norm(z64, axis=0) - n0) / n0) < 1e-9
+    finally:
+        L.cut_graph_free(g)
+
+
+@pytest.mark.timeout(600)
+def test_cfg2_full_flow_precision_study(L):
+    path = os.path.join(GOLD, "cfg2_flow_s10.npy")
+    if not os.path.exists(path):
+        pytest.skip("oracle golden not generated")
+    w = workloads.WORKLOADS[2]
+    inp = workloads.make_inputs(2)
+    zr = np.load(path)
+    g = U.graph(L, "majorana", 24, adjoint=False)
+    res = {}
+    for name in ("F64", "F32C", "F32X", "F32"):
+        U.say(f"[cfg2] full flow {name}")
+        z = _flow(L, g, inp.z0, inp.n_steps, getattr(L, "CUT_" + name), w)
+        res[name] = _rel_cols(z, zr)
+    U.say(f"[cfg2] relative errors at s=10 vs oracle: {res}")
+    assert res["F64"] < 1e-11
+    assert res["F32C"] < 1e-7 and res["F32X"] < 1e-7
+
+
+@pytest.mark.timeout(900)
+def test_cfg5_full_gradient(L):
+    path = os.path.join(GOLD, "cfg5_grad_s10.npy")
+    if not os.path.exists(path):
+        pytest.skip("oracle golden not generated")
+    from paper_2609_14831_amd.flow import flow
+    w = workloads.WORKLOADS[5]
+    inp = workloads.make_inputs(5, with_fd=32)
+    ref = np.load(path)
+    g = U.graph(L, "majorana", 24)
+    pairs = torch.tensor(A.MajoranaRegistry(24).pairs, device=DEV)
+    ns = [int(v) for v in inp.n_steps]
+    U.say("[cfg5] forward + adjoint (2000 steps, checkpoints every 16)")
+    z0 = torch.tensor(inp.z0, device=DEV, requires_grad=True)
+    loss = flow(z0, g, ns, L.CUT_GEN_G2, w.ds, w.delta, w.ckpt_every)[pairs, 0, :].sum()
+    loss.backward()
+    grad = z0.grad.cpu().numpy()
+    rel = np.linalg.norm(grad - ref) / np.linalg.norm(ref)
+    U.say(f"[cfg5] gradient vs oracle adjoint: {rel:.3e}")
+    assert rel < 1e-10
+    gnorm = np.linalg.norm(grad)
+    worst = 0.0
+    with torch.no_grad():
+        for q, d in enumerate(inp.fd_dirs):
+            v = torch.tensor(d[:, None, :], device=DEV)
+            eps = 1e-6
+            lp = flow(z0 + eps * v, g, ns, L.CUT_GEN_G2, w.ds, w.delta, w.ckpt_every)[pairs, 0, :].sum()
+            lm = flow(z0 - eps * v, g, ns, L.CUT_GEN_G2, w.ds, w.delta, w.ckpt_every)[pairs, 0, :].sum()
+            fd = float((lp - lm) / (2 * eps))
+            an = float(np.sum(grad[:, 0, :] * d))
+            err = abs(fd - an) / max(abs(fd), 1e-3 * gnorm)
+            worst = max(worst, err)
+    U.say(f"[cfg5] worst FD relative error over 32 directions: {worst:.3e}")
+    assert worst < 1e-6

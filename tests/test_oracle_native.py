@@ -15,6 +15,23 @@ def maj10():
     return A.majorana_graph(10)
 
 
+@pytest.mark.parametrize("m", [6, 10, 16])
+def test_c_records_match_numpy_records(m):
+    gc = native.majorana_graph(m)
+    gp = A.majorana_graph(m)
+    for f in ("k", "i", "j", "c"):
+        np.testing.assert_array_equal(getattr(gc, f), getattr(gp, f))
+
+
+def test_c_records_sampled_targets_m40():
+    reg = A.MajoranaRegistry(40)
+    t = np.array([0, 5, 779, 780, 50000, reg.N - 1])
+    gc = native.majorana_graph(40, targets=t)
+    gp = A.majorana_graph(40, targets=t)
+    for f in ("k", "i", "j", "c"):
+        np.testing.assert_array_equal(getattr(gc, f), getattr(gp, f))
+
+
 def test_engine_actions_match_numpy(maj10):
     g = maj10
     eng = native.Engine(g, "g2", 0.5)
