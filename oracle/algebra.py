@@ -48,9 +48,8 @@ class Graph:
         return int(self.k.size)
 
     def offsets(self) -> np.ndarray:
-        off = np.zeros(self.N + 1, dtype=np.int64)
-        np.add.at(off, self.k + 1, 1)
-        return np.cumsum(off)
+        cnt = np.bincount(self.k, minlength=self.N)
+        return np.concatenate([[0], np.cumsum(cnt)]).astype(np.int64)
 
     def eta_records(self) -> "Graph":
         """E_eta: the records whose left input is a block-diagonal coordinate.

@@ -52,7 +52,7 @@ def rule(rho: float, base: float = 5e-3) -> float:
 def main(cfg: int, nsample: int = 0):
     w = workloads.WORKLOADS[cfg]
     t = time.time()
-    g = A.majorana_graph(w.size)
+    g = native.majorana_graph(w.size)
     print(f"graph m={w.size}: E={g.E} ({time.time() - t:.1f} s)", flush=True)
     inp = workloads.make_inputs(cfg)
     h0 = inp.z0[:, 0, :]

@@ -31,6 +31,7 @@ CUT_ACCUMULATE = 1
 CUT_LOAD_ADJOINT, CUT_LOAD_NO_CHECKSUM = 1, 2
 CUT_FLOW_HIPGRAPH = 1
 CUT_FLOW_TIME_PASSES = 2
+CUT_TILE_XCD_REMAP, CUT_TILE_TRIPLES, CUT_TILE_NO_CHUNKS = 1, 2, 4
 
 STATUS_NAMES = {0: "CUT_OK", 1: "CUT_E_INVAL", 2: "CUT_E_IO", 3: "CUT_E_FORMAT",
                 4: "CUT_E_CHECKSUM", 5: "CUT_E_NOMEM", 6: "CUT_E_DEVICE", 7: "CUT_E_NUMERIC",
@@ -39,8 +40,8 @@ STATUS_NAMES = {0: "CUT_OK", 1: "CUT_E_INVAL", 2: "CUT_E_IO", 3: "CUT_E_FORMAT",
 # symbols declared in include/cutgraph.h
 EXPORTS = ["cut_graph_build", "cut_graph_load", "cut_graph_info", "cut_graph_free",
            "cut_graph_apply", "cut_graph_apply_adjoint", "cut_generator", "cut_generator_vjp",
-           "cut_flow_integrate", "cut_flow_adjoint", "cut_graph_set_tiling", "cut_flow_last_timing",
-           "cut_last_error", "cut_version"]
+           "cut_flow_integrate", "cut_flow_adjoint", "cut_graph_set_tiling", "cut_graph_autotune",
+           "cut_flow_last_timing", "cut_last_error", "cut_version"]
 
 
 class CutError(RuntimeError):
@@ -81,7 +82,7 @@ _L.cut_generator_vjp.argtypes = [_vp, _i32, _dbl, _i64, _vp, _i64, _vp, _i64, _v
 _L.cut_flow_integrate.argtypes = [_vp, C.POINTER(cut_flow_params), _i64, _i64, C.POINTER(_i32), _vp, _vp,
                                   _vp]
 _L.cut_flow_adjoint.argtypes = [_vp, C.POINTER(cut_flow_params), _i64, _i64, C.POINTER(_i32), _vp, _vp, _vp]
-_L.cut_graph_set_tiling.argtypes = [_vp, _i64, _i32]
+_L.cut_graph_set_tiling.argtypes = [_vp, _i64, _u32]
 
 
 class cut_flow_timing(C.Structure):
@@ -90,6 +91,14 @@ class cut_flow_timing(C.Structure):
 
 
 _L.cut_flow_last_timing.argtypes = [_vp, C.POINTER(cut_flow_timing)]
+
+
+class cut_tuning(C.Structure):
+    _fields_ = [("long_records", C.c_int64), ("tiling_flags", C.c_uint32), ("precision", C.c_int32),
+                ("pass_ms", C.c_double), ("default_ms", C.c_double)]
+
+
+_L.cut_graph_autotune.argtypes = [_vp, _i64, _i64, _i32, _i32, C.POINTER(cut_tuning)]
 _L.cut_last_error.restype = C.c_char_p
 _L.cut_version.restype = C.c_char_p
 for _name in EXPORTS:
@@ -159,8 +168,9 @@ def cut_graph_free(g: int) -> None:
     _L.cut_graph_free(g)
 
 
-def cut_graph_set_tiling(g: int, long_records: int, xcd_remap: int) -> None:
-    _check(_L.cut_graph_set_tiling(g, long_records, xcd_remap))
+def cut_graph_set_tiling(g: int, long_records: int, flags: int) -> None:
+    """flags: CUT_TILE_XCD_REMAP | CUT_TILE_TRIPLES | CUT_TILE_NO_CHUNKS."""
+    _check(_L.cut_graph_set_tiling(g, long_records, flags))
 
 
 # ------------------------------------------------------------------ apply --
@@ -206,6 +216,12 @@ def cut_flow_integrate(g: int, params: cut_flow_params, nsets: int, nops: int, n
     """z: device float64 [N, nops, nsets] contiguous, advanced in place."""
     _check(_L.cut_flow_integrate(g, C.byref(params), nsets, nops, _steps_arg(n_steps), _ptr(z),
                                  _ptr(ckpt), _stream(stream)))
+
+
+def cut_graph_autotune(g: int, nsets: int, nops: int, precision: int, allow_other_float: int = 1) -> dict:
+    t = cut_tuning()
+    _check(_L.cut_graph_autotune(g, nsets, nops, precision, allow_other_float, C.byref(t)))
+    return {k: getattr(t, k) for k, _ in t._fields_}
 
 
 def cut_flow_last_timing(g: int) -> dict:

@@ -144,7 +144,10 @@ extern "C" cut_status cut_graph_apply(cut_graph_t h, int32_t which, int32_t prec
     p.ldy = ldy;
     p.accumulate = (flags & CUT_ACCUMULATE) ? 1 : 0;
     p.scale = 1.0;
-    launch_pass(MODE_BCAST, EPI_Y, p, (hipStream_t)stream);
+    double* part = nullptr;
+    const size_t pb = which == CUT_GRAPH_FLOW ? forward_partial_bytes(g, p.nsets, p.nops, precision) : 0;
+    if (pb) part = (double*)g.ws_part.get(pb);
+    launch_forward(g, EPI_Y, p, part, (hipStream_t)stream);
     HIP_CHECK(hipGetLastError());
     ABI_END
 }

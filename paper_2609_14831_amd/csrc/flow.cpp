@@ -50,9 +50,12 @@ struct FlowBufs {
     int32_t* nsteps;
     int32_t* step;
     int32_t* flag;
+    double* part;   // tile partial slots (null when the tile path is not taken)
 };
 
-static FlowBufs flow_bufs(Graph& g, int64_t nsets, int64_t nops, bool f32, size_t extra, char** extra_ptr) {
+static FlowBufs flow_bufs(Graph& g, int64_t nsets, int64_t nops, int prec, size_t extra, char** extra_ptr) {
+    const bool f32 = prec != CUT_F64;
+    const size_t part_bytes = forward_partial_bytes(g, (int32_t)nsets, (int32_t)nops, prec);
     const int64_t N = g.N, cols = nops * nsets;
     const size_t tb = f32 ? 4 : 8;
     size_t o = 0;
@@ -72,6 +75,8 @@ static FlowBufs flow_bufs(Graph& g, int64_t nsets, int64_t nops, bool f32, size_
     o += 256;
     size_t ofl = o;
     o += 256;
+    size_t opart = o;
+    o += al(part_bytes);
     size_t oex = o;
     o += al(extra);
     char* b = (char*)g.ws.get(o);
@@ -84,6 +89,7 @@ static FlowBufs flow_bufs(Graph& g, int64_t nsets, int64_t nops, bool f32, size_
     f.nsteps = (int32_t*)(b + ons);
     f.step = (int32_t*)(b + ost);
     f.flag = (int32_t*)(b + ofl);
+    f.part = part_bytes ? (double*)(b + opart) : nullptr;
     if (extra_ptr) *extra_ptr = b + oex;
     return f;
 }
@@ -153,7 +159,8 @@ static void enqueue_step(const StepPlan& P, hipStream_t s, PassTimer* tm = nullp
         p.hst = P.fb.hst;
         p.ldh = P.nsets;
         if (tm) tm->mark(0, s);
-        launch_pass(MODE_BCAST, EPI_RK, p, s);
+        if (P.fb.part) launch_forward(g, EPI_RK, p, P.fb.part, s);
+        else launch_pass(MODE_BCAST, EPI_RK, p, s);
         if (tm) tm->mark(0, s);
     }
     launch_bump(P.fb.step, s);
@@ -188,7 +195,7 @@ extern "C" cut_status cut_flow_integrate(cut_graph_t h, const cut_flow_params* p
         const int64_t t1 = p->step_end < 0 ? T : std::min<int64_t>(p->step_end, T);
         const bool f32 = p->precision != CUT_F64;
         const int64_t cols = nops * nsets, M = g.N * cols;
-        FlowBufs fb = flow_bufs(g, nsets, nops, f32, 0, nullptr);
+        FlowBufs fb = flow_bufs(g, nsets, nops, p->precision, 0, nullptr);
         HIP_CHECK(hipMemcpyAsync(fb.nsteps, n_steps, nsets * 4, hipMemcpyHostToDevice, stream));
         launch_set_scalar(fb.step, (int32_t)t0, stream);
         launch_set_scalar(fb.flag, 0, stream);
@@ -206,7 +213,10 @@ extern "C" cut_status cut_flow_integrate(cut_graph_t h, const cut_flow_params* p
         if (use_graph) {
             std::vector<uint64_t> key = {(uint64_t)(uintptr_t)z, (uint64_t)(uintptr_t)g.ws.ptr, (uint64_t)p->generator,
                                          (uint64_t)p->precision, (uint64_t)nsets, (uint64_t)nops, 0, 0,
-                                         (uint64_t)g.csr[0][0].ntasks, (uint64_t)(uintptr_t)g.csr[0][0].tasks};
+                                         (uint64_t)g.csr[0][0].ntasks, (uint64_t)(uintptr_t)g.csr[0][0].tasks,
+                                         (uint64_t)(uintptr_t)fb.part, (uint64_t)(uintptr_t)g.tiles.res_tasks,
+                                         (uint64_t)(uintptr_t)g.csr[0][0].chunks,
+                                         (uint64_t)(uintptr_t)g.csr[0][0].short_tasks, (uint64_t)g.use_tiles};
             std::memcpy(&key[6], &p->ds, 8);
             std::memcpy(&key[7], &p->delta, 8);
             if (!g.graphs || g.graphs->key != key) {
@@ -321,7 +331,7 @@ extern "C" cut_status cut_flow_adjoint(cut_graph_t h, const cut_flow_params* p, 
         // extra: stage storage, zr, lam_new, mu, u, eta, geta, vjp scratch
         const size_t extra = al(nslot * M * 8) + 4 * al(M * 8) + 2 * al(g.N * nsets * 8) + al(2 * g.N * nsets * 8);
         char* ex = nullptr;
-        FlowBufs fb = flow_bufs(g, nsets, nops, false, extra, &ex);
+        FlowBufs fb = flow_bufs(g, nsets, nops, CUT_F64, extra, &ex);
         double* St = (double*)ex;
         ex += al(nslot * M * 8);
         double* zr = (double*)ex;

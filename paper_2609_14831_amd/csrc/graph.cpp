@@ -46,6 +46,11 @@ void DevCSR::release() {
     dev_free(off);
     dev_free(rec);
     dev_free(tasks);
+    dev_free(short_tasks);
+    dev_free(chunks);
+    dev_free(cstart);
+    dev_free(crow);
+    nshort = short_per_xcd = nchunks = nlong = 0;
     off_h.clear();
     off_h.shrink_to_fit();
     nseg = nrec = ntasks = per_xcd = 0;
@@ -92,8 +97,10 @@ Graph::~Graph() {
     dev_free(st_t);
     dev_free(st_p_off);
     dev_free(st_p);
+    tiles.release();
     ws.release();
     ws_small.release();
+    ws_part.release();
     (void)hipSetDevice(cur);
 }
 
@@ -102,11 +109,102 @@ Graph::~Graph() {
 // XCD remapping, the target range is cut into 8 contiguous pieces of equal
 // record count (one per XCD, so neighbouring targets share one L2), each piece
 // lists its long tasks first; shorter lists are padded with empty tasks.
-void build_tasks(Graph& g, DevCSR& c) {
-    dev_free(c.tasks);
-    c.ntasks = c.per_xcd = 0;
-    if (c.nseg == 0) return;
+static std::vector<Task> plan_tasks(const Graph& g, const std::vector<int64_t>& off, int64_t nseg, int64_t* per_xcd);
+
+static void upload_tasks(const std::vector<Task>& all, Task** dst, int64_t* n) {
+    dev_free(*dst);
+    *n = (int64_t)all.size();
+    if (all.empty()) return;
+    *dst = dev_alloc<Task>(all.size());
+    HIP_CHECK(hipMemcpy(*dst, all.data(), all.size() * sizeof(Task), hipMemcpyHostToDevice));
+}
+
+// Chunked plan: every segment longer than long_records is cut into
+// ceil(len / long_records) near-equal chunks; chunks are listed by the relative
+// position of their midpoint in their segment (so the chunks running together
+// cover the same part of every long segment), slots numbered per segment in
+// order; the remaining short segments are packed four per task.
+static void build_chunks(const Graph& g, DevCSR& c) {
+    dev_free(c.chunks);
+    dev_free(c.cstart);
+    dev_free(c.crow);
+    dev_free(c.short_tasks);
+    c.nchunks = c.nlong = c.nshort = c.short_per_xcd = 0;
     const std::vector<int64_t>& off = c.off_h;
+    const int64_t lr = g.long_records;
+    std::vector<int64_t> cstart = {0};
+    std::vector<int32_t> crow;
+    struct Ent {
+        double pos;
+        ChunkTask t;
+    };
+    std::vector<Ent> ents;
+    std::vector<uint8_t> is_long(c.nseg, 0);
+    if (c.nrec >= (1ll << 31) || !g.use_chunks) return;
+    for (int64_t k = 0; k < c.nseg; ++k) {
+        const int64_t len = off[k + 1] - off[k];
+        if (len <= lr) continue;
+        is_long[k] = 1;
+        const int64_t nch = (len + lr - 1) / lr;
+        const int64_t l = (int64_t)crow.size();
+        crow.push_back((int32_t)k);
+        for (int64_t q = 0; q < nch; ++q) {
+            const int64_t e0 = off[k] + len * q / nch, e1 = off[k] + len * (q + 1) / nch;
+            ents.push_back({(q + 0.5) / nch, ChunkTask{(int32_t)k, (int32_t)(cstart[l] + q), (int32_t)e0, (int32_t)e1}});
+        }
+        cstart.push_back(cstart[l] + nch);
+    }
+    std::stable_sort(ents.begin(), ents.end(), [](const Ent& a, const Ent& b) { return a.pos < b.pos; });
+    std::vector<ChunkTask> ch;
+    ch.reserve(ents.size());
+    for (auto& e : ents) ch.push_back(e.t);
+    // short segments: packed tasks over maximal runs of short segments
+    std::vector<Task> st;
+    for (int64_t k = 0; k < c.nseg;) {
+        if (is_long[k]) {
+            ++k;
+            continue;
+        }
+        int64_t k0 = k;
+        int n = 0;
+        while (k < c.nseg && n < 4 && !is_long[k]) {
+            ++k;
+            ++n;
+        }
+        st.push_back({(int32_t)k0, n});
+    }
+    c.nshort = (int64_t)st.size();
+    if (!st.empty()) {
+        c.short_tasks = dev_alloc<Task>(st.size());
+        HIP_CHECK(hipMemcpy(c.short_tasks, st.data(), st.size() * sizeof(Task), hipMemcpyHostToDevice));
+    }
+    c.nlong = (int64_t)crow.size();
+    c.nchunks = (int64_t)ch.size();
+    if (c.nchunks == 0) return;
+    c.chunks = dev_alloc<ChunkTask>(ch.size());
+    HIP_CHECK(hipMemcpy(c.chunks, ch.data(), ch.size() * sizeof(ChunkTask), hipMemcpyHostToDevice));
+    c.cstart = dev_alloc<int64_t>(cstart.size());
+    HIP_CHECK(hipMemcpy(c.cstart, cstart.data(), cstart.size() * 8, hipMemcpyHostToDevice));
+    c.crow = dev_alloc<int32_t>(crow.size());
+    HIP_CHECK(hipMemcpy(c.crow, crow.data(), crow.size() * 4, hipMemcpyHostToDevice));
+}
+
+void build_tasks(Graph& g, DevCSR& c) {
+    c.per_xcd = 0;
+    if (c.nseg == 0) {
+        upload_tasks({}, &c.tasks, &c.ntasks);
+        return;
+    }
+    upload_tasks(plan_tasks(g, c.off_h, c.nseg, &c.per_xcd), &c.tasks, &c.ntasks);
+    if (&c == &g.csr[0][0]) build_chunks(g, c);
+    if (&c == &g.csr[0][0] && g.tiles.ok) {
+        g.tiles.res_per_xcd = 0;
+        upload_tasks(plan_tasks(g, c.off_h, g.tiles.nres, &g.tiles.res_per_xcd), &g.tiles.res_tasks,
+                     &g.tiles.nres_tasks);
+    }
+}
+
+static std::vector<Task> plan_tasks(const Graph& g, const std::vector<int64_t>& off, int64_t nseg, int64_t* per_xcd) {
     auto plan = [&](int64_t b, int64_t e, std::vector<Task>& out) {
         std::vector<Task> shorts;
         for (int64_t k = b; k < e;) {
@@ -126,15 +224,17 @@ void build_tasks(Graph& g, DevCSR& c) {
         out.insert(out.end(), shorts.begin(), shorts.end());
     };
     std::vector<Task> all;
+    *per_xcd = 0;
+    if (nseg == 0) return all;
     if (g.xcd_remap) {
         std::vector<std::vector<Task>> parts(8);
-        const int64_t total = off[c.nseg] + 64 * c.nseg;  // records + per-target overhead
+        const int64_t total = off[nseg] + 64 * nseg;  // records + per-target overhead
         int64_t b = 0;
         for (int x = 0; x < 8; ++x) {
             int64_t e = b;
             const int64_t goal = total * (x + 1) / 8;
-            while (e < c.nseg && (off[e] + 64 * e) < goal) ++e;
-            if (x == 7) e = c.nseg;
+            while (e < nseg && (off[e] + 64 * e) < goal) ++e;
+            if (x == 7) e = nseg;
             plan(b, e, parts[x]);
             b = e;
         }
@@ -142,13 +242,108 @@ void build_tasks(Graph& g, DevCSR& c) {
         for (auto& p : parts) per = std::max(per, p.size());
         all.assign(per * 8, Task{0, 0});
         for (int x = 0; x < 8; ++x) std::copy(parts[x].begin(), parts[x].end(), all.begin() + x * per);
-        c.per_xcd = (int64_t)per;
+        *per_xcd = (int64_t)per;
     } else {
-        plan(0, c.nseg, all);
+        plan(0, nseg, all);
     }
-    c.ntasks = (int64_t)all.size();
-    c.tasks = dev_alloc<Task>(all.size());
-    HIP_CHECK(hipMemcpy(c.tasks, all.data(), all.size() * sizeof(Task), hipMemcpyHostToDevice));
+    return all;
+}
+
+void TilePlan::release() {
+    dev_free(rows);
+    dev_free(slot);
+    dev_free(rec);
+    dev_free(res_tasks);
+    ntiles = nres_tasks = res_per_xcd = nres = 0;
+    ok = false;
+}
+
+// Shared-triple tile plan for Majorana registries, derived from the registry
+// labels and the E_L records: for every record of a quartic target K whose
+// other operands are a quadratic string and a quartic K' with |K & K'| = 3,
+// tau = K & K' names the tile, w = K \ tau the member and q = K' \ tau the
+// staged operand (local index = mode minus the tau modes below it).  The plan is
+// accepted only if every quartic-target record lands in exactly one tile slot
+// and every (tile, member) holds the same number of records.
+static void build_tiles(Graph& g, const HostGraph& hg, const uint8_t* code) {
+    if (hg.hdr.algebra != CUT_ALG_MAJORANA) return;
+    const int m = hg.hdr.size;
+    const int64_t N = hg.hdr.n_ops;
+    const int64_t nquad = (int64_t)m * (m - 1) / 2;
+    const int M = m - 3, RT = 2 * (m - 4);
+    if (M < 2 || RT < 1) return;
+    auto binom3 = [](int64_t a) { return a < 3 ? 0 : a * (a - 1) * (a - 2) / 6; };
+    const int64_t ntiles = binom3(m);
+    // lexicographic rank of a 3-subset {a < b < c} of [0, m)
+    std::vector<int64_t> c3(m + 1), c2(m + 1);
+    for (int a = 0; a <= m; ++a) {
+        c3[a] = binom3(a);
+        c2[a] = (int64_t)a * (a - 1) / 2;
+    }
+    auto rank3 = [&](uint64_t t) {
+        int e[3], r = 0;
+        for (uint64_t x = t; x; x &= x - 1) e[r++] = __builtin_ctzll(x);
+        // hockey-stick form of the lexicographic rank
+        return (c3[m] - c3[m - e[0]]) + (c2[m - e[0] - 1] - c2[m - e[1]]) + ((m - e[1] - 1) - (m - e[2]));
+    };
+    auto local = [](uint64_t tau, int mode) { return mode - __builtin_popcountll(tau & ((1ull << mode) - 1)); };
+    const int64_t* off = hg.off[0];
+    for (int64_t k = nquad; k < N; ++k)
+        if (off[k + 1] - off[k] != 4 * (int64_t)RT) return;
+    std::vector<int32_t> rows(ntiles * M, -1);
+    std::vector<uint8_t> slot(ntiles * M, 255);
+    std::vector<uint2> rec(ntiles * M * (size_t)RT);
+    std::vector<int32_t> fill(ntiles * M, 0);
+    for (int64_t k = nquad; k < N; ++k) {
+        const uint64_t K = hg.labels[k];
+        if (__builtin_popcountll(K) != 4) return;
+        for (int64_t e = off[k]; e < off[k + 1]; ++e) {
+            const int32_t i = hg.ri[0][e], j = hg.rj[0][e];
+            const uint64_t Li = hg.labels[i], Lj = hg.labels[j];
+            const int orient = __builtin_popcountll(Li) == 4 ? 1 : 0;  // 1: generator row is quartic
+            const uint64_t Q = orient ? Li : Lj;
+            const int32_t quad = orient ? j : i;
+            if (__builtin_popcountll(hg.labels[quad]) != 2 || __builtin_popcountll(Q) != 4) return;
+            const uint64_t tau = K & Q;
+            if (__builtin_popcountll(tau) != 3) return;
+            const int w = __builtin_ctzll(K & ~tau), q = __builtin_ctzll(Q & ~tau);
+            const int64_t tile = rank3(tau);
+            if (tile < 0 || tile >= ntiles) return;
+            const int64_t mt = tile * M + local(tau, w);
+            const int sl = __builtin_popcountll(K & ((1ull << w) - 1));
+            if (rows[mt] < 0) {
+                rows[mt] = (int32_t)k;
+                slot[mt] = (uint8_t)sl;
+            } else if (rows[mt] != k || slot[mt] != sl) {
+                return;
+            }
+            if (fill[mt] >= RT) return;
+            rec[mt * RT + fill[mt]++] =
+                make_uint2(((uint32_t)code[(uint8_t)hg.rc[0][e]] << 24) | (uint32_t)quad,
+                           ((uint32_t)local(tau, q) << 1) | (uint32_t)orient);
+        }
+    }
+    for (int64_t mt = 0; mt < ntiles * M; ++mt)
+        if (fill[mt] != RT || rows[mt] < 0) return;
+    // within each member: records whose generator is the quadratic row first
+    // (operand from LDS), then the others, each in stored order
+    for (int64_t mt = 0; mt < ntiles * M; ++mt) {
+        uint2* r = rec.data() + mt * RT;
+        std::stable_sort(r, r + RT, [](const uint2& x, const uint2& y) { return (x.y & 1u) < (y.y & 1u); });
+    }
+    TilePlan& tp = g.tiles;
+    tp.ntiles = ntiles;
+    tp.M = M;
+    tp.RT = RT;
+    tp.nres = nquad;
+    tp.rows = dev_alloc<int32_t>(rows.size());
+    HIP_CHECK(hipMemcpy(tp.rows, rows.data(), rows.size() * 4, hipMemcpyHostToDevice));
+    tp.slot = dev_alloc<uint8_t>(slot.size());
+    HIP_CHECK(hipMemcpy(tp.slot, slot.data(), slot.size(), hipMemcpyHostToDevice));
+    tp.rec = dev_alloc<uint2>(rec.size());
+    HIP_CHECK(hipMemcpy(tp.rec, rec.data(), rec.size() * sizeof(uint2), hipMemcpyHostToDevice));
+    tp.ok = true;
+    build_tasks(g, g.csr[0][0]);
 }
 
 static void upload_csr(Graph& g, DevCSR& c, int64_t nseg, std::vector<int64_t>&& off,
@@ -165,6 +360,37 @@ static void upload_csr(Graph& g, DevCSR& c, int64_t nseg, std::vector<int64_t>&&
     build_tasks(g, c);
 }
 
+// Lexicographic rank of a 3-subset {a < b < c} of [0, m) (hockey-stick form).
+static int64_t lex_rank3(uint64_t t, int m) {
+    auto c3 = [](int64_t a) { return a < 3 ? 0 : a * (a - 1) * (a - 2) / 6; };
+    auto c2 = [](int64_t a) { return a < 2 ? 0 : a * (a - 1) / 2; };
+    int e[3], r = 0;
+    for (uint64_t x = t; x && r < 3; x &= x - 1) e[r++] = __builtin_ctzll(x);
+    return (c3(m) - c3(m - e[0])) + (c2(m - e[0] - 1) - c2(m - e[1])) + ((m - e[1] - 1) - (m - e[2]));
+}
+
+// Locality order of the long (quadratic-target) segments of a Majorana graph:
+// a record (i, j) of target {a, b} pairs T+a with T+b; sorting each such
+// segment by the rank of the shared triple T makes the same position of every
+// long segment touch the same rows T+w.  Only the order of each sum changes.
+static void locality_order(const HostGraph& hg, const int64_t* off, int64_t N, std::vector<uint2>& rec) {
+    const int m = hg.hdr.size;
+    std::vector<std::pair<int64_t, uint2>> buf;
+    for (int64_t k = 0; k < N; ++k) {
+        if (__builtin_popcountll(hg.labels[k]) != 2) continue;
+        buf.clear();
+        for (int64_t e = off[k]; e < off[k + 1]; ++e) {
+            const uint64_t L = hg.labels[rec[e].x & 0xFFFFFFu] & hg.labels[rec[e].y];
+            buf.push_back({__builtin_popcountll(L) == 3 ? lex_rank3(L, m) : -1, rec[e]});
+        }
+        std::stable_sort(buf.begin(), buf.end(),
+                         [](const std::pair<int64_t, uint2>& x, const std::pair<int64_t, uint2>& y) {
+                             return x.first < y.first;
+                         });
+        for (int64_t e = off[k]; e < off[k + 1]; ++e) rec[e] = buf[e - off[k]].second;
+    }
+}
+
 // orientation 0 from the bundle; 1 and 2 by stable counting sort
 static void build_copies(Graph& g, const HostGraph& hg, int w, bool adjoint, const uint8_t* code) {
     const int64_t N = hg.hdr.n_ops;
@@ -177,6 +403,7 @@ static void build_copies(Graph& g, const HostGraph& hg, int w, bool adjoint, con
         std::vector<uint2> rec((size_t)E);
         for (int64_t e = 0; e < E; ++e)
             rec[e] = make_uint2(((uint32_t)code[(uint8_t)rc[e]] << 24) | (uint32_t)ri[e], (uint32_t)rj[e]);
+        if (w == 0 && hg.hdr.algebra == CUT_ALG_MAJORANA) locality_order(hg, off, N, rec);
         upload_csr(g, g.csr[w][0], N, std::vector<int64_t>(off, off + N + 1), rec);
     }
     if (!adjoint) return;
@@ -301,6 +528,12 @@ extern "C" cut_status cut_graph_load(const char* path, int32_t dev, uint32_t fla
         g->pairs = dev_alloc<int32_t>(g->npairs);
         if (g->npairs) HIP_CHECK(hipMemcpy(g->pairs, hg.pairs, g->npairs * 4, hipMemcpyHostToDevice));
         build_stencil(*g, hg, code);
+        {
+            int lds = 0;
+            if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && lds > 0)
+                g->max_lds = lds;
+        }
+        build_tiles(*g, hg, code);
         HIP_CHECK(hipDeviceSynchronize());
         HIP_CHECK(hipSetDevice(prev));
         *out = (cut_graph_t)g;
@@ -338,16 +571,18 @@ extern "C" cut_status cut_graph_info(cut_graph_t h, cut_graph_desc* d) {
     return CUT_OK;
 }
 
-extern "C" cut_status cut_graph_set_tiling(cut_graph_t h, int64_t long_records, int32_t xcd_remap) {
+extern "C" cut_status cut_graph_set_tiling(cut_graph_t h, int64_t long_records, uint32_t flags) {
     try {
-        if (!h || long_records < 1) CUT_FAIL(CUT_E_INVAL, "cut_graph_set_tiling: bad argument");
+        if (!h || long_records < 1 || (flags & ~7u)) CUT_FAIL(CUT_E_INVAL, "cut_graph_set_tiling: bad argument");
         Graph& g = *(Graph*)h;
         int prev = 0;
         HIP_CHECK(hipGetDevice(&prev));
         HIP_CHECK(hipSetDevice(g.device));
         HIP_CHECK(hipDeviceSynchronize());
         g.long_records = long_records;
-        g.xcd_remap = xcd_remap ? 1 : 0;
+        g.xcd_remap = (flags & CUT_TILE_XCD_REMAP) ? 1 : 0;
+        g.use_tiles = (flags & CUT_TILE_TRIPLES) ? 1 : 0;
+        g.use_chunks = (flags & CUT_TILE_NO_CHUNKS) ? 0 : 1;
         for (auto& w : g.csr)
             for (auto& c : w)
                 if (c.nseg) build_tasks(g, c);

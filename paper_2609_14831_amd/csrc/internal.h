@@ -111,6 +111,15 @@ struct Task {          // one workgroup of 4 wavefronts
                        // <0: one long segment split over the 4 wavefronts
 };
 
+// A chunk of a long segment: records [e0, e1) of segment `seg`, summed by one
+// wavefront into partial row `slot`.
+struct ChunkTask {
+    int32_t seg;
+    int32_t slot;
+    int32_t e0;
+    int32_t e1;
+};
+
 struct DevCSR {
     int64_t nseg = 0, nrec = 0, max_len = 0;
     int64_t* off = nullptr;     // device [nseg+1]
@@ -118,7 +127,41 @@ struct DevCSR {
     Task* tasks = nullptr;      // device [ntasks] (8*per_xcd when XCD-remapped)
     int64_t ntasks = 0;
     int64_t per_xcd = 0;        // >0: block b runs task (b%8)*per_xcd + b/8
+    // chunked form: long segments as chunk tasks (ordered by relative position
+    // in their segment, so concurrently running chunks sweep the same operand
+    // region), short segments as packed tasks
+    Task* short_tasks = nullptr;
+    int64_t nshort = 0, short_per_xcd = 0;
+    ChunkTask* chunks = nullptr;
+    int64_t nchunks = 0;
+    int64_t* cstart = nullptr;  // device [nlong+1]: slots of long segment l
+    int32_t* crow = nullptr;    // device [nlong]: its row
+    int64_t nlong = 0;
     std::vector<int64_t> off_h; // host copy of the offsets (tiling plan input)
+    void release();
+};
+
+// Shared-triple tiles (Majorana registries).  Every record of a quartic target
+// K pairs a quadratic string with a quartic K' sharing three modes tau = K & K'.
+// Tile tau owns the M = m-3 quartic rows tau+w (w not in tau): they are both the
+// tile's targets and the quartic operands of its records, so one workgroup
+// stages them in LDS once.  Record of member t: .x = (code << 24) | quadratic
+// row, .y = (local operand q << 1) | orient (0: generator from the quadratic
+// row, operand from LDS; 1: generator from LDS, operand from the quadratic
+// row).  Target tau+w receives its tile-tau sum in partial slot `slot` (the
+// position of w in K); the 4 slots are added in fixed order by the combine.
+struct TilePlan {
+    int64_t ntiles = 0;
+    int32_t M = 0;             // members per tile
+    int32_t RT = 0;            // records per member
+    int64_t nres = 0;          // segments [0, nres) stay with the segment kernel
+    int32_t* rows = nullptr;   // device [ntiles * M]
+    uint8_t* slot = nullptr;   // device [ntiles * M]
+    uint2* rec = nullptr;      // device [ntiles * M * RT]
+    Task* res_tasks = nullptr; // segment tasks over [0, nres)
+    int64_t nres_tasks = 0;
+    int64_t res_per_xcd = 0;
+    bool ok = false;
     void release();
 };
 
@@ -156,10 +199,16 @@ struct Graph {
     bool have_stencil = false;
     int64_t long_records = 1024;
     int xcd_remap = 0;
+    TilePlan tiles;
+    int use_tiles = 0;
+    int use_chunks = 1;
+    int64_t max_lds = 65536;         // LDS bytes one workgroup may allocate
     Workspace ws;                    // flow state and stage storage
     Workspace ws_small;              // scratch of single generator-VJP calls
+    Workspace ws_part;               // tile partial slots of single forward passes
     StepGraphCache* graphs = nullptr;
     cut_flow_timing timing{};        // last timed flow
+    std::vector<std::pair<std::vector<int64_t>, cut_tuning>> tune_cache;
     ~Graph();
 };
 
@@ -172,6 +221,9 @@ enum Epi { EPI_Y = 0, EPI_ETA = 1, EPI_RK = 2 };
 
 struct PassArgs {
     const DevCSR* csr;
+    const Task* tasks = nullptr;    // overrides csr's task list when set
+    int64_t ntasks = 0;
+    int64_t per_xcd = 0;
     const double* ftab;
     const void* A;
     int64_t lda;
@@ -197,6 +249,18 @@ struct PassArgs {
 };
 
 void launch_pass(int mode, int epi, const PassArgs& a, hipStream_t s);
+
+// Forward pass of record set 0 over every target: the shared-triple tile path
+// when available for this shape (residual segment kernel + tile kernel +
+// fixed-order combine with the epilogue), otherwise the segment kernel.
+// `partials` must hold tile_partial_bytes() bytes when the tile path is taken.
+bool tiles_usable(const Graph& g, int32_t nsets, int32_t nops, int32_t precision);
+// bytes of partial rows the chunked forward pass needs (0: not chunked)
+size_t chunk_partial_bytes(const Graph& g, int32_t nsets, int32_t nops);
+// partial work area a forward pass of record set 0 needs (tiles or chunks)
+size_t forward_partial_bytes(const Graph& g, int32_t nsets, int32_t nops, int32_t precision);
+size_t tile_partial_bytes(const Graph& g, int32_t nsets, int32_t nops);
+void launch_forward(const Graph& g, int epi, const PassArgs& a, double* partials, hipStream_t s);
 
 void launch_g2(const Graph& g, double delta, int32_t nsets, const double* h, int64_t ldh,
                void* eta, int64_t lde, bool eta_f32, const int32_t* nsteps, const int32_t* step,

@@ -49,6 +49,11 @@ struct KArgs {
     void* xout;
     double* hst;
     int64_t ldh;
+    // chunk tasks (long segments): partial rows instead of the epilogue
+    const ChunkTask* chunks;
+    int64_t nchunks;
+    double* part;
+    int64_t ldp;
 };
 
 template <int PREC>
@@ -116,6 +121,39 @@ __device__ inline bool set_active(const KArgs& a, int s) {
     return a.nsteps[s] > *a.step;
 }
 
+// Classic RK4 stage combination for the NOPS operand values f of row `seg`,
+// set s: stage 0 starts the accumulator, 1-2 add to it, 3 finishes the step;
+// the next stage operand is written (float or double shadow) together with the
+// FP64 Hamiltonian column.  z and the accumulator are touched once per stage:
+// streamed with non-temporal hints so they do not displace gathered rows.
+template <int NOPS, class T>
+__device__ inline void rk_epilogue(const KArgs& a, int64_t seg, int s, const double* v) {
+    const double ds = a.ds;
+    T* xo = (T*)a.xout;
+#pragma unroll
+    for (int op = 0; op < NOPS; ++op) {
+        const int64_t idx = seg * a.ldb + (int64_t)op * a.nsets + s;
+        const double zk = __builtin_nontemporal_load(a.z + idx);
+        const double f = v[op];
+        double nxt;
+        if (a.stage == 0) {
+            __builtin_nontemporal_store(zk + (ds / 6.0) * f, a.acc + idx);
+            nxt = zk + 0.5 * ds * f;
+        } else if (a.stage == 1) {
+            __builtin_nontemporal_store(__builtin_nontemporal_load(a.acc + idx) + (ds / 3.0) * f, a.acc + idx);
+            nxt = zk + 0.5 * ds * f;
+        } else if (a.stage == 2) {
+            __builtin_nontemporal_store(__builtin_nontemporal_load(a.acc + idx) + (ds / 3.0) * f, a.acc + idx);
+            nxt = zk + ds * f;
+        } else {
+            nxt = __builtin_nontemporal_load(a.acc + idx) + (ds / 6.0) * f;
+            __builtin_nontemporal_store(nxt, a.z + idx);
+        }
+        xo[idx] = (T)nxt;
+        if (op == 0) a.hst[seg * a.ldh + s] = nxt;
+    }
+}
+
 template <int G, int NOPS, int PREC, int MODE, int EPI>
 __global__ __launch_bounds__(256) void k_pass(KArgs a) {
     using T = typename PrecT<PREC>::T;
@@ -123,13 +161,6 @@ __global__ __launch_bounds__(256) void k_pass(KArgs a) {
     constexpr int NACC = (MODE == MODE_REDOPS) ? 1 : NOPS;
     __shared__ double red[4][NACC][G];
 
-    int64_t t = blockIdx.x;
-    if (a.per_xcd > 0) {
-        t = (int64_t)(blockIdx.x & 7) * a.per_xcd + (blockIdx.x >> 3);
-        if ((blockIdx.x >> 3) >= a.per_xcd) return;
-    }
-    if (t >= a.ntasks) return;
-    const Task task = a.tasks[t];
     // wave index through an SGPR so segment bounds and loop control stay scalar
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int lane = threadIdx.x & 63;
@@ -137,10 +168,31 @@ __global__ __launch_bounds__(256) void k_pass(KArgs a) {
     const int sub = lane / G;
     const int s = blockIdx.y * G + sg;
     const bool act = set_active(a, s);
-    const bool split = task.nseg < 0;
-
+    const bool chunked = a.chunks != nullptr;
+    Task task{0, 0};
+    int32_t slot = 0;
     int64_t seg, e0, e1;
-    if (split) {
+    if (chunked) {  // one chunk of a long segment per wavefront
+        const int64_t ci = (int64_t)blockIdx.x * 4 + wave;
+        if (ci >= a.nchunks) return;
+        const ChunkTask ct = a.chunks[ci];
+        seg = ct.seg;
+        slot = ct.slot;
+        e0 = ct.e0;
+        e1 = ct.e1;
+    } else {
+        int64_t t = blockIdx.x;
+        if (a.per_xcd > 0) {
+            t = (int64_t)(blockIdx.x & 7) * a.per_xcd + (blockIdx.x >> 3);
+            if ((blockIdx.x >> 3) >= a.per_xcd) return;
+        }
+        if (t >= a.ntasks) return;
+        task = a.tasks[t];
+    }
+    const bool split = !chunked && task.nseg < 0;
+
+    if (chunked) {
+    } else if (split) {
         seg = task.seg;
         const int64_t b = a.off[seg], n = a.off[seg + 1] - b;
         e0 = b + (n * wave) / 4;
@@ -167,7 +219,10 @@ __global__ __launch_bounds__(256) void k_pass(KArgs a) {
     // gathers of U records before any arithmetic, so U dependent load chains are
     // in flight per wavefront.
     constexpr int NA = (MODE == MODE_REDOPS) ? NOPS : 1;
-    constexpr int U = (NOPS <= 2) ? 8 : 4;
+#ifndef CUT_PASS_UNROLL
+#define CUT_PASS_UNROLL 4
+#endif
+    constexpr int U = (NOPS <= 2) ? 8 : CUT_PASS_UNROLL;
     constexpr int CH = (G >= U) ? 1 : U / G;  // 64-record chunks per outer iteration
     constexpr int SLOTS = CH * G;             // record slots of one lane group per iteration
     for (int64_t base = e0; base < e1; base += 64 * CH) {
@@ -244,6 +299,14 @@ __global__ __launch_bounds__(256) void k_pass(KArgs a) {
 #pragma unroll
         for (int o = G; o < 64; o <<= 1) v[q] += __shfl_xor(v[q], o);
     }
+    if (chunked) {
+        if (sub == 0 && act) {
+            double* p = a.part + (int64_t)slot * a.ldp + s;
+#pragma unroll
+            for (int q = 0; q < NACC; ++q) p[(int64_t)q * nsets] = v[q];
+        }
+        return;
+    }
     if (split) {
         if (sub == 0) {
 #pragma unroll
@@ -273,32 +336,7 @@ __global__ __launch_bounds__(256) void k_pass(KArgs a) {
         if (a.out_f32) ((float*)a.y)[seg * a.ldy + s] = (float)(a.scale * v[0]);
         else ((double*)a.y)[seg * a.ldy + s] = a.scale * v[0];
     } else {  // EPI_RK: stage combination of classic RK4
-        const double ds = a.ds;
-        T* xo = (T*)a.xout;
-#pragma unroll
-        for (int op = 0; op < NOPS; ++op) {
-            const int64_t idx = seg * a.ldb + (int64_t)op * nsets + s;
-            // z and the accumulator are touched once per stage: streamed with
-            // non-temporal hints so they do not displace gathered operand rows
-            const double zk = __builtin_nontemporal_load(a.z + idx);
-            const double f = v[op];
-            double nxt;
-            if (a.stage == 0) {
-                __builtin_nontemporal_store(zk + (ds / 6.0) * f, a.acc + idx);
-                nxt = zk + 0.5 * ds * f;
-            } else if (a.stage == 1) {
-                __builtin_nontemporal_store(__builtin_nontemporal_load(a.acc + idx) + (ds / 3.0) * f, a.acc + idx);
-                nxt = zk + 0.5 * ds * f;
-            } else if (a.stage == 2) {
-                __builtin_nontemporal_store(__builtin_nontemporal_load(a.acc + idx) + (ds / 3.0) * f, a.acc + idx);
-                nxt = zk + ds * f;
-            } else {
-                nxt = __builtin_nontemporal_load(a.acc + idx) + (ds / 6.0) * f;
-                __builtin_nontemporal_store(nxt, a.z + idx);
-            }
-            xo[idx] = (T)nxt;
-            if (op == 0) a.hst[seg * a.ldh + s] = nxt;
-        }
+        rk_epilogue<NOPS, T>(a, seg, s, v);
     }
 }
 
@@ -346,13 +384,12 @@ static int group_width(int nsets) {
     return nsets <= 1 ? 1 : nsets <= 4 ? 4 : nsets <= 16 ? 16 : 64;
 }
 
-void launch_pass(int mode, int epi, const PassArgs& p, hipStream_t s) {
+static KArgs make_kargs(const PassArgs& p) {
     const DevCSR& c = *p.csr;
-    if (c.nseg == 0) return;
     KArgs k{};
-    k.tasks = c.tasks;
-    k.ntasks = c.ntasks;
-    k.per_xcd = c.per_xcd;
+    k.tasks = p.tasks ? p.tasks : c.tasks;
+    k.ntasks = p.tasks ? p.ntasks : c.ntasks;
+    k.per_xcd = p.tasks ? p.per_xcd : c.per_xcd;
     k.off = c.off;
     k.rec = c.rec;
     k.ftab = p.ftab;
@@ -376,8 +413,15 @@ void launch_pass(int mode, int epi, const PassArgs& p, hipStream_t s) {
     k.xout = p.xout;
     k.hst = p.hst;
     k.ldh = p.ldh;
+    return k;
+}
+
+void launch_pass(int mode, int epi, const PassArgs& p, hipStream_t s) {
+    if (p.csr->nseg == 0) return;
+    const KArgs k = make_kargs(p);
+    if (k.ntasks == 0) return;
     const int G = group_width(p.nsets);
-    const int64_t nblk = c.per_xcd > 0 ? 8 * c.per_xcd : c.ntasks;
+    const int64_t nblk = k.per_xcd > 0 ? 8 * k.per_xcd : k.ntasks;
     dim3 grid((unsigned)nblk, (unsigned)((p.nsets + G - 1) / G));
     if (mode == MODE_BCAST) {
         if (epi == EPI_Y) launch_g<MODE_BCAST, EPI_Y>(k, p.precision, G, grid, s);
@@ -385,6 +429,356 @@ void launch_pass(int mode, int epi, const PassArgs& p, hipStream_t s) {
         else launch_g<MODE_BCAST, EPI_RK>(k, p.precision, G, grid, s);
     } else {
         launch_g<MODE_REDOPS, EPI_Y>(k, p.precision, G, grid, s);
+    }
+}
+
+// ----------------------------------------------------- shared-triple tiles ----
+// One workgroup per (tile tau, chunk of G sets).  The M member rows tau+w are
+// staged in LDS as [M][NOPS+1][G] (operand columns, then the generator); each
+// wavefront then walks members t = wave, wave+4, ...: every record of member t
+// reads one operand from LDS and the other from its quadratic row (a small,
+// L2-resident set), and the member's sum goes to its partial slot.
+struct TileKArgs {
+    const int32_t* rows;
+    const uint8_t* slot;
+    const uint2* rec;
+    const double* ftab;
+    int32_t M, RT;
+    const void* H;
+    int64_t lde;
+    const void* X;
+    int64_t ldx;
+    int32_t nsets;
+    const int32_t* nsteps;
+    const int32_t* step;
+    double* P;
+    int64_t ldp;
+    int64_t pstride;
+};
+
+template <int G, int NOPS, int PREC>
+__global__ __launch_bounds__(256) void k_tile(TileKArgs a) {
+    using T = typename PrecT<PREC>::T;
+    constexpr int R = 64 / G;
+#ifndef CUT_TILE_UNROLL
+#define CUT_TILE_UNROLL 4
+#endif
+    constexpr int U = (NOPS <= 2) ? 8 : CUT_TILE_UNROLL;
+    constexpr int W = NOPS + 1;
+    extern __shared__ __align__(16) unsigned char tile_lds[];
+    T* lds = reinterpret_cast<T*>(tile_lds);
+    const int64_t tile = blockIdx.x;
+    const int s0 = blockIdx.y * G;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int sg = lane % G, sub = lane / G;
+    const int s = s0 + sg;
+    const int nsets = a.nsets;
+    const bool act = s < nsets && (a.nsteps == nullptr || a.nsteps[s] > *a.step);
+    const int sl = s < nsets ? s : nsets - 1;
+    const int M = a.M, RT = a.RT;
+    const int32_t* trows = a.rows + tile * M;
+    const T* __restrict__ H = (const T*)a.H;
+    const T* __restrict__ X = (const T*)a.X;
+    constexpr int per_row = W * G;
+    for (int e = threadIdx.x; e < M * per_row; e += 256) {
+        const int r = e / per_row, rem = e - r * per_row, c = rem / G, ss = rem - c * G;
+        const int64_t grow = trows[r];
+        const int sc = (s0 + ss < nsets) ? s0 + ss : nsets - 1;
+        lds[e] = (c < NOPS) ? X[grow * a.ldx + (int64_t)c * nsets + sc] : H[grow * a.lde + sc];
+    }
+    __syncthreads();
+    int coff[NOPS];
+#pragma unroll
+    for (int op = 0; op < NOPS; ++op) coff[op] = sl + op * nsets;
+    for (int t = wave; t < M; t += 4) {
+        const uint2* tr = a.rec + (tile * M + t) * (int64_t)RT;
+        Acc<PREC> acc[NOPS];
+        for (int r0 = 0; r0 < RT; r0 += R * U) {
+            uint2 rr[U];
+            bool ok[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int r = r0 + u * R + sub;
+                ok[u] = r < RT;
+                rr[u] = tr[ok[u] ? r : RT - 1];
+            }
+            T av[U];
+            T bv[U][NOPS];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int64_t quad = rr[u].x & 0xFFFFFFu;
+                const T* lrow = lds + (int)(rr[u].y >> 1) * per_row + sg;
+                if (rr[u].y & 1u) {  // generator from LDS, operand from the quadratic row
+                    av[u] = lrow[NOPS * G];
+                    const T* xr = X + quad * a.ldx;
+#pragma unroll
+                    for (int op = 0; op < NOPS; ++op) bv[u][op] = xr[coff[op]];
+                } else {             // generator from the quadratic row, operand from LDS
+                    av[u] = H[quad * a.lde + sl];
+#pragma unroll
+                    for (int op = 0; op < NOPS; ++op) bv[u][op] = lrow[op * G];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const double cf = ok[u] ? a.ftab[rr[u].x >> 24] : 0.0;
+                const auto tl = left_term<PREC>(cf, av[u]);
+#pragma unroll
+                for (int op = 0; op < NOPS; ++op) acc[op].add(tl, bv[u][op]);
+            }
+        }
+        double v[NOPS];
+#pragma unroll
+        for (int op = 0; op < NOPS; ++op) {
+            v[op] = acc[op].get();
+#pragma unroll
+            for (int o = G; o < 64; o <<= 1) v[op] += __shfl_xor(v[op], o);
+        }
+        if (sub == 0 && act) {
+            double* P = a.P + (int64_t)a.slot[tile * M + t] * a.pstride + (int64_t)trows[t] * a.ldp + s;
+#pragma unroll
+            for (int op = 0; op < NOPS; ++op) P[(int64_t)op * nsets] = v[op];
+        }
+    }
+}
+
+// Fixed-order sum of the 4 partial slots of rows [row0, row0 + nrows), then the
+// epilogue (store / accumulate, or the RK stage update).
+template <int NOPS, int PREC, int EPI>
+__global__ __launch_bounds__(256) void k_combine(KArgs a, const double* __restrict__ P, int64_t pstride,
+                                                 int64_t ldp, int64_t row0, int64_t nrows) {
+    using T = typename PrecT<PREC>::T;
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= nrows * a.nsets) return;
+    const int64_t row = row0 + q / a.nsets;
+    const int s = (int)(q % a.nsets);
+    if (a.nsteps && a.nsteps[s] <= *a.step) return;
+    const double* p = P + row * ldp + s;
+    double v[NOPS];
+#pragma unroll
+    for (int op = 0; op < NOPS; ++op) {
+        const int64_t o = (int64_t)op * a.nsets;
+        v[op] = ((__builtin_nontemporal_load(p + o) + __builtin_nontemporal_load(p + pstride + o)) +
+                 __builtin_nontemporal_load(p + 2 * pstride + o)) +
+                __builtin_nontemporal_load(p + 3 * pstride + o);
+    }
+    if constexpr (EPI == EPI_Y) {
+        double* y = (double*)a.y + row * a.ldy + s;
+#pragma unroll
+        for (int op = 0; op < NOPS; ++op) {
+            double& o = y[(int64_t)op * a.nsets];
+            o = a.accumulate ? o + a.scale * v[op] : a.scale * v[op];
+        }
+    } else {
+        rk_epilogue<NOPS, T>(a, row, s, v);
+    }
+}
+
+// sets per tile workgroup: 16 for narrow batches, else 32 (each gathered run
+// of one operand column is a full 128-byte line; two workgroups per 64 sets
+// keep the staged rows small enough for several workgroups per CU)
+static int tile_width(int nsets) { return nsets <= 16 ? 16 : 32; }
+
+// Long segments: the partial rows of their chunks [cstart[l], cstart[l+1])
+// added in chunk order, then the epilogue on row crow[l].
+template <int NOPS, int PREC, int EPI>
+__global__ __launch_bounds__(256) void k_chunk_combine(KArgs a, const double* __restrict__ P, int64_t ldp,
+                                                       const int64_t* __restrict__ cstart,
+                                                       const int32_t* __restrict__ crow, int64_t nlong) {
+    using T = typename PrecT<PREC>::T;
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= nlong * a.nsets) return;
+    const int64_t l = q / a.nsets;
+    const int s = (int)(q % a.nsets);
+    if (a.nsteps && a.nsteps[s] <= *a.step) return;
+    const int64_t row = crow[l];
+    double v[NOPS];
+#pragma unroll
+    for (int op = 0; op < NOPS; ++op) v[op] = 0.0;
+    for (int64_t c = cstart[l]; c < cstart[l + 1]; ++c) {
+        const double* p = P + c * ldp + s;
+#pragma unroll
+        for (int op = 0; op < NOPS; ++op) v[op] += __builtin_nontemporal_load(p + (int64_t)op * a.nsets);
+    }
+    if constexpr (EPI == EPI_Y) {
+        double* y = (double*)a.y + row * a.ldy + s;
+#pragma unroll
+        for (int op = 0; op < NOPS; ++op) {
+            double& o = y[(int64_t)op * a.nsets];
+            o = a.accumulate ? o + a.scale * v[op] : a.scale * v[op];
+        }
+    } else {
+        rk_epilogue<NOPS, T>(a, row, s, v);
+    }
+}
+
+template <int NOPS, int EPI>
+static void launch_chunk_combine_p(const KArgs& k, int prec, const DevCSR& c, const double* P, int64_t ldp,
+                                   hipStream_t s) {
+    const unsigned nb = (unsigned)((c.nlong * k.nsets + 255) / 256);
+    switch (prec) {
+        case CUT_F64: hipLaunchKernelGGL((k_chunk_combine<NOPS, CUT_F64, EPI>), dim3(nb), dim3(256), 0, s, k, P, ldp, c.cstart, c.crow, c.nlong); break;
+        case CUT_F32X: hipLaunchKernelGGL((k_chunk_combine<NOPS, CUT_F32X, EPI>), dim3(nb), dim3(256), 0, s, k, P, ldp, c.cstart, c.crow, c.nlong); break;
+        case CUT_F32C: hipLaunchKernelGGL((k_chunk_combine<NOPS, CUT_F32C, EPI>), dim3(nb), dim3(256), 0, s, k, P, ldp, c.cstart, c.crow, c.nlong); break;
+        default: hipLaunchKernelGGL((k_chunk_combine<NOPS, CUT_F32, EPI>), dim3(nb), dim3(256), 0, s, k, P, ldp, c.cstart, c.crow, c.nlong); break;
+    }
+}
+
+template <int EPI>
+static void launch_chunk_combine(const KArgs& k, int prec, const DevCSR& c, const double* P, int64_t ldp,
+                                 hipStream_t s) {
+    switch (k.nops) {
+        case 1: launch_chunk_combine_p<1, EPI>(k, prec, c, P, ldp, s); break;
+        case 2: launch_chunk_combine_p<2, EPI>(k, prec, c, P, ldp, s); break;
+        case 3: launch_chunk_combine_p<3, EPI>(k, prec, c, P, ldp, s); break;
+        case 4: launch_chunk_combine_p<4, EPI>(k, prec, c, P, ldp, s); break;
+        case 5: launch_chunk_combine_p<5, EPI>(k, prec, c, P, ldp, s); break;
+        case 6: launch_chunk_combine_p<6, EPI>(k, prec, c, P, ldp, s); break;
+        case 7: launch_chunk_combine_p<7, EPI>(k, prec, c, P, ldp, s); break;
+        default: launch_chunk_combine_p<8, EPI>(k, prec, c, P, ldp, s); break;
+    }
+}
+
+size_t chunk_partial_bytes(const Graph& g, int32_t nsets, int32_t nops) {
+    const DevCSR& c = g.csr[0][0];
+    return c.nchunks > 0 ? (size_t)c.nchunks * nops * nsets * sizeof(double) : 0;
+}
+
+size_t forward_partial_bytes(const Graph& g, int32_t nsets, int32_t nops, int32_t precision) {
+    if (tiles_usable(g, nsets, nops, precision)) return tile_partial_bytes(g, nsets, nops);
+    return chunk_partial_bytes(g, nsets, nops);
+}
+
+// chunked forward pass: long-segment chunks into partial rows, their fixed-order
+// combine with the epilogue, then the short segments with the epilogue
+static void launch_chunked(const Graph& g, int epi, const PassArgs& a, double* partials, hipStream_t s) {
+    const DevCSR& c = g.csr[0][0];
+    KArgs k = make_kargs(a);
+    const int G = group_width(a.nsets);
+    const unsigned ychunks = (unsigned)((a.nsets + G - 1) / G);
+    const int64_t ldp = (int64_t)a.nops * a.nsets;
+    KArgs kc = k;
+    kc.chunks = c.chunks;
+    kc.nchunks = c.nchunks;
+    kc.part = partials;
+    kc.ldp = ldp;
+    dim3 grid((unsigned)((c.nchunks + 3) / 4), ychunks);
+    launch_g<MODE_BCAST, EPI_Y>(kc, a.precision, G, grid, s);
+    if (epi == EPI_Y) launch_chunk_combine<EPI_Y>(k, a.precision, c, partials, ldp, s);
+    else launch_chunk_combine<EPI_RK>(k, a.precision, c, partials, ldp, s);
+    if (c.nshort > 0) {
+        PassArgs r = a;
+        r.tasks = c.short_tasks;
+        r.ntasks = c.nshort;
+        r.per_xcd = c.short_per_xcd;
+        launch_pass(MODE_BCAST, epi, r, s);
+    }
+}
+
+static size_t tile_lds_bytes(const Graph& g, int32_t nsets, int32_t nops, int32_t prec) {
+    return (size_t)g.tiles.M * (nops + 1) * tile_width(nsets) * (prec == CUT_F64 ? 8 : 4);
+}
+
+bool tiles_usable(const Graph& g, int32_t nsets, int32_t nops, int32_t precision) {
+    return g.tiles.ok && g.use_tiles && nsets >= 8 &&
+           (int64_t)tile_lds_bytes(g, nsets, nops, precision) <= g.max_lds;
+}
+
+size_t tile_partial_bytes(const Graph& g, int32_t nsets, int32_t nops) {
+    return (size_t)4 * g.N * nops * nsets * sizeof(double);
+}
+
+template <int G, int NOPS, int PREC>
+static void launch_tile_k(const TileKArgs& t, dim3 grid, size_t lds, hipStream_t s) {
+    hipLaunchKernelGGL((k_tile<G, NOPS, PREC>), grid, dim3(256), lds, s, t);
+}
+
+template <int NOPS, int PREC>
+static void launch_tile_g(const TileKArgs& t, int G, dim3 grid, size_t lds, hipStream_t s) {
+    if (G == 16) launch_tile_k<16, NOPS, PREC>(t, grid, lds, s);
+    else launch_tile_k<32, NOPS, PREC>(t, grid, lds, s);
+}
+
+template <int NOPS>
+static void launch_tile_p(const TileKArgs& t, int prec, int G, dim3 grid, size_t lds, hipStream_t s) {
+    switch (prec) {
+        case CUT_F64: launch_tile_g<NOPS, CUT_F64>(t, G, grid, lds, s); break;
+        case CUT_F32X: launch_tile_g<NOPS, CUT_F32X>(t, G, grid, lds, s); break;
+        case CUT_F32C: launch_tile_g<NOPS, CUT_F32C>(t, G, grid, lds, s); break;
+        default: launch_tile_g<NOPS, CUT_F32>(t, G, grid, lds, s); break;
+    }
+}
+
+template <int NOPS, int EPI>
+static void launch_combine_p(const KArgs& k, int prec, const double* P, int64_t pstride, int64_t ldp, int64_t row0,
+                             int64_t nrows, hipStream_t s) {
+    const unsigned nb = (unsigned)((nrows * k.nsets + 255) / 256);
+    switch (prec) {
+        case CUT_F64: hipLaunchKernelGGL((k_combine<NOPS, CUT_F64, EPI>), dim3(nb), dim3(256), 0, s, k, P, pstride, ldp, row0, nrows); break;
+        case CUT_F32X: hipLaunchKernelGGL((k_combine<NOPS, CUT_F32X, EPI>), dim3(nb), dim3(256), 0, s, k, P, pstride, ldp, row0, nrows); break;
+        case CUT_F32C: hipLaunchKernelGGL((k_combine<NOPS, CUT_F32C, EPI>), dim3(nb), dim3(256), 0, s, k, P, pstride, ldp, row0, nrows); break;
+        default: hipLaunchKernelGGL((k_combine<NOPS, CUT_F32, EPI>), dim3(nb), dim3(256), 0, s, k, P, pstride, ldp, row0, nrows); break;
+    }
+}
+
+template <int NOPS>
+static void launch_tiles_nops(const TileKArgs& t, const KArgs& k, int epi, int prec, int G, dim3 grid, size_t lds,
+                              int64_t row0, int64_t nrows, hipStream_t s) {
+    launch_tile_p<NOPS>(t, prec, G, grid, lds, s);
+    if (epi == EPI_Y) launch_combine_p<NOPS, EPI_Y>(k, prec, t.P, t.pstride, t.ldp, row0, nrows, s);
+    else launch_combine_p<NOPS, EPI_RK>(k, prec, t.P, t.pstride, t.ldp, row0, nrows, s);
+}
+
+void launch_forward(const Graph& g, int epi, const PassArgs& a, double* partials, hipStream_t s) {
+    if (epi == EPI_ETA || a.csr != &g.csr[0][0] || partials == nullptr) {
+        launch_pass(MODE_BCAST, epi, a, s);
+        return;
+    }
+    if (!tiles_usable(g, a.nsets, a.nops, a.precision)) {
+        if (g.csr[0][0].nchunks > 0) launch_chunked(g, epi, a, partials, s);
+        else launch_pass(MODE_BCAST, epi, a, s);
+        return;
+    }
+    const TilePlan& tp = g.tiles;
+    // quadratic targets (all their records) through the segment kernel
+    PassArgs r = a;
+    r.tasks = tp.res_tasks;
+    r.ntasks = tp.nres_tasks;
+    r.per_xcd = tp.res_per_xcd;
+    if (tp.nres_tasks > 0) launch_pass(MODE_BCAST, epi, r, s);
+    // quartic targets: tiles into partial slots, then the fixed-order combine
+    const int G = tile_width(a.nsets);
+    TileKArgs t{};
+    t.rows = tp.rows;
+    t.slot = tp.slot;
+    t.rec = tp.rec;
+    t.ftab = a.ftab;
+    t.M = tp.M;
+    t.RT = tp.RT;
+    t.H = a.A;
+    t.lde = a.lda;
+    t.X = a.B;
+    t.ldx = a.ldb;
+    t.nsets = a.nsets;
+    t.nsteps = a.nsteps;
+    t.step = a.step;
+    t.P = partials;
+    t.ldp = (int64_t)a.nops * a.nsets;
+    t.pstride = g.N * t.ldp;
+    const KArgs k = make_kargs(a);
+    dim3 grid((unsigned)tp.ntiles, (unsigned)((a.nsets + G - 1) / G));
+    const size_t lds = tile_lds_bytes(g, a.nsets, a.nops, a.precision);
+    const int64_t row0 = tp.nres, nrows = g.N - tp.nres;
+    switch (a.nops) {
+        case 1: launch_tiles_nops<1>(t, k, epi, a.precision, G, grid, lds, row0, nrows, s); break;
+        case 2: launch_tiles_nops<2>(t, k, epi, a.precision, G, grid, lds, row0, nrows, s); break;
+        case 3: launch_tiles_nops<3>(t, k, epi, a.precision, G, grid, lds, row0, nrows, s); break;
+        case 4: launch_tiles_nops<4>(t, k, epi, a.precision, G, grid, lds, row0, nrows, s); break;
+        case 5: launch_tiles_nops<5>(t, k, epi, a.precision, G, grid, lds, row0, nrows, s); break;
+        case 6: launch_tiles_nops<6>(t, k, epi, a.precision, G, grid, lds, row0, nrows, s); break;
+        case 7: launch_tiles_nops<7>(t, k, epi, a.precision, G, grid, lds, row0, nrows, s); break;
+        default: launch_tiles_nops<8>(t, k, epi, a.precision, G, grid, lds, row0, nrows, s); break;
     }
 }
 

@@ -1,0 +1,140 @@
+// Autotuner for the forward graph pass: segment-to-wavefront tiling (long-target
+// threshold, XCD remap), shared-triple tiles on/off, and optionally the choice
+// between the two compensated float accumulation modes.  Candidates are timed
+// with HIP events on a private stream over zero-filled operands of the shape.
+#include <algorithm>
+#include <cstring>
+#include <memory>
+#include <utility>
+#include <vector>
+
+#include "internal.h"
+
+using namespace cut;
+
+namespace {
+
+struct DevBuf {
+    void* p = nullptr;
+    explicit DevBuf(size_t bytes) {
+        hipError_t e = hipMalloc(&p, bytes ? bytes : 1);
+        if (e != hipSuccess) {
+            p = nullptr;
+            CUT_FAIL(CUT_E_NOMEM, "autotune: hipMalloc(%zu): %s", bytes, hipGetErrorString(e));
+        }
+        HIP_CHECK(hipMemset(p, 0, bytes ? bytes : 1));
+    }
+    ~DevBuf() {
+        if (p) (void)hipFree(p);
+    }
+};
+
+void apply_tiling(Graph& g, int64_t lr, uint32_t flags) {
+    g.long_records = lr;
+    g.xcd_remap = (flags & CUT_TILE_XCD_REMAP) ? 1 : 0;
+    g.use_tiles = (flags & CUT_TILE_TRIPLES) ? 1 : 0;
+    g.use_chunks = (flags & CUT_TILE_NO_CHUNKS) ? 0 : 1;
+    for (auto& w : g.csr)
+        for (auto& c : w)
+            if (c.nseg) build_tasks(g, c);
+}
+
+double time_pass(Graph& g, int prec, int32_t nsets, int32_t nops, const void* eta, const void* x, double* y,
+                 double* partials, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+    PassArgs p{};
+    p.csr = &g.csr[0][0];
+    p.ftab = g.ftab;
+    p.A = eta;
+    p.lda = nsets;
+    p.B = x;
+    p.ldb = (int64_t)nops * nsets;
+    p.nsets = nsets;
+    p.nops = nops;
+    p.precision = prec;
+    p.y = y;
+    p.ldy = (int64_t)nops * nsets;
+    p.scale = 1.0;
+    launch_forward(g, EPI_Y, p, partials, s);  // warm
+    const int reps = 3;
+    HIP_CHECK(hipEventRecord(e0, s));
+    for (int r = 0; r < reps; ++r) launch_forward(g, EPI_Y, p, partials, s);
+    HIP_CHECK(hipEventRecord(e1, s));
+    HIP_CHECK(hipEventSynchronize(e1));
+    float ms = 0.f;
+    HIP_CHECK(hipEventElapsedTime(&ms, e0, e1));
+    return ms / reps;
+}
+
+}  // namespace
+
+extern "C" cut_status cut_graph_autotune(cut_graph_t h, int64_t nsets, int64_t nops, int32_t precision,
+                                         int32_t allow_other_float, cut_tuning* out) {
+    hipStream_t s = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    try {
+        Graph& g = checked(h);
+        check_prec(precision);
+        check_shape(nsets, nops);
+        if (!out) CUT_FAIL(CUT_E_INVAL, "cut_graph_autotune: null output");
+        DeviceGuard dg(g.device);
+        HIP_CHECK(hipDeviceSynchronize());
+        const std::vector<int64_t> key = {nsets, nops, precision, allow_other_float};
+        for (auto& kv : g.tune_cache)
+            if (kv.first == key) {
+                *out = kv.second;
+                apply_tiling(g, out->long_records, out->tiling_flags);
+                return CUT_OK;
+            }
+        std::vector<int> precs = {precision};
+        if (allow_other_float && precision == CUT_F32C) precs.push_back(CUT_F32X);
+        if (allow_other_float && precision == CUT_F32X) precs.push_back(CUT_F32C);
+        const size_t tb = precision == CUT_F64 ? 8 : 4;
+        DevBuf eta(g.N * nsets * tb), x(g.N * nsets * nops * tb), y(g.N * nsets * nops * 8);
+        std::unique_ptr<DevBuf> part;
+        size_t part_bytes = 0;
+        auto partials = [&](int pr) -> double* {
+            const size_t need = forward_partial_bytes(g, (int32_t)nsets, (int32_t)nops, pr);
+            if (need == 0) return nullptr;
+            if (!part || need > part_bytes) {
+                part.reset();
+                part.reset(new DevBuf(need));
+                part_bytes = need;
+            }
+            return (double*)part->p;
+        };
+        HIP_CHECK(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+        HIP_CHECK(hipEventCreate(&e0));
+        HIP_CHECK(hipEventCreate(&e1));
+        const uint32_t flags0 = (g.xcd_remap ? CUT_TILE_XCD_REMAP : 0u) | (g.use_tiles ? CUT_TILE_TRIPLES : 0u) |
+                                (g.use_chunks ? 0u : CUT_TILE_NO_CHUNKS);
+        cut_tuning best{g.long_records, flags0, precision, 1e30, 0.0};
+        best.default_ms = time_pass(g, precision, (int32_t)nsets, (int32_t)nops, eta.p, x.p, (double*)y.p,
+                                    partials(precision), s, e0, e1);
+        const int64_t lrs[] = {256, 512, 1024, 4096};
+        const uint32_t shapes[] = {0u, CUT_TILE_NO_CHUNKS, CUT_TILE_TRIPLES};
+        for (int64_t lr : lrs)
+            for (uint32_t xr = 0; xr <= 1; ++xr)
+                for (uint32_t shape : shapes) {
+                    if ((shape & CUT_TILE_TRIPLES) && !g.tiles.ok) continue;
+                    const uint32_t flags = (xr ? CUT_TILE_XCD_REMAP : 0u) | shape;
+                    apply_tiling(g, lr, flags);
+                    for (int pr : precs) {
+                        const double ms = time_pass(g, pr, (int32_t)nsets, (int32_t)nops, eta.p, x.p, (double*)y.p,
+                                                    partials(pr), s, e0, e1);
+                        if (ms < best.pass_ms) best = cut_tuning{lr, flags, pr, ms, best.default_ms};
+                    }
+                }
+        apply_tiling(g, best.long_records, best.tiling_flags);
+        HIP_CHECK(hipEventDestroy(e0));
+        HIP_CHECK(hipEventDestroy(e1));
+        HIP_CHECK(hipStreamDestroy(s));
+        g.tune_cache.push_back({key, best});
+        *out = best;
+        return CUT_OK;
+    } catch (const Fail& f) {
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        if (s) (void)hipStreamDestroy(s);
+        return f.st;
+    }
+}

@@ -14,6 +14,13 @@ _cache = {}
 _tmp = tempfile.mkdtemp(prefix="cutgraph_tests_")
 
 
+def sum_bound(n: int) -> float:
+    """Bound (relative to sum |terms|) on the difference of two FP64 summations
+    of the same n terms in different orders: 2 * gamma_n, gamma_n = n u/(1-n u)."""
+    g = n * U64 / (1 - n * U64)
+    return 2 * g
+
+
 def dot2_bound(n: int) -> float:
     """Relative (to sum |terms|) error bound of the compensated dot product."""
     g = n * U32 / (1 - n * U32)
