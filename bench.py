@@ -47,6 +47,26 @@ def pass_bytes(N, E, nsets, nops, prec_bytes):
             + N * cols * (8 + 14) + N * cols * prec_bytes + N * nsets * 8)
 
 
+def measured_traffic(precision: str):
+    """HBM bytes per fused-pass launch from the committed counter summary, if it
+    was taken on the current kernel source (else None).
+
+    profiles/fused_pass_m40_counters.md carries a line
+    `traffic <precision> <kernels.hip sha256> <bytes per launch>`.
+    """
+    import hashlib
+    src = os.path.join(ROOT, "paper_2609_14831_amd", "csrc", "kernels.hip")
+    prof = os.path.join(ROOT, "profiles", "fused_pass_m40_counters.md")
+    if not os.path.exists(prof):
+        return None
+    digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    for line in open(prof):
+        parts = line.strip().strip("`").split()
+        if len(parts) == 4 and parts[0] == "traffic" and parts[1] == precision and parts[2] == digest:
+            return {"bytes_per_launch": float(parts[3])}
+    return None
+
+
 def cpu_baseline(inp, w, nsets, nops, budget_s=15.0):
     """Oracle (plain-C FP64 engine, all host threads) on a sample of targets."""
     import numpy as np
@@ -96,8 +116,9 @@ def main():
     ap.add_argument("--profile", action="store_true",
                     help="counter runs: a 1 GiB device copy (calibration), then the steps in "
                          "stream order (no hipGraph), nothing else")
-    ap.add_argument("--long-records", type=int, default=1024)
-    ap.add_argument("--xcd-remap", type=int, default=0)
+    ap.add_argument("--long-records", type=int, default=0,
+                    help="fixed tiling (long-target records); 0 = autotune")
+    ap.add_argument("--tiling-flags", type=int, default=0, help="CUT_TILE_* flags with --long-records")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the method's batch sharding "
@@ -123,7 +144,15 @@ def main():
     t0 = time.perf_counter()
     g = L.cut_graph_load(path, 0, 0)
     load_s = time.perf_counter() - t0
-    L.cut_graph_set_tiling(g, args.long_records, args.xcd_remap)
+    if args.long_records > 0:
+        L.cut_graph_set_tiling(g, args.long_records, args.tiling_flags)
+        tuning = {"long_records": args.long_records, "tiling_flags": args.tiling_flags, "autotuned": False}
+    else:
+        t0 = time.perf_counter()
+        tuning = L.cut_graph_autotune(g, w.nsets, w.nops, PREC, 0)
+        tuning["autotune_s"] = time.perf_counter() - t0
+        tuning["autotuned"] = True
+        log(f"autotuned: {tuning}")
     N, E = desc["n_ops"], desc["n_records"]
 
     inp = workloads.make_inputs(3)
@@ -180,7 +209,8 @@ def main():
                                             "two-sum) accumulation, FP64 result and RK state",
                                     "f32x": "float operands, products and sums in FP64, FP64 RK state",
                                     "f64": "FP64 throughout", "f32": "plain float sums"}[args.precision],
-                      "graph_compile_s": desc["build_seconds"], "graph_load_s": load_s}}
+                      "graph_compile_s": desc["build_seconds"], "graph_load_s": load_s,
+                      "tiling": tuning}}
     if args.minimal:
         print(json.dumps(out), flush=True)
         return
@@ -197,13 +227,37 @@ def main():
     achieved = bytes_per / (pass_ms * 1e-3) / 1e9
     flops_per = 2.0 * E * nsets * nops
     log(f"fused pass avg {pass_ms:.4f} ms ({tm['pass_launches']} launches), generator {gen_ms:.4f} ms")
+    traffic = measured_traffic(args.precision)
     out["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                       "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                       "kernel": "k_pass<64,8,prec,MODE_BCAST,EPI_RK> (fused graph pass + RK stage)",
+                       "frac": achieved / HBM_PEAK_GBS,
+                       "traffic": traffic["bytes_per_launch"] if traffic else None,
+                       "traffic_unit": "bytes per launch (FETCH_SIZE x copy factor + WRITE_SIZE)",
+                       "kernel": "fused graph pass with RK4 stage epilogue: k_pass<64,5,prec,0,2> "
+                                 "(long-target chunks + short targets) and k_chunk_combine<5,prec,2>",
                        "avg_launch_ms": pass_ms, "algorithmic_bytes_per_launch": bytes_per,
                        "fp64_equiv_tflops": flops_per / (pass_ms * 1e-3) / 1e12,
                        "fp64_vector_peak_tflops": FP64_VEC_TFLOPS}
     out["generator_avg_ms"] = gen_ms
+
+    # the other compensated float mode on the same workload (same steps)
+    alt = {"f32c": "f32x", "f32x": "f32c"}.get(args.precision)
+    if alt:
+        PALT = {"f32c": L.CUT_F32C, "f32x": L.CUT_F32X}[alt]
+        za = torch.tensor(inp.z0, device=dev).contiguous()
+        p = L.flow_params(L.CUT_GEN_G2, PALT, w.ds, w.delta, 0, flags=L.CUT_FLOW_HIPGRAPH,
+                          step_begin=0, step_end=W)
+        L.cut_flow_integrate(g, p, nsets, nops, ns, za)
+        p = L.flow_params(L.CUT_GEN_G2, PALT, w.ds, w.delta, 0, flags=L.CUT_FLOW_HIPGRAPH,
+                          step_begin=W, step_end=W + K)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        L.cut_flow_integrate(g, p, nsets, nops, ns, za)
+        torch.cuda.synchronize()
+        alt_wall = time.perf_counter() - t0
+        out["alt_precision"] = {"precision": alt, "value": contributions / alt_wall,
+                                "ms_per_step": alt_wall * 1e3 / K}
+        log(f"{alt}: {alt_wall * 1e3 / K:.3f} ms/step")
+        del za
 
     # plain FP64 flow, one operand column per pass (one set, H only)
     z1 = torch.tensor(inp.z0[:, :1, :1], device=dev).contiguous()

@@ -52,6 +52,7 @@ struct KArgs {
     // chunk tasks (long segments): partial rows instead of the epilogue
     const ChunkTask* chunks;
     int64_t nchunks;
+    int64_t nchunk_blocks;  // blocks [0, nchunk_blocks) take chunks, the rest `tasks`
     double* part;
     int64_t ldp;
 };
@@ -168,7 +169,7 @@ __global__ __launch_bounds__(256) void k_pass(KArgs a) {
     const int sub = lane / G;
     const int s = blockIdx.y * G + sg;
     const bool act = set_active(a, s);
-    const bool chunked = a.chunks != nullptr;
+    const bool chunked = a.chunks != nullptr && (int64_t)blockIdx.x < a.nchunk_blocks;
     Task task{0, 0};
     int32_t slot = 0;
     int64_t seg, e0, e1;
@@ -181,10 +182,12 @@ __global__ __launch_bounds__(256) void k_pass(KArgs a) {
         e0 = ct.e0;
         e1 = ct.e1;
     } else {
-        int64_t t = blockIdx.x;
+        // nchunk_blocks is a multiple of 8, so b keeps the XCD of the block
+        const int64_t b = (int64_t)blockIdx.x - (a.chunks ? a.nchunk_blocks : 0);
+        int64_t t = b;
         if (a.per_xcd > 0) {
-            t = (int64_t)(blockIdx.x & 7) * a.per_xcd + (blockIdx.x >> 3);
-            if ((blockIdx.x >> 3) >= a.per_xcd) return;
+            t = (b & 7) * a.per_xcd + (b >> 3);
+            if ((b >> 3) >= a.per_xcd) return;
         }
         if (t >= a.ntasks) return;
         task = a.tasks[t];
@@ -650,30 +653,31 @@ size_t forward_partial_bytes(const Graph& g, int32_t nsets, int32_t nops, int32_
     return chunk_partial_bytes(g, nsets, nops);
 }
 
-// chunked forward pass: long-segment chunks into partial rows, their fixed-order
-// combine with the epilogue, then the short segments with the epilogue
+// chunked forward pass: one launch whose first blocks sum long-segment chunks
+// into partial rows and whose other blocks run the short segments with the
+// epilogue; then the fixed-order combine of the partial rows with the epilogue
 static void launch_chunked(const Graph& g, int epi, const PassArgs& a, double* partials, hipStream_t s) {
     const DevCSR& c = g.csr[0][0];
-    KArgs k = make_kargs(a);
+    PassArgs r = a;
+    r.tasks = c.short_tasks;
+    r.ntasks = c.nshort;
+    r.per_xcd = c.short_per_xcd;
+    KArgs k = make_kargs(r);
     const int G = group_width(a.nsets);
     const unsigned ychunks = (unsigned)((a.nsets + G - 1) / G);
     const int64_t ldp = (int64_t)a.nops * a.nsets;
-    KArgs kc = k;
-    kc.chunks = c.chunks;
-    kc.nchunks = c.nchunks;
-    kc.part = partials;
-    kc.ldp = ldp;
-    dim3 grid((unsigned)((c.nchunks + 3) / 4), ychunks);
-    launch_g<MODE_BCAST, EPI_Y>(kc, a.precision, G, grid, s);
-    if (epi == EPI_Y) launch_chunk_combine<EPI_Y>(k, a.precision, c, partials, ldp, s);
-    else launch_chunk_combine<EPI_RK>(k, a.precision, c, partials, ldp, s);
-    if (c.nshort > 0) {
-        PassArgs r = a;
-        r.tasks = c.short_tasks;
-        r.ntasks = c.nshort;
-        r.per_xcd = c.short_per_xcd;
-        launch_pass(MODE_BCAST, epi, r, s);
-    }
+    k.chunks = c.chunks;
+    k.nchunks = c.nchunks;
+    k.nchunk_blocks = ((c.nchunks + 3) / 4 + 7) / 8 * 8;
+    k.part = partials;
+    k.ldp = ldp;
+    const int64_t nshort_blocks = c.short_per_xcd > 0 ? 8 * c.short_per_xcd : c.nshort;
+    dim3 grid((unsigned)(k.nchunk_blocks + nshort_blocks), ychunks);
+    if (epi == EPI_Y) launch_g<MODE_BCAST, EPI_Y>(k, a.precision, G, grid, s);
+    else launch_g<MODE_BCAST, EPI_RK>(k, a.precision, G, grid, s);
+    KArgs kc = make_kargs(a);
+    if (epi == EPI_Y) launch_chunk_combine<EPI_Y>(kc, a.precision, c, partials, ldp, s);
+    else launch_chunk_combine<EPI_RK>(kc, a.precision, c, partials, ldp, s);
 }
 
 static size_t tile_lds_bytes(const Graph& g, int32_t nsets, int32_t nops, int32_t prec) {

@@ -54,7 +54,7 @@ double time_pass(Graph& g, int prec, int32_t nsets, int32_t nops, const void* et
     p.y = y;
     p.ldy = (int64_t)nops * nsets;
     p.scale = 1.0;
-    launch_forward(g, EPI_Y, p, partials, s);  // warm
+    for (int w = 0; w < 2; ++w) launch_forward(g, EPI_Y, p, partials, s);  // warm
     const int reps = 3;
     HIP_CHECK(hipEventRecord(e0, s));
     for (int r = 0; r < reps; ++r) launch_forward(g, EPI_Y, p, partials, s);
