@@ -117,7 +117,8 @@ def main():
                     help="counter runs: a 1 GiB device copy (calibration), then the steps in "
                          "stream order (no hipGraph), nothing else")
     ap.add_argument("--long-records", type=int, default=0,
-                    help="fixed tiling (long-target records); 0 = autotune")
+                    help="fixed tiling (long-target threshold); 0 = autotune")
+    ap.add_argument("--chunk-records", type=int, default=512, help="chunk length with --long-records")
     ap.add_argument("--tiling-flags", type=int, default=0, help="CUT_TILE_* flags with --long-records")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -145,8 +146,9 @@ def main():
     g = L.cut_graph_load(path, 0, 0)
     load_s = time.perf_counter() - t0
     if args.long_records > 0:
-        L.cut_graph_set_tiling(g, args.long_records, args.tiling_flags)
-        tuning = {"long_records": args.long_records, "tiling_flags": args.tiling_flags, "autotuned": False}
+        L.cut_graph_set_tiling(g, args.long_records, args.chunk_records, args.tiling_flags)
+        tuning = {"long_records": args.long_records, "chunk_records": args.chunk_records,
+                  "tiling_flags": args.tiling_flags, "autotuned": False}
     else:
         t0 = time.perf_counter()
         tuning = L.cut_graph_autotune(g, w.nsets, w.nops, PREC, 0)

@@ -212,40 +212,49 @@ cut_status cut_flow_adjoint(cut_graph_t g, const cut_flow_params* p, int64_t nse
                             double* lambda, void* stream);
 
 /* ---------------------------------------------------------------- tuning --
- * Segment tiling: targets with more than `long_records` records are "long".
- * Forward passes over E_L cut every long target into chunks of about
- * `long_records` records, one wavefront each, listed by their relative position
- * in the target so that the chunks running together sweep the same operand
- * region (for Majorana graphs each long target's records are ordered at load by
- * the three modes its two operands share, which makes that region small); the
- * chunk sums are kept as partial rows and added in chunk order.  Other passes
- * split a long target over the four wavefronts of a workgroup.  Shorter targets
- * are packed four to a workgroup, one per wavefront.  CUT_TILE_XCD_REMAP maps
- * consecutive task ranges onto one XCD (one L2).  CUT_TILE_NO_CHUNKS turns the
- * chunked form off.
+ * Segment tiling of the graph passes.  Targets with more than `long_records`
+ * records are "long".  Forward passes over E_L cut every long target into
+ * chunks of about `chunk_records` records, one wavefront each, placed at their
+ * relative position in the target so that the chunks running together sweep
+ * the same operand region (for Majorana graphs every target's records are
+ * ordered at load by the three modes its quartic operands share with the other
+ * operand or the target, which makes that region small); the chunk sums are
+ * kept as partial rows and added in chunk order.  Other passes split a long
+ * target over the four wavefronts of a workgroup.  Shorter targets are packed
+ * four to a workgroup, one per wavefront.
+ * CUT_TILE_XCD_REMAP: consecutive chunk and task ranges run on one XCD (one L2).
+ * CUT_TILE_NO_CHUNKS: no chunked form.
+ * CUT_TILE_TRIPLE_CHUNKS (Majorana graphs): every quartic target K is also cut,
+ * into chunks of whole shared-triple groups (the records whose quartic operand
+ * is T+w for one triple T of K; about chunk_records records per chunk), placed
+ * at the rank of T, so the chunks of all targets containing T run together and
+ * read the rows T+w while they are in cache.
  * CUT_TILE_TRIPLES (Majorana graphs, forward passes, nsets >= 8): every record
  * of a quartic target pairs a quadratic string with a quartic string sharing
  * three modes tau with the target; the 4-subsets containing tau are both the
  * targets and the quartic operands of those records, so they are staged in LDS
  * once per tile and each target's four tile sums are added in fixed order.
  * The chunked and tile forms need a work area of partial rows, grown on first
- * use.  Rebuilds the task lists of every loaded copy.
- * Errors: CUT_E_INVAL, CUT_E_DEVICE. */
+ * use.  Rebuilds the task lists of every loaded copy; synchronises the device.
+ * Errors: CUT_E_INVAL (null handle, a length < 1, unknown flag), CUT_E_DEVICE. */
 #define CUT_TILE_XCD_REMAP 1u
 #define CUT_TILE_TRIPLES 2u
 #define CUT_TILE_NO_CHUNKS 4u
-cut_status cut_graph_set_tiling(cut_graph_t g, int64_t long_records, uint32_t flags);
+#define CUT_TILE_TRIPLE_CHUNKS 8u
+cut_status cut_graph_set_tiling(cut_graph_t g, int64_t long_records, int64_t chunk_records, uint32_t flags);
 
 /* Autotuner: times the forward graph pass for (nsets, nops) over candidate
- * tilings (long-target threshold 256/512/1024/4096 records, XCD remap off/on,
- * chunks on/off, shared-triple tiles on/off where available) and,
- * when `precision` is CUT_F32C or CUT_F32X and `allow_other_float` != 0, over
- * both compensated float modes; applies the fastest tiling to the graph and
- * returns the choice.  It allocates temporary operand buffers (zero-filled) and
- * synchronises the device.  Results are cached per (nsets, nops, precision).
+ * tilings (chunk length 64/128/256/512 records, XCD remap off/on, triple
+ * chunks, no chunks, shared-triple tiles where available; long-target
+ * threshold 1024) and, when `precision` is CUT_F32C or CUT_F32X and
+ * `allow_other_float` != 0, over both compensated float modes; applies the
+ * fastest tiling to the graph and returns the choice.  It allocates temporary
+ * operand buffers (zero-filled) and synchronises the device.  Results are cached
+ * per (nsets, nops, precision, allow_other_float).
  * Errors: CUT_E_INVAL, CUT_E_NOMEM, CUT_E_DEVICE. */
 typedef struct {
     int64_t long_records;
+    int64_t chunk_records;
     uint32_t tiling_flags;  /* CUT_TILE_* flags of the fastest configuration */
     int32_t precision;      /* fastest precision among the allowed ones */
     double pass_ms;         /* its average pass time */

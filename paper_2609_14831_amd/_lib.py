@@ -31,7 +31,7 @@ CUT_ACCUMULATE = 1
 CUT_LOAD_ADJOINT, CUT_LOAD_NO_CHECKSUM = 1, 2
 CUT_FLOW_HIPGRAPH = 1
 CUT_FLOW_TIME_PASSES = 2
-CUT_TILE_XCD_REMAP, CUT_TILE_TRIPLES, CUT_TILE_NO_CHUNKS = 1, 2, 4
+CUT_TILE_XCD_REMAP, CUT_TILE_TRIPLES, CUT_TILE_NO_CHUNKS, CUT_TILE_TRIPLE_CHUNKS = 1, 2, 4, 8
 
 STATUS_NAMES = {0: "CUT_OK", 1: "CUT_E_INVAL", 2: "CUT_E_IO", 3: "CUT_E_FORMAT",
                 4: "CUT_E_CHECKSUM", 5: "CUT_E_NOMEM", 6: "CUT_E_DEVICE", 7: "CUT_E_NUMERIC",
@@ -82,7 +82,7 @@ _L.cut_generator_vjp.argtypes = [_vp, _i32, _dbl, _i64, _vp, _i64, _vp, _i64, _v
 _L.cut_flow_integrate.argtypes = [_vp, C.POINTER(cut_flow_params), _i64, _i64, C.POINTER(_i32), _vp, _vp,
                                   _vp]
 _L.cut_flow_adjoint.argtypes = [_vp, C.POINTER(cut_flow_params), _i64, _i64, C.POINTER(_i32), _vp, _vp, _vp]
-_L.cut_graph_set_tiling.argtypes = [_vp, _i64, _u32]
+_L.cut_graph_set_tiling.argtypes = [_vp, _i64, _i64, _u32]
 
 
 class cut_flow_timing(C.Structure):
@@ -94,7 +94,8 @@ _L.cut_flow_last_timing.argtypes = [_vp, C.POINTER(cut_flow_timing)]
 
 
 class cut_tuning(C.Structure):
-    _fields_ = [("long_records", C.c_int64), ("tiling_flags", C.c_uint32), ("precision", C.c_int32),
+    _fields_ = [("long_records", C.c_int64), ("chunk_records", C.c_int64), ("tiling_flags", C.c_uint32),
+                ("precision", C.c_int32),
                 ("pass_ms", C.c_double), ("default_ms", C.c_double)]
 
 
@@ -168,9 +169,9 @@ def cut_graph_free(g: int) -> None:
     _L.cut_graph_free(g)
 
 
-def cut_graph_set_tiling(g: int, long_records: int, flags: int) -> None:
-    """flags: CUT_TILE_XCD_REMAP | CUT_TILE_TRIPLES | CUT_TILE_NO_CHUNKS."""
-    _check(_L.cut_graph_set_tiling(g, long_records, flags))
+def cut_graph_set_tiling(g: int, long_records: int, chunk_records: int, flags: int) -> None:
+    """flags: CUT_TILE_XCD_REMAP | CUT_TILE_TRIPLES | CUT_TILE_NO_CHUNKS | CUT_TILE_TRIPLE_CHUNKS."""
+    _check(_L.cut_graph_set_tiling(g, long_records, chunk_records, flags))
 
 
 # ------------------------------------------------------------------ apply --

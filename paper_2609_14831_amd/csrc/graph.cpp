@@ -1,13 +1,14 @@
 // Graph load: validated reload of a bundle (Sec. 2.3) and the device layout.
 //
 // Device layout per record set (E_L, E_eta):
-//   orientation 0: grouped by target k, records (a=i, b=j) in stored (i, j) order
+//   orientation 0: grouped by target k, records (a=i, b=j); Majorana graphs in
+//   locality order (by shared triple), others in stored (i, j) order
 //   orientation 1: grouped by right input j, records (a=i, b=k), ordered (k, i)
 //   orientation 2: grouped by left input i, records (a=k, b=j), ordered (k, j)
 // Orientations 1 and 2 are the reverse traversals of the same records used by
 // the adjoint (Sec. 2.4); they are built by a stable counting sort on the host.
-// Each record is 8 bytes: int32 (factor code << 24 | a), int32 b, with the
-// factor looked up in a table of at most 256 distinct values.
+// Each record is 8 bytes: uint32 (f_hi << 24 | a), uint32 (f_lo << 24 | b), where
+// (f_hi, f_lo) is the bf16 bit pattern of the integer factor (exact for int8).
 #include <algorithm>
 #include <cstdarg>
 #include <cstdio>
@@ -50,7 +51,7 @@ void DevCSR::release() {
     dev_free(chunks);
     dev_free(cstart);
     dev_free(crow);
-    nshort = short_per_xcd = nchunks = nlong = 0;
+    nshort = short_per_xcd = nchunks = nlong = nslots = 0;
     off_h.clear();
     off_h.shrink_to_fit();
     nseg = nrec = ntasks = per_xcd = 0;
@@ -119,19 +120,36 @@ static void upload_tasks(const std::vector<Task>& all, Task** dst, int64_t* n) {
     HIP_CHECK(hipMemcpy(*dst, all.data(), all.size() * sizeof(Task), hipMemcpyHostToDevice));
 }
 
-// Chunked plan: every segment longer than long_records is cut into
-// ceil(len / long_records) near-equal chunks; chunks are listed by the relative
-// position of their midpoint in their segment (so the chunks running together
-// cover the same part of every long segment), slots numbered per segment in
-// order; the remaining short segments are packed four per task.
+// Lexicographic rank of a 3-subset {a < b < c} of [0, m) (hockey-stick form).
+static int64_t lex_rank3(uint64_t t, int m) {
+    auto c3 = [](int64_t a) { return a < 3 ? 0 : a * (a - 1) * (a - 2) / 6; };
+    auto c2 = [](int64_t a) { return a < 2 ? 0 : a * (a - 1) / 2; };
+    int e[3], r = 0;
+    for (uint64_t x = t; x && r < 3; x &= x - 1) e[r++] = __builtin_ctzll(x);
+    return (c3(m) - c3(m - e[0])) + (c2(m - e[0] - 1) - c2(m - e[1])) + ((m - e[1] - 1) - (m - e[2]));
+}
+
+// Chunked plan.  Every segment longer than long_records is cut into
+// ceil(len / chunk_records) near-equal chunks, placed at the relative position
+// of their midpoint in the segment (chunks at the same position of different
+// long segments read the same operand rows once the segments are in locality
+// order).  With triple chunks (Majorana graphs whose quartic targets come in 4
+// shared-triple groups), every quartic target is cut into chunks of whole
+// groups, about chunk_records records each, placed at the rank of the chunk's
+// first triple among all triples; the chunks of the targets that share a triple
+// then run together and read that triple's rows.  Chunks are listed by
+// position; partial-row slots are numbered per segment in chunk order.  With
+// XCD remapping the list is cut into 8 contiguous pieces, piece x running on
+// XCD x (block b on XCD b % 8), padded with empty chunks.  The remaining short
+// segments are packed four per task (same XCD split).
 static void build_chunks(const Graph& g, DevCSR& c) {
     dev_free(c.chunks);
     dev_free(c.cstart);
     dev_free(c.crow);
     dev_free(c.short_tasks);
-    c.nchunks = c.nlong = c.nshort = c.short_per_xcd = 0;
+    c.nchunks = c.nlong = c.nshort = c.short_per_xcd = c.nslots = 0;
     const std::vector<int64_t>& off = c.off_h;
-    const int64_t lr = g.long_records;
+    const int64_t lr = g.long_records, cr = std::max<int64_t>(1, g.chunk_records);
     std::vector<int64_t> cstart = {0};
     std::vector<int32_t> crow;
     struct Ent {
@@ -141,37 +159,99 @@ static void build_chunks(const Graph& g, DevCSR& c) {
     std::vector<Ent> ents;
     std::vector<uint8_t> is_long(c.nseg, 0);
     if (c.nrec >= (1ll << 31) || !g.use_chunks) return;
+    const int m = g.hdr.size;
+    const bool fam = g.triple_chunks && g.triple_groups && g.hdr.algebra == CUT_ALG_MAJORANA &&
+                     (int64_t)g.labels_h.size() == c.nseg && m >= 4;
+    const double ntrip = (double)m * (m - 1) * (m - 2) / 6.0;
     for (int64_t k = 0; k < c.nseg; ++k) {
         const int64_t len = off[k + 1] - off[k];
-        if (len <= lr) continue;
+        const bool quart = fam && len > 0 && __builtin_popcountll(g.labels_h[k]) == 4;
+        if (!quart && len <= lr) continue;
         is_long[k] = 1;
-        const int64_t nch = (len + lr - 1) / lr;
         const int64_t l = (int64_t)crow.size();
         crow.push_back((int32_t)k);
-        for (int64_t q = 0; q < nch; ++q) {
-            const int64_t e0 = off[k] + len * q / nch, e1 = off[k] + len * (q + 1) / nch;
-            ents.push_back({(q + 0.5) / nch, ChunkTask{(int32_t)k, (int32_t)(cstart[l] + q), (int32_t)e0, (int32_t)e1}});
+        int64_t nch = 0;
+        if (quart) {
+            const int64_t q = len / 4;
+            const int gpc = (int)std::min<int64_t>(4, std::max<int64_t>(1, (cr + q / 2) / q));
+            int e[4], r = 0;
+            for (uint64_t x = g.labels_h[k]; x && r < 4; x &= x - 1) e[r++] = __builtin_ctzll(x);
+            for (int t0 = 0; t0 < 4; t0 += gpc, ++nch) {
+                const int t1 = std::min(4, t0 + gpc);
+                // group t of K = {e0<e1<e2<e3} reads the rows of the triple K - e[3-t]
+                const uint64_t T = g.labels_h[k] & ~(1ull << e[3 - t0]);
+                ents.push_back({(double)lex_rank3(T, m) / ntrip,
+                                ChunkTask{(int32_t)k, (int32_t)(cstart[l] + nch), (int32_t)(off[k] + t0 * q),
+                                          (int32_t)(off[k] + t1 * q)}});
+            }
+        } else {
+            nch = (len + cr - 1) / cr;
+            for (int64_t q = 0; q < nch; ++q) {
+                const int64_t e0 = off[k] + len * q / nch, e1 = off[k] + len * (q + 1) / nch;
+                ents.push_back({(q + 0.5) / nch, ChunkTask{(int32_t)k, (int32_t)(cstart[l] + q), (int32_t)e0, (int32_t)e1}});
+            }
         }
         cstart.push_back(cstart[l] + nch);
     }
     std::stable_sort(ents.begin(), ents.end(), [](const Ent& a, const Ent& b) { return a.pos < b.pos; });
     std::vector<ChunkTask> ch;
-    ch.reserve(ents.size());
-    for (auto& e : ents) ch.push_back(e.t);
+    const ChunkTask pad{-1, 0, 0, 0};
+    if (g.xcd_remap && !ents.empty()) {
+        const int64_t nblk = ((int64_t)ents.size() + 3) / 4, per = (nblk + 7) / 8;
+        ch.assign((size_t)(8 * per * 4), pad);
+        for (int64_t b = 0; b < 8 * per; ++b) {
+            const int64_t src = (b % 8) * per + b / 8;  // block of the sorted list
+            for (int w = 0; w < 4; ++w) {
+                const int64_t i = src * 4 + w;
+                if (src < nblk && i < (int64_t)ents.size()) ch[b * 4 + w] = ents[i].t;
+            }
+        }
+    } else {
+        ch.reserve(ents.size());
+        for (auto& e : ents) ch.push_back(e.t);
+    }
     // short segments: packed tasks over maximal runs of short segments
+    auto pack = [&](int64_t b, int64_t e, std::vector<Task>& out) {
+        for (int64_t k = b; k < e;) {
+            if (is_long[k]) {
+                ++k;
+                continue;
+            }
+            int64_t k0 = k;
+            int n = 0;
+            while (k < e && n < 4 && !is_long[k]) {
+                ++k;
+                ++n;
+            }
+            out.push_back({(int32_t)k0, n});
+        }
+    };
     std::vector<Task> st;
-    for (int64_t k = 0; k < c.nseg;) {
-        if (is_long[k]) {
-            ++k;
-            continue;
+    if (g.xcd_remap) {
+        int64_t total = 0;
+        for (int64_t k = 0; k < c.nseg; ++k)
+            if (!is_long[k]) total += off[k + 1] - off[k] + 64;
+        std::vector<std::vector<Task>> parts(8);
+        int64_t b = 0, acc = 0;
+        for (int x = 0; x < 8; ++x) {
+            int64_t e = b;
+            const int64_t goal = total * (x + 1) / 8;
+            while (e < c.nseg && (x == 7 || acc < goal)) {
+                if (!is_long[e]) acc += off[e + 1] - off[e] + 64;
+                ++e;
+            }
+            pack(b, e, parts[x]);
+            b = e;
         }
-        int64_t k0 = k;
-        int n = 0;
-        while (k < c.nseg && n < 4 && !is_long[k]) {
-            ++k;
-            ++n;
+        size_t per = 0;
+        for (auto& p : parts) per = std::max(per, p.size());
+        if (per > 0) {
+            st.assign(per * 8, Task{0, 0});
+            for (int x = 0; x < 8; ++x) std::copy(parts[x].begin(), parts[x].end(), st.begin() + x * per);
+            c.short_per_xcd = (int64_t)per;
         }
-        st.push_back({(int32_t)k0, n});
+    } else {
+        pack(0, c.nseg, st);
     }
     c.nshort = (int64_t)st.size();
     if (!st.empty()) {
@@ -180,6 +260,7 @@ static void build_chunks(const Graph& g, DevCSR& c) {
     }
     c.nlong = (int64_t)crow.size();
     c.nchunks = (int64_t)ch.size();
+    c.nslots = cstart.back();
     if (c.nchunks == 0) return;
     c.chunks = dev_alloc<ChunkTask>(ch.size());
     HIP_CHECK(hipMemcpy(c.chunks, ch.data(), ch.size() * sizeof(ChunkTask), hipMemcpyHostToDevice));
@@ -202,6 +283,23 @@ void build_tasks(Graph& g, DevCSR& c) {
         upload_tasks(plan_tasks(g, c.off_h, g.tiles.nres, &g.tiles.res_per_xcd), &g.tiles.res_tasks,
                      &g.tiles.nres_tasks);
     }
+}
+
+void apply_tiling(Graph& g, int64_t long_records, int64_t chunk_records, uint32_t flags) {
+    g.long_records = long_records;
+    g.chunk_records = chunk_records;
+    g.xcd_remap = (flags & CUT_TILE_XCD_REMAP) ? 1 : 0;
+    g.use_tiles = (flags & CUT_TILE_TRIPLES) ? 1 : 0;
+    g.use_chunks = (flags & CUT_TILE_NO_CHUNKS) ? 0 : 1;
+    g.triple_chunks = (flags & CUT_TILE_TRIPLE_CHUNKS) ? 1 : 0;
+    for (auto& w : g.csr)
+        for (auto& c : w)
+            if (c.nseg) build_tasks(g, c);
+}
+
+uint32_t tiling_flags(const Graph& g) {
+    return (g.xcd_remap ? CUT_TILE_XCD_REMAP : 0u) | (g.use_tiles ? CUT_TILE_TRIPLES : 0u) |
+           (g.use_chunks ? 0u : CUT_TILE_NO_CHUNKS) | (g.triple_chunks ? CUT_TILE_TRIPLE_CHUNKS : 0u);
 }
 
 static std::vector<Task> plan_tasks(const Graph& g, const std::vector<int64_t>& off, int64_t nseg, int64_t* per_xcd) {
@@ -360,39 +458,72 @@ static void upload_csr(Graph& g, DevCSR& c, int64_t nseg, std::vector<int64_t>&&
     build_tasks(g, c);
 }
 
-// Lexicographic rank of a 3-subset {a < b < c} of [0, m) (hockey-stick form).
-static int64_t lex_rank3(uint64_t t, int m) {
-    auto c3 = [](int64_t a) { return a < 3 ? 0 : a * (a - 1) * (a - 2) / 6; };
-    auto c2 = [](int64_t a) { return a < 2 ? 0 : a * (a - 1) / 2; };
-    int e[3], r = 0;
-    for (uint64_t x = t; x && r < 3; x &= x - 1) e[r++] = __builtin_ctzll(x);
-    return (c3(m) - c3(m - e[0])) + (c2(m - e[0] - 1) - c2(m - e[1])) + ((m - e[1] - 1) - (m - e[2]));
-}
 
-// Locality order of the long (quadratic-target) segments of a Majorana graph:
-// a record (i, j) of target {a, b} pairs T+a with T+b; sorting each such
-// segment by the rank of the shared triple T makes the same position of every
-// long segment touch the same rows T+w.  Only the order of each sum changes.
-static void locality_order(const HostGraph& hg, const int64_t* off, int64_t N, std::vector<uint2>& rec) {
+// Locality order of the segments of a Majorana graph.  Every record of a
+// quadratic target {a, b} (beyond the quadratic x quadratic ones) pairs T+a with
+// T+b, and every record of a quartic target K pairs a quadratic string with a
+// quartic string sharing three modes T with K; in both cases the quartic
+// operands of the record are rows T+w.  Each segment is sorted (stably) by the
+// lexicographic rank of T, so the same position of every quadratic target
+// touches the same rows, and a quartic target's records fall into groups that
+// each read the rows of one triple.  Only the order of each sum changes.
+// Returns whether every quartic target has 4 equal groups (its 4 triples).
+static bool locality_order(const HostGraph& hg, const int64_t* off, int64_t N, std::vector<uint2>& rec) {
     const int m = hg.hdr.size;
+    bool groups = true;
     std::vector<std::pair<int64_t, uint2>> buf;
     for (int64_t k = 0; k < N; ++k) {
-        if (__builtin_popcountll(hg.labels[k]) != 2) continue;
+        const uint64_t K = hg.labels[k];
+        const int deg = __builtin_popcountll(K);
+        if (deg != 2 && deg != 4) {
+            groups = false;
+            continue;
+        }
         buf.clear();
         for (int64_t e = off[k]; e < off[k + 1]; ++e) {
-            const uint64_t L = hg.labels[rec[e].x & 0xFFFFFFu] & hg.labels[rec[e].y];
-            buf.push_back({__builtin_popcountll(L) == 3 ? lex_rank3(L, m) : -1, rec[e]});
+            const uint64_t Li = hg.labels[rec[e].x & 0xFFFFFFu], Lj = hg.labels[rec[e].y & 0xFFFFFFu];
+            uint64_t T = 0;
+            if (deg == 2) T = Li & Lj;
+            else T = K & (__builtin_popcountll(Li) == 4 ? Li : Lj);
+            buf.push_back({__builtin_popcountll(T) == 3 ? lex_rank3(T, m) : -1, rec[e]});
         }
         std::stable_sort(buf.begin(), buf.end(),
                          [](const std::pair<int64_t, uint2>& x, const std::pair<int64_t, uint2>& y) {
                              return x.first < y.first;
                          });
         for (int64_t e = off[k]; e < off[k + 1]; ++e) rec[e] = buf[e - off[k]].second;
+        if (deg == 4 && groups) {
+            // 4 groups of len/4 records, each with one key, keys ascending
+            const int64_t len = off[k + 1] - off[k], q = len / 4;
+            if (len == 0 || len % 4 != 0) {
+                groups = false;
+                continue;
+            }
+            for (int t = 0; t < 4 && groups; ++t) {
+                const int64_t key = buf[t * q].first;
+                if (key < 0 || (t > 0 && key <= buf[(t - 1) * q].first)) groups = false;
+                for (int64_t r = t * q; r < (t + 1) * q && groups; ++r)
+                    if (buf[r].first != key) groups = false;
+            }
+        }
     }
+    return groups;
+}
+
+// Device record of factor c and operand rows a (left) and b (right), both below
+// 2^24: the factor's bf16 bit pattern (exact for every int8 value) rides in the
+// top bytes, high byte with a and low byte with b, so the kernels rebuild the
+// FP32 factor with integer operations instead of a table lookup.
+static inline uint2 pack_record(int8_t c, uint32_t a, uint32_t b) {
+    const float f = (float)c;
+    uint32_t bits;
+    std::memcpy(&bits, &f, 4);
+    const uint32_t h = bits >> 16;  // the low 16 bits are zero for |c| <= 256
+    return make_uint2(((h >> 8) << 24) | a, ((h & 0xFFu) << 24) | b);
 }
 
 // orientation 0 from the bundle; 1 and 2 by stable counting sort
-static void build_copies(Graph& g, const HostGraph& hg, int w, bool adjoint, const uint8_t* code) {
+static void build_copies(Graph& g, const HostGraph& hg, int w, bool adjoint) {
     const int64_t N = hg.hdr.n_ops;
     const int64_t E = w == 0 ? hg.hdr.n_records : hg.hdr.n_gen_records;
     const int64_t* off = hg.off[w];
@@ -402,8 +533,8 @@ static void build_copies(Graph& g, const HostGraph& hg, int w, bool adjoint, con
     {
         std::vector<uint2> rec((size_t)E);
         for (int64_t e = 0; e < E; ++e)
-            rec[e] = make_uint2(((uint32_t)code[(uint8_t)rc[e]] << 24) | (uint32_t)ri[e], (uint32_t)rj[e]);
-        if (w == 0 && hg.hdr.algebra == CUT_ALG_MAJORANA) locality_order(hg, off, N, rec);
+            rec[e] = pack_record(rc[e], (uint32_t)ri[e], (uint32_t)rj[e]);
+        if (w == 0 && hg.hdr.algebra == CUT_ALG_MAJORANA) g.triple_groups = locality_order(hg, off, N, rec);
         upload_csr(g, g.csr[w][0], N, std::vector<int64_t>(off, off + N + 1), rec);
     }
     if (!adjoint) return;
@@ -416,9 +547,8 @@ static void build_copies(Graph& g, const HostGraph& hg, int w, bool adjoint, con
         std::vector<uint2> rec((size_t)E);
         for (int64_t k = 0; k < N; ++k)
             for (int64_t e = off[k]; e < off[k + 1]; ++e) {
-                const uint32_t cc = (uint32_t)code[(uint8_t)rc[e]] << 24;
-                if (o == 1) rec[cur[rj[e]]++] = make_uint2(cc | (uint32_t)ri[e], (uint32_t)k);
-                else rec[cur[ri[e]]++] = make_uint2(cc | (uint32_t)k, (uint32_t)rj[e]);
+                if (o == 1) rec[cur[rj[e]]++] = pack_record(rc[e], (uint32_t)ri[e], (uint32_t)k);
+                else rec[cur[ri[e]]++] = pack_record(rc[e], (uint32_t)k, (uint32_t)rj[e]);
             }
         upload_csr(g, g.csr[w][o], N, std::move(noff), rec);
     }
@@ -515,12 +645,17 @@ extern "C" cut_status cut_graph_load(const char* path, int32_t dev, uint32_t fla
         g->N = N;
         g->gen_sign = hg.hdr.gen_sign;
         g->nfactors = (int)ftab.size();
-        g->ftab = dev_alloc<double>(256);
+        // 256 FP64 factors, then the same 256 factors in FP32 (exact: small integers)
+        g->ftab = dev_alloc<double>(256 + 128);
         ftab.resize(256, 0.0);
-        HIP_CHECK(hipMemcpy(g->ftab, ftab.data(), 256 * sizeof(double), hipMemcpyHostToDevice));
+        std::vector<double> both(256 + 128, 0.0);
+        std::copy(ftab.begin(), ftab.end(), both.begin());
+        for (int v = 0; v < 256; ++v) reinterpret_cast<float*>(both.data() + 256)[v] = (float)ftab[v];
+        HIP_CHECK(hipMemcpy(g->ftab, both.data(), both.size() * sizeof(double), hipMemcpyHostToDevice));
         const bool adj = (flags & CUT_LOAD_ADJOINT) != 0;
-        build_copies(*g, hg, 0, adj, code);
-        build_copies(*g, hg, 1, adj, code);
+        g->labels_h.assign(hg.labels, hg.labels + N);
+        build_copies(*g, hg, 0, adj);
+        build_copies(*g, hg, 1, adj);
         g->have_adjoint = adj;
         g->diag = dev_alloc<uint8_t>(N);
         HIP_CHECK(hipMemcpy(g->diag, hg.diag, N, hipMemcpyHostToDevice));
@@ -571,22 +706,15 @@ extern "C" cut_status cut_graph_info(cut_graph_t h, cut_graph_desc* d) {
     return CUT_OK;
 }
 
-extern "C" cut_status cut_graph_set_tiling(cut_graph_t h, int64_t long_records, uint32_t flags) {
+extern "C" cut_status cut_graph_set_tiling(cut_graph_t h, int64_t long_records, int64_t chunk_records,
+                                           uint32_t flags) {
     try {
-        if (!h || long_records < 1 || (flags & ~7u)) CUT_FAIL(CUT_E_INVAL, "cut_graph_set_tiling: bad argument");
+        if (!h || long_records < 1 || chunk_records < 1 || (flags & ~15u))
+            CUT_FAIL(CUT_E_INVAL, "cut_graph_set_tiling: bad argument");
         Graph& g = *(Graph*)h;
-        int prev = 0;
-        HIP_CHECK(hipGetDevice(&prev));
-        HIP_CHECK(hipSetDevice(g.device));
+        DeviceGuard dg(g.device);
         HIP_CHECK(hipDeviceSynchronize());
-        g.long_records = long_records;
-        g.xcd_remap = (flags & CUT_TILE_XCD_REMAP) ? 1 : 0;
-        g.use_tiles = (flags & CUT_TILE_TRIPLES) ? 1 : 0;
-        g.use_chunks = (flags & CUT_TILE_NO_CHUNKS) ? 0 : 1;
-        for (auto& w : g.csr)
-            for (auto& c : w)
-                if (c.nseg) build_tasks(g, c);
-        HIP_CHECK(hipSetDevice(prev));
+        apply_tiling(g, long_records, chunk_records, flags);
         return CUT_OK;
     } catch (const Fail& f) {
         return f.st;

@@ -103,16 +103,17 @@ void read_bundle(const char* path, bool verify_checksums, HostGraph& out);
 
 // ------------------------------------------------------------- device side --
 // One record stream grouped by output segment.  Each record is a uint2:
-// .x = (factor code << 24) | a,  .y = b, where a indexes the "left" operand
-// (broadcast over ops) and b the "right" operand of that traversal.
+// .x = (f_hi << 24) | a,  .y = (f_lo << 24) | b, where a indexes the "left"
+// operand (broadcast over ops) and b the "right" operand of that traversal, and
+// (f_hi, f_lo) are the two bytes of the factor's bf16 bit pattern.
 struct Task {          // one workgroup of 4 wavefronts
     int32_t seg;       // first segment
     int32_t nseg;      // >0: that many short segments, one per wavefront;
                        // <0: one long segment split over the 4 wavefronts
 };
 
-// A chunk of a long segment: records [e0, e1) of segment `seg`, summed by one
-// wavefront into partial row `slot`.
+// A chunk of a segment: records [e0, e1) of segment `seg`, summed by one
+// wavefront into partial row `slot` (seg < 0: padding, no work).
 struct ChunkTask {
     int32_t seg;
     int32_t slot;
@@ -137,6 +138,7 @@ struct DevCSR {
     int64_t* cstart = nullptr;  // device [nlong+1]: slots of long segment l
     int32_t* crow = nullptr;    // device [nlong]: its row
     int64_t nlong = 0;
+    int64_t nslots = 0;         // partial rows (chunks of all segments)
     std::vector<int64_t> off_h; // host copy of the offsets (tiling plan input)
     void release();
 };
@@ -180,7 +182,7 @@ struct Graph {
     int64_t N = 0;
     double gen_sign = 1.0;
     int nfactors = 0;
-    double* ftab = nullptr;          // device [256]
+    double* ftab = nullptr;          // device [256] FP64 factors, then [256] FP32 copies
     // record streams: [set][orientation] set 0 = E_L, 1 = E_eta;
     // orientation 0 = by target k (a=i, b=j), 1 = by right input j (a=i, b=k),
     // 2 = by left input i (a=k, b=j)
@@ -198,7 +200,13 @@ struct Graph {
     int4* st_p = nullptr;            // entries: x = S, y = partner, z = factor code
     bool have_stencil = false;
     int64_t long_records = 1024;
+    int64_t chunk_records = 512;     // records per chunk of a long target
     int xcd_remap = 0;
+    int triple_chunks = 0;           // cut quartic Majorana targets by shared triple
+    // Majorana quartic targets whose records come in 4 equal shared-triple
+    // groups, in ascending triple rank (checked at load)
+    bool triple_groups = false;
+    std::vector<uint64_t> labels_h;  // registry labels (host copy)
     TilePlan tiles;
     int use_tiles = 0;
     int use_chunks = 1;
@@ -214,6 +222,9 @@ struct Graph {
 
 // tiling plan (host) -> device task list
 void build_tasks(Graph& g, DevCSR& c);
+// sets the tiling parameters and rebuilds the task lists of every loaded copy
+void apply_tiling(Graph& g, int64_t long_records, int64_t chunk_records, uint32_t flags);
+uint32_t tiling_flags(const Graph& g);
 
 // --------------------------------------------------------------- kernels ----
 enum Mode { MODE_BCAST = 0, MODE_REDOPS = 1 };

@@ -19,6 +19,8 @@
 // stage combination fused into the flow pass, Eq. coflow integrated at fixed ds).
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "internal.h"
 
 namespace cut {
@@ -55,6 +57,9 @@ struct KArgs {
     int64_t nchunk_blocks;  // blocks [0, nchunk_blocks) take chunks, the rest `tasks`
     double* part;
     int64_t ldp;
+    // both operand arrays span less than 2 GiB: gathers address rows by a
+    // 32-bit scalar offset from one buffer resource per array
+    int32_t buf32;
 };
 
 template <int PREC>
@@ -114,6 +119,33 @@ __device__ inline auto left_term(double cf, typename PrecT<PREC>::T av) {
     if constexpr (PREC == CUT_F64) return cf * av;
     else if constexpr (PREC == CUT_F32X) return cf * (double)av;
     else return (float)cf * av;
+}
+
+// FP32 bit pattern of the factor of a device record: its bf16 bit pattern is
+// split over the top bytes of the two row indices (high byte with the left row).
+__device__ __forceinline__ uint32_t record_factor_bits(uint32_t x, uint32_t y) {
+    return (x & 0xFF000000u) | ((y >> 24) << 16);
+}
+
+__device__ __forceinline__ int64_t uniform64(int64_t v) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)((uint64_t)v >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+// Gather of one element of a row through a buffer resource built (on the
+// scalar unit) from the uniform row address: the lane's byte offset is the only
+// per-lane operand, so a gather costs no vector address arithmetic.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t row_rsrc(const void* row, int64_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(row), (short)0, (int)bytes, 0x00020000);
+}
+template <class T>
+__device__ __forceinline__ T buf_load(__amdgpu_buffer_rsrc_t r, uint32_t voff, int32_t soff) {
+    if constexpr (sizeof(T) == 4) {
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, soff, 0));
+    } else {
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, soff, 0));
+    }
 }
 
 __device__ inline bool set_active(const KArgs& a, int s) {
@@ -177,6 +209,7 @@ __global__ __launch_bounds__(256) void k_pass(KArgs a) {
         const int64_t ci = (int64_t)blockIdx.x * 4 + wave;
         if (ci >= a.nchunks) return;
         const ChunkTask ct = a.chunks[ci];
+        if (ct.seg < 0) return;  // padding of the XCD split
         seg = ct.seg;
         slot = ct.slot;
         e0 = ct.e0;
@@ -207,6 +240,10 @@ __global__ __launch_bounds__(256) void k_pass(KArgs a) {
         e1 = a.off[seg + 1];
     }
 
+    // segment bounds are wavefront-uniform: keep them (and the loop control
+    // derived from them) on the scalar unit
+    e0 = uniform64(e0);
+    e1 = uniform64(e1);
     Acc<PREC> acc[NACC];
     const T* __restrict__ A = (const T*)a.A;
     const T* __restrict__ B = (const T*)a.B;
@@ -214,83 +251,178 @@ __global__ __launch_bounds__(256) void k_pass(KArgs a) {
     // lanes of inactive sets compute on an in-range column and are discarded
     // at the epilogue; no load is ever predicated
     const int sl = s < nsets ? s : nsets - 1;
-    int coff[NOPS];
+    // lane byte offsets of the gathered columns within a row: 32-bit and
+    // unsigned, so each gather takes the (uniform) row address as its scalar
+    // base and needs no per-lane address arithmetic
+    uint32_t boff[NOPS];
 #pragma unroll
-    for (int op = 0; op < NOPS; ++op) coff[op] = sl + op * nsets;
-    // Records are fetched cooperatively, 64 per wavefront load (one per lane),
-    // then handed to the lane groups by cross-lane moves; each group issues the
-    // gathers of U records before any arithmetic, so U dependent load chains are
-    // in flight per wavefront.
+    for (int op = 0; op < NOPS; ++op) boff[op] = (uint32_t)(sl + op * nsets) * (uint32_t)sizeof(T);
     constexpr int NA = (MODE == MODE_REDOPS) ? NOPS : 1;
 #ifndef CUT_PASS_UNROLL
 #define CUT_PASS_UNROLL 4
 #endif
     constexpr int U = (NOPS <= 2) ? 8 : CUT_PASS_UNROLL;
-    constexpr int CH = (G >= U) ? 1 : U / G;  // 64-record chunks per outer iteration
-    constexpr int SLOTS = CH * G;             // record slots of one lane group per iteration
-    for (int64_t base = e0; base < e1; base += 64 * CH) {
-        uint2 mine[CH];
+    // The gathers of U records are all issued before any arithmetic, so U
+    // dependent load chains are in flight per lane group; then accum() adds the
+    // U terms.  A record slot past the segment end holds a valid clamped record
+    // and gets factor zero.
+    auto accum = [&](const T (&av)[U][NA], const T (&bv)[U][NOPS], const float (&fc)[U]) {
 #pragma unroll
-        for (int c = 0; c < CH; ++c) {
-            // clamped (always valid) address; slots past e1 are masked by cnt
-            const int64_t idx = base + c * 64 + lane;
-            // records are read once per pass: non-temporal
-            const unsigned long long rv = __builtin_nontemporal_load(
-                (const unsigned long long*)a.rec + (idx < e1 ? idx : e1 - 1));
-            mine[c] = make_uint2((uint32_t)rv, (uint32_t)(rv >> 32));
+        for (int u = 0; u < U; ++u) {
+            const double cf = (double)fc[u];
+            if constexpr (MODE == MODE_BCAST && (PREC == CUT_F32C || PREC == CUT_F32)) {
+                const float tl = fc[u] * av[u][0];
+#pragma unroll
+                for (int op = 0; op < NOPS; ++op) acc[op].add(tl, bv[u][op]);
+            } else if constexpr (MODE == MODE_BCAST) {
+                const auto tl = left_term<PREC>(cf, av[u][0]);
+#pragma unroll
+                for (int op = 0; op < NOPS; ++op) acc[op].add(tl, bv[u][op]);
+            } else if constexpr (PREC == CUT_F64 || PREC == CUT_F32X) {
+                // sum over operand columns first, then one scaled accumulation
+                double d = 0.0;
+#pragma unroll
+                for (int op = 0; op < NOPS; ++op) d = __builtin_fma((double)av[u][op], (double)bv[u][op], d);
+                acc[0].v = __builtin_fma(cf, d, acc[0].v);
+            } else {
+#pragma unroll
+                for (int op = 0; op < NOPS; ++op) acc[0].add(fc[u] * av[u][op], bv[u][op]);
+            }
         }
-        const int cnt = (int)((e1 - base) < 64 * CH ? (e1 - base) : 64 * CH);
+    };
+    // records given as (x, y) words; okm[u] all ones for a live slot, else zero
+    auto consume = [&](const uint32_t (&rx)[U], const uint32_t (&ry)[U], const uint32_t (&okm)[U]) {
+        T av[U][NA];
+        T bv[U][NOPS];
+        float fc[U];
 #pragma unroll
-        for (int t0 = 0; t0 < SLOTS; t0 += U) {
-            if (t0 * R >= cnt) break;
-            uint32_t rx[U], ry[U];
-            bool ok[U];
+        for (int u = 0; u < U; ++u) {
+            const T* arow = A + (int64_t)(rx[u] & 0xFFFFFFu) * a.lda;
+            const T* brow = B + (int64_t)(ry[u] & 0xFFFFFFu) * a.ldb;
+            fc[u] = __builtin_bit_cast(float, record_factor_bits(rx[u], ry[u]) & okm[u]);
+            if constexpr (G == 64) {  // one record per wavefront: uniform rows
+                const auto ra = row_rsrc(arow, a.lda * (int64_t)sizeof(T));
+                const auto rb = row_rsrc(brow, a.ldb * (int64_t)sizeof(T));
+#pragma unroll
+                for (int q = 0; q < NA; ++q) av[u][q] = buf_load<T>(ra, boff[q], 0);
+#pragma unroll
+                for (int op = 0; op < NOPS; ++op) bv[u][op] = buf_load<T>(rb, boff[op], 0);
+            } else {
+                const char* ac = reinterpret_cast<const char*>(arow);
+                const char* bc = reinterpret_cast<const char*>(brow);
+#pragma unroll
+                for (int q = 0; q < NA; ++q) av[u][q] = *reinterpret_cast<const T*>(ac + boff[q]);
+#pragma unroll
+                for (int op = 0; op < NOPS; ++op) bv[u][op] = *reinterpret_cast<const T*>(bc + boff[op]);
+            }
+        }
+        accum(av, bv, fc);
+    };
+    if constexpr (G == 64) {
+        // One record per wavefront step: records come through scalar loads
+        // (uniform index, read-only stream).  32-bit positions within the
+        // segment keep the compares scalar (no scalar 64-bit signed compare).
+        typedef const __attribute__((address_space(4))) unsigned long long ConstRec;
+        const ConstRec* rp = (const ConstRec*)a.rec + e0;
+        const int32_t n = (int32_t)(e1 - e0);
+        // records q0 .. q0+U-1 (clamped to the last one past the end; no branch,
+        // so the loads stay in flight across the code that follows)
+        auto fetch = [&](int32_t q0, uint32_t (&x)[U], uint32_t (&y)[U]) {
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                const int t = t0 + u;
-                const int c = t / G;
-                const int src = (t % G) * R + sub;
-                if constexpr (G == 64) {
-                    rx[u] = (uint32_t)__builtin_amdgcn_readlane((int)mine[c].x, src);
-                    ry[u] = (uint32_t)__builtin_amdgcn_readlane((int)mine[c].y, src);
-                } else {
+                const int32_t q = q0 + u < n ? q0 + u : n - 1;
+                const unsigned long long r = rp[q];
+                x[u] = (uint32_t)r;
+                y[u] = (uint32_t)(r >> 32);
+            }
+        };
+        auto live = [&](int32_t b, uint32_t (&okm)[U]) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) okm[u] = ~(uint32_t)((n - 1 - (b + u)) >> 31);  // integer ops: scalar
+        };
+        if (a.buf32) {
+            // Both operand arrays below 2 GiB: one buffer resource per array,
+            // rows addressed by 32-bit scalar offsets.  Scalar loads complete
+            // out of order, so any use of one group's records waits for every
+            // scalar load in flight: each group's offsets and factors are
+            // derived first, and only then (past a scheduling barrier) are the
+            // records of the group after next fetched into the same registers.
+            const auto rsA = row_rsrc(A, 0x7FFFFFFF);
+            const auto rsB = row_rsrc(B, 0x7FFFFFFF);
+            const int32_t lda_b = (int32_t)(a.lda * (int64_t)sizeof(T));
+            const int32_t ldb_b = (int32_t)(a.ldb * (int64_t)sizeof(T));
+            auto group = [&](int32_t b, uint32_t (&x)[U], uint32_t (&y)[U]) {
+                uint32_t okm[U];
+                live(b, okm);
+                int32_t sa[U], sb[U];
+                float fc[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    sa[u] = (int32_t)(x[u] & 0xFFFFFFu) * lda_b;
+                    sb[u] = (int32_t)(y[u] & 0xFFFFFFu) * ldb_b;
+                    fc[u] = __builtin_bit_cast(float, record_factor_bits(x[u], y[u]) & okm[u]);
+                }
+                __builtin_amdgcn_sched_barrier(0);
+                fetch(b + 2 * U, x, y);
+                T av[U][NA];
+                T bv[U][NOPS];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+#pragma unroll
+                    for (int q = 0; q < NA; ++q) av[u][q] = buf_load<T>(rsA, boff[q], sa[u]);
+#pragma unroll
+                    for (int op = 0; op < NOPS; ++op) bv[u][op] = buf_load<T>(rsB, boff[op], sb[u]);
+                }
+                accum(av, bv, fc);
+            };
+            uint32_t xa[U], ya[U], xb[U], yb[U];
+            if (n > 0) fetch(0, xa, ya);
+            if (n > U) fetch(U, xb, yb);
+            for (int32_t b = 0; b < n; b += 2 * U) {
+                group(b, xa, ya);
+                if (b + U >= n) break;
+                group(b + U, xb, yb);
+            }
+        } else {
+            uint32_t rx[U], ry[U];
+            for (int32_t b = 0; b < n; b += U) {
+                fetch(b, rx, ry);
+                uint32_t okm[U];
+                live(b, okm);
+                consume(rx, ry, okm);
+            }
+        }
+    } else {
+        // Records are fetched cooperatively, 64 per wavefront load (one per
+        // lane), then handed to the lane groups by cross-lane moves.
+        constexpr int CH = (G >= U) ? 1 : U / G;  // 64-record chunks per outer iteration
+        constexpr int SLOTS = CH * G;             // record slots of one lane group per iteration
+        for (int64_t base = e0; base < e1; base += 64 * CH) {
+            uint2 mine[CH];
+#pragma unroll
+            for (int c = 0; c < CH; ++c) {
+                // clamped (always valid) address; slots past e1 are masked by cnt
+                const int64_t idx = base + c * 64 + lane;
+                // records are read once per pass: non-temporal
+                const unsigned long long rv = __builtin_nontemporal_load(
+                    (const unsigned long long*)a.rec + (idx < e1 ? idx : e1 - 1));
+                mine[c] = make_uint2((uint32_t)rv, (uint32_t)(rv >> 32));
+            }
+            const int cnt = (int)((e1 - base) < 64 * CH ? (e1 - base) : 64 * CH);
+#pragma unroll
+            for (int t0 = 0; t0 < SLOTS; t0 += U) {
+                if (t0 * R >= cnt) break;
+                uint32_t rx[U], ry[U], okm[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int t = t0 + u;
+                    const int c = t / G;
+                    const int src = (t % G) * R + sub;
                     rx[u] = (uint32_t)__shfl((int)mine[c].x, src);
                     ry[u] = (uint32_t)__shfl((int)mine[c].y, src);
+                    okm[u] = t * R + sub < cnt ? 0xFFFFFFFFu : 0u;
                 }
-                ok[u] = t * R + sub < cnt;
-            }
-            // slots past the segment end hold the (valid) clamped last record;
-            // their factor is zeroed below
-            T av[U][NA];
-            T bv[U][NOPS];
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                // row base (uniform when G == 64) + loop-invariant lane offsets
-                const T* arow = A + (int64_t)(rx[u] & 0xFFFFFFu) * a.lda;
-                const T* brow = B + (int64_t)ry[u] * a.ldb;
-#pragma unroll
-                for (int q = 0; q < NA; ++q) av[u][q] = arow[coff[q]];
-#pragma unroll
-                for (int op = 0; op < NOPS; ++op) bv[u][op] = brow[coff[op]];
-            }
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const double cf = ok[u] ? a.ftab[rx[u] >> 24] : 0.0;
-                if constexpr (MODE == MODE_BCAST) {
-                    const auto tl = left_term<PREC>(cf, av[u][0]);
-#pragma unroll
-                    for (int op = 0; op < NOPS; ++op) acc[op].add(tl, bv[u][op]);
-                } else if constexpr (PREC == CUT_F64 || PREC == CUT_F32X) {
-                    // sum over operand columns first, then one scaled accumulation
-                    double d = 0.0;
-#pragma unroll
-                    for (int op = 0; op < NOPS; ++op) d = __builtin_fma((double)av[u][op], (double)bv[u][op], d);
-                    acc[0].v = __builtin_fma(cf, d, acc[0].v);
-                } else {
-                    const float fc = (float)cf;
-#pragma unroll
-                    for (int op = 0; op < NOPS; ++op) acc[0].add(fc * av[u][op], bv[u][op]);
-                }
+                consume(rx, ry, okm);
             }
         }
     }
@@ -416,6 +548,9 @@ static KArgs make_kargs(const PassArgs& p) {
     k.xout = p.xout;
     k.hst = p.hst;
     k.ldh = p.ldh;
+    const int64_t esz = p.precision == CUT_F64 ? 8 : 4;
+    const int64_t ld = p.lda > p.ldb ? p.lda : p.ldb;
+    k.buf32 = (c.nseg * ld * esz < (int64_t)0x7FFFFFFF) ? 1 : 0;
     return k;
 }
 
@@ -645,7 +780,7 @@ static void launch_chunk_combine(const KArgs& k, int prec, const DevCSR& c, cons
 
 size_t chunk_partial_bytes(const Graph& g, int32_t nsets, int32_t nops) {
     const DevCSR& c = g.csr[0][0];
-    return c.nchunks > 0 ? (size_t)c.nchunks * nops * nsets * sizeof(double) : 0;
+    return c.nchunks > 0 ? (size_t)c.nslots * nops * nsets * sizeof(double) : 0;
 }
 
 size_t forward_partial_bytes(const Graph& g, int32_t nsets, int32_t nops, int32_t precision) {

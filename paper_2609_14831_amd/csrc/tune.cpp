@@ -29,16 +29,6 @@ struct DevBuf {
     }
 };
 
-void apply_tiling(Graph& g, int64_t lr, uint32_t flags) {
-    g.long_records = lr;
-    g.xcd_remap = (flags & CUT_TILE_XCD_REMAP) ? 1 : 0;
-    g.use_tiles = (flags & CUT_TILE_TRIPLES) ? 1 : 0;
-    g.use_chunks = (flags & CUT_TILE_NO_CHUNKS) ? 0 : 1;
-    for (auto& w : g.csr)
-        for (auto& c : w)
-            if (c.nseg) build_tasks(g, c);
-}
-
 double time_pass(Graph& g, int prec, int32_t nsets, int32_t nops, const void* eta, const void* x, double* y,
                  double* partials, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
     PassArgs p{};
@@ -82,7 +72,7 @@ extern "C" cut_status cut_graph_autotune(cut_graph_t h, int64_t nsets, int64_t n
         for (auto& kv : g.tune_cache)
             if (kv.first == key) {
                 *out = kv.second;
-                apply_tiling(g, out->long_records, out->tiling_flags);
+                apply_tiling(g, out->long_records, out->chunk_records, out->tiling_flags);
                 return CUT_OK;
             }
         std::vector<int> precs = {precision};
@@ -105,26 +95,28 @@ extern "C" cut_status cut_graph_autotune(cut_graph_t h, int64_t nsets, int64_t n
         HIP_CHECK(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
         HIP_CHECK(hipEventCreate(&e0));
         HIP_CHECK(hipEventCreate(&e1));
-        const uint32_t flags0 = (g.xcd_remap ? CUT_TILE_XCD_REMAP : 0u) | (g.use_tiles ? CUT_TILE_TRIPLES : 0u) |
-                                (g.use_chunks ? 0u : CUT_TILE_NO_CHUNKS);
-        cut_tuning best{g.long_records, flags0, precision, 1e30, 0.0};
+        cut_tuning best{g.long_records, g.chunk_records, tiling_flags(g), precision, 1e30, 0.0};
         best.default_ms = time_pass(g, precision, (int32_t)nsets, (int32_t)nops, eta.p, x.p, (double*)y.p,
                                     partials(precision), s, e0, e1);
-        const int64_t lrs[] = {256, 512, 1024, 4096};
-        const uint32_t shapes[] = {0u, CUT_TILE_NO_CHUNKS, CUT_TILE_TRIPLES};
-        for (int64_t lr : lrs)
+        const int64_t lr = 1024;
+        const int64_t crs[] = {64, 128, 256, 512};
+        const uint32_t shapes[] = {0u, CUT_TILE_TRIPLE_CHUNKS, CUT_TILE_NO_CHUNKS, CUT_TILE_TRIPLES};
+        for (int64_t cr : crs)
             for (uint32_t xr = 0; xr <= 1; ++xr)
                 for (uint32_t shape : shapes) {
                     if ((shape & CUT_TILE_TRIPLES) && !g.tiles.ok) continue;
+                    if ((shape & CUT_TILE_TRIPLE_CHUNKS) && !g.triple_groups) continue;
+                    // the chunk length does not change the unchunked and tile forms
+                    if ((shape & (CUT_TILE_NO_CHUNKS | CUT_TILE_TRIPLES)) && cr != crs[0]) continue;
                     const uint32_t flags = (xr ? CUT_TILE_XCD_REMAP : 0u) | shape;
-                    apply_tiling(g, lr, flags);
+                    apply_tiling(g, lr, cr, flags);
                     for (int pr : precs) {
                         const double ms = time_pass(g, pr, (int32_t)nsets, (int32_t)nops, eta.p, x.p, (double*)y.p,
                                                     partials(pr), s, e0, e1);
-                        if (ms < best.pass_ms) best = cut_tuning{lr, flags, pr, ms, best.default_ms};
+                        if (ms < best.pass_ms) best = cut_tuning{lr, cr, flags, pr, ms, best.default_ms};
                     }
                 }
-        apply_tiling(g, best.long_records, best.tiling_flags);
+        apply_tiling(g, best.long_records, best.chunk_records, best.tiling_flags);
         HIP_CHECK(hipEventDestroy(e0));
         HIP_CHECK(hipEventDestroy(e1));
         HIP_CHECK(hipStreamDestroy(s));

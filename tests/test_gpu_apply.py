@@ -71,9 +71,14 @@ CASES = [("epq", 8, 1, 1), ("epq", 8, 4, 2), ("majorana", 8, 1, 1), ("majorana",
 PRECS = ["F64", "F32X", "F32C", "F32"]
 
 
-# (long-target threshold, CUT_TILE_* flags): default chunked form; 16-record
-# chunks with XCD remap; shared-triple tiles; four-wavefront split (no chunks)
-@pytest.mark.parametrize("tiling", [(1024, 0), (16, 1), (64, 3), (64, 4)])
+# (long-target threshold, chunk length, CUT_TILE_* flags): default chunked form;
+# 16-record chunks with XCD remap; shared-triple tiles; four-wavefront split (no
+# chunks); shared-triple chunks of quartic targets (one or two triples a chunk,
+# with and without XCD remap)
+TILINGS = [(1024, 512, 0), (16, 16, 1), (64, 64, 3), (64, 64, 4), (1024, 8, 9), (16, 32, 9), (1024, 128, 8)]
+
+
+@pytest.mark.parametrize("tiling", TILINGS)
 @pytest.mark.parametrize("prec", PRECS)
 @pytest.mark.parametrize("alg,size,nsets,nops", CASES)
 def test_apply_parity(L, alg, size, nsets, nops, prec, tiling):
@@ -93,7 +98,7 @@ def test_apply_parity(L, alg, size, nsets, nops, prec, tiling):
         acc = {"F32X": U.sum_bound(seg), "F32C": U.dot2_bound(seg), "F32": seg * U.U32}[prec]
         U.assert_within(y, ref32, acc * S + 1e-300, f"{prec} vs oracle on float operands")
         U.assert_within(y, OGr.apply(og, eta, x), (2 * U.U32 + acc) * S + 1e-300, f"{prec} vs FP64 oracle")
-    L.cut_graph_set_tiling(g, 1024, 0)
+    L.cut_graph_set_tiling(g, 1024, 512, 0)
 
 
 def test_apply_accumulate_and_gen_records(L):
@@ -113,12 +118,13 @@ def test_apply_bitwise_deterministic(L):
     g = U.graph(L, "majorana", 16)
     og = oracle_graph("majorana", 16)
     eta, x = _inputs(og.N, 16, 3, seed=9)
-    L.cut_graph_set_tiling(g, 32, 1)
-    for P in (L.CUT_F64, L.CUT_F32C):
-        a = _run_apply(L, g, P, eta, x, 16, 3)
-        b = _run_apply(L, g, P, eta, x, 16, 3)
-        assert np.array_equal(a, b)
-    L.cut_graph_set_tiling(g, 1024, 0)
+    for tiling in ((32, 32, 1), (1024, 16, 9)):
+        L.cut_graph_set_tiling(g, *tiling)
+        for P in (L.CUT_F64, L.CUT_F32C):
+            a = _run_apply(L, g, P, eta, x, 16, 3)
+            b = _run_apply(L, g, P, eta, x, 16, 3)
+            assert np.array_equal(a, b)
+    L.cut_graph_set_tiling(g, 1024, 512, 0)
 
 
 @pytest.mark.parametrize("prec", ["F64", "F32X", "F32C"])

@@ -61,7 +61,8 @@ def cfg3(L):
     w = workloads.WORKLOADS[3]
     U.say("[cfg3] build + load m=40")
     g = U.graph(L, "majorana", 40, adjoint=False)
-    L.cut_graph_set_tiling(g, 1024, 0)   # bench default
+    # the tiling the benchmark runs: autotuned for 64 sets x 5 operands, F32C
+    U.say(f"[cfg3] autotuned {L.cut_graph_autotune(g, w.nsets, w.nops, L.CUT_F32C, 0)}")
     return g, w, workloads.make_inputs(3)
 
 
@@ -86,8 +87,11 @@ def test_cfg3_two_rk4_steps_every_coefficient(L, cfg3, cfg3_oracle):
 
 
 @pytest.mark.timeout(300)
-def test_cfg3_sampled_single_actions(L, cfg3):
+@pytest.mark.parametrize("tiling", [None, (1024, 512, 0), (1024, 64, 9), (1024, 128, 8)])
+def test_cfg3_sampled_single_actions(L, cfg3, tiling):
     g, w, inp = cfg3
+    if tiling is not None:
+        L.cut_graph_set_tiling(g, *tiling)
     reg = A.MajoranaRegistry(40)
     rows = np.array([0, 1, 779, 780, 781, 40000, reg.N - 1] +
                     list(np.random.default_rng(5).integers(0, reg.N, 25)))
@@ -107,7 +111,9 @@ def test_cfg3_sampled_single_actions(L, cfg3):
         got = y.cpu().numpy().reshape(reg.N, 5, 64)[rows]
         bound = {"F64": U.sum_bound(16948), "F32X": 2 * U.U32 + U.sum_bound(16948),
                  "F32C": 2 * U.U32 + U.dot2_bound(16948)}[name] * S + 1e-300
-        U.assert_within(got, ref, bound, f"cfg3 sampled {name}")
+        U.assert_within(got, ref, bound, f"cfg3 sampled {name} tiling {tiling}")
+    t = L.cut_graph_autotune(g, w.nsets, w.nops, L.CUT_F32C, 0)   # cached: restores the tuned tiling
+    L.cut_graph_set_tiling(g, t["long_records"], t["chunk_records"], t["tiling_flags"])
 
 
 @pytest.mark.timeout(900)
@@ -130,8 +136,9 @@ def test_cfg4_stress_graph(L):
         ref = OGr.apply_rows(og, eta, inp.z0, rows)
         ga = A.Graph("majorana", 64, og.N, og.k, og.i, og.j, np.abs(og.c), og.diag, og.pairs, 1.0)
         S = OGr.apply_rows(ga, np.abs(eta), np.abs(inp.z0), rows)
-        for name in ("F64", "F32C"):
-            U.say(f"[cfg4] apply {name}")
+        for name, tiling in (("F64", (1024, 512, 0)), ("F32C", (1024, 512, 0)), ("F32C", (1024, 128, 9))):
+            U.say(f"[cfg4] apply {name} tiling {tiling}")
+            L.cut_graph_set_tiling(g, *tiling)
             P = getattr(L, "CUT_" + name)
             dt = torch.float64 if P == L.CUT_F64 else torch.float32
             y = torch.zeros((reg.N, 16), dtype=torch.float64, device=DEV)
@@ -140,7 +147,7 @@ def test_cfg4_stress_graph(L):
             torch.cuda.synchronize()
             got = y.cpu().numpy().reshape(reg.N, 1, 16)[rows]
             bound = {"F64": U.sum_bound(75764), "F32C": 2 * U.U32 + U.dot2_bound(75764)}[name] * S + 1e-300
-            U.assert_within(got, ref, bound, f"cfg4 sampled {name}")
+            U.assert_within(got, ref, bound, f"cfg4 sampled {name} tiling {tiling}")
         U.say("[cfg4] 20-step flows")
         z64 = _flow(L, g, inp.z0, inp.n_steps, L.CUT_F64, w, steps=20)
         z32 = _flow(L, g, inp.z0, inp.n_steps, L.CUT_F32C, w, steps=20)
