@@ -230,13 +230,16 @@ def main():
     flops_per = 2.0 * E * nsets * nops
     log(f"fused pass avg {pass_ms:.4f} ms ({tm['pass_launches']} launches), generator {gen_ms:.4f} ms")
     traffic = measured_traffic(args.precision)
+    gathered = E * (nsets + nops * nsets) * pbytes   # one eta row + one operand row per record
     out["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                        "frac": achieved / HBM_PEAK_GBS,
                        "traffic": traffic["bytes_per_launch"] if traffic else None,
-                       "traffic_unit": "bytes per launch (FETCH_SIZE x copy factor + WRITE_SIZE)",
+                       "traffic_unit": "bytes per fused pass (FETCH_SIZE x copy factor + WRITE_SIZE)",
                        "kernel": "fused graph pass with RK4 stage epilogue: k_pass<64,5,prec,0,2> "
-                                 "(long-target chunks + short targets) and k_chunk_combine<5,prec,2>",
+                                 "(chunks of the quadratic targets + quartic targets) and k_chunk_combine<5,prec,2>",
                        "avg_launch_ms": pass_ms, "algorithmic_bytes_per_launch": bytes_per,
+                       "gathered_row_bytes_per_launch": gathered,
+                       "gathered_row_rate_GBs": gathered / (pass_ms * 1e-3) / 1e9,
                        "fp64_equiv_tflops": flops_per / (pass_ms * 1e-3) / 1e12,
                        "fp64_vector_peak_tflops": FP64_VEC_TFLOPS}
     out["generator_avg_ms"] = gen_ms
@@ -261,7 +264,9 @@ def main():
         log(f"{alt}: {alt_wall * 1e3 / K:.3f} ms/step")
         del za
 
-    # plain FP64 flow, one operand column per pass (one set, H only)
+    # plain FP64 flow, one operand column per pass (one set, H only), in the
+    # tiling tuned for that shape
+    out["plain_fp64_flow_tiling"] = L.cut_graph_autotune(g, 1, 1, L.CUT_F64, 0)
     z1 = torch.tensor(inp.z0[:, :1, :1], device=dev).contiguous()
     ns1 = [ns[0]]
     p = L.flow_params(L.CUT_GEN_G2, L.CUT_F64, w.ds, w.delta, 0, flags=L.CUT_FLOW_HIPGRAPH,
