@@ -229,6 +229,12 @@ cut_status cut_flow_adjoint(cut_graph_t g, const cut_flow_params* p, int64_t nse
  * is T+w for one triple T of K; about chunk_records records per chunk), placed
  * at the rank of T, so the chunks of all targets containing T run together and
  * read the rows T+w while they are in cache.
+ * CUT_TILE_QUAD_BLOCKS (Majorana graphs, forward passes in the float modes with
+ * nops <= 6): every quadratic target {u, v} pairs the rows T+u and T+v over all
+ * triples T outside {u, v}; modes are grouped by 8, and one workgroup owns the
+ * (up to 64) targets of two groups and a range of triples, stages the rows T+w
+ * of its 16 modes in LDS once per triple and keeps its targets' sums in
+ * registers; each (target, range) sum is a partial row added in fixed order.
  * CUT_TILE_TRIPLES (Majorana graphs, forward passes, nsets >= 8): every record
  * of a quartic target pairs a quadratic string with a quartic string sharing
  * three modes tau with the target; the 4-subsets containing tau are both the
@@ -241,6 +247,7 @@ cut_status cut_flow_adjoint(cut_graph_t g, const cut_flow_params* p, int64_t nse
 #define CUT_TILE_TRIPLES 2u
 #define CUT_TILE_NO_CHUNKS 4u
 #define CUT_TILE_TRIPLE_CHUNKS 8u
+#define CUT_TILE_QUAD_BLOCKS 16u
 cut_status cut_graph_set_tiling(cut_graph_t g, int64_t long_records, int64_t chunk_records, uint32_t flags);
 
 /* Autotuner: times the forward graph pass for (nsets, nops) over candidate

@@ -32,6 +32,7 @@ CUT_LOAD_ADJOINT, CUT_LOAD_NO_CHECKSUM = 1, 2
 CUT_FLOW_HIPGRAPH = 1
 CUT_FLOW_TIME_PASSES = 2
 CUT_TILE_XCD_REMAP, CUT_TILE_TRIPLES, CUT_TILE_NO_CHUNKS, CUT_TILE_TRIPLE_CHUNKS = 1, 2, 4, 8
+CUT_TILE_QUAD_BLOCKS = 16
 
 STATUS_NAMES = {0: "CUT_OK", 1: "CUT_E_INVAL", 2: "CUT_E_IO", 3: "CUT_E_FORMAT",
                 4: "CUT_E_CHECKSUM", 5: "CUT_E_NOMEM", 6: "CUT_E_DEVICE", 7: "CUT_E_NUMERIC",
@@ -170,7 +171,8 @@ def cut_graph_free(g: int) -> None:
 
 
 def cut_graph_set_tiling(g: int, long_records: int, chunk_records: int, flags: int) -> None:
-    """flags: CUT_TILE_XCD_REMAP | CUT_TILE_TRIPLES | CUT_TILE_NO_CHUNKS | CUT_TILE_TRIPLE_CHUNKS."""
+    """flags: CUT_TILE_XCD_REMAP | CUT_TILE_TRIPLES | CUT_TILE_NO_CHUNKS | CUT_TILE_TRIPLE_CHUNKS
+    | CUT_TILE_QUAD_BLOCKS."""
     _check(_L.cut_graph_set_tiling(g, long_records, chunk_records, flags))
 
 

@@ -213,10 +213,7 @@ extern "C" cut_status cut_flow_integrate(cut_graph_t h, const cut_flow_params* p
         if (use_graph) {
             std::vector<uint64_t> key = {(uint64_t)(uintptr_t)z, (uint64_t)(uintptr_t)g.ws.ptr, (uint64_t)p->generator,
                                          (uint64_t)p->precision, (uint64_t)nsets, (uint64_t)nops, 0, 0,
-                                         (uint64_t)g.csr[0][0].ntasks, (uint64_t)(uintptr_t)g.csr[0][0].tasks,
-                                         (uint64_t)(uintptr_t)fb.part, (uint64_t)(uintptr_t)g.tiles.res_tasks,
-                                         (uint64_t)(uintptr_t)g.csr[0][0].chunks,
-                                         (uint64_t)(uintptr_t)g.csr[0][0].short_tasks, (uint64_t)g.use_tiles};
+                                         g.tiling_gen, (uint64_t)(uintptr_t)fb.part};
             std::memcpy(&key[6], &p->ds, 8);
             std::memcpy(&key[7], &p->delta, 8);
             if (!g.graphs || g.graphs->key != key) {

@@ -14,6 +14,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <unordered_map>
 
 #include "internal.h"
 
@@ -43,15 +44,39 @@ static void dev_free(T*& p) {
     p = nullptr;
 }
 
-void DevCSR::release() {
-    dev_free(off);
-    dev_free(rec);
-    dev_free(tasks);
+void ChunkPlan::release() {
     dev_free(short_tasks);
     dev_free(chunks);
     dev_free(cstart);
     dev_free(crow);
     nshort = short_per_xcd = nchunks = nlong = nslots = 0;
+}
+
+void QuadBlockPlan::release_tiling() {
+    dev_free(tslot);
+    cp.release();
+    active = false;
+}
+
+void QuadBlockPlan::release() {
+    release_tiling();
+    dev_free(row4);
+    dev_free(tmask);
+    dev_free(bpair);
+    dev_free(sgn);
+    fmag = 0.f;
+    qrow.clear();
+    lead.clear();
+    ok = false;
+    m = ng = nbp = nr = 0;
+    ntrip = 0;
+}
+
+void DevCSR::release() {
+    dev_free(off);
+    dev_free(rec);
+    dev_free(tasks);
+    cp.release();
     off_h.clear();
     off_h.shrink_to_fit();
     nseg = nrec = ntasks = per_xcd = 0;
@@ -99,6 +124,7 @@ Graph::~Graph() {
     dev_free(st_p_off);
     dev_free(st_p);
     tiles.release();
+    qb.release();
     ws.release();
     ws_small.release();
     ws_part.release();
@@ -142,12 +168,12 @@ static int64_t lex_rank3(uint64_t t, int m) {
 // XCD remapping the list is cut into 8 contiguous pieces, piece x running on
 // XCD x (block b on XCD b % 8), padded with empty chunks.  The remaining short
 // segments are packed four per task (same XCD split).
-static void build_chunks(const Graph& g, DevCSR& c) {
-    dev_free(c.chunks);
-    dev_free(c.cstart);
-    dev_free(c.crow);
-    dev_free(c.short_tasks);
-    c.nchunks = c.nlong = c.nshort = c.short_per_xcd = c.nslots = 0;
+// With `quad` (quadratic-target blocks) every quadratic target becomes one
+// chunk of its leading records followed by qb.nr partial slots that the block
+// kernel fills; seg_slot[k] receives the first of those block slots.
+static void build_chunks(const Graph& g, const DevCSR& c, ChunkPlan& out, bool quad,
+                         std::vector<int64_t>* seg_slot = nullptr) {
+    out.release();
     const std::vector<int64_t>& off = c.off_h;
     const int64_t lr = g.long_records, cr = std::max<int64_t>(1, g.chunk_records);
     std::vector<int64_t> cstart = {0};
@@ -163,15 +189,23 @@ static void build_chunks(const Graph& g, DevCSR& c) {
     const bool fam = g.triple_chunks && g.triple_groups && g.hdr.algebra == CUT_ALG_MAJORANA &&
                      (int64_t)g.labels_h.size() == c.nseg && m >= 4;
     const double ntrip = (double)m * (m - 1) * (m - 2) / 6.0;
+    if (seg_slot) seg_slot->assign(c.nseg, -1);
     for (int64_t k = 0; k < c.nseg; ++k) {
         const int64_t len = off[k + 1] - off[k];
         const bool quart = fam && len > 0 && __builtin_popcountll(g.labels_h[k]) == 4;
-        if (!quart && len <= lr) continue;
+        const bool qtarget = quad && __builtin_popcountll(g.labels_h[k]) == 2;
+        if (!quart && !qtarget && len <= lr) continue;
         is_long[k] = 1;
         const int64_t l = (int64_t)crow.size();
         crow.push_back((int32_t)k);
         int64_t nch = 0;
-        if (quart) {
+        if (qtarget) {
+            // leading records in one chunk (slot 0), then the block slots
+            ents.push_back({0.0, ChunkTask{(int32_t)k, (int32_t)cstart[l], (int32_t)off[k],
+                                           (int32_t)(off[k] + g.qb.lead[k])}});
+            if (seg_slot) (*seg_slot)[k] = cstart[l] + 1;
+            nch = 1 + g.qb.nr;
+        } else if (quart) {
             const int64_t q = len / 4;
             const int gpc = (int)std::min<int64_t>(4, std::max<int64_t>(1, (cr + q / 2) / q));
             int e[4], r = 0;
@@ -248,36 +282,68 @@ static void build_chunks(const Graph& g, DevCSR& c) {
         if (per > 0) {
             st.assign(per * 8, Task{0, 0});
             for (int x = 0; x < 8; ++x) std::copy(parts[x].begin(), parts[x].end(), st.begin() + x * per);
-            c.short_per_xcd = (int64_t)per;
+            out.short_per_xcd = (int64_t)per;
         }
     } else {
         pack(0, c.nseg, st);
     }
-    c.nshort = (int64_t)st.size();
+    out.nshort = (int64_t)st.size();
     if (!st.empty()) {
-        c.short_tasks = dev_alloc<Task>(st.size());
-        HIP_CHECK(hipMemcpy(c.short_tasks, st.data(), st.size() * sizeof(Task), hipMemcpyHostToDevice));
+        out.short_tasks = dev_alloc<Task>(st.size());
+        HIP_CHECK(hipMemcpy(out.short_tasks, st.data(), st.size() * sizeof(Task), hipMemcpyHostToDevice));
     }
-    c.nlong = (int64_t)crow.size();
-    c.nchunks = (int64_t)ch.size();
-    c.nslots = cstart.back();
-    if (c.nchunks == 0) return;
-    c.chunks = dev_alloc<ChunkTask>(ch.size());
-    HIP_CHECK(hipMemcpy(c.chunks, ch.data(), ch.size() * sizeof(ChunkTask), hipMemcpyHostToDevice));
-    c.cstart = dev_alloc<int64_t>(cstart.size());
-    HIP_CHECK(hipMemcpy(c.cstart, cstart.data(), cstart.size() * 8, hipMemcpyHostToDevice));
-    c.crow = dev_alloc<int32_t>(crow.size());
-    HIP_CHECK(hipMemcpy(c.crow, crow.data(), crow.size() * 4, hipMemcpyHostToDevice));
+    out.nlong = (int64_t)crow.size();
+    out.nchunks = (int64_t)ch.size();
+    out.nslots = cstart.back();
+    if (out.nlong == 0) return;
+    if (!ch.empty()) {
+        out.chunks = dev_alloc<ChunkTask>(ch.size());
+        HIP_CHECK(hipMemcpy(out.chunks, ch.data(), ch.size() * sizeof(ChunkTask), hipMemcpyHostToDevice));
+    }
+    out.cstart = dev_alloc<int64_t>(cstart.size());
+    HIP_CHECK(hipMemcpy(out.cstart, cstart.data(), cstart.size() * 8, hipMemcpyHostToDevice));
+    out.crow = dev_alloc<int32_t>(crow.size());
+    HIP_CHECK(hipMemcpy(out.crow, crow.data(), crow.size() * 4, hipMemcpyHostToDevice));
+}
+
+// Per-tiling tables of the quadratic-target blocks: the chunked form with the
+// leading records of every quadratic target as chunks, and for every block
+// pair and local target t = 8 iu + iv (u = 8 g1 + iu, v = 8 g2 + iv, u < v) its
+// first block partial slot (range r of triples [r ntrip / nr, (r+1) ntrip / nr)
+// in lexicographic order goes to slot + r).
+static void build_qb_tiling(Graph& g, const DevCSR& c) {
+    QuadBlockPlan& q = g.qb;
+    q.release_tiling();
+    if (!q.ok || !g.use_quadblocks || !g.use_chunks || c.nrec >= (1ll << 31)) return;
+    std::vector<int64_t> seg_slot;
+    build_chunks(g, c, q.cp, true, &seg_slot);
+    const int m = q.m;
+    std::vector<int32_t> tslot((size_t)q.nbp * 64, -1);
+    int bp = 0;
+    for (int g1 = 0; g1 < q.ng; ++g1)
+        for (int g2 = g1; g2 < q.ng; ++g2, ++bp)
+            for (int t = 0; t < 64; ++t) {
+                const int u = 8 * g1 + t / 8, v = 8 * g2 + t % 8;
+                if (u >= m || v >= m || u >= v) continue;
+                tslot[(size_t)bp * 64 + t] = (int32_t)seg_slot[q.qrow[u * m + v]];
+            }
+    q.tslot = dev_alloc<int32_t>(tslot.size());
+    HIP_CHECK(hipMemcpy(q.tslot, tslot.data(), tslot.size() * 4, hipMemcpyHostToDevice));
+    q.active = true;
 }
 
 void build_tasks(Graph& g, DevCSR& c) {
+    ++g.tiling_gen;
     c.per_xcd = 0;
     if (c.nseg == 0) {
         upload_tasks({}, &c.tasks, &c.ntasks);
         return;
     }
     upload_tasks(plan_tasks(g, c.off_h, c.nseg, &c.per_xcd), &c.tasks, &c.ntasks);
-    if (&c == &g.csr[0][0]) build_chunks(g, c);
+    if (&c == &g.csr[0][0]) {
+        build_chunks(g, c, c.cp, false);
+        build_qb_tiling(g, c);
+    }
     if (&c == &g.csr[0][0] && g.tiles.ok) {
         g.tiles.res_per_xcd = 0;
         upload_tasks(plan_tasks(g, c.off_h, g.tiles.nres, &g.tiles.res_per_xcd), &g.tiles.res_tasks,
@@ -292,6 +358,7 @@ void apply_tiling(Graph& g, int64_t long_records, int64_t chunk_records, uint32_
     g.use_tiles = (flags & CUT_TILE_TRIPLES) ? 1 : 0;
     g.use_chunks = (flags & CUT_TILE_NO_CHUNKS) ? 0 : 1;
     g.triple_chunks = (flags & CUT_TILE_TRIPLE_CHUNKS) ? 1 : 0;
+    g.use_quadblocks = (flags & CUT_TILE_QUAD_BLOCKS) ? 1 : 0;
     for (auto& w : g.csr)
         for (auto& c : w)
             if (c.nseg) build_tasks(g, c);
@@ -299,7 +366,8 @@ void apply_tiling(Graph& g, int64_t long_records, int64_t chunk_records, uint32_
 
 uint32_t tiling_flags(const Graph& g) {
     return (g.xcd_remap ? CUT_TILE_XCD_REMAP : 0u) | (g.use_tiles ? CUT_TILE_TRIPLES : 0u) |
-           (g.use_chunks ? 0u : CUT_TILE_NO_CHUNKS) | (g.triple_chunks ? CUT_TILE_TRIPLE_CHUNKS : 0u);
+           (g.use_chunks ? 0u : CUT_TILE_NO_CHUNKS) | (g.triple_chunks ? CUT_TILE_TRIPLE_CHUNKS : 0u) |
+           (g.use_quadblocks ? CUT_TILE_QUAD_BLOCKS : 0u);
 }
 
 static std::vector<Task> plan_tasks(const Graph& g, const std::vector<int64_t>& off, int64_t nseg, int64_t* per_xcd) {
@@ -522,6 +590,103 @@ static inline uint2 pack_record(int8_t c, uint32_t a, uint32_t b) {
     return make_uint2(((h >> 8) << 24) | a, ((h & 0xFFu) << 24) | b);
 }
 
+// Quadratic-target blocks (see QuadBlockPlan): built only if every quadratic
+// target's records, in locality order, are its leading records followed by
+// exactly the pairs (T+u, T+v), (T+v, T+u) for every triple T outside {u, v}
+// in lexicographic order.  Anything else leaves the plan off.
+static void build_quadblocks(Graph& g, const HostGraph& hg, const int64_t* off, const std::vector<uint2>& rec) {
+    QuadBlockPlan& q = g.qb;
+    q.release();
+    const int m = hg.hdr.size;
+    const int64_t N = hg.hdr.n_ops;
+    if (m < 5 || m > 64) return;
+    std::unordered_map<uint64_t, int32_t> idx;
+    idx.reserve((size_t)N * 2);
+    for (int64_t k = 0; k < N; ++k) idx.emplace(hg.labels[k], (int32_t)k);
+    std::vector<int32_t> qrow((size_t)m * m, -1);
+    for (int64_t k = 0; k < N; ++k) {
+        const uint64_t L = hg.labels[k];
+        if (__builtin_popcountll(L) != 2) continue;
+        const int u = __builtin_ctzll(L), v = __builtin_ctzll(L & (L - 1));
+        if (v >= m) return;
+        qrow[(size_t)u * m + v] = (int32_t)k;
+    }
+    for (int u = 0; u < m; ++u)
+        for (int v = u + 1; v < m; ++v)
+            if (qrow[(size_t)u * m + v] < 0) return;
+    std::vector<uint64_t> tm;
+    for (int a = 0; a < m; ++a)
+        for (int b = a + 1; b < m; ++b)
+            for (int d = b + 1; d < m; ++d) tm.push_back((1ull << a) | (1ull << b) | (1ull << d));
+    const int64_t ntrip = (int64_t)tm.size();
+    std::vector<int32_t> row4((size_t)ntrip * m, -1);
+    for (int64_t t = 0; t < ntrip; ++t)
+        for (int w = 0; w < m; ++w) {
+            if (tm[t] >> w & 1) continue;
+            const auto it = idx.find(tm[t] | (1ull << w));
+            if (it == idx.end()) return;
+            row4[(size_t)t * m + w] = it->second;
+        }
+    std::vector<int32_t> lead(N, 0);
+    const uint32_t M24 = 0xFFFFFFu;
+    const int ng = (m + 7) / 8, nbp = ng * (ng + 1) / 2;
+    std::vector<int32_t> bp_of((size_t)ng * ng, -1);
+    for (int g1 = 0, b = 0; g1 < ng; ++g1)
+        for (int g2 = g1; g2 < ng; ++g2) bp_of[(size_t)g1 * ng + g2] = b++;
+    std::vector<uint32_t> sgn((size_t)nbp * 8 * ntrip, 0);
+    uint32_t fbits = 0;  // FP32 bit pattern of the common magnitude
+    auto factor_bits = [](const uint2& r) { return (r.x & 0xFF000000u) | ((r.y >> 24) << 16); };
+    for (int u = 0; u < m; ++u)
+        for (int v = u + 1; v < m; ++v) {
+            const int32_t k = qrow[(size_t)u * m + v];
+            int64_t e = off[k];
+            while (e < off[k + 1] &&
+                   __builtin_popcountll(hg.labels[rec[e].x & M24] & hg.labels[rec[e].y & M24]) != 3)
+                ++e;
+            lead[k] = (int32_t)(e - off[k]);
+            const uint64_t uv = (1ull << u) | (1ull << v);
+            uint32_t* sg = sgn.data() + ((size_t)bp_of[(size_t)(u / 8) * ng + v / 8] * 8 + u % 8) * ntrip;
+            const int j = v % 8;
+            for (int64_t t = 0; t < ntrip; ++t) {
+                if (tm[t] & uv) continue;
+                const uint32_t ru = (uint32_t)row4[(size_t)t * m + u], rv = (uint32_t)row4[(size_t)t * m + v];
+                if (e + 2 > off[k + 1]) return;
+                if ((rec[e].x & M24) != ru || (rec[e].y & M24) != rv) return;
+                if ((rec[e + 1].x & M24) != rv || (rec[e + 1].y & M24) != ru) return;
+                for (int h = 0; h < 2; ++h) {
+                    const uint32_t fb = factor_bits(rec[e + h]);
+                    if (fbits == 0) fbits = fb & 0x7FFFFFFFu;
+                    if ((fb & 0x7FFFFFFFu) != fbits) return;  // one magnitude only
+                    if (fb >> 31) sg[t] |= 1u << (2 * j + h);
+                }
+                e += 2;
+            }
+            if (e != off[k + 1]) return;
+        }
+    if (fbits == 0) return;
+    q.m = m;
+    q.ntrip = ntrip;
+    q.ng = ng;
+    q.nbp = nbp;
+    std::memcpy(&q.fmag, &fbits, 4);
+    // about 1024 workgroups (two rounds of two 8-wavefront groups per CU)
+    q.nr = (int32_t)std::max<int64_t>(1, std::min<int64_t>(ntrip, (1024 + q.nbp - 1) / q.nbp));
+    std::vector<int2> bp;
+    for (int g1 = 0; g1 < q.ng; ++g1)
+        for (int g2 = g1; g2 < q.ng; ++g2) bp.push_back(make_int2(8 * g1, 8 * g2));
+    q.row4 = dev_alloc<int32_t>(row4.size());
+    HIP_CHECK(hipMemcpy(q.row4, row4.data(), row4.size() * 4, hipMemcpyHostToDevice));
+    q.tmask = dev_alloc<uint64_t>(tm.size());
+    HIP_CHECK(hipMemcpy(q.tmask, tm.data(), tm.size() * 8, hipMemcpyHostToDevice));
+    q.bpair = dev_alloc<int2>(bp.size());
+    HIP_CHECK(hipMemcpy(q.bpair, bp.data(), bp.size() * sizeof(int2), hipMemcpyHostToDevice));
+    q.sgn = dev_alloc<uint32_t>(sgn.size());
+    HIP_CHECK(hipMemcpy(q.sgn, sgn.data(), sgn.size() * 4, hipMemcpyHostToDevice));
+    q.qrow = std::move(qrow);
+    q.lead = std::move(lead);
+    q.ok = true;
+}
+
 // orientation 0 from the bundle; 1 and 2 by stable counting sort
 static void build_copies(Graph& g, const HostGraph& hg, int w, bool adjoint) {
     const int64_t N = hg.hdr.n_ops;
@@ -534,7 +699,10 @@ static void build_copies(Graph& g, const HostGraph& hg, int w, bool adjoint) {
         std::vector<uint2> rec((size_t)E);
         for (int64_t e = 0; e < E; ++e)
             rec[e] = pack_record(rc[e], (uint32_t)ri[e], (uint32_t)rj[e]);
-        if (w == 0 && hg.hdr.algebra == CUT_ALG_MAJORANA) g.triple_groups = locality_order(hg, off, N, rec);
+        if (w == 0 && hg.hdr.algebra == CUT_ALG_MAJORANA) {
+            g.triple_groups = locality_order(hg, off, N, rec);
+            build_quadblocks(g, hg, off, rec);
+        }
         upload_csr(g, g.csr[w][0], N, std::vector<int64_t>(off, off + N + 1), rec);
     }
     if (!adjoint) return;
@@ -709,7 +877,7 @@ extern "C" cut_status cut_graph_info(cut_graph_t h, cut_graph_desc* d) {
 extern "C" cut_status cut_graph_set_tiling(cut_graph_t h, int64_t long_records, int64_t chunk_records,
                                            uint32_t flags) {
     try {
-        if (!h || long_records < 1 || chunk_records < 1 || (flags & ~15u))
+        if (!h || long_records < 1 || chunk_records < 1 || (flags & ~31u))
             CUT_FAIL(CUT_E_INVAL, "cut_graph_set_tiling: bad argument");
         Graph& g = *(Graph*)h;
         DeviceGuard dg(g.device);

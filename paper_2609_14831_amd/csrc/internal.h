@@ -121,6 +121,22 @@ struct ChunkTask {
     int32_t e1;
 };
 
+// Chunked form of a forward pass: chunk tasks (a range of one segment's
+// records, summed into a partial row), packed tasks over the remaining short
+// segments, and per chunked segment the partial-row slots [cstart[l],
+// cstart[l+1]) added in order into row crow[l].
+struct ChunkPlan {
+    ChunkTask* chunks = nullptr;
+    int64_t nchunks = 0;        // including the padding of the XCD split
+    Task* short_tasks = nullptr;
+    int64_t nshort = 0, short_per_xcd = 0;
+    int64_t* cstart = nullptr;  // device [nlong+1]
+    int32_t* crow = nullptr;    // device [nlong]
+    int64_t nlong = 0;
+    int64_t nslots = 0;         // partial rows
+    void release();
+};
+
 struct DevCSR {
     int64_t nseg = 0, nrec = 0, max_len = 0;
     int64_t* off = nullptr;     // device [nseg+1]
@@ -128,17 +144,10 @@ struct DevCSR {
     Task* tasks = nullptr;      // device [ntasks] (8*per_xcd when XCD-remapped)
     int64_t ntasks = 0;
     int64_t per_xcd = 0;        // >0: block b runs task (b%8)*per_xcd + b/8
-    // chunked form: long segments as chunk tasks (ordered by relative position
-    // in their segment, so concurrently running chunks sweep the same operand
-    // region), short segments as packed tasks
-    Task* short_tasks = nullptr;
-    int64_t nshort = 0, short_per_xcd = 0;
-    ChunkTask* chunks = nullptr;
-    int64_t nchunks = 0;
-    int64_t* cstart = nullptr;  // device [nlong+1]: slots of long segment l
-    int32_t* crow = nullptr;    // device [nlong]: its row
-    int64_t nlong = 0;
-    int64_t nslots = 0;         // partial rows (chunks of all segments)
+    // chunked form (forward passes over E_L): long segments as chunk tasks
+    // placed by relative position in their segment, so concurrently running
+    // chunks sweep the same operand region
+    ChunkPlan cp;
     std::vector<int64_t> off_h; // host copy of the offsets (tiling plan input)
     void release();
 };
@@ -164,6 +173,38 @@ struct TilePlan {
     int64_t nres_tasks = 0;
     int64_t res_per_xcd = 0;
     bool ok = false;
+    void release();
+};
+
+// Blocks of quadratic targets (Majorana registries).  Beyond its leading
+// quadratic x quadratic records, quadratic target {u, v} (u < v) holds, for
+// every triple T of modes outside {u, v} in lexicographic order, the record
+// pair (T+u, T+v), (T+v, T+u) -- checked record by record at load.  Modes are
+// grouped by 8; one workgroup owns the targets {u, v} with u in group g1 and v
+// in group g2 (g1 <= g2, at most 64) and a range of triples: per triple it
+// stages the <= 16 rows T+w of its modes in LDS, so each row feeds up to 16
+// records from LDS instead of 16 gathers, and the targets' sums stay in
+// registers across the range; each (target, range) sum is one partial row.
+// The records' factors are re-encoded at load as sign bits per (group pair,
+// wavefront, triple) with one common magnitude (checked against every record).
+struct QuadBlockPlan {
+    bool ok = false;
+    int32_t m = 0, ng = 0, nbp = 0, nr = 0;  // modes, mode groups, group pairs, triple ranges
+    int64_t ntrip = 0;
+    int32_t* row4 = nullptr;     // device [ntrip * m]: row of T+w, -1 when w is in T
+    uint64_t* tmask = nullptr;   // device [ntrip]: mode mask of triple T
+    int2* bpair = nullptr;       // device [nbp]: first modes of group 1 and group 2
+    uint32_t* sgn = nullptr;     // device [nbp * 8 * ntrip]: sign bits of the records of
+                                 // wavefront w's targets at triple T (2 per target: bit 2j
+                                 // for (T+u, T+v), bit 2j+1 for (T+v, T+u)), 1 = negative
+    float fmag = 0.f;            // common magnitude of those factors
+    std::vector<int32_t> qrow;   // host: quadratic target rows, by pair (u, v) as u * m + v
+    std::vector<int32_t> lead;   // host [N]: leading records of quadratic target rows
+    // per tiling (rebuilt with the task lists)
+    int32_t* tslot = nullptr;    // device [nbp * 64]: first block partial slot, -1 no target
+    ChunkPlan cp;                // leading records of the quadratic targets + the rest
+    bool active = false;         // plan built for the current tiling
+    void release_tiling();
     void release();
 };
 
@@ -209,6 +250,9 @@ struct Graph {
     std::vector<uint64_t> labels_h;  // registry labels (host copy)
     TilePlan tiles;
     int use_tiles = 0;
+    QuadBlockPlan qb;
+    int use_quadblocks = 0;
+    uint64_t tiling_gen = 0;         // bumped whenever task lists are rebuilt
     int use_chunks = 1;
     int64_t max_lds = 65536;         // LDS bytes one workgroup may allocate
     Workspace ws;                    // flow state and stage storage
@@ -271,6 +315,7 @@ size_t chunk_partial_bytes(const Graph& g, int32_t nsets, int32_t nops);
 // partial work area a forward pass of record set 0 needs (tiles or chunks)
 size_t forward_partial_bytes(const Graph& g, int32_t nsets, int32_t nops, int32_t precision);
 size_t tile_partial_bytes(const Graph& g, int32_t nsets, int32_t nops);
+bool quadblocks_usable(const Graph& g, int32_t nsets, int32_t nops, int32_t precision);
 void launch_forward(const Graph& g, int epi, const PassArgs& a, double* partials, hipStream_t s);
 
 void launch_g2(const Graph& g, double delta, int32_t nsets, const double* h, int64_t ldh,

@@ -752,7 +752,7 @@ __global__ __launch_bounds__(256) void k_chunk_combine(KArgs a, const double* __
 }
 
 template <int NOPS, int EPI>
-static void launch_chunk_combine_p(const KArgs& k, int prec, const DevCSR& c, const double* P, int64_t ldp,
+static void launch_chunk_combine_p(const KArgs& k, int prec, const ChunkPlan& c, const double* P, int64_t ldp,
                                    hipStream_t s) {
     const unsigned nb = (unsigned)((c.nlong * k.nsets + 255) / 256);
     switch (prec) {
@@ -764,7 +764,7 @@ static void launch_chunk_combine_p(const KArgs& k, int prec, const DevCSR& c, co
 }
 
 template <int EPI>
-static void launch_chunk_combine(const KArgs& k, int prec, const DevCSR& c, const double* P, int64_t ldp,
+static void launch_chunk_combine(const KArgs& k, int prec, const ChunkPlan& c, const double* P, int64_t ldp,
                                  hipStream_t s) {
     switch (k.nops) {
         case 1: launch_chunk_combine_p<1, EPI>(k, prec, c, P, ldp, s); break;
@@ -779,8 +779,10 @@ static void launch_chunk_combine(const KArgs& k, int prec, const DevCSR& c, cons
 }
 
 size_t chunk_partial_bytes(const Graph& g, int32_t nsets, int32_t nops) {
-    const DevCSR& c = g.csr[0][0];
-    return c.nchunks > 0 ? (size_t)c.nslots * nops * nsets * sizeof(double) : 0;
+    const ChunkPlan& c = g.csr[0][0].cp;
+    size_t slots = c.nlong > 0 ? (size_t)c.nslots : 0;
+    if (g.qb.active) slots = std::max(slots, (size_t)g.qb.cp.nslots);
+    return slots * nops * nsets * sizeof(double);
 }
 
 size_t forward_partial_bytes(const Graph& g, int32_t nsets, int32_t nops, int32_t precision) {
@@ -788,11 +790,217 @@ size_t forward_partial_bytes(const Graph& g, int32_t nsets, int32_t nops, int32_
     return chunk_partial_bytes(g, nsets, nops);
 }
 
+// ------------------------------------------------ quadratic-target blocks ----
+// One workgroup (8 wavefronts) per (group pair, triple range), 64 coefficient
+// sets per blockIdx.y.  Wavefront w owns mode u = g1 + w and the targets
+// {u, v}, v = g2 + j (j < 8, u < v); lane = set.  Per triple T of the range (in
+// lexicographic order) the rows T+w of the group modes are staged in LDS
+// ([slot][op columns, then eta][64 sets]); wavefront w stages slots 2w, 2w+1
+// (slot w on a diagonal pair) with one buffer load per 64-set run at a
+// uniform row offset, loading the next triple's rows during the current
+// triple's arithmetic and writing them to the other buffer.  Each live target
+// adds its two records (T+u, T+v), (T+v, T+u) from LDS; the factors are the
+// common magnitude with the sign bits of the plan.  Row indices and sign words
+// of 64 consecutive triples are fetched with one vector load and handed out by
+// readlane.  The sum of target j over the range is partial row tslot + r.
+struct QBArgs {
+    const int32_t* row4;
+    const uint64_t* tmask;
+    const int2* bpair;
+    const uint32_t* sgn;
+    const int32_t* tslot;
+    float fmag;
+    int32_t m, nr;
+    int64_t ntrip;
+    const void* A;
+    int64_t lda;
+    const void* B;
+    int64_t ldb;
+    int32_t nsets;
+    const int32_t* nsteps;
+    const int32_t* step;
+    double* part;
+    int64_t ldp;
+};
+
+template <int NOPS, int PREC>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k_qblock(QBArgs a) {
+    using T = typename PrecT<PREC>::T;
+    constexpr int ROW = (NOPS + 1) * 64;   // staged elements per row
+    extern __shared__ __align__(16) unsigned char qb_lds[];
+    T* lds = reinterpret_cast<T*>(qb_lds);  // [2][16][ROW]
+    const int bp = (int)(blockIdx.x / (unsigned)a.nr), r = (int)(blockIdx.x % (unsigned)a.nr);
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int lane = threadIdx.x & 63;
+    const int nsets = a.nsets;
+    const int s = (int)blockIdx.y * 64 + lane;
+    const int sl = s < nsets ? s : nsets - 1;
+    const int m = a.m;
+    const int2 gp = a.bpair[bp];
+    const bool diag = gp.x == gp.y;
+    const int64_t t0 = (int64_t)r * a.ntrip / a.nr, t1 = (int64_t)(r + 1) * a.ntrip / a.nr;
+    const int u = gp.x + wave;
+    const auto rsA = row_rsrc(a.A, 0x7FFFFFFF);
+    const auto rsB = row_rsrc(a.B, 0x7FFFFFFF);
+    const int32_t lda_b = (int32_t)(a.lda * (int64_t)sizeof(T)), ldb_b = (int32_t)(a.ldb * (int64_t)sizeof(T));
+    const uint32_t voff = (uint32_t)sl * (uint32_t)sizeof(T);
+    // staging slots of this wavefront and their modes
+    const int nmine = diag ? 1 : 2;
+    int smode[2];
+    int sslot[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        sslot[h] = diag ? wave : 2 * wave + h;
+        smode[h] = sslot[h] < 8 ? gp.x + sslot[h] : gp.y + (sslot[h] - 8);
+    }
+    int32_t slot[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) slot[j] = __builtin_amdgcn_readfirstlane(a.tslot[bp * 64 + wave * 8 + j]);
+    const float fpos = a.fmag;
+    const uint32_t* sgw = a.sgn + ((int64_t)bp * 8 + wave) * a.ntrip;
+    Acc<PREC> acc[8][NOPS];
+    // per-window (64 triples) lane data: row of each staging slot, sign word
+    int32_t rowv[2] = {-1, -1};
+    uint32_t sgv = 0;
+    auto window = [&](int64_t tw) {
+        const int64_t ti = tw + lane;
+        const bool in = ti < t1;
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+            rowv[h] = (in && h < nmine && smode[h] < m) ? a.row4[ti * m + smode[h]] : -1;
+        sgv = in ? sgw[ti] : 0u;
+    };
+    T nxt[2][NOPS + 1];
+    auto load_rows = [&](int64_t ti) {
+        const int li = (int)((ti - t0) & 63);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int32_t row = __builtin_amdgcn_readlane(rowv[h], li);
+            if (h < nmine && row >= 0) {
+#pragma unroll
+                for (int c = 0; c < NOPS; ++c) nxt[h][c] = buf_load<T>(rsB, voff, row * ldb_b + c * nsets * (int32_t)sizeof(T));
+                nxt[h][NOPS] = buf_load<T>(rsA, voff, row * lda_b);
+            }
+        }
+    };
+    auto store_rows = [&](int buf) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            if (h >= nmine) continue;
+            T* dst = lds + (buf * 16 + sslot[h]) * ROW + lane;
+#pragma unroll
+            for (int c = 0; c <= NOPS; ++c) dst[c * 64] = nxt[h][c];
+        }
+    };
+    if (t0 < t1) {
+        window(t0);
+        load_rows(t0);
+        store_rows(0);
+    }
+    __syncthreads();
+    for (int64_t ti = t0; ti < t1; ++ti) {
+        const int buf = (int)((ti - t0) & 1);
+        const int li = (int)((ti - t0) & 63);
+        const uint32_t sbits = (uint32_t)__builtin_amdgcn_readlane((int)sgv, li);
+        const bool more = ti + 1 < t1;
+        if (more) {
+            if (li == 63) window(ti + 1);
+            load_rows(ti + 1);
+        }
+        const uint64_t tmk = a.tmask[ti];
+        if (u < m && !((tmk >> u) & 1)) {
+            const T* lu = lds + (buf * 16 + wave) * ROW + lane;
+            const T eu = lu[NOPS * 64];
+            T xu[NOPS];
+#pragma unroll
+            for (int op = 0; op < NOPS; ++op) xu[op] = lu[op * 64];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int v = gp.y + j;
+                if (slot[j] < 0 || ((tmk >> v) & 1)) continue;
+                const T* lv = lds + (buf * 16 + (diag ? j : 8 + j)) * ROW + lane;
+                const T ev = lv[NOPS * 64];
+                const float f1 = (sbits >> (2 * j)) & 1u ? -fpos : fpos;      // record (T+u, T+v)
+                const float f2 = (sbits >> (2 * j + 1)) & 1u ? -fpos : fpos;  // record (T+v, T+u)
+                const auto tu = left_term<PREC>((double)f1, eu);
+                const auto tv = left_term<PREC>((double)f2, ev);
+#pragma unroll
+                for (int op = 0; op < NOPS; ++op) {
+                    acc[j][op].add(tu, lv[op * 64]);
+                    acc[j][op].add(tv, xu[op]);
+                }
+            }
+        }
+        if (more) store_rows(buf ^ 1);
+        __syncthreads();
+    }
+    const bool act = s < nsets && (a.nsteps == nullptr || a.nsteps[s] > *a.step);
+    if (!act) return;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        if (slot[j] < 0) continue;
+        double* P = a.part + (int64_t)(slot[j] + r) * a.ldp + s;
+#pragma unroll
+        for (int op = 0; op < NOPS; ++op) P[(int64_t)op * nsets] = acc[j][op].get();
+    }
+}
+
+static size_t qblock_lds_bytes(int32_t nops, int32_t precision) {
+    return (size_t)2 * 16 * (nops + 1) * 64 * (precision == CUT_F64 ? 8 : 4);
+}
+
+bool quadblocks_usable(const Graph& g, int32_t nsets, int32_t nops, int32_t precision) {
+    (void)nsets;
+    return g.qb.active && g.use_quadblocks && nops <= 5 && qblock_lds_bytes(nops, precision) <= 65536;
+}
+
+template <int NOPS>
+static void launch_qblock_n(const QBArgs& q, int prec, dim3 grid, size_t lds, hipStream_t s) {
+    switch (prec) {
+        case CUT_F64: hipLaunchKernelGGL((k_qblock<NOPS, CUT_F64>), grid, dim3(512), lds, s, q); break;
+        case CUT_F32X: hipLaunchKernelGGL((k_qblock<NOPS, CUT_F32X>), grid, dim3(512), lds, s, q); break;
+        case CUT_F32C: hipLaunchKernelGGL((k_qblock<NOPS, CUT_F32C>), grid, dim3(512), lds, s, q); break;
+        default: hipLaunchKernelGGL((k_qblock<NOPS, CUT_F32>), grid, dim3(512), lds, s, q); break;
+    }
+}
+
+static void launch_qblock(const Graph& g, const PassArgs& a, double* partials, int64_t ldp, hipStream_t s) {
+    const QuadBlockPlan& qp = g.qb;
+    QBArgs q{};
+    q.row4 = qp.row4;
+    q.tmask = qp.tmask;
+    q.bpair = qp.bpair;
+    q.sgn = qp.sgn;
+    q.tslot = qp.tslot;
+    q.fmag = qp.fmag;
+    q.m = qp.m;
+    q.nr = qp.nr;
+    q.ntrip = qp.ntrip;
+    q.A = a.A;
+    q.lda = a.lda;
+    q.B = a.B;
+    q.ldb = a.ldb;
+    q.nsets = a.nsets;
+    q.nsteps = a.nsteps;
+    q.step = a.step;
+    q.part = partials;
+    q.ldp = ldp;
+    dim3 grid((unsigned)(qp.nbp * qp.nr), (unsigned)((a.nsets + 63) / 64));
+    const size_t lds = qblock_lds_bytes(a.nops, a.precision);
+    switch (a.nops) {
+        case 1: launch_qblock_n<1>(q, a.precision, grid, lds, s); break;
+        case 2: launch_qblock_n<2>(q, a.precision, grid, lds, s); break;
+        case 3: launch_qblock_n<3>(q, a.precision, grid, lds, s); break;
+        case 4: launch_qblock_n<4>(q, a.precision, grid, lds, s); break;
+        default: launch_qblock_n<5>(q, a.precision, grid, lds, s); break;
+    }
+}
+
 // chunked forward pass: one launch whose first blocks sum long-segment chunks
 // into partial rows and whose other blocks run the short segments with the
 // epilogue; then the fixed-order combine of the partial rows with the epilogue
-static void launch_chunked(const Graph& g, int epi, const PassArgs& a, double* partials, hipStream_t s) {
-    const DevCSR& c = g.csr[0][0];
+static void launch_chunked(const Graph& g, const ChunkPlan& c, int epi, const PassArgs& a, double* partials,
+                           hipStream_t s, bool quad = false) {
     PassArgs r = a;
     r.tasks = c.short_tasks;
     r.ntasks = c.nshort;
@@ -803,13 +1011,16 @@ static void launch_chunked(const Graph& g, int epi, const PassArgs& a, double* p
     const int64_t ldp = (int64_t)a.nops * a.nsets;
     k.chunks = c.chunks;
     k.nchunks = c.nchunks;
-    k.nchunk_blocks = ((c.nchunks + 3) / 4 + 7) / 8 * 8;
+    k.nchunk_blocks = c.chunks ? ((c.nchunks + 3) / 4 + 7) / 8 * 8 : 0;
     k.part = partials;
     k.ldp = ldp;
     const int64_t nshort_blocks = c.short_per_xcd > 0 ? 8 * c.short_per_xcd : c.nshort;
-    dim3 grid((unsigned)(k.nchunk_blocks + nshort_blocks), ychunks);
-    if (epi == EPI_Y) launch_g<MODE_BCAST, EPI_Y>(k, a.precision, G, grid, s);
-    else launch_g<MODE_BCAST, EPI_RK>(k, a.precision, G, grid, s);
+    if (k.nchunk_blocks + nshort_blocks > 0) {
+        dim3 grid((unsigned)(k.nchunk_blocks + nshort_blocks), ychunks);
+        if (epi == EPI_Y) launch_g<MODE_BCAST, EPI_Y>(k, a.precision, G, grid, s);
+        else launch_g<MODE_BCAST, EPI_RK>(k, a.precision, G, grid, s);
+    }
+    if (quad) launch_qblock(g, a, partials, ldp, s);
     KArgs kc = make_kargs(a);
     if (epi == EPI_Y) launch_chunk_combine<EPI_Y>(kc, a.precision, c, partials, ldp, s);
     else launch_chunk_combine<EPI_RK>(kc, a.precision, c, partials, ldp, s);
@@ -875,7 +1086,8 @@ void launch_forward(const Graph& g, int epi, const PassArgs& a, double* partials
         return;
     }
     if (!tiles_usable(g, a.nsets, a.nops, a.precision)) {
-        if (g.csr[0][0].nchunks > 0) launch_chunked(g, epi, a, partials, s);
+        if (quadblocks_usable(g, a.nsets, a.nops, a.precision)) launch_chunked(g, g.qb.cp, epi, a, partials, s, true);
+        else if (g.csr[0][0].cp.nlong > 0) launch_chunked(g, g.csr[0][0].cp, epi, a, partials, s);
         else launch_pass(MODE_BCAST, epi, a, s);
         return;
     }
