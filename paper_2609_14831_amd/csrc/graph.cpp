@@ -55,6 +55,7 @@ void ChunkPlan::release() {
 void QuadBlockPlan::release_tiling() {
     dev_free(tslot);
     cp.release();
+    cp_lead.release();
     active = false;
 }
 
@@ -172,7 +173,7 @@ static int64_t lex_rank3(uint64_t t, int m) {
 // chunk of its leading records followed by qb.nr partial slots that the block
 // kernel fills; seg_slot[k] receives the first of those block slots.
 static void build_chunks(const Graph& g, const DevCSR& c, ChunkPlan& out, bool quad,
-                         std::vector<int64_t>* seg_slot = nullptr) {
+                         std::vector<int64_t>* seg_slot = nullptr, bool skip_quartic = false) {
     out.release();
     const std::vector<int64_t>& off = c.off_h;
     const int64_t lr = g.long_records, cr = std::max<int64_t>(1, g.chunk_records);
@@ -192,6 +193,10 @@ static void build_chunks(const Graph& g, const DevCSR& c, ChunkPlan& out, bool q
     if (seg_slot) seg_slot->assign(c.nseg, -1);
     for (int64_t k = 0; k < c.nseg; ++k) {
         const int64_t len = off[k + 1] - off[k];
+        if (skip_quartic && __builtin_popcountll(g.labels_h[k]) == 4) {
+            is_long[k] = 1;  // handled by the tile kernel: neither chunk nor short task
+            continue;
+        }
         const bool quart = fam && len > 0 && __builtin_popcountll(g.labels_h[k]) == 4;
         const bool qtarget = quad && __builtin_popcountll(g.labels_h[k]) == 2;
         if (!quart && !qtarget && len <= lr) continue;
@@ -317,6 +322,14 @@ static void build_qb_tiling(Graph& g, const DevCSR& c) {
     if (!q.ok || !g.use_quadblocks || !g.use_chunks || c.nrec >= (1ll << 31)) return;
     std::vector<int64_t> seg_slot;
     build_chunks(g, c, q.cp, true, &seg_slot);
+    if (g.use_tiles && g.tiles.ok) {
+        // same slots for the quadratic targets: their rows precede the quartic ones
+        std::vector<int64_t> seg_lead;
+        build_chunks(g, c, q.cp_lead, true, &seg_lead, true);
+        for (int64_t k = 0; k < c.nseg; ++k)
+            if (__builtin_popcountll(g.labels_h[k]) == 2 && seg_lead[k] != seg_slot[k])
+                CUT_FAIL(CUT_E_FORMAT, "quadratic-target blocks: slot numbering mismatch");
+    }
     const int m = q.m;
     std::vector<int32_t> tslot((size_t)q.nbp * 64, -1);
     int bp = 0;
@@ -484,18 +497,23 @@ static void build_tiles(Graph& g, const HostGraph& hg, const uint8_t* code) {
                 return;
             }
             if (fill[mt] >= RT) return;
+            // factor as the top half of its FP32 bit pattern (exact for int8)
+            const float f = (float)hg.rc[0][e];
+            uint32_t fb;
+            std::memcpy(&fb, &f, 4);
             rec[mt * RT + fill[mt]++] =
-                make_uint2(((uint32_t)code[(uint8_t)hg.rc[0][e]] << 24) | (uint32_t)quad,
-                           ((uint32_t)local(tau, q) << 1) | (uint32_t)orient);
+                make_uint2((uint32_t)quad, (fb & 0xFFFF0000u) | ((uint32_t)local(tau, q) << 1) | (uint32_t)orient);
         }
     }
     for (int64_t mt = 0; mt < ntiles * M; ++mt)
         if (fill[mt] != RT || rows[mt] < 0) return;
     // within each member: records whose generator is the quadratic row first
-    // (operand from LDS), then the others, each in stored order
+    // (operand from LDS), then the others, each in stored order; the two halves
+    // must be equal (every partner T+q contributes one record of each kind)
     for (int64_t mt = 0; mt < ntiles * M; ++mt) {
         uint2* r = rec.data() + mt * RT;
         std::stable_sort(r, r + RT, [](const uint2& x, const uint2& y) { return (x.y & 1u) < (y.y & 1u); });
+        if (RT % 2 != 0 || (r[RT / 2 - 1].y & 1u) != 0 || (r[RT / 2].y & 1u) != 1) return;
     }
     TilePlan& tp = g.tiles;
     tp.ntiles = ntiles;

@@ -156,11 +156,12 @@ struct DevCSR {
 // K pairs a quadratic string with a quartic K' sharing three modes tau = K & K'.
 // Tile tau owns the M = m-3 quartic rows tau+w (w not in tau): they are both the
 // tile's targets and the quartic operands of its records, so one workgroup
-// stages them in LDS once.  Record of member t: .x = (code << 24) | quadratic
-// row, .y = (local operand q << 1) | orient (0: generator from the quadratic
-// row, operand from LDS; 1: generator from LDS, operand from the quadratic
-// row).  Target tau+w receives its tile-tau sum in partial slot `slot` (the
-// position of w in K); the 4 slots are added in fixed order by the combine.
+// stages them in LDS once.  Record of member t: .x = quadratic row, .y =
+// (top half of the FP32 factor << 16) | (local operand q << 1) | orient (0:
+// generator from the quadratic row, operand from LDS; 1: generator from LDS,
+// operand from the quadratic row); the orient-0 records form the first half.
+// Target tau+w receives its tile-tau sum in partial slot `slot` (the position
+// of w in K); the 4 slots are added in fixed order by the combine.
 struct TilePlan {
     int64_t ntiles = 0;
     int32_t M = 0;             // members per tile
@@ -203,6 +204,7 @@ struct QuadBlockPlan {
     // per tiling (rebuilt with the task lists)
     int32_t* tslot = nullptr;    // device [nbp * 64]: first block partial slot, -1 no target
     ChunkPlan cp;                // leading records of the quadratic targets + the rest
+    ChunkPlan cp_lead;           // leading records only (quartic targets in tiles)
     bool active = false;         // plan built for the current tiling
     void release_tiling();
     void release();

@@ -645,8 +645,8 @@ __global__ __launch_bounds__(256) void k_tile(TileKArgs a) {
             T bv[U][NOPS];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                const int64_t quad = rr[u].x & 0xFFFFFFu;
-                const T* lrow = lds + (int)(rr[u].y >> 1) * per_row + sg;
+                const int64_t quad = rr[u].x;
+                const T* lrow = lds + (int)((rr[u].y >> 1) & 0x7FFFu) * per_row + sg;
                 if (rr[u].y & 1u) {  // generator from LDS, operand from the quadratic row
                     av[u] = lrow[NOPS * G];
                     const T* xr = X + quad * a.ldx;
@@ -660,7 +660,7 @@ __global__ __launch_bounds__(256) void k_tile(TileKArgs a) {
             }
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                const double cf = ok[u] ? a.ftab[rr[u].x >> 24] : 0.0;
+                const double cf = ok[u] ? (double)__builtin_bit_cast(float, rr[u].y & 0xFFFF0000u) : 0.0;
                 const auto tl = left_term<PREC>(cf, av[u]);
 #pragma unroll
                 for (int op = 0; op < NOPS; ++op) acc[op].add(tl, bv[u][op]);
@@ -677,6 +677,101 @@ __global__ __launch_bounds__(256) void k_tile(TileKArgs a) {
             double* P = a.P + (int64_t)a.slot[tile * M + t] * a.pstride + (int64_t)trows[t] * a.ldp + s;
 #pragma unroll
             for (int op = 0; op < NOPS; ++op) P[(int64_t)op * nsets] = v[op];
+        }
+    }
+}
+
+// Tile kernel for 64-set chunks (blockIdx.y): one workgroup of 8 wavefronts
+// per tile, lane = set.  The M member rows are staged in LDS ([member][op
+// columns, then eta][64 sets]) by wavefront-uniform 64-set runs through buffer
+// loads; wavefront w then takes members w, w+8, ...  A member's RT records (a
+// vector load of 64 at a time, handed out by readlane) come in two halves:
+// first generator = quadratic row (one gather) with the operand from LDS, then
+// generator from LDS with the operand = quadratic row (NOPS gathers); each
+// batch of U records issues its gathers before any arithmetic.
+template <int NOPS, int PREC>
+__global__ __launch_bounds__(512) void k_tile64(TileKArgs a) {
+    using T = typename PrecT<PREC>::T;
+    constexpr int ROW = (NOPS + 1) * 64;
+    constexpr int U = 4;
+    extern __shared__ __align__(16) unsigned char t64_lds[];
+    T* lds = reinterpret_cast<T*>(t64_lds);  // [M][ROW]
+    const int64_t tile = blockIdx.x;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int lane = threadIdx.x & 63;
+    const int nsets = a.nsets;
+    const int s = (int)blockIdx.y * 64 + lane;
+    const int sl = s < nsets ? s : nsets - 1;
+    const bool act = s < nsets && (a.nsteps == nullptr || a.nsteps[s] > *a.step);
+    const int M = a.M, RT = a.RT, half = RT / 2;
+    const int32_t* trows = a.rows + tile * M;
+    const auto rsH = row_rsrc(a.H, 0x7FFFFFFF);
+    const auto rsX = row_rsrc(a.X, 0x7FFFFFFF);
+    const int32_t lde_b = (int32_t)(a.lde * (int64_t)sizeof(T)), ldx_b = (int32_t)(a.ldx * (int64_t)sizeof(T));
+    const uint32_t voff = (uint32_t)sl * (uint32_t)sizeof(T);
+    for (int q = wave; q < M * (NOPS + 1); q += 8) {
+        const int mr = q / (NOPS + 1), c = q - mr * (NOPS + 1);
+        const int32_t grow = __builtin_amdgcn_readfirstlane(trows[mr]);
+        const T v = c < NOPS ? buf_load<T>(rsX, voff, grow * ldx_b + c * nsets * (int32_t)sizeof(T))
+                             : buf_load<T>(rsH, voff, grow * lde_b);
+        lds[mr * ROW + c * 64 + lane] = v;
+    }
+    __syncthreads();
+    for (int t = wave; t < M; t += 8) {
+        const uint2* tr = a.rec + (tile * M + t) * (int64_t)RT;
+        Acc<PREC> acc[NOPS];
+        uint2 mine = tr[lane < RT ? lane : RT - 1];
+        int base = 0;  // first record held in `mine`
+        auto rec_at = [&](int r, uint32_t& x, uint32_t& y) {
+            if (r - base >= 64) {
+                base += 64;
+                mine = tr[base + lane < RT ? base + lane : RT - 1];
+            }
+            x = (uint32_t)__builtin_amdgcn_readlane((int)mine.x, r - base);
+            y = (uint32_t)__builtin_amdgcn_readlane((int)mine.y, r - base);
+        };
+        // first half: generator = quadratic row eta, operand from LDS
+        for (int r0 = 0; r0 < half; r0 += U) {
+            uint32_t rx[U], ry[U];
+            T gv[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                rec_at(r0 + u < half ? r0 + u : half - 1, rx[u], ry[u]);
+                gv[u] = buf_load<T>(rsH, voff, (int32_t)rx[u] * lde_b);
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const uint32_t fb = r0 + u < half ? (ry[u] & 0xFFFF0000u) : 0u;
+                const auto tl = left_term<PREC>((double)__builtin_bit_cast(float, fb), gv[u]);
+                const T* lrow = lds + (int)((ry[u] >> 1) & 0x7FFFu) * ROW + lane;
+#pragma unroll
+                for (int op = 0; op < NOPS; ++op) acc[op].add(tl, lrow[op * 64]);
+            }
+        }
+        // second half: generator from LDS, operand = quadratic row
+        for (int r0 = half; r0 < RT; r0 += U) {
+            uint32_t rx[U], ry[U];
+            T bv[U][NOPS];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                rec_at(r0 + u < RT ? r0 + u : RT - 1, rx[u], ry[u]);
+#pragma unroll
+                for (int op = 0; op < NOPS; ++op)
+                    bv[u][op] = buf_load<T>(rsX, voff, (int32_t)rx[u] * ldx_b + op * nsets * (int32_t)sizeof(T));
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const uint32_t fb = r0 + u < RT ? (ry[u] & 0xFFFF0000u) : 0u;
+                const T* lrow = lds + (int)((ry[u] >> 1) & 0x7FFFu) * ROW + lane;
+                const auto tl = left_term<PREC>((double)__builtin_bit_cast(float, fb), lrow[NOPS * 64]);
+#pragma unroll
+                for (int op = 0; op < NOPS; ++op) acc[op].add(tl, bv[u][op]);
+            }
+        }
+        if (act) {
+            double* P = a.P + (int64_t)a.slot[tile * M + t] * a.pstride + (int64_t)trows[t] * a.ldp + s;
+#pragma unroll
+            for (int op = 0; op < NOPS; ++op) P[(int64_t)op * nsets] = acc[op].get();
         }
     }
 }
@@ -716,7 +811,12 @@ __global__ __launch_bounds__(256) void k_combine(KArgs a, const double* __restri
 // sets per tile workgroup: 16 for narrow batches, else 32 (each gathered run
 // of one operand column is a full 128-byte line; two workgroups per 64 sets
 // keep the staged rows small enough for several workgroups per CU)
-static int tile_width(int nsets) { return nsets <= 16 ? 16 : 32; }
+// sets per tile workgroup: 64 (the 8-wavefront kernel) when the member rows of
+// 64 sets fit in 64 KiB of LDS, else 32 or 16
+static int tile_width(const Graph& g, int nsets, int nops, int prec) {
+    if (nsets > 32 && (size_t)g.tiles.M * (nops + 1) * 64 * (prec == CUT_F64 ? 8 : 4) <= 65536) return 64;
+    return nsets <= 16 ? 16 : 32;
+}
 
 // Long segments: the partial rows of their chunks [cstart[l], cstart[l+1])
 // added in chunk order, then the epilogue on row crow[l].
@@ -785,8 +885,14 @@ size_t chunk_partial_bytes(const Graph& g, int32_t nsets, int32_t nops) {
     return slots * nops * nsets * sizeof(double);
 }
 
+static bool quad_and_tiles(const Graph& g, int32_t nsets, int32_t nops, int32_t precision);
+
 size_t forward_partial_bytes(const Graph& g, int32_t nsets, int32_t nops, int32_t precision) {
-    if (tiles_usable(g, nsets, nops, precision)) return tile_partial_bytes(g, nsets, nops);
+    if (tiles_usable(g, nsets, nops, precision)) {
+        size_t b = tile_partial_bytes(g, nsets, nops);
+        if (quad_and_tiles(g, nsets, nops, precision)) b += (size_t)g.qb.cp_lead.nslots * nops * nsets * sizeof(double);
+        return b;
+    }
     return chunk_partial_bytes(g, nsets, nops);
 }
 
@@ -1027,12 +1133,18 @@ static void launch_chunked(const Graph& g, const ChunkPlan& c, int epi, const Pa
 }
 
 static size_t tile_lds_bytes(const Graph& g, int32_t nsets, int32_t nops, int32_t prec) {
-    return (size_t)g.tiles.M * (nops + 1) * tile_width(nsets) * (prec == CUT_F64 ? 8 : 4);
+    return (size_t)g.tiles.M * (nops + 1) * tile_width(g, nsets, nops, prec) * (prec == CUT_F64 ? 8 : 4);
 }
 
 bool tiles_usable(const Graph& g, int32_t nsets, int32_t nops, int32_t precision) {
     return g.tiles.ok && g.use_tiles && nsets >= 8 &&
            (int64_t)tile_lds_bytes(g, nsets, nops, precision) <= g.max_lds;
+}
+
+// partial rows of the forward pass with quadratic-target blocks and tiles: the
+// block plan's slots, then 4 tile slots per row
+static bool quad_and_tiles(const Graph& g, int32_t nsets, int32_t nops, int32_t precision) {
+    return quadblocks_usable(g, nsets, nops, precision) && g.qb.cp_lead.nlong > 0;
 }
 
 size_t tile_partial_bytes(const Graph& g, int32_t nsets, int32_t nops) {
@@ -1046,7 +1158,8 @@ static void launch_tile_k(const TileKArgs& t, dim3 grid, size_t lds, hipStream_t
 
 template <int NOPS, int PREC>
 static void launch_tile_g(const TileKArgs& t, int G, dim3 grid, size_t lds, hipStream_t s) {
-    if (G == 16) launch_tile_k<16, NOPS, PREC>(t, grid, lds, s);
+    if (G == 64) hipLaunchKernelGGL((k_tile64<NOPS, PREC>), grid, dim3(512), lds, s, t);
+    else if (G == 16) launch_tile_k<16, NOPS, PREC>(t, grid, lds, s);
     else launch_tile_k<32, NOPS, PREC>(t, grid, lds, s);
 }
 
@@ -1092,14 +1205,22 @@ void launch_forward(const Graph& g, int epi, const PassArgs& a, double* partials
         return;
     }
     const TilePlan& tp = g.tiles;
-    // quadratic targets (all their records) through the segment kernel
-    PassArgs r = a;
-    r.tasks = tp.res_tasks;
-    r.ntasks = tp.nres_tasks;
-    r.per_xcd = tp.res_per_xcd;
-    if (tp.nres_tasks > 0) launch_pass(MODE_BCAST, epi, r, s);
+    const int64_t ldp = (int64_t)a.nops * a.nsets;
+    double* tpart = partials;
+    if (quad_and_tiles(g, a.nsets, a.nops, a.precision)) {
+        // quadratic targets: leading records (chunks) + blocks, own partial rows
+        launch_chunked(g, g.qb.cp_lead, epi, a, partials, s, true);
+        tpart = partials + g.qb.cp_lead.nslots * ldp;
+    } else {
+        // quadratic targets (all their records) through the segment kernel
+        PassArgs r = a;
+        r.tasks = tp.res_tasks;
+        r.ntasks = tp.nres_tasks;
+        r.per_xcd = tp.res_per_xcd;
+        if (tp.nres_tasks > 0) launch_pass(MODE_BCAST, epi, r, s);
+    }
     // quartic targets: tiles into partial slots, then the fixed-order combine
-    const int G = tile_width(a.nsets);
+    const int G = tile_width(g, a.nsets, a.nops, a.precision);
     TileKArgs t{};
     t.rows = tp.rows;
     t.slot = tp.slot;
@@ -1114,8 +1235,8 @@ void launch_forward(const Graph& g, int epi, const PassArgs& a, double* partials
     t.nsets = a.nsets;
     t.nsteps = a.nsteps;
     t.step = a.step;
-    t.P = partials;
-    t.ldp = (int64_t)a.nops * a.nsets;
+    t.P = tpart;
+    t.ldp = ldp;
     t.pstride = g.N * t.ldp;
     const KArgs k = make_kargs(a);
     dim3 grid((unsigned)tp.ntiles, (unsigned)((a.nsets + G - 1) / G));

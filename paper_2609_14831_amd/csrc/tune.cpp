@@ -101,15 +101,16 @@ extern "C" cut_status cut_graph_autotune(cut_graph_t h, int64_t nsets, int64_t n
         const int64_t lr = 1024;
         const int64_t crs[] = {64, 128, 256, 512};
         const uint32_t shapes[] = {0u, CUT_TILE_TRIPLE_CHUNKS, CUT_TILE_NO_CHUNKS, CUT_TILE_TRIPLES,
-                                   CUT_TILE_QUAD_BLOCKS, CUT_TILE_QUAD_BLOCKS | CUT_TILE_TRIPLE_CHUNKS};
+                                   CUT_TILE_QUAD_BLOCKS, CUT_TILE_QUAD_BLOCKS | CUT_TILE_TRIPLE_CHUNKS,
+                                   CUT_TILE_QUAD_BLOCKS | CUT_TILE_TRIPLES};
         for (int64_t cr : crs)
             for (uint32_t xr = 0; xr <= 1; ++xr)
                 for (uint32_t shape : shapes) {
                     if ((shape & CUT_TILE_TRIPLES) && !g.tiles.ok) continue;
                     if ((shape & CUT_TILE_TRIPLE_CHUNKS) && !g.triple_groups) continue;
                     if ((shape & CUT_TILE_QUAD_BLOCKS) && !g.qb.ok) continue;
-                    // the chunk length does not change the unchunked and tile forms
-                    if ((shape & (CUT_TILE_NO_CHUNKS | CUT_TILE_TRIPLES)) && cr != crs[0]) continue;
+                    // the chunk length does not change the unchunked, tile and block forms
+                    if ((shape & (CUT_TILE_NO_CHUNKS | CUT_TILE_TRIPLES | CUT_TILE_QUAD_BLOCKS)) && cr != crs[3]) continue;
                     const uint32_t flags = (xr ? CUT_TILE_XCD_REMAP : 0u) | shape;
                     apply_tiling(g, lr, cr, flags);
                     for (int pr : precs) {

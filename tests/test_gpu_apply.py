@@ -75,9 +75,9 @@ PRECS = ["F64", "F32X", "F32C", "F32"]
 # 16-record chunks with XCD remap; shared-triple tiles; four-wavefront split (no
 # chunks); shared-triple chunks of quartic targets (one or two triples a chunk,
 # with and without XCD remap); quadratic-target blocks (alone, with remap, with
-# triple chunks)
+# triple chunks, with shared-triple tiles)
 TILINGS = [(1024, 512, 0), (16, 16, 1), (64, 64, 3), (64, 64, 4), (1024, 8, 9), (16, 32, 9), (1024, 128, 8),
-           (1024, 512, 16), (1024, 512, 17), (1024, 16, 25)]
+           (1024, 512, 16), (1024, 512, 17), (1024, 16, 25), (1024, 512, 18), (64, 64, 19)]
 
 
 @pytest.mark.parametrize("tiling", TILINGS)
@@ -120,7 +120,7 @@ def test_apply_bitwise_deterministic(L):
     g = U.graph(L, "majorana", 16)
     og = oracle_graph("majorana", 16)
     eta, x = _inputs(og.N, 16, 3, seed=9)
-    for tiling in ((32, 32, 1), (1024, 16, 9), (1024, 512, 17)):
+    for tiling in ((32, 32, 1), (1024, 16, 9), (1024, 512, 17), (1024, 512, 19)):
         L.cut_graph_set_tiling(g, *tiling)
         for P in (L.CUT_F64, L.CUT_F32C):
             a = _run_apply(L, g, P, eta, x, 16, 3)

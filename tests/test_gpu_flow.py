@@ -55,15 +55,22 @@ def test_epq_wegner_flow_full_config(L):
     np.testing.assert_allclose(np.linalg.eigvalsh(H), np.linalg.eigvalsh(H0), atol=1e-7)
 
 
+# default chunked form; quadratic-target blocks; blocks + shared-triple tiles
+FLOW_TILINGS = [(1024, 512, 0), (1024, 512, 17), (1024, 512, 19)]
+
+
+@pytest.mark.parametrize("tiling", FLOW_TILINGS)
 @pytest.mark.parametrize("prec", ["F64", "F32X", "F32C"])
-def test_majorana_flow_ragged(L, prec):
-    U.say(f"[flow] majorana m=12 ragged {prec}")
+def test_majorana_flow_ragged(L, prec, tiling):
+    U.say(f"[flow] majorana m=12 ragged {prec} tiling {tiling}")
     m = 12
     g = U.graph(L, "majorana", m)
+    L.cut_graph_set_tiling(g, *tiling)
     og = A.majorana_graph(m)
     z0 = workloads.small_majorana(m, 5, 3, seed=21)
     ns = np.array([40, 0, 17, 40, 3], dtype=np.int32)
     z, _ = _flow(L, g, z0, ns, L.CUT_GEN_G2, getattr(L, "CUT_" + prec), 1e-2)
+    L.cut_graph_set_tiling(g, 1024, 512, 0)
     gen, _ = OG.make_generator(og, "g2", 0.5)
     zr, _ = OF.integrate(og, gen, z0, 1e-2, ns)
     np.testing.assert_array_equal(z[:, :, 1], z0[:, :, 1])   # zero steps: untouched
@@ -73,14 +80,37 @@ def test_majorana_flow_ragged(L, prec):
             assert r < (1e-13 if prec == "F64" else 1e-7), (s, op, r)
 
 
-def test_flow_graph_replay_matches_stream_path(L):
+@pytest.mark.parametrize("tiling", FLOW_TILINGS)
+def test_majorana_flow_many_sets(L, tiling):
+    """40 ragged sets x 2 operands (64-lane form, tiles usable), F32C, hipGraph."""
+    U.say(f"[flow] majorana m=12 40 sets tiling {tiling}")
+    m = 12
+    g = U.graph(L, "majorana", m)
+    L.cut_graph_set_tiling(g, *tiling)
+    og = A.majorana_graph(m)
+    z0 = workloads.small_majorana(m, 40, 2, seed=23)
+    ns = np.array([(7 * b) % 23 + 1 for b in range(40)], dtype=np.int32)
+    z, _ = _flow(L, g, z0, ns, L.CUT_GEN_G2, L.CUT_F32C, 1e-2)
+    L.cut_graph_set_tiling(g, 1024, 512, 0)
+    gen, _ = OG.make_generator(og, "g2", 0.5)
+    zr, _ = OF.integrate(og, gen, z0, 1e-2, ns)
+    for s in range(40):
+        for op in range(2):
+            r = _rel(z[:, op, s], zr[:, op, s])
+            assert r < 1e-7, (s, op, r)
+
+
+@pytest.mark.parametrize("tiling", FLOW_TILINGS)
+def test_flow_graph_replay_matches_stream_path(L, tiling):
     m = 10
     g = U.graph(L, "majorana", m)
+    L.cut_graph_set_tiling(g, *tiling)
     z0 = workloads.small_majorana(m, 4, 2, seed=8)
     ns = [25, 10, 25, 1]
     a, _ = _flow(L, g, z0, ns, L.CUT_GEN_G2, L.CUT_F32C, 1e-2, flags=L.CUT_FLOW_HIPGRAPH)
     b, _ = _flow(L, g, z0, ns, L.CUT_GEN_G2, L.CUT_F32C, 1e-2, flags=0)
     c, _ = _flow(L, g, z0, ns, L.CUT_GEN_G2, L.CUT_F32C, 1e-2, flags=L.CUT_FLOW_HIPGRAPH)
+    L.cut_graph_set_tiling(g, 1024, 512, 0)
     assert np.array_equal(a, b) and np.array_equal(a, c)
 
 
