@@ -688,12 +688,13 @@ __global__ __launch_bounds__(256) void k_tile(TileKArgs a) {
 // vector load of 64 at a time, handed out by readlane) come in two halves:
 // first generator = quadratic row (one gather) with the operand from LDS, then
 // generator from LDS with the operand = quadratic row (NOPS gathers); each
-// batch of U records issues its gathers before any arithmetic.
+// batch of 4 records issues its gathers before any arithmetic.
 template <int NOPS, int PREC>
 __global__ __launch_bounds__(512) void k_tile64(TileKArgs a) {
     using T = typename PrecT<PREC>::T;
     constexpr int ROW = (NOPS + 1) * 64;
-    constexpr int U = 4;
+    constexpr int UA = 4;  // records per batch, first half (one gather each)
+    constexpr int U = 4;   // records per batch, second half (NOPS gathers each)
     extern __shared__ __align__(16) unsigned char t64_lds[];
     T* lds = reinterpret_cast<T*>(t64_lds);  // [M][ROW]
     const int64_t tile = blockIdx.x;
@@ -731,16 +732,16 @@ __global__ __launch_bounds__(512) void k_tile64(TileKArgs a) {
             y = (uint32_t)__builtin_amdgcn_readlane((int)mine.y, r - base);
         };
         // first half: generator = quadratic row eta, operand from LDS
-        for (int r0 = 0; r0 < half; r0 += U) {
-            uint32_t rx[U], ry[U];
-            T gv[U];
+        for (int r0 = 0; r0 < half; r0 += UA) {
+            uint32_t rx[UA], ry[UA];
+            T gv[UA];
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
+            for (int u = 0; u < UA; ++u) {
                 rec_at(r0 + u < half ? r0 + u : half - 1, rx[u], ry[u]);
                 gv[u] = buf_load<T>(rsH, voff, (int32_t)rx[u] * lde_b);
             }
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
+            for (int u = 0; u < UA; ++u) {
                 const uint32_t fb = r0 + u < half ? (ry[u] & 0xFFFF0000u) : 0u;
                 const auto tl = left_term<PREC>((double)__builtin_bit_cast(float, fb), gv[u]);
                 const T* lrow = lds + (int)((ry[u] >> 1) & 0x7FFFu) * ROW + lane;
