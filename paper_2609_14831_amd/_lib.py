@@ -18,6 +18,11 @@ if not os.path.exists(LIB_PATH):
     raise ImportError(
         f"libcutgraph.so not built at {LIB_PATH}; run `python -c 'import __graft_entry__ as g; g.build()'`")
 
+# torch ships its own HIP and HSA runtimes; loading it first makes the library
+# bind to those (same sonames) instead of bringing a second runtime into the
+# process, which leaves one of the two without a device
+import torch  # noqa: E402,F401
+
 _L = C.CDLL(LIB_PATH)
 
 # status codes / enums (mirror include/cutgraph.h)
