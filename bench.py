@@ -248,6 +248,7 @@ def main():
     alt = {"f32c": "f32x", "f32x": "f32c"}.get(args.precision)
     if alt:
         PALT = {"f32c": L.CUT_F32C, "f32x": L.CUT_F32X}[alt]
+        alt_tuning = L.cut_graph_autotune(g, w.nsets, w.nops, PALT, 0) if args.long_records <= 0 else None
         za = torch.tensor(inp.z0, device=dev).contiguous()
         p = L.flow_params(L.CUT_GEN_G2, PALT, w.ds, w.delta, 0, flags=L.CUT_FLOW_HIPGRAPH,
                           step_begin=0, step_end=W)
@@ -260,7 +261,7 @@ def main():
         torch.cuda.synchronize()
         alt_wall = time.perf_counter() - t0
         out["alt_precision"] = {"precision": alt, "value": contributions / alt_wall,
-                                "ms_per_step": alt_wall * 1e3 / K}
+                                "ms_per_step": alt_wall * 1e3 / K, "tiling": alt_tuning}
         log(f"{alt}: {alt_wall * 1e3 / K:.3f} ms/step")
         del za
 

@@ -252,12 +252,14 @@ cut_status cut_graph_set_tiling(cut_graph_t g, int64_t long_records, int64_t chu
 
 /* Autotuner: times the forward graph pass for (nsets, nops) over candidate
  * tilings (chunk length 64/128/256/512 records, XCD remap off/on, triple
- * chunks, no chunks, shared-triple tiles where available; long-target
- * threshold 1024) and, when `precision` is CUT_F32C or CUT_F32X and
- * `allow_other_float` != 0, over both compensated float modes; applies the
- * fastest tiling to the graph and returns the choice.  It allocates temporary
- * operand buffers (zero-filled) and synchronises the device.  Results are cached
- * per (nsets, nops, precision, allow_other_float).
+ * chunks, no chunks, shared-triple tiles and quadratic-target blocks where
+ * available; long-target threshold 1024) and, when `precision` is CUT_F32C or
+ * CUT_F32X and `allow_other_float` != 0, over both compensated float modes;
+ * applies the fastest tiling to the graph (a candidate must beat the best so
+ * far, starting with the graph's current tiling, by at least 2 %) and returns
+ * the choice.  It allocates temporary operand buffers (zero-filled) and
+ * synchronises the device.  Results are cached per (nsets, nops, precision,
+ * allow_other_float).
  * Errors: CUT_E_INVAL, CUT_E_NOMEM, CUT_E_DEVICE. */
 typedef struct {
     int64_t long_records;
