@@ -45,7 +45,7 @@ double time_pass(Graph& g, int prec, int32_t nsets, int32_t nops, const void* et
     p.ldy = (int64_t)nops * nsets;
     p.scale = 1.0;
     for (int w = 0; w < 2; ++w) launch_forward(g, EPI_Y, p, partials, s);  // warm
-    const int reps = 5;
+    const int reps = 3;
     HIP_CHECK(hipEventRecord(e0, s));
     for (int r = 0; r < reps; ++r) launch_forward(g, EPI_Y, p, partials, s);
     HIP_CHECK(hipEventRecord(e1, s));
@@ -95,13 +95,18 @@ extern "C" cut_status cut_graph_autotune(cut_graph_t h, int64_t nsets, int64_t n
         HIP_CHECK(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
         HIP_CHECK(hipEventCreate(&e0));
         HIP_CHECK(hipEventCreate(&e1));
-        // the incumbent is the configuration the graph had; a candidate replaces
-        // the best only when at least 2 % faster, so near-ties keep a stable choice
-        cut_tuning best{g.long_records, g.chunk_records, tiling_flags(g), precision, 1e30, 0.0};
-        best.default_ms = time_pass(g, precision, (int32_t)nsets, (int32_t)nops, eta.p, x.p, (double*)y.p,
-                                    partials(precision), s, e0, e1);
-        best.pass_ms = best.default_ms;
-        const double gain = 0.98;
+        // Candidates (the graph's current tiling first) are timed round-robin
+        // over 3 rounds and compared by their median, so clock drift during
+        // tuning affects all of them alike; a candidate replaces the best only
+        // when at least 2 % faster, so near-ties keep a stable choice.
+        struct Cand {
+            int64_t lr, cr;
+            uint32_t flags;
+            int prec;
+            double ms[3];
+        };
+        std::vector<Cand> cands;
+        cands.push_back({g.long_records, g.chunk_records, tiling_flags(g), precision, {0, 0, 0}});
         const int64_t lr = 1024;
         const int64_t crs[] = {64, 128, 256, 512};
         const uint32_t shapes[] = {0u, CUT_TILE_TRIPLE_CHUNKS, CUT_TILE_NO_CHUNKS, CUT_TILE_TRIPLES,
@@ -116,13 +121,23 @@ extern "C" cut_status cut_graph_autotune(cut_graph_t h, int64_t nsets, int64_t n
                     // the chunk length does not change the unchunked, tile and block forms
                     if ((shape & (CUT_TILE_NO_CHUNKS | CUT_TILE_TRIPLES | CUT_TILE_QUAD_BLOCKS)) && cr != crs[3]) continue;
                     const uint32_t flags = (xr ? CUT_TILE_XCD_REMAP : 0u) | shape;
-                    apply_tiling(g, lr, cr, flags);
-                    for (int pr : precs) {
-                        const double ms = time_pass(g, pr, (int32_t)nsets, (int32_t)nops, eta.p, x.p, (double*)y.p,
-                                                    partials(pr), s, e0, e1);
-                        if (ms < gain * best.pass_ms) best = cut_tuning{lr, cr, flags, pr, ms, best.default_ms};
-                    }
+                    for (int pr : precs) cands.push_back({lr, cr, flags, pr, {0, 0, 0}});
                 }
+        for (int round = 0; round < 3; ++round)
+            for (Cand& c : cands) {
+                apply_tiling(g, c.lr, c.cr, c.flags);
+                c.ms[round] = time_pass(g, c.prec, (int32_t)nsets, (int32_t)nops, eta.p, x.p, (double*)y.p,
+                                        partials(c.prec), s, e0, e1);
+            }
+        auto median = [](const double* v) { return std::max(std::min(v[0], v[1]), std::min(std::max(v[0], v[1]), v[2])); };
+        const Cand& c0 = cands[0];
+        cut_tuning best{c0.lr, c0.cr, c0.flags, c0.prec, median(c0.ms), median(c0.ms)};
+        const double gain = 0.98;
+        for (size_t i = 1; i < cands.size(); ++i) {
+            const double ms = median(cands[i].ms);
+            if (ms < gain * best.pass_ms)
+                best = cut_tuning{cands[i].lr, cands[i].cr, cands[i].flags, cands[i].prec, ms, best.default_ms};
+        }
         apply_tiling(g, best.long_records, best.chunk_records, best.tiling_flags);
         HIP_CHECK(hipEventDestroy(e0));
         HIP_CHECK(hipEventDestroy(e1));
