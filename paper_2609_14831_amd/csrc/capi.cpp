@@ -41,7 +41,6 @@ void eval_generator(Graph& g, int kind, double delta, int32_t nsets, const doubl
     } else {
         PassArgs p{};
         p.csr = &g.csr[1][0];
-        p.ftab = g.ftab;
         p.A = h;
         p.lda = ldh;
         p.B = h;
@@ -80,7 +79,6 @@ void eval_generator_vjp(Graph& g, int kind, double delta, int32_t nsets, const d
     // eta_k = s_g sum c h_i h_j over E_eta: d/dh_i via the i-grouped copy,
     // d/dh_j via the j-grouped copy, both accumulated into g_h
     PassArgs p{};
-    p.ftab = g.ftab;
     p.nsets = nsets;
     p.nops = 1;
     p.precision = CUT_F64;
@@ -132,7 +130,6 @@ extern "C" cut_status cut_graph_apply(cut_graph_t h, int32_t which, int32_t prec
     DeviceGuard dg(g.device);
     PassArgs p{};
     p.csr = &g.csr[which][0];
-    p.ftab = g.ftab;
     p.A = eta;
     p.lda = lde;
     p.B = x;
@@ -169,7 +166,6 @@ extern "C" cut_status cut_graph_apply_adjoint(cut_graph_t h, int32_t which, int3
         CUT_FAIL(CUT_E_INVAL, "cut_graph_apply_adjoint: bad x / g_eta");
     DeviceGuard dg(g.device);
     PassArgs p{};
-    p.ftab = g.ftab;
     p.nsets = (int32_t)nsets;
     p.nops = (int32_t)nops;
     p.precision = precision;

@@ -141,7 +141,6 @@ static void enqueue_step(const StepPlan& P, hipStream_t s, PassTimer* tm = nullp
         if (tm) tm->mark(1, s);
         PassArgs p{};
         p.csr = &g.csr[0][0];
-        p.ftab = g.ftab;
         p.A = P.fb.eta;
         p.lda = P.nsets;
         p.B = P.xin[st];
@@ -283,7 +282,6 @@ static void jt(Graph& g, const cut_flow_params* p, int32_t nsets, int32_t nops, 
     const int64_t cols = (int64_t)nops * nsets;
     eval_generator(g, p->generator, p->delta, nsets, Z, cols, eta, nsets, false, nsteps, step, s);
     PassArgs a{};
-    a.ftab = g.ftab;
     a.nsets = nsets;
     a.nops = nops;
     a.precision = CUT_F64;

@@ -831,13 +831,11 @@ extern "C" cut_status cut_graph_load(const char* path, int32_t dev, uint32_t fla
         g->N = N;
         g->gen_sign = hg.hdr.gen_sign;
         g->nfactors = (int)ftab.size();
-        // 256 FP64 factors, then the same 256 factors in FP32 (exact: small integers)
-        g->ftab = dev_alloc<double>(256 + 128);
+        // factor dictionary of the G2 stencil tables (the record streams carry
+        // their factors themselves)
+        g->ftab = dev_alloc<double>(256);
         ftab.resize(256, 0.0);
-        std::vector<double> both(256 + 128, 0.0);
-        std::copy(ftab.begin(), ftab.end(), both.begin());
-        for (int v = 0; v < 256; ++v) reinterpret_cast<float*>(both.data() + 256)[v] = (float)ftab[v];
-        HIP_CHECK(hipMemcpy(g->ftab, both.data(), both.size() * sizeof(double), hipMemcpyHostToDevice));
+        HIP_CHECK(hipMemcpy(g->ftab, ftab.data(), 256 * sizeof(double), hipMemcpyHostToDevice));
         const bool adj = (flags & CUT_LOAD_ADJOINT) != 0;
         g->labels_h.assign(hg.labels, hg.labels + N);
         build_copies(*g, hg, 0, adj);

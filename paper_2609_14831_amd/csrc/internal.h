@@ -225,7 +225,7 @@ struct Graph {
     int64_t N = 0;
     double gen_sign = 1.0;
     int nfactors = 0;
-    double* ftab = nullptr;          // device [256] FP64 factors, then [256] FP32 copies
+    double* ftab = nullptr;          // device [256]: factor dictionary of the stencil tables
     // record streams: [set][orientation] set 0 = E_L, 1 = E_eta;
     // orientation 0 = by target k (a=i, b=j), 1 = by right input j (a=i, b=k),
     // 2 = by left input i (a=k, b=j)
@@ -281,7 +281,6 @@ struct PassArgs {
     const Task* tasks = nullptr;    // overrides csr's task list when set
     int64_t ntasks = 0;
     int64_t per_xcd = 0;
-    const double* ftab;
     const void* A;
     int64_t lda;
     const void* B;

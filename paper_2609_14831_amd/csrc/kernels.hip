@@ -31,7 +31,6 @@ struct KArgs {
     int64_t per_xcd;  // >0: task = (bid % 8) * per_xcd + bid / 8
     const int64_t* off;
     const uint2* rec;
-    const double* ftab;
     const void* A;
     int64_t lda;
     const void* B;
@@ -527,7 +526,6 @@ static KArgs make_kargs(const PassArgs& p) {
     k.per_xcd = p.tasks ? p.per_xcd : c.per_xcd;
     k.off = c.off;
     k.rec = c.rec;
-    k.ftab = p.ftab;
     k.A = p.A;
     k.lda = p.lda;
     k.B = p.B;
@@ -580,7 +578,6 @@ struct TileKArgs {
     const int32_t* rows;
     const uint8_t* slot;
     const uint2* rec;
-    const double* ftab;
     int32_t M, RT;
     const void* H;
     int64_t lde;
@@ -710,12 +707,29 @@ __global__ __launch_bounds__(512) void k_tile64(TileKArgs a) {
     const auto rsX = row_rsrc(a.X, 0x7FFFFFFF);
     const int32_t lde_b = (int32_t)(a.lde * (int64_t)sizeof(T)), ldx_b = (int32_t)(a.ldx * (int64_t)sizeof(T));
     const uint32_t voff = (uint32_t)sl * (uint32_t)sizeof(T);
-    for (int q = wave; q < M * (NOPS + 1); q += 8) {
-        const int mr = q / (NOPS + 1), c = q - mr * (NOPS + 1);
-        const int32_t grow = __builtin_amdgcn_readfirstlane(trows[mr]);
-        const T v = c < NOPS ? buf_load<T>(rsX, voff, grow * ldx_b + c * nsets * (int32_t)sizeof(T))
-                             : buf_load<T>(rsH, voff, grow * lde_b);
-        lds[mr * ROW + c * 64 + lane] = v;
+    // staging in batches of 16 runs per wavefront: all loads of a batch are in
+    // flight before the first LDS store
+    constexpr int SB = 16;
+    const int nruns = M * (NOPS + 1);
+    for (int q0 = wave; q0 < nruns; q0 += 8 * SB) {
+        T v[SB];
+#pragma unroll
+        for (int k = 0; k < SB; ++k) {
+            const int q = q0 + 8 * k;
+            const int qc = q < nruns ? q : nruns - 1;
+            const int mr = qc / (NOPS + 1), c = qc - mr * (NOPS + 1);
+            const int32_t grow = __builtin_amdgcn_readfirstlane(trows[mr]);
+            v[k] = c < NOPS ? buf_load<T>(rsX, voff, grow * ldx_b + c * nsets * (int32_t)sizeof(T))
+                            : buf_load<T>(rsH, voff, grow * lde_b);
+        }
+#pragma unroll
+        for (int k = 0; k < SB; ++k) {
+            const int q = q0 + 8 * k;
+            if (q < nruns) {
+                const int mr = q / (NOPS + 1), c = q - mr * (NOPS + 1);
+                lds[mr * ROW + c * 64 + lane] = v[k];
+            }
+        }
     }
     __syncthreads();
     for (int t = wave; t < M; t += 8) {
@@ -1226,7 +1240,6 @@ void launch_forward(const Graph& g, int epi, const PassArgs& a, double* partials
     t.rows = tp.rows;
     t.slot = tp.slot;
     t.rec = tp.rec;
-    t.ftab = a.ftab;
     t.M = tp.M;
     t.RT = tp.RT;
     t.H = a.A;

@@ -33,7 +33,6 @@ double time_pass(Graph& g, int prec, int32_t nsets, int32_t nops, const void* et
                  double* partials, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
     PassArgs p{};
     p.csr = &g.csr[0][0];
-    p.ftab = g.ftab;
     p.A = eta;
     p.lda = nsets;
     p.B = x;

@@ -77,13 +77,22 @@ def test_cfg3_two_rk4_steps_every_coefficient(L, cfg3, cfg3_oracle):
     g, w, inp = cfg3
     U.say("[cfg3] oracle 2 RK4 steps on 64 sets x 5 operands")
     zr, _ = native.Engine(cfg3_oracle, "g2", w.delta).flow(inp.z0, w.ds, [2] * w.nsets)
-    for name, tol in (("F32C", 1e-7), ("F32X", 1e-7), ("F64", 1e-11)):
-        U.say(f"[cfg3] GPU 2 steps {name}")
+    # each precision in the tiling the benchmark's autotuner picks for it (F32C
+    # first: the fixture tuned it), F32X also with quadratic-target blocks + tiles
+    runs = (("F32C", 1e-7, None), ("F32X", 1e-7, "auto"), ("F32X", 1e-7, (1024, 512, 19)), ("F64", 1e-11, None))
+    for name, tol, tiling in runs:
+        if tiling == "auto":
+            U.say(f"[cfg3] autotuned {L.cut_graph_autotune(g, w.nsets, w.nops, L.CUT_F32X, 0)}")
+        elif tiling is not None:
+            L.cut_graph_set_tiling(g, *tiling)
+        U.say(f"[cfg3] GPU 2 steps {name} tiling {tiling}")
         z = _flow(L, g, inp.z0, inp.n_steps, getattr(L, "CUT_" + name), w, steps=2)
         r = _rel_cols(z - inp.z0, zr - inp.z0)
         U.say(f"[cfg3] {name}: max relative error of the 2-step increment {r:.3e}")
         assert _rel_cols(z, zr) < tol
         assert r < (1e-6 if name != "F64" else 1e-10)
+    t = L.cut_graph_autotune(g, w.nsets, w.nops, L.CUT_F32C, 0)   # cached: restores the F32C tiling
+    L.cut_graph_set_tiling(g, t["long_records"], t["chunk_records"], t["tiling_flags"])
 
 
 @pytest.mark.timeout(300)
