@@ -16,12 +16,16 @@ docstring:
   grouped by target; an action is a sum over the target's records.
 * Sec. 2.4, Eqs. (forward-coeff), (dual), (duality-invariant) and the graph-level
   adjoint paragraph: the adjoint accumulates the same factor into the input
-  coordinate.
+  coordinate; Eq. (directional-derivative): the derivative of one action is the
+  induced generator variation plus the linear response to the operand.
 
 Modules:
   algebra   registries and contribution records, from the operator algebra
   graph     forward action, the two adjoint traversals
-  gen       generators (Wegner graph pass; G2 normalised Wegner; G1 literal)
+  gen       generators (Wegner graph pass; G2 normalised Wegner), their JVPs
+            and VJPs
+  deriv     directional derivative and transpose of one projected action
+            (Eq. directional-derivative), pairing defect, finite-difference scan
   flow      classic RK4 coflow, ragged sets, discrete adjoint with checkpoints
   native    ctypes wrapper of ``ref_engine.c`` (plain C loops for large graphs)
   ds_select power iteration used to fix the integration step

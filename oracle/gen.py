@@ -35,6 +35,22 @@ def wegner_graph(g: Graph, h: np.ndarray) -> np.ndarray:
     return g.gen_sign * out
 
 
+def wegner_graph_jvp(g: Graph, h: np.ndarray, dh: np.ndarray) -> np.ndarray:
+    """Directional derivative of wegner_graph along dh.  The generator is a
+    bilinear function of (Dh, (I-D)h), so by the product rule (the derivative of
+    the generator that Eq. directional-derivative calls for) it is
+    W(D dh, (I-D)h) + W(Dh, (I-D) dh)."""
+    ge = g.eta_records()
+    dmask = g.diag[:, None]
+    a0, b0 = np.where(dmask, h, 0.0), np.where(dmask, 0.0, h)
+    a1, b1 = np.where(dmask, dh, 0.0), np.where(dmask, 0.0, dh)
+    contrib = ge.c[:, None] * (a1[ge.i] * b0[ge.j] + a0[ge.i] * b1[ge.j])
+    out = np.zeros_like(h)
+    for s in range(h.shape[1]):
+        out[:, s] = np.bincount(ge.k, weights=contrib[:, s], minlength=g.N)
+    return g.gen_sign * out
+
+
 def wegner_graph_vjp(g: Graph, h: np.ndarray, gbar: np.ndarray) -> np.ndarray:
     ge = g.eta_records()
     dmask = g.diag.astype(float)
@@ -84,6 +100,23 @@ class G2:
         eta[self.reg.diag] = 0.0
         return eta
 
+    def jvp(self, h: np.ndarray, dh: np.ndarray) -> np.ndarray:
+        """Directional derivative of eta along dh by the quotient rule:
+        d eta_S = (dN_S Q_S - N_S dQ_S) / Q_S^2 with
+        dN_S = -sum_a c (d eps_a h_partner + eps_a dh_partner) and
+        dQ_S = 8 sum_a eps_a d eps_a; zero on block-diagonal strings."""
+        N, Q = self._nq(h)
+        dN = np.zeros_like(h)
+        dQ = np.zeros_like(h)
+        for a, (S, P, c) in enumerate(self.stencil):
+            pa = self.reg.pairs[a]
+            eps, deps = h[pa][None, :], dh[pa][None, :]
+            dN[S] += -c[:, None] * (deps * h[P] + eps * dh[P])
+            dQ[S] += 8.0 * eps * deps
+        out = (dN * Q - N * dQ) / (Q * Q)
+        out[self.reg.diag] = 0.0
+        return out
+
     def vjp(self, h: np.ndarray, gbar: np.ndarray) -> np.ndarray:
         """d/dh of sum(gbar * eta(h)) by the product and quotient rules."""
         N, Q = self._nq(h)
@@ -108,4 +141,13 @@ def make_generator(g: Graph, kind: str, delta: float = 0.5):
     if kind == "g2":
         gen = G2(g.size, delta)
         return gen, gen.vjp
+    raise ValueError(kind)
+
+
+def make_generator_jvp(g: Graph, kind: str, delta: float = 0.5):
+    """Returns jvp(h, dh) = eta'(h) dh for the named generator."""
+    if kind == "wegner_graph":
+        return lambda h, dh: wegner_graph_jvp(g, h, dh)
+    if kind == "g2":
+        return G2(g.size, delta).jvp
     raise ValueError(kind)
