@@ -61,7 +61,10 @@ typedef enum {
 /* Record sets stored in a graph (Eq. graph-actions). */
 typedef enum {
     CUT_GRAPH_FLOW = 0,     /* E_L: the retained action F_k(h, x) */
-    CUT_GRAPH_GEN = 1       /* E_eta: block-generator records (left input diagonal) */
+    CUT_GRAPH_GEN = 1,      /* E_eta: block-generator records (left input diagonal) */
+    CUT_GRAPH_OUTSIDE = 2   /* E_C: the optional outside-space action C_q(h, x)
+                               (Eq. projected-flow; Eq. graph-actions, third line);
+                               targets are the outside registry rows */
 } cut_which;
 
 /* Arithmetic of a graph pass. */
@@ -84,6 +87,7 @@ typedef enum {
                                  + delta^2 (the diagonal of ad_{H_0}^2) */
 } cut_generator_kind;
 
+#define CUT_BUILD_OUTSIDE 1u  /* build flags: also compile the outside-space records */
 #define CUT_ACCUMULATE   1u   /* apply flags: y += result instead of y = result */
 #define CUT_LOAD_ADJOINT 1u   /* load flags: also build the input-sorted copies */
 #define CUT_LOAD_NO_CHECKSUM 2u /* load flags: skip section checksums (bounds are
@@ -96,6 +100,8 @@ typedef struct {
     int64_t n_records;      /* |E_L| */
     int64_t n_gen_records;  /* |E_eta| */
     int64_t n_pairs;        /* diagonal quadratic coordinates (pair energies) */
+    int64_t n_out_ops;      /* outside registry size (0 without E_C) */
+    int64_t n_out_records;  /* |E_C| */
     uint64_t checksum;      /* combined checksum of the record sections */
     int64_t file_bytes;     /* bundle size on disk */
     double build_seconds;   /* compiler wall time (cut_graph_build only) */
@@ -110,11 +116,19 @@ typedef struct {
  * bundle holds the registry labels, block mask, pair list, rules identifier,
  * factor precision (int8), the target-grouped records of E_L and E_eta and one
  * checksum per section.  Two builds are bitwise identical.
+ * With CUT_BUILD_OUTSIDE (Majorana, m <= 32) the bundle also holds the outside
+ * registry (every 6-subset of the modes, lexicographic) and the target-grouped
+ * records E_C of the degree-6 part of [eta, X] that the projection drops
+ * (Eq. projected-flow): two quartics sharing one mode, 20 (m - 6) records per
+ * outside target.  They never feed the flow; they give the diagnostic action
+ * C_q (Eq. graph-actions, third line).
  * `threads` <= 0 selects the hardware concurrency.  `desc` (nullable) receives
- * the sizes.  Errors: CUT_E_INVAL (unknown algebra, size out of range: E_pq
- * 1..64, Majorana even 4..64), CUT_E_IO, CUT_E_NOMEM. */
+ * the sizes.  Errors: CUT_E_INVAL (unknown algebra or flag, size out of range:
+ * E_pq 1..64, Majorana even 4..64; CUT_BUILD_OUTSIDE with E_pq, whose registry
+ * is closed), CUT_E_UNSUPPORTED (CUT_BUILD_OUTSIDE above 32 modes), CUT_E_IO,
+ * CUT_E_NOMEM. */
 cut_status cut_graph_build(int32_t algebra, int32_t size, const char* path, int32_t threads,
-                           cut_graph_desc* desc);
+                           uint32_t flags, cut_graph_desc* desc);
 
 /* ------------------------------------------------------------------- load --
  * cut_graph_load: map and validate a bundle (magic, version, header checksum,
@@ -122,7 +136,9 @@ cut_status cut_graph_build(int32_t algebra, int32_t size, const char* path, int3
  * monotone and complete, every index < N, every factor nonzero), then upload
  * the target-sorted record stream to `hip_device` (Sec. 2.3: validated reload).
  * With CUT_LOAD_ADJOINT the input-sorted copies used by the adjoint are built
- * too.  On success *out owns all device memory; release with cut_graph_free.
+ * too.  Outside-space records, when the bundle has them, are uploaded in their
+ * target order (forward action only).  On success *out owns all device memory;
+ * release with cut_graph_free.
  * Errors: CUT_E_IO, CUT_E_FORMAT, CUT_E_CHECKSUM, CUT_E_NOMEM, CUT_E_DEVICE,
  * CUT_E_UNSUPPORTED (N >= 2^24 or more than 256 distinct factors). */
 cut_status cut_graph_load(const char* path, int32_t hip_device, uint32_t flags, cut_graph_t* out);
@@ -136,7 +152,9 @@ void cut_graph_free(cut_graph_t g);
  * for 0 <= k < N, 0 <= op < nops, 0 <= s < nsets.  eta and x are double* for
  * CUT_F64 and float* otherwise; y is always double*.  Requires nsets >= 1,
  * 1 <= nops <= 8, lde >= nsets, ldx >= nops*nsets, ldy >= nops*nsets.
- * y must not alias eta or x. */
+ * y must not alias eta or x.  With which = CUT_GRAPH_OUTSIDE, y has one row per
+ * outside registry entry (n_out_ops rows; CUT_E_INVAL if the bundle has no
+ * outside-space records). */
 cut_status cut_graph_apply(cut_graph_t g, int32_t which, int32_t precision, int64_t nsets,
                            int64_t nops, const void* eta, int64_t lde, const void* x,
                            int64_t ldx, double* y, int64_t ldy, uint32_t flags, void* stream);
@@ -146,7 +164,8 @@ cut_status cut_graph_apply(cut_graph_t g, int32_t which, int32_t precision, int6
  *   g_x[j][op*nsets+s]  (=|+=) sum_{e: j_e=j} c_e * eta[i_e][s] * w[k_e][op*nsets+s]
  *   g_eta[i][s]         (=|+=) sum_{e: i_e=i} c_e * sum_op w[k_e][op*nsets+s] * x[j_e][op*nsets+s]
  * Either output may be NULL (then its inputs may be NULL too).  Needs a graph
- * loaded with CUT_LOAD_ADJOINT (else CUT_E_INVAL).  Types as cut_graph_apply. */
+ * loaded with CUT_LOAD_ADJOINT (else CUT_E_INVAL).  Types as cut_graph_apply.
+ * which = CUT_GRAPH_OUTSIDE is not supported (CUT_E_INVAL). */
 cut_status cut_graph_apply_adjoint(cut_graph_t g, int32_t which, int32_t precision, int64_t nsets,
                                    int64_t nops, const void* eta, int64_t lde, const void* x,
                                    int64_t ldx, const void* w, int64_t ldw, double* g_x,
@@ -164,6 +183,54 @@ cut_status cut_generator(cut_graph_t g, int32_t kind, double delta, int64_t nset
 cut_status cut_generator_vjp(cut_graph_t g, int32_t kind, double delta, int64_t nsets,
                              const double* h, int64_t ldh, const double* gbar, int64_t ldg,
                              double* g_h, int64_t ldgh, void* stream);
+
+/* ------------------------------------------------------------ derivatives --
+ * Derivatives of one projected action F(h, x) = L(eta(h)) x (Sec. 2.4,
+ * Eq. directional-derivative): h is the Hamiltonian column that defines the
+ * generator ([N][nsets], double), x the operand ([N][nops*nsets], double, in
+ * the layout of cut_graph_apply).  x is independent of h here; to differentiate
+ * the Hamiltonian's own right-hand side pass h also as operand 0 and dh also as
+ * its tangent.  The generator is `kind` with regulariser `delta` as in
+ * cut_generator.
+ *
+ * cut_generator_jvp: deta[r][s] = sum_q (d eta_r / d h_q) dh[q][s] (double,
+ * FP64 arithmetic): the quotient rule for CUT_GEN_G2, the product rule over the
+ * E_eta records for CUT_GEN_WEGNER_GRAPH.  Errors as cut_generator. */
+cut_status cut_generator_jvp(cut_graph_t g, int32_t kind, double delta, int64_t nsets,
+                             const double* h, int64_t ldh, const double* dh, int64_t lddh,
+                             double* deta, int64_t ldde, void* stream);
+
+/* cut_graph_jvp: the directional derivative (Eq. directional-derivative)
+ *   dy = apply(eta'(h) dh, x) + apply(eta(h), dx)
+ * (the induced generator variation plus the linear response), and, when y is
+ * not NULL, the action itself y = apply(eta(h), x).  Either tangent may be NULL
+ * (a zero direction; not both); x may be NULL only when dh and y are.  All
+ * pointers are double device memory; ld* are leading dimensions in elements
+ * (ldh, lddh >= nsets; ldx, lddx, ldy, lddy >= nops*nsets).  The generator and
+ * its derivative are FP64; the graph passes use `precision` (for the float
+ * modes eta, eta'(h) dh, x and dx are rounded to float once).  Outputs are
+ * overwritten and must not alias an input.  Uses the forward tiling of
+ * cut_graph_set_tiling and a work area kept in the handle (grown on demand,
+ * synchronising).  Errors: CUT_E_INVAL, CUT_E_UNSUPPORTED (G2 without a
+ * pair-flip registry), CUT_E_NOMEM, CUT_E_DEVICE. */
+cut_status cut_graph_jvp(cut_graph_t g, int32_t kind, double delta, int32_t precision, int64_t nsets,
+                         int64_t nops, const double* h, int64_t ldh, const double* dh, int64_t lddh,
+                         const double* x, int64_t ldx, const double* dx, int64_t lddx, double* y,
+                         int64_t ldy, double* dy, int64_t lddy, void* stream);
+
+/* cut_graph_vjp: the transpose of cut_graph_jvp for a cotangent w of F
+ * ([N][nops*nsets], double):
+ *   g_x (=|+=) L(eta(h))^T w                     (records grouped by right input)
+ *   g_h (=|+=) eta'(h)^T geta,  geta[i][s] = sum_{e: i_e=i} c_e sum_op w[k_e][op*nsets+s] x[j_e][op*nsets+s]
+ * (records grouped by left input, then the generator VJP); `=|+=` follows
+ * CUT_ACCUMULATE in flags.  Either output may be NULL (not both); x may be NULL
+ * when g_h is.  Passes use `precision` (w, x and eta rounded to float once in
+ * the float modes); the generator VJP is FP64.  Needs a graph loaded with
+ * CUT_LOAD_ADJOINT.  Outputs must not alias an input.  Errors as cut_graph_jvp. */
+cut_status cut_graph_vjp(cut_graph_t g, int32_t kind, double delta, int32_t precision, int64_t nsets,
+                         int64_t nops, const double* h, int64_t ldh, const double* x, int64_t ldx,
+                         const double* w, int64_t ldw, double* g_h, int64_t ldgh, double* g_x,
+                         int64_t ldgx, uint32_t flags, void* stream);
 
 /* ------------------------------------------------------------------- flow --
  * Coflow of H and nops-1 observables (Eq. coflow; Eq. forward-coeff) with the

@@ -235,6 +235,84 @@ def majorana_closed_form_counts(m: int) -> Tuple[int, int, int]:
     return q, f, comb(m, 2) * q + comb(m, 4) * f
 
 
+# ----------------------------------------------------------------------------
+# Outside-space records E_C (Majorana strings)
+# ----------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class OutsideGraph:
+    """Records of the outside-space action C (Eq. projected-flow, C_X =
+    (I - P)[eta, X]; Eq. graph-actions, third line): target q indexes the
+    outside registry (here every 6-subset, lexicographic), inputs i and j the
+    operator registry.  Grouped by q, then (i, j)."""
+
+    size: int
+    N: int                  # operator registry size (inputs)
+    n_out: int              # outside registry size (targets)
+    k: np.ndarray
+    i: np.ndarray
+    j: np.ndarray
+    c: np.ndarray
+    masks: np.ndarray       # uint64 [n_out]
+
+    @property
+    def E(self) -> int:
+        return int(self.k.size)
+
+    def offsets(self) -> np.ndarray:
+        cnt = np.bincount(self.k, minlength=self.n_out)
+        return np.concatenate([[0], np.cumsum(cnt)]).astype(np.int64)
+
+
+def majorana_outside_masks(m: int) -> np.ndarray:
+    """Every 6-subset of the m modes as a bitmask, lexicographic."""
+    out = []
+    for S in itertools.combinations(range(m), 6):
+        v = 0
+        for a in S:
+            v |= 1 << a
+        out.append(v)
+    return np.array(out, dtype=np.uint64)
+
+
+def majorana_outside_graph(m: int, targets: Optional[np.ndarray] = None) -> OutsideGraph:
+    """The degree-6 part of [i Gamma_A, Gamma_B] over all registry pairs.
+
+    Brute force per outside target Q over the left input A: B = A xor Q must be
+    a registry string that anticommutes with A, and the factor is the bracket
+    coefficient.  Two even strings of degree <= 4 reach degree 6 only as two
+    quartics sharing one mode, so every stored pair is of that kind; the test
+    suite checks the completeness against dense commutators.
+    """
+    reg = MajoranaRegistry(m)
+    omasks = majorana_outside_masks(m)
+    tl = np.arange(omasks.size) if targets is None else np.asarray(targets, dtype=np.int64)
+    ks, is_, js, cs = [], [], [], []
+    A = reg.masks
+    for t in tl:
+        B = A ^ omasks[t]
+        dB = _popcount(B)
+        keep = ((dB == 2) | (dB == 4)) & ((_popcount(A & B) % 2) == 1)
+        ii = np.nonzero(keep)[0].astype(np.int64)
+        jj = reg.index_of(B[ii])
+        assert np.all(jj >= 0)
+        ks.append(np.full(ii.size, t, dtype=np.int64))
+        is_.append(ii)
+        js.append(jj)
+        cs.append(bracket_coeff(A[ii], B[ii], m))
+    cat = (lambda parts, dt: np.concatenate(parts).astype(dt) if parts else np.zeros(0, dt))
+    return OutsideGraph(m, reg.N, int(omasks.size), cat(ks, np.int64), cat(is_, np.int64),
+                        cat(js, np.int64), cat(cs, np.float64), omasks)
+
+
+def majorana_outside_count(m: int) -> int:
+    """|E_C| by counting: a 6-subset Q splits into an ordered pair of triples
+    (T1, T2) in C(6,3) = 20 ways, and the shared mode s is any of the m - 6
+    modes outside Q: records (T1+s, T2+s)."""
+    from math import comb
+    return 20 * (m - 6) * comb(m, 6)
+
+
 def graph_for(algebra: str, size: int) -> Graph:
     if algebra == "epq":
         return epq_graph(size)

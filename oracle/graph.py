@@ -9,6 +9,8 @@ operand column of a set uses that set's eta.
 * adjoint_x    g_x[j] = sum_{e : j_e = j} c_e eta_{i_e} w_{k_e}   (the adjoint
                traversal accumulates into the input coordinate, Sec. 2.4)
 * adjoint_eta  g_eta[i] = sum_{e : i_e = i} c_e sum_op w_{k_e} x_{j_e}
+* apply_outside  C_q = sum_{e in E_C(q)} c_e eta_{i_e} x_{j_e}   (the optional
+               outside-space action, Eq. graph-actions third line)
 
 All factors are real, so the conjugation of the adjoint is the identity.
 """
@@ -41,6 +43,12 @@ def adjoint_x(g: Graph, eta: np.ndarray, w: np.ndarray) -> np.ndarray:
 def adjoint_eta(g: Graph, w: np.ndarray, x: np.ndarray) -> np.ndarray:
     contrib = g.c[:, None] * np.sum(w[g.k] * x[g.j], axis=1)
     return _scatter(g.i, contrib, g.N)
+
+
+def apply_outside(og, eta: np.ndarray, x: np.ndarray) -> np.ndarray:
+    """C [n_out, nops, nsets] for an OutsideGraph ``og``."""
+    contrib = og.c[:, None, None] * eta[og.i][:, None, :] * x[og.j]
+    return _scatter(og.k, contrib, og.n_out)
 
 
 def apply_rows(g: Graph, eta: np.ndarray, x: np.ndarray, rows: np.ndarray) -> np.ndarray:

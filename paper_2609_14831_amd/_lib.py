@@ -29,7 +29,8 @@ _L = C.CDLL(LIB_PATH)
 CUT_OK, CUT_E_INVAL, CUT_E_IO, CUT_E_FORMAT, CUT_E_CHECKSUM = 0, 1, 2, 3, 4
 CUT_E_NOMEM, CUT_E_DEVICE, CUT_E_NUMERIC, CUT_E_UNSUPPORTED = 5, 6, 7, 8
 CUT_ALG_EPQ, CUT_ALG_MAJORANA = 1, 2
-CUT_GRAPH_FLOW, CUT_GRAPH_GEN = 0, 1
+CUT_GRAPH_FLOW, CUT_GRAPH_GEN, CUT_GRAPH_OUTSIDE = 0, 1, 2
+CUT_BUILD_OUTSIDE = 1
 CUT_F64, CUT_F32C, CUT_F32X, CUT_F32 = 0, 1, 2, 3
 CUT_GEN_WEGNER_GRAPH, CUT_GEN_G2 = 1, 2
 CUT_ACCUMULATE = 1
@@ -46,6 +47,7 @@ STATUS_NAMES = {0: "CUT_OK", 1: "CUT_E_INVAL", 2: "CUT_E_IO", 3: "CUT_E_FORMAT",
 # symbols declared in include/cutgraph.h
 EXPORTS = ["cut_graph_build", "cut_graph_load", "cut_graph_info", "cut_graph_free",
            "cut_graph_apply", "cut_graph_apply_adjoint", "cut_generator", "cut_generator_vjp",
+           "cut_generator_jvp", "cut_graph_jvp", "cut_graph_vjp",
            "cut_flow_integrate", "cut_flow_adjoint", "cut_graph_set_tiling", "cut_graph_autotune",
            "cut_flow_last_timing", "cut_last_error", "cut_version"]
 
@@ -59,7 +61,7 @@ class CutError(RuntimeError):
 class cut_graph_desc(C.Structure):
     _fields_ = [("algebra", C.c_int32), ("size", C.c_int32), ("n_ops", C.c_int64),
                 ("n_records", C.c_int64), ("n_gen_records", C.c_int64), ("n_pairs", C.c_int64),
-                ("checksum", C.c_uint64), ("file_bytes", C.c_int64), ("build_seconds", C.c_double),
+                ("n_out_ops", C.c_int64), ("n_out_records", C.c_int64), ("checksum", C.c_uint64), ("file_bytes", C.c_int64), ("build_seconds", C.c_double),
                 ("identifier", C.c_char * 96)]
 
     def as_dict(self):
@@ -75,7 +77,7 @@ class cut_flow_params(C.Structure):
 
 
 _vp, _i32, _i64, _u32, _dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_uint32, C.c_double
-_L.cut_graph_build.argtypes = [_i32, _i32, C.c_char_p, _i32, C.POINTER(cut_graph_desc)]
+_L.cut_graph_build.argtypes = [_i32, _i32, C.c_char_p, _i32, _u32, C.POINTER(cut_graph_desc)]
 _L.cut_graph_load.argtypes = [C.c_char_p, _i32, _u32, C.POINTER(_vp)]
 _L.cut_graph_info.argtypes = [_vp, C.POINTER(cut_graph_desc)]
 _L.cut_graph_free.argtypes = [_vp]
@@ -85,6 +87,11 @@ _L.cut_graph_apply_adjoint.argtypes = [_vp, _i32, _i32, _i64, _i64, _vp, _i64, _
                                        _vp, _i64, _vp, _i64, _u32, _vp]
 _L.cut_generator.argtypes = [_vp, _i32, _dbl, _i64, _vp, _i64, _vp, _i64, _vp]
 _L.cut_generator_vjp.argtypes = [_vp, _i32, _dbl, _i64, _vp, _i64, _vp, _i64, _vp, _i64, _vp]
+_L.cut_generator_jvp.argtypes = [_vp, _i32, _dbl, _i64, _vp, _i64, _vp, _i64, _vp, _i64, _vp]
+_L.cut_graph_jvp.argtypes = [_vp, _i32, _dbl, _i32, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _i64, _vp, _i64,
+                             _vp, _i64, _vp, _i64, _vp]
+_L.cut_graph_vjp.argtypes = [_vp, _i32, _dbl, _i32, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _i64, _vp, _i64,
+                             _vp, _i64, _u32, _vp]
 _L.cut_flow_integrate.argtypes = [_vp, C.POINTER(cut_flow_params), _i64, _i64, C.POINTER(_i32), _vp, _vp,
                                   _vp]
 _L.cut_flow_adjoint.argtypes = [_vp, C.POINTER(cut_flow_params), _i64, _i64, C.POINTER(_i32), _vp, _vp, _vp]
@@ -152,9 +159,10 @@ def _stream(stream):
 
 
 # ---------------------------------------------------------------- compile --
-def cut_graph_build(algebra: int, size: int, path: str, threads: int = 0) -> dict:
+def cut_graph_build(algebra: int, size: int, path: str, threads: int = 0, flags: int = 0) -> dict:
+    """flags: CUT_BUILD_OUTSIDE to include the outside-space records."""
     d = cut_graph_desc()
-    _check(_L.cut_graph_build(algebra, size, path.encode(), threads, C.byref(d)))
+    _check(_L.cut_graph_build(algebra, size, path.encode(), threads, flags, C.byref(d)))
     return d.as_dict()
 
 
@@ -206,6 +214,31 @@ def cut_generator(g: int, kind: int, delta: float, nsets: int, h, eta, stream=No
 def cut_generator_vjp(g: int, kind: int, delta: float, nsets: int, h, gbar, g_h, stream=None) -> None:
     _check(_L.cut_generator_vjp(g, kind, delta, nsets, _ptr(h), _ld(h, nsets), _ptr(gbar),
                                 _ld(gbar, nsets), _ptr(g_h), _ld(g_h, nsets), _stream(stream)))
+
+
+# ------------------------------------------------------------ derivatives --
+def cut_generator_jvp(g: int, kind: int, delta: float, nsets: int, h, dh, deta, stream=None) -> None:
+    _check(_L.cut_generator_jvp(g, kind, delta, nsets, _ptr(h), _ld(h, nsets), _ptr(dh), _ld(dh, nsets),
+                                _ptr(deta), _ld(deta, nsets), _stream(stream)))
+
+
+def cut_graph_jvp(g: int, kind: int, delta: float, precision: int, nsets: int, nops: int, h, dh, x, dx,
+                  y, dy, stream=None) -> None:
+    """dy = apply(eta'(h) dh, x) + apply(eta(h), dx); y = apply(eta(h), x) when given.
+    dh, dx, x and y may be None as the C function allows."""
+    cols = nops * nsets
+    _check(_L.cut_graph_jvp(g, kind, delta, precision, nsets, nops, _ptr(h), _ld(h, nsets), _ptr(dh),
+                            _ld(dh, nsets), _ptr(x), _ld(x, cols), _ptr(dx), _ld(dx, cols), _ptr(y),
+                            _ld(y, cols), _ptr(dy), _ld(dy, cols), _stream(stream)))
+
+
+def cut_graph_vjp(g: int, kind: int, delta: float, precision: int, nsets: int, nops: int, h, x, w,
+                  g_h, g_x, flags: int = 0, stream=None) -> None:
+    """g_x (=|+=) L(eta(h))^T w; g_h (=|+=) eta'(h)^T geta(w, x); either output may be None."""
+    cols = nops * nsets
+    _check(_L.cut_graph_vjp(g, kind, delta, precision, nsets, nops, _ptr(h), _ld(h, nsets), _ptr(x),
+                            _ld(x, cols), _ptr(w), _ld(w, cols), _ptr(g_h), _ld(g_h, nsets), _ptr(g_x),
+                            _ld(g_x, cols), flags, _stream(stream)))
 
 
 # ------------------------------------------------------------------- flow --

@@ -238,6 +238,52 @@ struct Algebra {
                   [](const Rec& x, const Rec& y) { return x.i != y.i ? x.i < y.i : x.j < y.j; });
     }
 
+    // Outside registry of a Majorana graph: every 6-subset of the modes,
+    // lexicographic (the degree-6 strings [eta, X] reaches outside the
+    // degree <= 4 registry, Eq. projected-flow).
+    std::vector<uint64_t> outside_labels() const {
+        std::vector<uint64_t> out;
+        const int m = size;
+        int c[6] = {0, 1, 2, 3, 4, 5};
+        if (m < 6) return out;
+        for (;;) {
+            uint64_t L = 0;
+            for (int t = 0; t < 6; ++t) L |= 1ull << c[t];
+            out.push_back(L);
+            int t = 5;
+            while (t >= 0 && c[t] == m - 6 + t) --t;
+            if (t < 0) break;
+            ++c[t];
+            for (int u = t + 1; u < 6; ++u) c[u] = c[u - 1] + 1;
+        }
+        return out;
+    }
+
+    // Records of outside target Q (degree 6): [i Gamma_A, Gamma_B] has a
+    // degree-6 part only for two quartics sharing one mode, so A = T1 + s and
+    // B = T2 + s for an ordered split of Q into triples (T1, T2) and a mode s
+    // outside Q.  Sorted by (i, j).
+    void expand_outside(uint64_t Q, std::vector<Rec>& out) const {
+        out.clear();
+        const int m = size;
+        const uint64_t full = (m == 64) ? ~0ull : ((1ull << m) - 1);
+        int q[6], n = 0;
+        for (uint64_t x = Q; x; x &= x - 1) q[n++] = __builtin_ctzll(x);
+        for (int a = 0; a < 6; ++a)
+            for (int b = a + 1; b < 6; ++b)
+                for (int c = b + 1; c < 6; ++c) {
+                    const uint64_t T1 = (1ull << q[a]) | (1ull << q[b]) | (1ull << q[c]);
+                    const uint64_t T2 = Q ^ T1;
+                    for (uint64_t xs = full & ~Q; xs; xs &= xs - 1) {
+                        const uint64_t sbit = xs & (~xs + 1);
+                        const uint64_t A = T1 | sbit, B = T2 | sbit;
+                        out.push_back({(int32_t)rk.rank(A), (int32_t)rk.rank(B), maj_factor(A, B)});
+                    }
+                }
+        std::sort(out.begin(), out.end(),
+                  [](const Rec& x, const Rec& y) { return x.i != y.i ? x.i < y.i : x.j < y.j; });
+    }
+
     std::string identifier() const {
         char buf[96];
         if (kind == CUT_ALG_EPQ)
@@ -274,7 +320,7 @@ static void parallel_for(int64_t n, int threads, const std::function<void(int64_
 using namespace cut;
 
 extern "C" cut_status cut_graph_build(int32_t algebra, int32_t size, const char* path,
-                                      int32_t threads, cut_graph_desc* desc) {
+                                      int32_t threads, uint32_t flags, cut_graph_desc* desc) {
     int fd = -1;
     void* map = MAP_FAILED;
     size_t map_bytes = 0;
@@ -289,6 +335,12 @@ extern "C" cut_status cut_graph_build(int32_t algebra, int32_t size, const char*
         } else {
             CUT_FAIL(CUT_E_INVAL, "cut_graph_build: unknown algebra %d", algebra);
         }
+        if (flags & ~CUT_BUILD_OUTSIDE) CUT_FAIL(CUT_E_INVAL, "cut_graph_build: unknown flags %#x", flags);
+        const bool outside = (flags & CUT_BUILD_OUTSIDE) != 0;
+        if (outside && algebra != CUT_ALG_MAJORANA)
+            CUT_FAIL(CUT_E_INVAL, "cut_graph_build: the E_pq registry is closed, it has no outside-space records");
+        if (outside && size > 32)
+            CUT_FAIL(CUT_E_UNSUPPORTED, "cut_graph_build: outside-space records only up to 32 modes");
         int nt = threads > 0 ? threads : (int)std::max(1u, std::thread::hardware_concurrency());
         Algebra alg(algebra, size);
         const int64_t N = alg.N;
@@ -311,20 +363,40 @@ extern "C" cut_status cut_graph_build(int32_t algebra, int32_t size, const char*
             cntG[k + 1] += cntG[k];
         }
         const int64_t E = cntL[N], Eg = cntG[N];
+        // outside-space set E_C: same two traversals over the outside registry
+        std::vector<uint64_t> olab;
+        std::vector<int64_t> cntC(1, 0);
+        if (outside) {
+            olab = alg.outside_labels();
+            cntC.assign(olab.size() + 1, 0);
+            parallel_for((int64_t)olab.size(), nt, [&](int64_t b, int64_t e) {
+                std::vector<Rec> buf;
+                for (int64_t q = b; q < e; ++q) {
+                    alg.expand_outside(olab[(size_t)q], buf);
+                    cntC[q + 1] = (int64_t)buf.size();
+                }
+            });
+            for (size_t q = 0; q < olab.size(); ++q) cntC[q + 1] += cntC[q];
+        }
+        const int64_t Nc = (int64_t)olab.size(), Ec = cntC.back();
+        const int nsec = outside ? SEC_COUNT_OUT : SEC_COUNT;
 
         // exact section sizes -> file layout
         struct Sz {
             uint32_t id, eb;
             uint64_t count;
-        } secs[SEC_COUNT] = {{SEC_LABELS, 8, (uint64_t)N},        {SEC_DIAG, 1, (uint64_t)N},
-                             {SEC_PAIRS, 4, alg.pairs.size()},     {SEC_FLOW_OFF, 8, (uint64_t)N + 1},
-                             {SEC_FLOW_I, 4, (uint64_t)E},         {SEC_FLOW_J, 4, (uint64_t)E},
-                             {SEC_FLOW_C, 1, (uint64_t)E},         {SEC_GEN_OFF, 8, (uint64_t)N + 1},
-                             {SEC_GEN_I, 4, (uint64_t)Eg},         {SEC_GEN_J, 4, (uint64_t)Eg},
-                             {SEC_GEN_C, 1, (uint64_t)Eg}};
-        SectionEntry tab[SEC_COUNT];
-        uint64_t pos = align64(sizeof(BundleHeader) + sizeof(tab));
-        for (int s = 0; s < SEC_COUNT; ++s) {
+        } secs[SEC_COUNT_OUT] = {{SEC_LABELS, 8, (uint64_t)N},        {SEC_DIAG, 1, (uint64_t)N},
+                                 {SEC_PAIRS, 4, alg.pairs.size()},     {SEC_FLOW_OFF, 8, (uint64_t)N + 1},
+                                 {SEC_FLOW_I, 4, (uint64_t)E},         {SEC_FLOW_J, 4, (uint64_t)E},
+                                 {SEC_FLOW_C, 1, (uint64_t)E},         {SEC_GEN_OFF, 8, (uint64_t)N + 1},
+                                 {SEC_GEN_I, 4, (uint64_t)Eg},         {SEC_GEN_J, 4, (uint64_t)Eg},
+                                 {SEC_GEN_C, 1, (uint64_t)Eg},         {SEC_OUT_LABELS, 8, (uint64_t)Nc},
+                                 {SEC_OUT_OFF, 8, (uint64_t)Nc + 1},   {SEC_OUT_I, 4, (uint64_t)Ec},
+                                 {SEC_OUT_J, 4, (uint64_t)Ec},         {SEC_OUT_C, 1, (uint64_t)Ec}};
+        SectionEntry tab[SEC_COUNT_OUT];
+        const size_t tab_bytes = nsec * sizeof(SectionEntry);
+        uint64_t pos = align64(sizeof(BundleHeader) + tab_bytes);
+        for (int s = 0; s < nsec; ++s) {
             tab[s] = {secs[s].id, secs[s].eb, pos, secs[s].count, 0};
             pos = align64(pos + secs[s].count * secs[s].eb);
         }
@@ -351,6 +423,10 @@ extern "C" cut_status cut_graph_build(int32_t algebra, int32_t size, const char*
         int32_t* Gi = (int32_t*)sec(8);
         int32_t* Gj = (int32_t*)sec(9);
         int8_t* Gc = (int8_t*)sec(10);
+        if (outside) {
+            std::memcpy(sec(11), olab.data(), Nc * 8);
+            std::memcpy(sec(12), cntC.data(), (Nc + 1) * 8);
+        }
 
         // traversal 2: regenerate and write every record in place
         parallel_for(N, nt, [&](int64_t b, int64_t e) {
@@ -373,7 +449,26 @@ extern "C" cut_status cut_graph_build(int32_t algebra, int32_t size, const char*
             }
         });
 
-        for (int s = 0; s < SEC_COUNT; ++s) tab[s].checksum = checksum64(sec(s), tab[s].count * tab[s].elem_bytes);
+        if (outside) {
+            int32_t* Ci = (int32_t*)sec(13);
+            int32_t* Cj = (int32_t*)sec(14);
+            int8_t* Cc = (int8_t*)sec(15);
+            parallel_for(Nc, nt, [&](int64_t b, int64_t e) {
+                std::vector<Rec> buf;
+                for (int64_t q = b; q < e; ++q) {
+                    alg.expand_outside(olab[(size_t)q], buf);
+                    int64_t p = cntC[q];
+                    for (auto& r : buf) {
+                        Ci[p] = r.i;
+                        Cj[p] = r.j;
+                        Cc[p] = r.c;
+                        ++p;
+                    }
+                }
+            });
+        }
+
+        for (int s = 0; s < nsec; ++s) tab[s].checksum = checksum64(sec(s), tab[s].count * tab[s].elem_bytes);
         BundleHeader h{};
         std::memcpy(h.magic, kMagic, 8);
         h.version = kVersion;
@@ -386,17 +481,19 @@ extern "C" cut_status cut_graph_build(int32_t algebra, int32_t size, const char*
         h.n_pairs = (int64_t)alg.pairs.size();
         h.factor_bytes = 1;
         h.gen_sign = alg.gen_sign;
-        h.n_sections = SEC_COUNT;
+        h.n_sections = (uint32_t)nsec;
+        h.n_out_ops = Nc;
+        h.n_out_records = Ec;
         h.section_table_offset = sizeof(BundleHeader);
         h.file_bytes = file_bytes;
         uint64_t rc = 0;
-        for (int s = 3; s < SEC_COUNT; ++s) rc = mix64(rc ^ tab[s].checksum);
+        for (int s = 3; s < nsec; ++s) rc = mix64(rc ^ tab[s].checksum);
         h.records_checksum = rc;
         std::string id = alg.identifier();
         std::strncpy(h.identifier, id.c_str(), sizeof h.identifier - 1);
         h.header_checksum = 0;
-        std::memcpy(base + sizeof(BundleHeader), tab, sizeof tab);
-        h.header_checksum = checksum64(&h, sizeof h) ^ checksum64(tab, sizeof tab);
+        std::memcpy(base + sizeof(BundleHeader), tab, tab_bytes);
+        h.header_checksum = checksum64(&h, sizeof h) ^ checksum64(tab, tab_bytes);
         std::memcpy(base, &h, sizeof h);
         if (::msync(map, map_bytes, MS_SYNC) != 0) CUT_FAIL(CUT_E_IO, "msync failed");
         ::munmap(map, map_bytes);
@@ -412,6 +509,8 @@ extern "C" cut_status cut_graph_build(int32_t algebra, int32_t size, const char*
             desc->n_records = E;
             desc->n_gen_records = Eg;
             desc->n_pairs = h.n_pairs;
+            desc->n_out_ops = Nc;
+            desc->n_out_records = Ec;
             desc->checksum = rc;
             desc->file_bytes = (int64_t)file_bytes;
             desc->build_seconds =
@@ -462,41 +561,50 @@ void read_bundle(const char* path, bool verify, HostGraph& g) {
     if (std::memcmp(h.magic, kMagic, 8) != 0) CUT_FAIL(CUT_E_FORMAT, "%s: not a graph bundle", path);
     if (h.version != kVersion || h.header_bytes != sizeof(BundleHeader))
         CUT_FAIL(CUT_E_FORMAT, "%s: unsupported bundle version %u", path, h.version);
-    if (h.n_sections != SEC_COUNT || h.section_table_offset != sizeof(BundleHeader))
+    if ((h.n_sections != SEC_COUNT && h.n_sections != SEC_COUNT_OUT) ||
+        h.section_table_offset != sizeof(BundleHeader))
         CUT_FAIL(CUT_E_FORMAT, "%s: bad section table", path);
+    const int nsec = (int)h.n_sections;
+    const size_t tab_bytes = nsec * sizeof(SectionEntry);
+    if (fbytes < sizeof(BundleHeader) + tab_bytes) CUT_FAIL(CUT_E_FORMAT, "%s: truncated section table", path);
     if (h.file_bytes != fbytes) CUT_FAIL(CUT_E_FORMAT, "%s: size %llu, header says %llu", path,
                                          (unsigned long long)fbytes, (unsigned long long)h.file_bytes);
-    SectionEntry tab[SEC_COUNT];
-    std::memcpy(tab, base + sizeof h, sizeof tab);
+    SectionEntry tab[SEC_COUNT_OUT];
+    std::memcpy(tab, base + sizeof h, tab_bytes);
     {
         BundleHeader hz = h;
         hz.header_checksum = 0;
-        if ((checksum64(&hz, sizeof hz) ^ checksum64(tab, sizeof tab)) != h.header_checksum)
+        if ((checksum64(&hz, sizeof hz) ^ checksum64(tab, tab_bytes)) != h.header_checksum)
             CUT_FAIL(CUT_E_CHECKSUM, "%s: header checksum mismatch", path);
     }
     const int64_t N = h.n_ops;
     if (N <= 0 || h.n_records < 0 || h.n_gen_records < 0 || h.n_pairs < 0 || h.n_pairs > N)
         CUT_FAIL(CUT_E_FORMAT, "%s: bad sizes", path);
+    const bool outside = nsec == SEC_COUNT_OUT;
+    if (outside ? (h.n_out_ops < 0 || h.n_out_records < 0) : (h.n_out_ops != 0 || h.n_out_records != 0))
+        CUT_FAIL(CUT_E_FORMAT, "%s: bad outside-space sizes", path);
     if (h.factor_bytes != 1 || (h.gen_sign != 1 && h.gen_sign != -1))
         CUT_FAIL(CUT_E_FORMAT, "%s: bad factor format", path);
-    const uint64_t want[SEC_COUNT][2] = {
+    const uint64_t want[SEC_COUNT_OUT][2] = {
         {SEC_LABELS, (uint64_t)N},          {SEC_DIAG, (uint64_t)N},
         {SEC_PAIRS, (uint64_t)h.n_pairs},   {SEC_FLOW_OFF, (uint64_t)N + 1},
         {SEC_FLOW_I, (uint64_t)h.n_records}, {SEC_FLOW_J, (uint64_t)h.n_records},
         {SEC_FLOW_C, (uint64_t)h.n_records}, {SEC_GEN_OFF, (uint64_t)N + 1},
         {SEC_GEN_I, (uint64_t)h.n_gen_records}, {SEC_GEN_J, (uint64_t)h.n_gen_records},
-        {SEC_GEN_C, (uint64_t)h.n_gen_records}};
-    const uint32_t eb[SEC_COUNT] = {8, 1, 4, 8, 4, 4, 1, 8, 4, 4, 1};
-    const void* ptr[SEC_COUNT];
-    for (int s = 0; s < SEC_COUNT; ++s) {
+        {SEC_GEN_C, (uint64_t)h.n_gen_records}, {SEC_OUT_LABELS, (uint64_t)h.n_out_ops},
+        {SEC_OUT_OFF, (uint64_t)h.n_out_ops + 1}, {SEC_OUT_I, (uint64_t)h.n_out_records},
+        {SEC_OUT_J, (uint64_t)h.n_out_records}, {SEC_OUT_C, (uint64_t)h.n_out_records}};
+    const uint32_t eb[SEC_COUNT_OUT] = {8, 1, 4, 8, 4, 4, 1, 8, 4, 4, 1, 8, 8, 4, 4, 1};
+    const void* ptr[SEC_COUNT_OUT];
+    for (int s = 0; s < nsec; ++s) {
         const SectionEntry& e = tab[s];
         if (e.id != want[s][0] || e.count != want[s][1] || e.elem_bytes != eb[s] || (e.offset & 63) ||
-            e.offset < sizeof h + sizeof tab || e.offset > fbytes || e.count * e.elem_bytes > fbytes - e.offset)
+            e.offset < sizeof h + tab_bytes || e.offset > fbytes || e.count * e.elem_bytes > fbytes - e.offset)
             CUT_FAIL(CUT_E_FORMAT, "%s: section %d malformed", path, s);
         ptr[s] = base + e.offset;
     }
     if (verify) {
-        for (int s = 0; s < SEC_COUNT; ++s)
+        for (int s = 0; s < nsec; ++s)
             if (checksum64(ptr[s], tab[s].count * tab[s].elem_bytes) != tab[s].checksum)
                 CUT_FAIL(CUT_E_CHECKSUM, "%s: section %d checksum mismatch", path, s);
     }
@@ -510,12 +618,20 @@ void read_bundle(const char* path, bool verify, HostGraph& g) {
         g.rj[w] = (const int32_t*)ptr[5 + 4 * w];
         g.rc[w] = (const int8_t*)ptr[6 + 4 * w];
     }
+    if (outside) {
+        g.out_labels = (const uint64_t*)ptr[11];
+        g.off[2] = (const int64_t*)ptr[12];
+        g.ri[2] = (const int32_t*)ptr[13];
+        g.rj[2] = (const int32_t*)ptr[14];
+        g.rc[2] = (const int8_t*)ptr[15];
+    }
     // structural validation: offsets monotone and complete, indices in range
-    for (int w = 0; w < 2; ++w) {
-        const int64_t E = w == 0 ? h.n_records : h.n_gen_records;
+    for (int w = 0; w < (outside ? 3 : 2); ++w) {
+        const int64_t E = w == 0 ? h.n_records : w == 1 ? h.n_gen_records : h.n_out_records;
+        const int64_t nseg = w == 2 ? h.n_out_ops : N;
         const int64_t* off = g.off[w];
-        if (off[0] != 0 || off[N] != E) CUT_FAIL(CUT_E_FORMAT, "%s: offsets incomplete", path);
-        for (int64_t k = 0; k < N; ++k)
+        if (off[0] != 0 || off[nseg] != E) CUT_FAIL(CUT_E_FORMAT, "%s: offsets incomplete", path);
+        for (int64_t k = 0; k < nseg; ++k)
             if (off[k + 1] < off[k]) CUT_FAIL(CUT_E_FORMAT, "%s: offsets not monotone at %lld", path, (long long)k);
         const int32_t* ri = g.ri[w];
         const int32_t* rj = g.rj[w];

@@ -104,24 +104,15 @@ void eval_generator_vjp(Graph& g, int kind, double delta, int32_t nsets, const d
 
 using namespace cut;
 
-#define ABI_BEGIN try {
-#define ABI_END                               \
-    return CUT_OK;                            \
-    }                                         \
-    catch (const Fail& f) {                   \
-        return f.st;                          \
-    }                                         \
-    catch (const std::bad_alloc&) {           \
-        set_error("out of host memory");      \
-        return CUT_E_NOMEM;                   \
-    }
-
 extern "C" cut_status cut_graph_apply(cut_graph_t h, int32_t which, int32_t precision, int64_t nsets,
                                       int64_t nops, const void* eta, int64_t lde, const void* x, int64_t ldx,
                                       double* y, int64_t ldy, uint32_t flags, void* stream) {
     ABI_BEGIN
     Graph& g = checked(h);
-    if (which != CUT_GRAPH_FLOW && which != CUT_GRAPH_GEN) CUT_FAIL(CUT_E_INVAL, "unknown record set %d", which);
+    if (which != CUT_GRAPH_FLOW && which != CUT_GRAPH_GEN && which != CUT_GRAPH_OUTSIDE)
+        CUT_FAIL(CUT_E_INVAL, "unknown record set %d", which);
+    if (which == CUT_GRAPH_OUTSIDE && !g.have_outside)
+        CUT_FAIL(CUT_E_INVAL, "cut_graph_apply: the bundle has no outside-space records");
     check_prec(precision);
     check_shape(nsets, nops);
     if (!eta || !x || !y) CUT_FAIL(CUT_E_INVAL, "cut_graph_apply: null operand");
@@ -155,7 +146,8 @@ extern "C" cut_status cut_graph_apply_adjoint(cut_graph_t h, int32_t which, int3
                                               double* g_eta, int64_t ldge, uint32_t flags, void* stream) {
     ABI_BEGIN
     Graph& g = checked(h);
-    if (which != CUT_GRAPH_FLOW && which != CUT_GRAPH_GEN) CUT_FAIL(CUT_E_INVAL, "unknown record set %d", which);
+    if (which != CUT_GRAPH_FLOW && which != CUT_GRAPH_GEN)
+        CUT_FAIL(CUT_E_INVAL, "cut_graph_apply_adjoint: record set %d has no adjoint copies", which);
     check_prec(precision);
     check_shape(nsets, nops);
     if (!g.have_adjoint) CUT_FAIL(CUT_E_INVAL, "adjoint needs a graph loaded with CUT_LOAD_ADJOINT");

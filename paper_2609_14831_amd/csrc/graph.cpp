@@ -129,6 +129,7 @@ Graph::~Graph() {
     ws.release();
     ws_small.release();
     ws_part.release();
+    ws_deriv.release();
     (void)hipSetDevice(cur);
 }
 
@@ -812,8 +813,8 @@ extern "C" cut_status cut_graph_load(const char* path, int32_t dev, uint32_t fla
         std::vector<double> ftab;
         {
             bool seen[256] = {false};
-            for (int w = 0; w < 2; ++w) {
-                const int64_t E = w == 0 ? hg.hdr.n_records : hg.hdr.n_gen_records;
+            for (int w = 0; w < 3; ++w) {
+                const int64_t E = w == 0 ? hg.hdr.n_records : w == 1 ? hg.hdr.n_gen_records : hg.hdr.n_out_records;
                 for (int64_t e = 0; e < E; ++e) seen[(uint8_t)hg.rc[w][e]] = true;
             }
             for (int v = -128; v < 128; ++v)
@@ -841,6 +842,16 @@ extern "C" cut_status cut_graph_load(const char* path, int32_t dev, uint32_t fla
         build_copies(*g, hg, 0, adj);
         build_copies(*g, hg, 1, adj);
         g->have_adjoint = adj;
+        if (hg.hdr.n_sections == SEC_COUNT_OUT) {
+            // outside-space records: target order only, segments = outside rows
+            const int64_t Nc = hg.hdr.n_out_ops, Ec = hg.hdr.n_out_records;
+            std::vector<uint2> rec((size_t)Ec);
+            for (int64_t e = 0; e < Ec; ++e)
+                rec[e] = pack_record(hg.rc[2][e], (uint32_t)hg.ri[2][e], (uint32_t)hg.rj[2][e]);
+            upload_csr(*g, g->csr[2][0], Nc, std::vector<int64_t>(hg.off[2], hg.off[2] + Nc + 1), rec);
+            g->have_outside = true;
+            g->n_out = Nc;
+        }
         g->diag = dev_alloc<uint8_t>(N);
         HIP_CHECK(hipMemcpy(g->diag, hg.diag, N, hipMemcpyHostToDevice));
         g->npairs = hg.hdr.n_pairs;
@@ -884,6 +895,8 @@ extern "C" cut_status cut_graph_info(cut_graph_t h, cut_graph_desc* d) {
     d->n_records = g.hdr.n_records;
     d->n_gen_records = g.hdr.n_gen_records;
     d->n_pairs = g.hdr.n_pairs;
+    d->n_out_ops = g.hdr.n_out_ops;
+    d->n_out_records = g.hdr.n_out_records;
     d->checksum = g.hdr.records_checksum;
     d->file_bytes = (int64_t)g.hdr.file_bytes;
     std::strncpy(d->identifier, g.hdr.identifier, sizeof d->identifier - 1);

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <new>
 #include <string>
 #include <vector>
 
@@ -28,12 +29,24 @@ struct Fail {
             CUT_FAIL(CUT_E_DEVICE, "%s: %s (%s:%d)", #expr, hipGetErrorString(e_), __FILE__, \
                      __LINE__);                                                          \
     } while (0)
+// body of an extern "C" entry point: no exception crosses the ABI
+#define ABI_BEGIN try {
+#define ABI_END                                   \
+    return CUT_OK;                                \
+    }                                             \
+    catch (const ::cut::Fail& f) {                \
+        return f.st;                              \
+    }                                             \
+    catch (const std::bad_alloc&) {               \
+        ::cut::set_error("out of host memory");   \
+        return CUT_E_NOMEM;                       \
+    }
 
 // ---------------------------------------------------------------- bundle ----
 // File layout (little-endian): BundleHeader at 0, then 64-byte aligned
 // sections listed by the section table that follows the header.
 constexpr char kMagic[8] = {'C', 'U', 'T', 'G', 'R', 'P', 'H', '1'};
-constexpr uint32_t kVersion = 1;
+constexpr uint32_t kVersion = 2;
 
 enum SectionId : uint32_t {
     SEC_LABELS = 1,    // uint64[N] registry labels (Majorana bitmask; E_pq p<<32|q)
@@ -47,7 +60,14 @@ enum SectionId : uint32_t {
     SEC_GEN_I = 9,     // int32[Eg]
     SEC_GEN_J = 10,    // int32[Eg]
     SEC_GEN_C = 11,    // int8[Eg]
-    SEC_COUNT = 11
+    SEC_COUNT = 11,    // sections of every bundle
+    // optional outside-space set E_C (Majorana graphs built with CUT_BUILD_OUTSIDE)
+    SEC_OUT_LABELS = 12,  // uint64[Nc] outside registry labels (6-subset bitmasks)
+    SEC_OUT_OFF = 13,     // int64[Nc+1]
+    SEC_OUT_I = 14,       // int32[Ec]
+    SEC_OUT_J = 15,       // int32[Ec]
+    SEC_OUT_C = 16,       // int8[Ec]
+    SEC_COUNT_OUT = 16    // sections of a bundle with E_C
 };
 
 struct SectionEntry {
@@ -76,8 +96,10 @@ struct BundleHeader {
     uint64_t file_bytes;
     uint64_t records_checksum;
     char identifier[96];
-    uint64_t header_checksum;  // of the header with this field zero
-    uint8_t pad[256 - 8 - 4 - 4 - 4 - 4 - 8 * 4 - 4 - 4 - 4 - 4 - 8 * 3 - 96 - 8];
+    uint64_t header_checksum;  // of the header and section table with this field zero
+    int64_t n_out_ops;         // outside registry size (0: no E_C)
+    int64_t n_out_records;     // |E_C|
+    uint8_t pad[256 - 8 - 4 - 4 - 4 - 4 - 8 * 4 - 4 - 4 - 4 - 4 - 8 * 3 - 96 - 8 - 8 * 2];
 };
 static_assert(sizeof(BundleHeader) == 256, "header must be 256 bytes");
 
@@ -89,10 +111,12 @@ struct HostGraph {
     const uint64_t* labels = nullptr;
     const uint8_t* diag = nullptr;
     const int32_t* pairs = nullptr;
-    const int64_t* off[2] = {nullptr, nullptr};
-    const int32_t* ri[2] = {nullptr, nullptr};
-    const int32_t* rj[2] = {nullptr, nullptr};
-    const int8_t* rc[2] = {nullptr, nullptr};
+    // record sets: 0 = E_L, 1 = E_eta, 2 = E_C (absent: null, size 0)
+    const int64_t* off[3] = {nullptr, nullptr, nullptr};
+    const int32_t* ri[3] = {nullptr, nullptr, nullptr};
+    const int32_t* rj[3] = {nullptr, nullptr, nullptr};
+    const int8_t* rc[3] = {nullptr, nullptr, nullptr};
+    const uint64_t* out_labels = nullptr;
     void* map = nullptr;
     size_t map_bytes = 0;
     ~HostGraph();
@@ -226,11 +250,14 @@ struct Graph {
     double gen_sign = 1.0;
     int nfactors = 0;
     double* ftab = nullptr;          // device [256]: factor dictionary of the stencil tables
-    // record streams: [set][orientation] set 0 = E_L, 1 = E_eta;
+    // record streams: [set][orientation] set 0 = E_L, 1 = E_eta, 2 = E_C
+    // (orientation 0 only, segments = outside registry rows);
     // orientation 0 = by target k (a=i, b=j), 1 = by right input j (a=i, b=k),
     // 2 = by left input i (a=k, b=j)
-    DevCSR csr[2][3];
+    DevCSR csr[3][3];
     bool have_adjoint = false;
+    bool have_outside = false;
+    int64_t n_out = 0;               // outside registry size
     // block mask and pairs
     uint8_t* diag = nullptr;         // device [N]
     int32_t* pairs = nullptr;        // device [npairs]
@@ -260,6 +287,7 @@ struct Graph {
     Workspace ws;                    // flow state and stage storage
     Workspace ws_small;              // scratch of single generator-VJP calls
     Workspace ws_part;               // tile partial slots of single forward passes
+    Workspace ws_deriv;              // generator, tangent and float shadows of derivative calls
     StepGraphCache* graphs = nullptr;
     cut_flow_timing timing{};        // last timed flow
     std::vector<std::pair<std::vector<int64_t>, cut_tuning>> tune_cache;
@@ -325,10 +353,15 @@ void launch_g2(const Graph& g, double delta, int32_t nsets, const double* h, int
 void launch_g2_vjp(const Graph& g, double delta, int32_t nsets, const double* h, int64_t ldh,
                    const double* gbar, int64_t ldg, double* g_h, int64_t ldgh, double* tmp,
                    hipStream_t s);
+void launch_g2_jvp(const Graph& g, double delta, int32_t nsets, const double* h, int64_t ldh,
+                   const double* dh, int64_t lddh, double* deta, int64_t ldde, hipStream_t s);
 
 // elementwise helpers
 void launch_prep_state(const double* z, int64_t rows, int32_t nops, int32_t nsets, void* xsh,
                        bool f32, double* hst, hipStream_t s);
+void launch_round_f32(const double* src, int64_t lds, int64_t rows, int64_t cols, float* dst, int64_t ldd,
+                      hipStream_t s);
+void launch_zero2d(double* dst, int64_t ld, int64_t rows, int64_t cols, hipStream_t s);
 void launch_bump(int32_t* step, hipStream_t s);
 void launch_set_scalar(int32_t* p, int32_t v, hipStream_t s);
 void launch_adj_combine(int64_t rows, int32_t ncols, int32_t nsets, const int32_t* nsteps,
@@ -348,6 +381,8 @@ void eval_generator(Graph& g, int kind, double delta, int32_t nsets, const doubl
 void eval_generator_vjp(Graph& g, int kind, double delta, int32_t nsets, const double* h, int64_t ldh,
                         const double* gbar, int64_t ldg, double* g_h, int64_t ldgh, double* tmp,
                         hipStream_t s);
+void eval_generator_jvp(Graph& g, int kind, double delta, int32_t nsets, const double* h, int64_t ldh,
+                        const double* dh, int64_t lddh, double* deta, int64_t ldde, hipStream_t s);
 struct DeviceGuard {
     int prev = -1;
     explicit DeviceGuard(int dev);

@@ -823,9 +823,6 @@ __global__ __launch_bounds__(256) void k_combine(KArgs a, const double* __restri
     }
 }
 
-// sets per tile workgroup: 16 for narrow batches, else 32 (each gathered run
-// of one operand column is a full 128-byte line; two workgroups per 64 sets
-// keep the staged rows small enough for several workgroups per CU)
 // sets per tile workgroup: 64 (the 8-wavefront kernel) when the member rows of
 // 64 sets fit in 64 KiB of LDS, else 32 or 16
 static int tile_width(const Graph& g, int nsets, int nops, int prec) {
@@ -1369,6 +1366,43 @@ __global__ void k_g2_vjp_pairs(int64_t npairs, int32_t nsets, const int64_t* __r
     if (lane == 0) g_h[pa * ldgh + s] += acc;
 }
 
+// G2 directional derivative along dh (quotient rule), FP64:
+//   d eta_S = s_g (dnum Q - num dQ) / Q^2,  num = sum_t c_t eps_t h_{p_t},
+//   dnum = sum_t c_t (d eps_t h_{p_t} + eps_t dh_{p_t}),  dQ = 2 sum_t c_t^2 eps_t d eps_t
+__global__ void k_g2_jvp(int64_t N, int32_t nsets, const int4* __restrict__ st,
+                         const int32_t* __restrict__ pairs, const double* __restrict__ ftab, double gsign,
+                         double d2, const double* __restrict__ h, int64_t ldh, const double* __restrict__ dh,
+                         int64_t lddh, double* deta, int64_t ldde) {
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t S = gid / nsets;
+    const int s = (int)(gid % nsets);
+    if (S >= N) return;
+    double num = 0.0, q = 0.0, dnum = 0.0, dq = 0.0;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const int4 e = st[S * 4 + t];
+        if (e.x < 0) break;
+        const double c = ftab[e.z];
+        const int64_t pa = pairs[e.y];
+        const double eps = h[pa * ldh + s], deps = dh[pa * lddh + s];
+        const double hp = h[(int64_t)e.x * ldh + s], dhp = dh[(int64_t)e.x * lddh + s];
+        num = __builtin_fma(c * eps, hp, num);
+        dnum = __builtin_fma(c * deps, hp, __builtin_fma(c * eps, dhp, dnum));
+        q = __builtin_fma(c * eps, c * eps, q);
+        dq = __builtin_fma(2.0 * c * c * eps, deps, dq);
+    }
+    const bool has = st[S * 4].x >= 0;
+    q += d2;
+    deta[S * ldde + s] = has ? gsign * (dnum * q - num * dq) / (q * q) : 0.0;
+}
+
+void launch_g2_jvp(const Graph& g, double delta, int32_t nsets, const double* h, int64_t ldh,
+                   const double* dh, int64_t lddh, double* deta, int64_t ldde, hipStream_t s) {
+    const int64_t n = g.N * nsets;
+    hipLaunchKernelGGL(k_g2_jvp, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, g.N, nsets, g.stencil,
+                       g.pairs, g.ftab, g.gen_sign, delta * delta, h, ldh, dh, lddh, deta, ldde);
+}
+
 void launch_g2(const Graph& g, double delta, int32_t nsets, const double* h, int64_t ldh, void* eta,
                int64_t lde, bool eta_f32, const int32_t* nsteps, const int32_t* step, hipStream_t s) {
     const int64_t n = g.N * nsets;
@@ -1411,6 +1445,37 @@ void launch_prep_state(const double* z, int64_t rows, int32_t nops, int32_t nset
     const int64_t n = rows * nops * nsets;
     hipLaunchKernelGGL(k_prep_state, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, z, rows, nops,
                        nsets, xsh, (int)f32, hst);
+}
+
+// dst[r][c] = float(src[r][c]) (round to nearest even) for r < rows, c < cols
+__global__ void k_round_f32(const double* __restrict__ src, int64_t lds, int64_t rows, int64_t cols,
+                            float* __restrict__ dst, int64_t ldd) {
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= rows * cols) return;
+    const int64_t r = q / cols, c = q % cols;
+    dst[r * ldd + c] = (float)src[r * lds + c];
+}
+
+void launch_round_f32(const double* src, int64_t lds, int64_t rows, int64_t cols, float* dst, int64_t ldd,
+                      hipStream_t s) {
+    const int64_t n = rows * cols;
+    if (n == 0) return;
+    hipLaunchKernelGGL(k_round_f32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, src, lds, rows, cols,
+                       dst, ldd);
+}
+
+// dst[r][c] = 0 for r < rows, c < cols (a kernel, not a memset, so that the
+// clear can sit inside a captured graph)
+__global__ void k_zero2d(double* dst, int64_t ld, int64_t rows, int64_t cols) {
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= rows * cols) return;
+    dst[(q / cols) * ld + q % cols] = 0.0;
+}
+
+void launch_zero2d(double* dst, int64_t ld, int64_t rows, int64_t cols, hipStream_t s) {
+    const int64_t n = rows * cols;
+    if (n == 0) return;
+    hipLaunchKernelGGL(k_zero2d, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, dst, ld, rows, cols);
 }
 
 __global__ void k_bump(int32_t* step) {

@@ -40,6 +40,14 @@ def dense_strings(m: int):
     return subs, np.array(mats)
 
 
+def dense_strings_of_degree(m: int, d: int):
+    """(subsets, Gamma_S matrices) for every d-subset, lexicographic."""
+    g = jw_majoranas(m)
+    subs = list(itertools.combinations(range(m), d))
+    mats = [(1j ** (d * (d - 1) // 2)) * reduce(np.matmul, [g[a] for a in S]) for S in subs]
+    return subs, np.array(mats)
+
+
 def project(mats: np.ndarray, M: np.ndarray) -> np.ndarray:
     """Coefficients Tr(Gamma_K M) / dim over the registry (orthonormal basis)."""
     dim = M.shape[-1]

@@ -9,9 +9,11 @@ import numpy as np
 HEADER = 256
 SECTION = 32
 NAMES = {1: "labels", 2: "diag", 3: "pairs", 4: "flow_off", 5: "flow_i", 6: "flow_j", 7: "flow_c",
-         8: "gen_off", 9: "gen_i", 10: "gen_j", 11: "gen_c"}
+         8: "gen_off", 9: "gen_i", 10: "gen_j", 11: "gen_c", 12: "out_labels", 13: "out_off",
+         14: "out_i", 15: "out_j", 16: "out_c"}
 DT = {1: np.uint64, 2: np.uint8, 3: np.int32, 4: np.int64, 5: np.int32, 6: np.int32, 7: np.int8,
-      8: np.int64, 9: np.int32, 10: np.int32, 11: np.int8}
+      8: np.int64, 9: np.int32, 10: np.int32, 11: np.int8, 12: np.uint64, 13: np.int64, 14: np.int32,
+      15: np.int32, 16: np.int8}
 
 
 def read(path: str) -> dict:
@@ -23,7 +25,9 @@ def read(path: str) -> dict:
     out = {"n_ops": struct.unpack_from("<q", b, 24)[0],
            "n_records": struct.unpack_from("<q", b, 32)[0],
            "gen_sign": struct.unpack_from("<i", b, 60)[0],
-           "identifier": b[96:192].split(b"\0")[0].decode()}
+           "identifier": b[96:192].split(b"\0")[0].decode(),
+           "n_out_ops": struct.unpack_from("<q", b, 200)[0],
+           "n_out_records": struct.unpack_from("<q", b, 208)[0]}
     out["sections"] = {}
     for s in range(n_sections):
         sid, eb, off, cnt, ck = struct.unpack_from("<IIQQQ", b, table + s * SECTION)

@@ -137,3 +137,73 @@ def test_build_rejects_bad_arguments(tmpdir_mod):
     with pytest.raises(L.CutError) as e:
         L.cut_graph_build(L.CUT_ALG_EPQ, 4, "/nonexistent_dir/x.cgb")
     assert e.value.status == L.CUT_E_IO
+
+
+def _build_outside(tmpdir, m, threads=0, name=None):
+    p = str(tmpdir / (name or f"out_{m}_{threads}.cgb"))
+    L.cut_graph_build(L.CUT_ALG_MAJORANA, m, p, threads, L.CUT_BUILD_OUTSIDE)
+    return p
+
+
+@pytest.mark.parametrize("m", [6, 8, 12, 16])
+def test_outside_records_bit_exact_vs_oracle(tmpdir_mod, m):
+    """E_C (Eq. projected-flow C_X; Eq. graph-actions third line) in the bundle
+    equals the oracle's brute-force records; E_L and E_eta are unchanged by the
+    flag."""
+    d = bundle_io.read(_build_outside(tmpdir_mod, m))
+    og = A.majorana_outside_graph(m)
+    assert d["n_out_ops"] == og.n_out == math.comb(m, 6)
+    assert d["n_out_records"] == og.E == A.majorana_outside_count(m)
+    np.testing.assert_array_equal(d["out_labels"], og.masks)
+    k, i, j, c = bundle_io.records(d, "out")
+    np.testing.assert_array_equal(k, og.k)
+    np.testing.assert_array_equal(i, og.i)
+    np.testing.assert_array_equal(j, og.j)
+    np.testing.assert_array_equal(c, og.c)
+    plain = bundle_io.read(_build(tmpdir_mod, L.CUT_ALG_MAJORANA, m, name=f"plain_{m}.cgb"))
+    for name in ("flow_off", "flow_i", "flow_j", "flow_c", "gen_off", "gen_i", "gen_j", "gen_c"):
+        np.testing.assert_array_equal(d[name], plain[name])
+    assert plain["n_out_ops"] == 0 and 12 not in plain["sections"]
+
+
+def test_outside_build_deterministic_and_sized(tmpdir_mod):
+    a = _build_outside(tmpdir_mod, 14, threads=1, name="oa.cgb")
+    b = _build_outside(tmpdir_mod, 14, threads=5, name="ob.cgb")
+    assert open(a, "rb").read() == open(b, "rb").read()
+    p = str(tmpdir_mod / "o24.cgb")
+    desc = L.cut_graph_build(L.CUT_ALG_MAJORANA, 24, p, 0, L.CUT_BUILD_OUTSIDE)
+    assert desc["n_out_ops"] == 134_596 and desc["n_out_records"] == 48_454_560
+    d = bundle_io.read(p)
+    cnt = np.diff(d["out_off"])
+    assert np.all(cnt == 20 * 18)
+    rng = np.random.default_rng(3)
+    og = A.majorana_outside_graph(24, targets=np.concatenate([[0, 134_595], rng.integers(0, 134_596, 6)]))
+    for t in np.unique(og.k):
+        sl = slice(d["out_off"][t], d["out_off"][t + 1])
+        sel = og.k == t
+        np.testing.assert_array_equal(d["out_i"][sl], og.i[sel])
+        np.testing.assert_array_equal(d["out_j"][sl], og.j[sel])
+        np.testing.assert_array_equal(d["out_c"][sl].astype(float), og.c[sel])
+    os.remove(p)
+
+
+def test_outside_build_flags_and_corruption(tmpdir_mod):
+    p = str(tmpdir_mod / "ox.cgb")
+    for alg, size, flags, status in ((L.CUT_ALG_EPQ, 4, L.CUT_BUILD_OUTSIDE, L.CUT_E_INVAL),
+                                     (L.CUT_ALG_MAJORANA, 34, L.CUT_BUILD_OUTSIDE, L.CUT_E_UNSUPPORTED),
+                                     (L.CUT_ALG_MAJORANA, 8, 2, L.CUT_E_INVAL)):
+        with pytest.raises(L.CutError) as e:
+            L.cut_graph_build(alg, size, p, 0, flags)
+        assert e.value.status == status
+    src = _build_outside(tmpdir_mod, 8, name="ov.cgb")
+    d = bundle_io.read(src)
+    off_i, _, _ = d["sections"][14]
+    off_c, _, _ = d["sections"][16]
+    off_o, _, _ = d["sections"][13]
+    assert _load_status(_corrupt(src, str(tmpdir_mod / "oc1"), off_i + 1)) == L.CUT_E_CHECKSUM
+    bad = _corrupt(src, str(tmpdir_mod / "oc2"), off_i + 3, value=0x7F)
+    assert _load_status(bad, L.CUT_LOAD_NO_CHECKSUM) == L.CUT_E_FORMAT
+    bad = _corrupt(src, str(tmpdir_mod / "oc3"), off_c, value=0)
+    assert _load_status(bad, L.CUT_LOAD_NO_CHECKSUM) == L.CUT_E_FORMAT
+    bad = _corrupt(src, str(tmpdir_mod / "oc4"), off_o + 8 * 28, value=0x33)   # last offset != E_C
+    assert _load_status(bad, L.CUT_LOAD_NO_CHECKSUM) == L.CUT_E_FORMAT

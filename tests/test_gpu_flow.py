@@ -187,3 +187,31 @@ def test_flow_function_autograd_config5_reduced(L):
             fd = float((lp - lm) / (2 * eps))
             an = float(np.sum(grad[:, 0, :] * d))
             assert abs(fd - an) <= 1e-6 * max(abs(fd), 1e-3 * np.linalg.norm(grad)), (fd, an)
+
+
+def test_pairing_drift_100_steps(L):
+    """Duality invariant of the discrete flow (Eq. duality-invariant): an
+    operand X flowed 100 RK4 steps with H on the config-2 graph (m = 24, 8 sets,
+    FP64), and a dual w pulled back through the same steps by cut_flow_adjoint
+    with no Hamiltonian cotangent, keep <w(0), X(0)> = <w(T), X(T)> up to
+    rounding: X(T) is linear in X(0) for a fixed H(0), and w(0) is the
+    transpose of that linear map applied to w(T)."""
+    U.say("[pairing drift] m=24 8 sets 100 steps")
+    m, nsets, ds, T, C = 24, 8, 5e-3, 100, 16
+    g = U.graph(L, "majorana", m)
+    z0 = workloads.small_majorana(m, nsets, 2, seed=81)
+    ns = [T] * nsets
+    z, ck = _flow(L, g, z0, ns, L.CUT_GEN_G2, L.CUT_F64, ds, ckpt_every=C)
+    w_end = np.zeros_like(z0)
+    w_end[:, 1, :] = workloads.random_dense((z0.shape[0], nsets), seed=82)
+    lam = torch.tensor(w_end, device=DEV).contiguous()
+    L.cut_flow_adjoint(g, L.flow_params(L.CUT_GEN_G2, L.CUT_F64, ds, 0.5, C), nsets, 2, ns, ck, lam)
+    torch.cuda.synchronize()
+    w0 = lam.cpu().numpy()[:, 1, :]
+    before = np.sum(w0 * z0[:, 1, :], axis=0)
+    after = np.sum(w_end[:, 1, :] * z[:, 1, :], axis=0)
+    scale = np.sum(np.abs(w0 * z0[:, 1, :]), axis=0) + np.sum(np.abs(w_end[:, 1, :] * z[:, 1, :]), axis=0)
+    drift = np.abs(after - before)
+    U.say(f"[pairing drift] max |<w(T),X(T)> - <w(0),X(0)>| = {drift.max():.3e}, "
+          f"relative {np.max(drift / scale):.3e}, |<w,X>| ~ {np.abs(after).max():.3e}")
+    assert np.all(drift < 1e-13 * scale)

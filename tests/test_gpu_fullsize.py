@@ -4,6 +4,7 @@
   configuration bench.py times (G2 generator, compensated float passes, RK4 steps
   replayed from one hipGraph, default tiling): two whole RK4 steps of every
   coefficient against the oracle's C engine; sampled single actions per target;
+* config 3 directional derivative (cut_graph_jvp) on sampled targets;
 * config 4 (m=64, 457.7M records, 16 sets): sampled single actions per target,
   norm conservation over a short flow, float passes vs FP64 passes;
 * config 2: the whole flow to s=10 against the oracle's stored flow;
@@ -123,6 +124,43 @@ def test_cfg3_sampled_single_actions(L, cfg3, tiling):
         U.assert_within(got, ref, bound, f"cfg3 sampled {name} tiling {tiling}")
     t = L.cut_graph_autotune(g, w.nsets, w.nops, L.CUT_F32C, 0)   # cached: restores the tuned tiling
     L.cut_graph_set_tiling(g, t["long_records"], t["chunk_records"], t["tiling_flags"])
+
+
+@pytest.mark.timeout(300)
+def test_cfg3_sampled_directional_derivative(L, cfg3):
+    """cut_graph_jvp at full size (64 sets x 5 operands, the benchmark's tiling)
+    on sampled targets: dy = apply(eta'(h) dh, x) + apply(eta(h), dx) and
+    y = apply(eta(h), x) against the oracle's rows; bounds as the sampled
+    single actions, with S the sums over |terms| of both products."""
+    g, w, inp = cfg3
+    reg = A.MajoranaRegistry(40)
+    rows = np.array([0, 5, 779, 780, 90000, reg.N - 1] + list(np.random.default_rng(7).integers(0, reg.N, 20)))
+    og = A.majorana_graph(40, targets=rows)
+    ga = A.Graph("majorana", 40, og.N, og.k, og.i, og.j, np.abs(og.c), og.diag, og.pairs, 1.0)
+    h = inp.z0[:, 0, :]
+    x = inp.z0
+    dh = workloads.random_dense(h.shape, seed=71)
+    dx = workloads.random_dense(x.shape, seed=72)
+    gen = OG.G2(40, w.delta)
+    eta, deta = gen(h), gen.jvp(h, dh)
+    ref = OGr.apply_rows(og, deta, x, rows) + OGr.apply_rows(og, eta, dx, rows)
+    S = OGr.apply_rows(ga, np.abs(deta), np.abs(x), rows) + OGr.apply_rows(ga, np.abs(eta), np.abs(dx), rows)
+    yref = OGr.apply_rows(og, eta, x, rows)
+    Sy = OGr.apply_rows(ga, np.abs(eta), np.abs(x), rows)
+    for name in ("F32C", "F64"):
+        P = getattr(L, "CUT_" + name)
+        U.say(f"[cfg3] jvp {name}")
+        y = torch.zeros((reg.N, 320), dtype=torch.float64, device=DEV)
+        dy = torch.zeros((reg.N, 320), dtype=torch.float64, device=DEV)
+        L.cut_graph_jvp(g, L.CUT_GEN_G2, w.delta, P, 64, 5, torch.tensor(h, device=DEV).contiguous(),
+                        torch.tensor(dh, device=DEV), torch.tensor(x.reshape(reg.N, 320), device=DEV),
+                        torch.tensor(dx.reshape(reg.N, 320), device=DEV), y, dy)
+        torch.cuda.synchronize()
+        pb = {"F64": U.sum_bound(16948), "F32C": 2 * U.U32 + U.dot2_bound(16948)}[name]
+        got = dy.cpu().numpy().reshape(reg.N, 5, 64)[rows]
+        U.assert_within(got, ref, pb * S + 1e-12 * np.abs(ref).max(), f"cfg3 jvp dy {name}")
+        goty = y.cpu().numpy().reshape(reg.N, 5, 64)[rows]
+        U.assert_within(goty, yref, pb * Sy + 1e-12 * np.abs(yref).max(), f"cfg3 jvp y {name}")
 
 
 @pytest.mark.timeout(900)
