@@ -105,6 +105,83 @@ def cpu_baseline(inp, w, nsets, nops, budget_s=15.0):
                       f"{el:.1f} s; plain-C oracle engine with OpenMP"}
 
 
+def _time_calls(torch, fn, reps):
+    """Mean wall time of `reps` stream-ordered calls of fn (after one warm call)."""
+    fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / reps
+
+
+def derivative_leg(L, torch, g, inp, w, prec, E):
+    """cut_graph_jvp on the headline workload: 64 sets x 5 operands, both tangents."""
+    import numpy as np
+    dev = torch.device("cuda:0")
+    N, nops, nsets = inp.z0.shape
+    cols = nops * nsets
+    h = torch.tensor(np.ascontiguousarray(inp.z0[:, 0, :]), device=dev)
+    x = torch.tensor(inp.z0.reshape(N, cols), device=dev)
+    gen = torch.Generator(device="cpu").manual_seed(5)
+    dh = torch.randn((N, nsets), generator=gen, dtype=torch.float64).to(dev)
+    dx = torch.randn((N, cols), generator=gen, dtype=torch.float64).to(dev)
+    dy = torch.empty((N, cols), dtype=torch.float64, device=dev)
+    y = torch.empty_like(dy)
+
+    def jvp():
+        L.cut_graph_jvp(g, L.CUT_GEN_G2, w.delta, prec, nsets, nops, h, dh, x, dx, None, dy)
+
+    def jvp_y():
+        L.cut_graph_jvp(g, L.CUT_GEN_G2, w.delta, prec, nsets, nops, h, dh, x, dx, y, dy)
+
+    t1 = _time_calls(torch, jvp, 10)
+    t2 = _time_calls(torch, jvp_y, 10)
+    return {"call": "cut_graph_jvp (dh and dx), 64 sets x 5 operands", "ms": t1 * 1e3,
+            "ms_with_action": t2 * 1e3, "passes": 2, "contributions_per_s": 2 * E * cols / t1,
+            "unit": "contributions×batch/s"}
+
+
+def outside_leg(L, torch, tmp):
+    """The outside-space action C_q (Eq. graph-actions, third line) on the
+    m = 32 Majorana graph: 906,192 outside targets, 471.2M records (the scale of
+    the paper's diagnostic-enabled stress graph); one FP64 column (a single
+    action) and 8 sets x 3 operands in the compensated float mode."""
+    dev = torch.device("cuda:0")
+    m = 32
+    path = os.path.join(tmp, "m32_outside.cgb")
+    t0 = time.perf_counter()
+    desc = L.cut_graph_build(L.CUT_ALG_MAJORANA, m, path, 0, L.CUT_BUILD_OUTSIDE)
+    build_s = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    g = L.cut_graph_load(path, 0, 0)
+    load_s = time.perf_counter() - t0
+    N, Nc, Ec = desc["n_ops"], desc["n_out_ops"], desc["n_out_records"]
+    res = {"graph": f"majorana m={m}: N={N}, outside targets {Nc}, E_C={Ec} records, "
+                    f"E_L={desc['n_records']} records",
+           "compile_s": build_s, "load_s": load_s, "bundle_bytes": desc["file_bytes"]}
+    gen = torch.Generator(device="cpu").manual_seed(7)
+    for name, prec, nsets, nops in (("f64_one_column", L.CUT_F64, 1, 1), ("f32c_8x3", L.CUT_F32C, 8, 3)):
+        dt = torch.float64 if prec == L.CUT_F64 else torch.float32
+        eta = torch.randn((N, nsets), generator=gen, dtype=torch.float64).to(dev).to(dt)
+        x = torch.randn((N, nsets * nops), generator=gen, dtype=torch.float64).to(dev).to(dt)
+        y = torch.empty((Nc, nsets * nops), dtype=torch.float64, device=dev)
+
+        def call():
+            L.cut_graph_apply(g, L.CUT_GRAPH_OUTSIDE, prec, nsets, nops, eta, x, y)
+
+        ts = _time_calls(torch, call, 10)
+        stream_bytes = 8 * Ec + 8 * (Nc + 1) + 8 * Nc * nsets * nops   # records, offsets, output
+        res[name] = {"ms": ts * 1e3, "records_per_s": Ec / ts,
+                     "contributions_per_s": Ec * nsets * nops / ts,
+                     "stream_GBs": stream_bytes / ts / 1e9}
+        del eta, x, y
+    L.cut_graph_free(g)
+    os.remove(path)
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -112,6 +189,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--precision", default="f32c", choices=["f32c", "f32x", "f64", "f32"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-outside", action="store_true", help="skip the outside-space action leg")
     ap.add_argument("--minimal", action="store_true", help="timed flow only")
     ap.add_argument("--profile", action="store_true",
                     help="counter runs: a 1 GiB device copy (calibration), then the steps in "
@@ -283,8 +361,19 @@ def main():
     out["plain_fp64_flow"] = {"value": plain, "unit": "contributions×batch/s",
                               "columns": 1, "ratio_batched_over_plain": value / plain}
     log(f"plain FP64 one-column flow {plain:.3e}/s; batched/plain = {value / plain:.1f}x")
+    # directional derivative of one action at the headline shape (Sec. 2.4,
+    # Eq. directional-derivative): generator + its JVP + two forward passes
+    t = L.cut_graph_autotune(g, w.nsets, w.nops, PREC, 0) if args.long_records <= 0 else None
+    if t is not None:
+        L.cut_graph_set_tiling(g, t["long_records"], t["chunk_records"], t["tiling_flags"])
+    out["derivative"] = derivative_leg(L, torch, g, inp, w, PREC, E)
+    log(f"jvp: {out['derivative']}")
     L.cut_graph_free(g)
     os.remove(path)
+
+    if not args.no_outside:
+        out["outside_space"] = outside_leg(L, torch, tmp)
+        log(f"outside-space action: {out['outside_space']}")
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(inp, w, nsets, nops)

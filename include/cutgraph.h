@@ -255,14 +255,24 @@ typedef struct {
     uint32_t flags;         /* CUT_FLOW_HIPGRAPH */
     int64_t step_begin;     /* first global step to take (normally 0) */
     int64_t step_end;       /* one past the last step; < 0 = max(n_steps) */
+    double* outside_norm2;  /* NULL, or device [nops*nsets] doubles: outside-space
+                               diagnostic, see cut_flow_integrate */
 } cut_flow_params;
 
 /* cut_flow_integrate: advances z in place over global steps [step_begin,
  * step_end).  n_steps is a HOST array of nsets int32.  If ckpt is not NULL and
  * ckpt_every > 0, slot c of ckpt (each N*nops*nsets doubles, device) receives z
- * at global step c*ckpt_every for every such step in range.  Errors:
- * CUT_E_INVAL, CUT_E_UNSUPPORTED (G2 on a non-Majorana graph), CUT_E_DEVICE,
- * CUT_E_NOMEM, CUT_E_NUMERIC (non-finite z after the flow). */
+ * at global step c*ckpt_every for every such step in range.
+ * Outside-space diagnostic (Eq. projected-flow, C_X = (I - P)[eta, X], which
+ * never feeds the flow): if outside_norm2 is not NULL the graph must hold E_C,
+ * and every step a set takes adds sum_s b_s ds sum_q C_q(Z_s)^2 to
+ * outside_norm2[op*nsets + s] (b = 1/6, 1/3, 1/3, 1/6, Z_s the RK stage states,
+ * C the outside-space action with the stage generator, in the pass precision;
+ * sums of squares in FP64, fixed order): the RK4 quadrature of the integral of
+ * |C_X|^2 over the flow.  The flowed z is bitwise the same with or without it.
+ * Errors: CUT_E_INVAL (also outside_norm2 without E_C), CUT_E_UNSUPPORTED (G2
+ * on a non-Majorana graph), CUT_E_DEVICE, CUT_E_NOMEM, CUT_E_NUMERIC (non-finite
+ * z after the flow). */
 cut_status cut_flow_integrate(cut_graph_t g, const cut_flow_params* p, int64_t nsets,
                               int64_t nops, const int32_t* n_steps, double* z, double* ckpt,
                               void* stream);
@@ -273,7 +283,8 @@ cut_status cut_flow_integrate(cut_graph_t g, const cut_flow_params* p, int64_t n
  * a cut_flow_integrate call from step 0 with the same parameters, and a graph
  * loaded with CUT_LOAD_ADJOINT.  lambda (device, layout of z): in dL/dz at the
  * end of the flow, out dL/dz at step 0.  Each checkpoint block is recomputed
- * forward in FP64 with its stage states kept; all adjoint passes are FP64. */
+ * forward in FP64 with its stage states kept; all adjoint passes are FP64.
+ * outside_norm2 is ignored. */
 cut_status cut_flow_adjoint(cut_graph_t g, const cut_flow_params* p, int64_t nsets,
                             int64_t nops, const int32_t* n_steps, const double* ckpt,
                             double* lambda, void* stream);

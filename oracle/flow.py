@@ -45,6 +45,35 @@ def rk4_step(g: Graph, gen: Callable, z: np.ndarray, ds: float,
     return np.where(active[None, None, :], znew, z)
 
 
+RK4_WEIGHTS = (1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0)
+
+
+def integrate_outside(g: Graph, gen: Callable, og, z0: np.ndarray, ds: float,
+                      n_steps) -> Tuple[np.ndarray, np.ndarray]:
+    """The flow of ``integrate`` plus the outside-space diagnostic (Eq.
+    projected-flow: C_X = (I - P)[eta, X] never feeds the flow).  Returns
+    (z_end, leak[nops, nsets]) with leak = sum over the steps each set takes of
+    sum_s b_s ds sum_q C_q(Z_s)^2: the RK4 quadrature, over the same stage
+    states, of the integral of |C_X|^2 (b = 1/6, 1/3, 1/3, 1/6; Z_s the stage
+    states, C evaluated with the stage generator eta(Z_s,h))."""
+    n_steps = np.asarray(n_steps)
+    z = z0.copy()
+    leak = np.zeros(z0.shape[1:])
+    for t in range(int(n_steps.max()) if n_steps.size else 0):
+        active = n_steps > t
+        stage, ks = z, []
+        for s, b in enumerate(RK4_WEIGHTS):
+            k, eta = rhs(g, gen, stage)
+            C = G.apply_outside(og, eta, stage)
+            leak += np.where(active[None, :], b * ds * np.sum(C * C, axis=0), 0.0)
+            ks.append(k)
+            if s < 3:
+                stage = z + (0.5 if s < 2 else 1.0) * ds * k
+        znew = z + (ds / 6.0) * (ks[0] + 2.0 * ks[1] + 2.0 * ks[2] + ks[3])
+        z = np.where(active[None, None, :], znew, z)
+    return z, leak
+
+
 def integrate(g: Graph, gen: Callable, z0: np.ndarray, ds: float, n_steps,
               ckpt_every: int = 0) -> Tuple[np.ndarray, List[np.ndarray]]:
     """Flows every set for its own n_b steps; returns (z_end, checkpoints).

@@ -73,7 +73,7 @@ class cut_graph_desc(C.Structure):
 class cut_flow_params(C.Structure):
     _fields_ = [("generator", C.c_int32), ("precision", C.c_int32), ("ds", C.c_double),
                 ("delta", C.c_double), ("ckpt_every", C.c_int32), ("flags", C.c_uint32),
-                ("step_begin", C.c_int64), ("step_end", C.c_int64)]
+                ("step_begin", C.c_int64), ("step_end", C.c_int64), ("outside_norm2", C.c_void_p)]
 
 
 _vp, _i32, _i64, _u32, _dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_uint32, C.c_double
@@ -243,8 +243,11 @@ def cut_graph_vjp(g: int, kind: int, delta: float, precision: int, nsets: int, n
 
 # ------------------------------------------------------------------- flow --
 def flow_params(generator: int, precision: int, ds: float, delta: float = 0.5, ckpt_every: int = 0,
-                flags: int = CUT_FLOW_HIPGRAPH, step_begin: int = 0, step_end: int = -1):
-    return cut_flow_params(generator, precision, ds, delta, ckpt_every, flags, step_begin, step_end)
+                flags: int = CUT_FLOW_HIPGRAPH, step_begin: int = 0, step_end: int = -1, outside_norm2=None):
+    """outside_norm2: None, or a device float64 tensor of nops*nsets elements that
+    the flow accumulates the outside-space diagnostic into."""
+    return cut_flow_params(generator, precision, ds, delta, ckpt_every, flags, step_begin, step_end,
+                           _ptr(outside_norm2))
 
 
 def _steps_arg(n_steps):

@@ -59,7 +59,7 @@ void eval_generator(Graph& g, int kind, double delta, int32_t nsets, const doubl
 
 void check_generator(const Graph& g, int kind) {
     if (kind == CUT_GEN_G2) {
-        if (!g.have_stencil)
+        if (g.hdr.algebra != CUT_ALG_MAJORANA || !g.have_stencil)
             CUT_FAIL(CUT_E_UNSUPPORTED, "G2 generator needs a pair-flip registry (Majorana strings)");
     } else if (kind != CUT_GEN_WEGNER_GRAPH) {
         CUT_FAIL(CUT_E_INVAL, "unknown generator %d", kind);

@@ -105,6 +105,11 @@ struct StepPlan {
     // stage operand pointers: stage s reads xin[s], writes xout[s]
     void* xin[4];
     void* xout[4];
+    // outside-space diagnostic (null when off): accumulated column norms, the
+    // stage's outside action [n_out][cols] and the partial sums of its squares
+    double* onorm = nullptr;
+    double* cbuf = nullptr;
+    double* cpart = nullptr;
 };
 
 // HIP events bracketing launches (kind 0 = graph pass, 1 = generator)
@@ -139,6 +144,27 @@ static void enqueue_step(const StepPlan& P, hipStream_t s, PassTimer* tm = nullp
         eval_generator(g, P.gen, P.delta, P.nsets, P.fb.hst, P.nsets, P.fb.eta, P.nsets, f32, P.fb.nsteps,
                        P.fb.step, s);
         if (tm) tm->mark(1, s);
+        if (P.onorm) {
+            // C(eta_s, Z_s) over E_C, then b_s ds sum_q C_q^2 per column
+            static const double b[4] = {1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0};
+            PassArgs c{};
+            c.csr = &g.csr[2][0];
+            c.A = P.fb.eta;
+            c.lda = P.nsets;
+            c.B = P.xin[st];
+            c.ldb = cols;
+            c.nsets = P.nsets;
+            c.nops = P.nops;
+            c.precision = P.prec;
+            c.nsteps = P.fb.nsteps;
+            c.step = P.fb.step;
+            c.y = P.cbuf;
+            c.ldy = cols;
+            c.scale = 1.0;
+            launch_pass(MODE_BCAST, EPI_Y, c, s);
+            launch_colsq_accumulate(P.cbuf, g.n_out, cols, P.nsets, P.cpart, kColsqParts, P.fb.nsteps, P.fb.step,
+                                    b[st] * P.ds, P.onorm, s);
+        }
         PassArgs p{};
         p.csr = &g.csr[0][0];
         p.A = P.fb.eta;
@@ -194,7 +220,12 @@ extern "C" cut_status cut_flow_integrate(cut_graph_t h, const cut_flow_params* p
         const int64_t t1 = p->step_end < 0 ? T : std::min<int64_t>(p->step_end, T);
         const bool f32 = p->precision != CUT_F64;
         const int64_t cols = nops * nsets, M = g.N * cols;
-        FlowBufs fb = flow_bufs(g, nsets, nops, p->precision, 0, nullptr);
+        const bool outside = p->outside_norm2 != nullptr;
+        if (outside && !g.have_outside)
+            CUT_FAIL(CUT_E_INVAL, "flow: outside_norm2 needs a graph with outside-space records");
+        const size_t ob = outside ? al(g.n_out * cols * 8) + al((size_t)kColsqParts * cols * 8) : 0;
+        char* oex = nullptr;
+        FlowBufs fb = flow_bufs(g, nsets, nops, p->precision, ob, &oex);
         HIP_CHECK(hipMemcpyAsync(fb.nsteps, n_steps, nsets * 4, hipMemcpyHostToDevice, stream));
         launch_set_scalar(fb.step, (int32_t)t0, stream);
         launch_set_scalar(fb.flag, 0, stream);
@@ -204,6 +235,11 @@ extern "C" cut_status cut_flow_integrate(cut_graph_t h, const cut_flow_params* p
             P.xin[st] = fb.xsh[st & 1];
             P.xout[st] = fb.xsh[(st + 1) & 1];
         }
+        if (outside) {
+            P.onorm = p->outside_norm2;
+            P.cbuf = (double*)oex;
+            P.cpart = (double*)(oex + al(g.n_out * cols * 8));
+        }
         const bool use_graph = (p->flags & CUT_FLOW_HIPGRAPH) && t1 - t0 > 1;
         const bool timed = !use_graph && (p->flags & CUT_FLOW_TIME_PASSES);
         PassTimer timer;
@@ -212,7 +248,8 @@ extern "C" cut_status cut_flow_integrate(cut_graph_t h, const cut_flow_params* p
         if (use_graph) {
             std::vector<uint64_t> key = {(uint64_t)(uintptr_t)z, (uint64_t)(uintptr_t)g.ws.ptr, (uint64_t)p->generator,
                                          (uint64_t)p->precision, (uint64_t)nsets, (uint64_t)nops, 0, 0,
-                                         g.tiling_gen, (uint64_t)(uintptr_t)fb.part};
+                                         g.tiling_gen, (uint64_t)(uintptr_t)fb.part,
+                                         (uint64_t)(uintptr_t)p->outside_norm2};
             std::memcpy(&key[6], &p->ds, 8);
             std::memcpy(&key[7], &p->delta, 8);
             if (!g.graphs || g.graphs->key != key) {

@@ -362,6 +362,12 @@ void launch_prep_state(const double* z, int64_t rows, int32_t nops, int32_t nset
 void launch_round_f32(const double* src, int64_t lds, int64_t rows, int64_t cols, float* dst, int64_t ldd,
                       hipStream_t s);
 void launch_zero2d(double* dst, int64_t ld, int64_t rows, int64_t cols, hipStream_t s);
+// out[c] += weight * sum_r y[r][c]^2 for columns of active sets (fixed order;
+// part holds nparts * cols doubles)
+constexpr int32_t kColsqParts = 256;
+void launch_colsq_accumulate(const double* y, int64_t rows, int64_t cols, int32_t nsets, double* part,
+                             int32_t nparts, const int32_t* nsteps, const int32_t* step, double weight,
+                             double* out, hipStream_t s);
 void launch_bump(int32_t* step, hipStream_t s);
 void launch_set_scalar(int32_t* p, int32_t v, hipStream_t s);
 void launch_adj_combine(int64_t rows, int32_t ncols, int32_t nsets, const int32_t* nsteps,

@@ -1478,6 +1478,46 @@ void launch_zero2d(double* dst, int64_t ld, int64_t rows, int64_t cols, hipStrea
     hipLaunchKernelGGL(k_zero2d, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, dst, ld, rows, cols);
 }
 
+// Column sums of squares of y [rows][cols], deterministic in two kernels:
+// block (bx, by) covers 64 columns from bx*64 and the rows by*4 + w + q*4*gridDim.y
+// (w = wavefront), summed in that order, then its 4 wavefronts in order ->
+// part[by][c]; k_colsq_finish adds the partial rows in order, scales by
+// `weight` and accumulates into out[c] for the columns of active sets.
+__global__ __launch_bounds__(256) void k_colsq_partial(const double* __restrict__ y, int64_t rows, int64_t cols,
+                                                       double* __restrict__ part) {
+    __shared__ double red[4][64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t c = (int64_t)blockIdx.x * 64 + lane;
+    double acc = 0.0;
+    if (c < cols)
+        for (int64_t r = (int64_t)blockIdx.y * 4 + w; r < rows; r += (int64_t)gridDim.y * 4) {
+            const double v = y[r * cols + c];
+            acc = __builtin_fma(v, v, acc);
+        }
+    red[w][lane] = acc;
+    __syncthreads();
+    if (w == 0 && c < cols) part[(int64_t)blockIdx.y * cols + c] = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
+}
+
+__global__ void k_colsq_finish(const double* __restrict__ part, int32_t nparts, int64_t cols, int32_t nsets,
+                               const int32_t* nsteps, const int32_t* step, double weight, double* out) {
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= cols) return;
+    if (nsteps && nsteps[c % nsets] <= *step) return;
+    double acc = 0.0;
+    for (int b = 0; b < nparts; ++b) acc += part[(int64_t)b * cols + c];
+    out[c] += weight * acc;
+}
+
+void launch_colsq_accumulate(const double* y, int64_t rows, int64_t cols, int32_t nsets, double* part,
+                             int32_t nparts, const int32_t* nsteps, const int32_t* step, double weight,
+                             double* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_colsq_partial, dim3((unsigned)((cols + 63) / 64), (unsigned)nparts), dim3(256), 0, s, y,
+                       rows, cols, part);
+    hipLaunchKernelGGL(k_colsq_finish, dim3((unsigned)((cols + 255) / 256)), dim3(256), 0, s, part, nparts, cols,
+                       nsets, nsteps, step, weight, out);
+}
+
 __global__ void k_bump(int32_t* step) {
     if (threadIdx.x == 0) *step += 1;
 }

@@ -42,6 +42,17 @@ def graph(L, alg: str, size: int, adjoint: bool = True):
     return _cache[key]
 
 
+def outside_graph(L, m: int):
+    """Majorana graph built with the outside-space records E_C."""
+    key = ("majorana-outside", m)
+    if key not in _cache:
+        path = os.path.join(_tmp, f"majorana_out_{m}.cgb")
+        if not os.path.exists(path):
+            L.cut_graph_build(L.CUT_ALG_MAJORANA, m, path, 0, L.CUT_BUILD_OUTSIDE)
+        _cache[key] = L.cut_graph_load(path, 0, 0)
+    return _cache[key]
+
+
 def bundle_path(L, alg: str, size: int) -> str:
     path = os.path.join(_tmp, f"{alg}_{size}.cgb")
     if not os.path.exists(path):

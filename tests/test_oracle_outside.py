@@ -55,3 +55,58 @@ def test_outside_records_structure_and_antisymmetry():
     key = {(int(k), int(i), int(j)): c for k, i, j, c in zip(og.k, og.i, og.j, og.c)}
     for (k, i, j), c in list(key.items())[:5000]:
         assert key[(k, j, i)] == -c
+
+
+def test_flow_outside_diagnostic_matches_dense_commutators():
+    """One RK4 step at m = 8: the leak equals sum_s b_s ds |(I - P)[eta_s, Z_s]|^2
+    with the outside part taken from dense matrices as the full Frobenius norm
+    (orthonormal string basis) minus the registry part, and the flowed state
+    equals the plain integrator's."""
+    from oracle import flow as OF
+    from oracle import gen as OG
+    m = 8
+    subs, mats = brute.dense_strings(m)
+    dim = mats.shape[-1]
+    g = A.majorana_graph(m)
+    og = A.majorana_outside_graph(m)
+    gen, _ = OG.make_generator(g, "g2", 0.5)
+    rng = np.random.default_rng(4)
+    z0 = rng.normal(size=(g.N, 2, 2))
+    ds = 0.05
+    z1, leak = OF.integrate_outside(g, gen, og, z0, ds, [1, 1])
+    zr, _ = OF.integrate(g, gen, z0, ds, [1, 1])
+    np.testing.assert_array_equal(z1, zr)
+    ref = np.zeros((2, 2))
+    stage, ks = z0, []
+    for s, b in enumerate(OF.RK4_WEIGHTS):
+        k, eta = OF.rhs(g, gen, stage)
+        for op in range(2):
+            for st in range(2):
+                etaop = np.einsum("a,axy->xy", 1j * eta[:, st], mats)
+                xop = np.einsum("a,axy->xy", stage[:, op, st], mats)
+                M = etaop @ xop - xop @ etaop
+                total = np.sum(np.abs(M) ** 2) / dim
+                inside = np.sum(np.abs(brute.project(mats, M)) ** 2)
+                ref[op, st] += b * ds * (total - inside)
+        ks.append(k)
+        if s < 3:
+            stage = z0 + (0.5 if s < 2 else 1.0) * ds * k
+    assert np.max(ref) > 1e-3
+    np.testing.assert_allclose(leak, ref, rtol=1e-10)
+
+
+def test_flow_outside_zero_in_closed_quadratic_algebra():
+    """Quadratic strings close under the bracket: with no quartic coefficients
+    the flow never leaves degree 2 and the outside action vanishes."""
+    from oracle import flow as OF
+    from oracle import gen as OG
+    m = 10
+    g = A.majorana_graph(m)
+    og = A.majorana_outside_graph(m)
+    gen, _ = OG.make_generator(g, "g2", 0.5)
+    rng = np.random.default_rng(5)
+    z0 = np.zeros((g.N, 2, 3))
+    nq = m * (m - 1) // 2
+    z0[:nq] = rng.normal(size=(nq, 2, 3))
+    _, leak = OF.integrate_outside(g, gen, og, z0, 0.02, [5, 3, 0])
+    assert np.all(leak == 0.0)
