@@ -28,6 +28,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 FP64_VEC_TFLOPS = 78.6
+FP64_MFMA_TFLOPS = 78.6   # dense FP64 matrix peak (the vector FP64 peak is the same figure)
 
 
 def log(msg):
@@ -143,6 +144,107 @@ def derivative_leg(L, torch, g, inp, w, prec, E):
             "unit": "contributions×batch/s"}
 
 
+def assembly_leg(L, torch, N):
+    """Multi-operator assembly (Sec. 3.4): 1024 output combinations of a
+    120-operator transformed library over N registry rows, FP64 on the matrix
+    cores; torch's FP64 matmul (the vendor BLAS) on the same operands as a
+    reference point."""
+    dev = torch.device("cuda:0")
+    S, K = 120, 1024
+    gen = torch.Generator(device="cpu").manual_seed(11)
+    X = torch.randn((N, S), generator=gen, dtype=torch.float64).to(dev)
+    W = torch.randn((S, K), generator=gen, dtype=torch.float64).to(dev)
+    Y = torch.empty((N, K), dtype=torch.float64, device=dev)
+    t = _time_calls(torch, lambda: L.cut_assemble(X, W, Y), 20)
+    tb = _time_calls(torch, lambda: torch.matmul(X, W, out=Y), 20)
+    flops = 2.0 * N * S * K
+    return {"shape": f"Y[{N}, {K}] = X[{N}, {S}] W[{S}, {K}], FP64", "ms": t * 1e3,
+            "tflops": flops / t / 1e12, "peak_tflops": FP64_MFMA_TFLOPS,
+            "frac": flops / t / 1e12 / FP64_MFMA_TFLOPS, "vendor_blas_ms": tb * 1e3,
+            "bytes_min": 8 * (N * S + S * K + N * K)}
+
+
+def pauli_boson_leg(L, torch, tmp):
+    """The paper's own algebra at its benchmark size (Sec. 3.2-3.3): five boson
+    modes, complete degree-four Pauli-boson registry (4,004 labels), generator
+    and retained flow 7,017,036 records, outside space 345,388,180 records.
+    FP64 on complex coefficients (real-split rows), Wegner block generator,
+    a batch of eight operators (the Hamiltonian and seven Hermitian operators):
+    one retained-flow action (generator + retained pass), the same with the
+    outside-space action, and a 100-step RK4 flow without and with the
+    outside-space diagnostic at every right-hand side."""
+    import numpy as np
+    import workloads
+    dev = torch.device("cuda:0")
+    M, p = 5, 4
+    path = os.path.join(tmp, "pb5.cgb")
+    t0 = time.perf_counter()
+    desc = L.cut_graph_build(L.CUT_ALG_PAULI_BOSON, 256 * M + p, path, 0, L.CUT_BUILD_OUTSIDE)
+    build_s = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    g = L.cut_graph_load(path, 0, 0)
+    load_s = time.perf_counter() - t0
+    os.remove(path)
+    N, NG, Nc = desc["n_ops"], desc["n_gen_ops"], desc["n_out_ops"]
+    W = (3 * p).bit_length()
+    labels = [workloads.pb_label(int(k), M, W) for k in L.cut_graph_labels(g, 0)]
+    rng = np.random.default_rng([260914831, 55])
+    nops, nsets = 8, 1
+    # H with small off-diagonal parts (the projected flow of a complete boson
+    # registry is stiff), seven Hermitian operators with O(1) coefficients
+    z0 = np.stack([workloads.pb_hermitian(labels, rng, 1.0, 0.02 if o == 0 else 1.0) for o in range(nops)], 1)
+    z0 = workloads.real_split(z0)[:, :, None]                                 # [2N, 8, 1]
+    x = torch.tensor(z0.reshape(2 * N, nops), device=dev)
+    h = x[:, :1].contiguous()
+    eta = torch.empty((2 * NG, 1), dtype=torch.float64, device=dev)
+    y = torch.empty((2 * N, nops), dtype=torch.float64, device=dev)
+    yc = torch.empty((2 * Nc, nops), dtype=torch.float64, device=dev)
+
+    def retained():
+        L.cut_generator(g, L.CUT_GEN_WEGNER_GRAPH, 0.0, nsets, h, eta)
+        L.cut_graph_apply(g, L.CUT_GRAPH_FLOW, L.CUT_F64, nsets, nops, eta, x, y)
+
+    def diagnostic():
+        retained()
+        L.cut_graph_apply(g, L.CUT_GRAPH_OUTSIDE, L.CUT_F64, nsets, nops, eta, x, yc)
+
+    t_ret = _time_calls(torch, retained, 20)
+    t_diag = _time_calls(torch, diagnostic, 5)
+    ds, steps = 1e-3, 100
+
+    def flow(with_diag):
+        z = torch.tensor(z0, device=dev).contiguous()
+        leak = torch.zeros(nops * nsets, dtype=torch.float64, device=dev) if with_diag else None
+        prm = L.flow_params(L.CUT_GEN_WEGNER_GRAPH, L.CUT_F64, ds, 0.0, 0, outside_norm2=leak)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        L.cut_flow_integrate(g, prm, nsets, nops, [steps], z)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, z
+
+    try:
+        flow(False)                       # capture the step graph once
+        t_flow, z_plain = flow(False)
+        t_flow_d, z_diag = flow(True)
+        same = bool(torch.equal(z_plain, z_diag))
+    except L.CutError as e:               # reported, not hidden: the leg records the failure
+        t_flow = t_flow_d = None
+        same = None
+        log(f"pauli-boson flow failed: {e}")
+    L.cut_graph_free(g)
+    return {"graph": f"pauli-boson M={M} p={p}: {N} labels, generator registry {NG}, outside registry {Nc}; "
+                     f"E_eta {desc['n_gen_records']} + E_L {desc['n_records']} = "
+                     f"{desc['n_gen_records'] + desc['n_records']} production records, "
+                     f"E_C {desc['n_out_records']} outside-space records",
+            "compile_s": build_s, "load_s": load_s, "bundle_bytes": desc["file_bytes"],
+            "batch": "8 operators (H + 7), FP64 complex (real-split), Wegner block generator",
+            "retained_action_ms": t_ret * 1e3, "action_with_outside_ms": t_diag * 1e3,
+            "flow_100_steps_s": t_flow, "flow_100_steps_with_outside_s": t_flow_d,
+            "trajectory_unchanged_by_diagnostic": same,
+            "paper_h100": {"retained_action_ms": 0.632, "action_with_outside_ms": 48.439,
+                           "flow_100_steps_s": 0.498, "flow_100_steps_with_outside_s": 22.216}}
+
+
 def outside_leg(L, torch, tmp):
     """The outside-space action C_q (Eq. graph-actions, third line) on the
     m = 32 Majorana graph: 906,192 outside targets, 471.2M records (the scale of
@@ -190,6 +292,8 @@ def main():
     ap.add_argument("--precision", default="f32c", choices=["f32c", "f32x", "f64", "f32"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-outside", action="store_true", help="skip the outside-space action leg")
+    ap.add_argument("--only", choices=["assembly", "outside", "pauli_boson"],
+                    help="run only that leg and print its JSON (for profiling)")
     ap.add_argument("--minimal", action="store_true", help="timed flow only")
     ap.add_argument("--profile", action="store_true",
                     help="counter runs: a 1 GiB device copy (calibration), then the steps in "
@@ -213,6 +317,19 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
     w = workloads.WORKLOADS[3]
+    if args.only == "assembly":
+        import math
+        n40 = math.comb(w.size, 2) + math.comb(w.size, 4)     # registry rows of the m = 40 graph
+        print(json.dumps({"assembly": assembly_leg(L, torch, n40)}), flush=True)
+        return
+    if args.only == "pauli_boson":
+        print(json.dumps({"pauli_boson": pauli_boson_leg(L, torch, tempfile.mkdtemp(prefix="cutgraph_bench_"))}),
+              flush=True)
+        return
+    if args.only == "outside":
+        print(json.dumps({"outside_space": outside_leg(L, torch, tempfile.mkdtemp(prefix="cutgraph_bench_"))}),
+              flush=True)
+        return
     PREC = {"f32c": L.CUT_F32C, "f32x": L.CUT_F32X, "f64": L.CUT_F64, "f32": L.CUT_F32}[args.precision]
     pbytes = 8 if PREC == L.CUT_F64 else 4
 
@@ -371,9 +488,14 @@ def main():
     L.cut_graph_free(g)
     os.remove(path)
 
+    out["assembly"] = assembly_leg(L, torch, N)
+    log(f"assembly: {out['assembly']}")
+
     if not args.no_outside:
         out["outside_space"] = outside_leg(L, torch, tmp)
         log(f"outside-space action: {out['outside_space']}")
+        out["pauli_boson"] = pauli_boson_leg(L, torch, tmp)
+        log(f"pauli-boson five-mode graph: {out['pauli_boson']}")
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(inp, w, nsets, nops)

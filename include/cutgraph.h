@@ -53,9 +53,15 @@ typedef enum {
 typedef enum {
     CUT_ALG_EPQ = 1,        /* one-body fermion operators E_pq, size = n orbitals,
                                registry index p*n+q, [E_pq,E_rs] = d_qr E_ps - d_ps E_rq */
-    CUT_ALG_MAJORANA = 2    /* even Majorana strings of degree 2 and 4 over m = size
+    CUT_ALG_MAJORANA = 2,   /* even Majorana strings of degree 2 and 4 over m = size
                                modes, registry = 2-subsets then 4-subsets, each
                                lexicographic; generator basis i*Gamma_S */
+    CUT_ALG_PAULI_BOSON = 3 /* Pauli-boson labels B_{tau,c,a} = sigma_tau prod_m
+                               (b_m^+)^{c_m} b_m^{a_m} (Eq. monomial) over M boson
+                               modes, the complete degree-p registry |c|+|a| <= p
+                               (4 C(2M+p, p) labels, Eq. basis-size); size =
+                               256 M + p (M in 1..5).  Complex coefficients; the
+                               generator [H_d, H_od] has a registry of its own */
 } cut_algebra;
 
 /* Record sets stored in a graph (Eq. graph-actions). */
@@ -102,6 +108,7 @@ typedef struct {
     int64_t n_pairs;        /* diagonal quadratic coordinates (pair energies) */
     int64_t n_out_ops;      /* outside registry size (0 without E_C) */
     int64_t n_out_records;  /* |E_C| */
+    int64_t n_gen_ops;      /* generator registry size (0: the operator registry) */
     uint64_t checksum;      /* combined checksum of the record sections */
     int64_t file_bytes;     /* bundle size on disk */
     double build_seconds;   /* compiler wall time (cut_graph_build only) */
@@ -144,6 +151,20 @@ cut_status cut_graph_build(int32_t algebra, int32_t size, const char* path, int3
 cut_status cut_graph_load(const char* path, int32_t hip_device, uint32_t flags, cut_graph_t* out);
 
 cut_status cut_graph_info(cut_graph_t g, cut_graph_desc* desc);
+
+/* cut_graph_labels: copies the labels of a registry into host memory `out` of
+ * exactly n entries: which = CUT_GRAPH_FLOW the operator registry (n_ops),
+ * CUT_GRAPH_GEN the generator registry (n_gen_ops, or the operator registry
+ * when n_gen_ops is 0), CUT_GRAPH_OUTSIDE the outside registry (n_out_ops).
+ * Label keys: E_pq p << 32 | q; Majorana the bitmask of the string's modes;
+ * Pauli-boson W-bit fields, W the bit length of 3p, from the most significant:
+ * total degree, tau (2 bits: 0 = I, 1 = x, 2 = y, 3 = z), then c_1, a_1, ...,
+ * c_M, a_M (their numeric order is the registry order).  Pauli-boson
+ * coefficient vectors are complex and stored real-split on the device: a
+ * registry of n labels has 2n rows, row r the real and row n + r the imaginary
+ * part of coefficient r (operands, generator, outputs alike).
+ * Errors: CUT_E_INVAL (null argument, unknown or absent registry, n mismatch). */
+cut_status cut_graph_labels(cut_graph_t g, int32_t which, uint64_t* out, int64_t n);
 void cut_graph_free(cut_graph_t g);
 
 /* ------------------------------------------------------------------ apply --
@@ -152,9 +173,13 @@ void cut_graph_free(cut_graph_t g);
  * for 0 <= k < N, 0 <= op < nops, 0 <= s < nsets.  eta and x are double* for
  * CUT_F64 and float* otherwise; y is always double*.  Requires nsets >= 1,
  * 1 <= nops <= 8, lde >= nsets, ldx >= nops*nsets, ldy >= nops*nsets.
- * y must not alias eta or x.  With which = CUT_GRAPH_OUTSIDE, y has one row per
- * outside registry entry (n_out_ops rows; CUT_E_INVAL if the bundle has no
- * outside-space records). */
+ * y must not alias eta or x.  Row counts: x has one row per operator row,
+ * eta one per generator row (the same unless the generator has a registry of its
+ * own, n_gen_ops > 0), y one per target row: operator rows for CUT_GRAPH_FLOW,
+ * generator rows for CUT_GRAPH_GEN (whose inputs are both operator rows), outside
+ * rows for CUT_GRAPH_OUTSIDE (CUT_E_INVAL if the bundle has no outside-space
+ * records).  Pauli-boson graphs have twice as many rows as labels (real-split,
+ * see cut_graph_labels). */
 cut_status cut_graph_apply(cut_graph_t g, int32_t which, int32_t precision, int64_t nsets,
                            int64_t nops, const void* eta, int64_t lde, const void* x,
                            int64_t ldx, double* y, int64_t ldy, uint32_t flags, void* stream);
@@ -173,10 +198,11 @@ cut_status cut_graph_apply_adjoint(cut_graph_t g, int32_t which, int32_t precisi
                                    void* stream);
 
 /* -------------------------------------------------------------- generator --
- * cut_generator: eta[r][s] from h[r][s] (both double, [N][nsets] with leading
- * dimensions), for CUT_GEN_WEGNER_GRAPH (eta_k = s_g sum_{E_eta(k)} c (Dh)_i
- * ((I-D)h)_j, s_g = +1 for E_pq and -1 for Majorana strings, whose generator
- * basis is i*Gamma) or CUT_GEN_G2 (Majorana only; eta = 0 on diagonal strings).
+ * cut_generator: eta[r][s] from h[r][s] (both double with leading dimensions;
+ * h has the operator rows, eta the generator rows), for CUT_GEN_WEGNER_GRAPH
+ * (eta_k = s_g sum_{E_eta(k)} c (Dh)_i ((I-D)h)_j, s_g = +1 for E_pq and
+ * Pauli-boson labels, -1 for Majorana strings, whose generator basis is
+ * i*Gamma) or CUT_GEN_G2 (Majorana only; eta = 0 on diagonal strings).
  * cut_generator_vjp: g_h[r][s] += sum_S gbar[S][s] d eta_S / d h_r. */
 cut_status cut_generator(cut_graph_t g, int32_t kind, double delta, int64_t nsets,
                          const double* h, int64_t ldh, double* eta, int64_t lde, void* stream);
@@ -231,6 +257,21 @@ cut_status cut_graph_vjp(cut_graph_t g, int32_t kind, double delta, int32_t prec
                          int64_t nops, const double* h, int64_t ldh, const double* x, int64_t ldx,
                          const double* w, int64_t ldw, double* g_h, int64_t ldgh, double* g_x,
                          int64_t ldgx, uint32_t flags, void* stream);
+
+/* --------------------------------------------------------------- assembly --
+ * cut_assemble: output operators as linear combinations of a transformed
+ * source library (Sec. 2.4, last paragraph; Sec. 3.4: one completed transform
+ * serves many output combinations without another expansion):
+ *   Y[n][k] (=|+=) sum_{s < S} X[n][s] * W[s][k],   0 <= n < N, 0 <= k < K,
+ * X [N][ldx] the transformed coefficient vectors of the S sources (one column
+ * per source, e.g. the operand columns of a flowed state), W [S][ldw] the
+ * weights, Y [N][ldy]; all double, device memory owned by the caller; `=|+=`
+ * follows CUT_ACCUMULATE.  FP64 on the matrix cores (MFMA 16x16x4 FP64; each
+ * output is summed in chunks of 4 sources in source order).  Needs no graph.
+ * Requires S >= 1, K >= 1, N >= 0, ldx >= S, ldw >= K, ldy >= K, K <= 4194240;
+ * Y must not alias X or W.  Errors: CUT_E_INVAL, CUT_E_DEVICE. */
+cut_status cut_assemble(const double* X, int64_t ldx, int64_t N, int64_t S, const double* W, int64_t ldw,
+                        int64_t K, double* Y, int64_t ldy, uint32_t flags, void* stream);
 
 /* ------------------------------------------------------------------- flow --
  * Coflow of H and nops-1 observables (Eq. coflow; Eq. forward-coeff) with the

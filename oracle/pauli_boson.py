@@ -1,0 +1,198 @@
+"""Pauli-boson operator algebra and its compiled records (exact arithmetic).
+
+Test infrastructure (see the package docstring).
+
+Sec. 2.1, Eq. monomial: operator labels B_{tau,c,a} = sigma_tau prod_m
+(b_m^dagger)^{c_m} b_m^{a_m}, tau in {I, x, y, z}, c, a in N_0^M.  The complete
+degree-p registry holds every label with |c| + |a| <= p; its size is
+4 C(2M + p, p) (Eq. basis-size).  Products are evaluated in the full bosonic
+algebra and normal ordered before membership in the registry is tested.  The
+block-diagonal coordinates (mask D) are the I and sigma_z labels with c = a
+(joint sigma_z / boson-number blocks).
+
+Sec. 2.2, Eq. graph-actions: with the generator eta = [H_d, H_od] (Eq.
+block-generator) expanded exactly,
+  E_eta: xi_a = sum alpha (Dh)_i ((I-D)h)_j   over i in D, j not in D,
+         [B_i, B_j] = sum_a alpha B_a  (a ranges over the generator registry:
+         every label that occurs);
+  E_L:   F_k = sum beta xi_a x_j    over the generator registry a and the
+         registry j, [B_a, B_j] = sum_k beta B_k with k in the registry;
+  E_C:   the same terms with k outside the registry (optional diagnostic).
+Factors are Gaussian integers (sigma products contribute powers of i, normal
+ordering contributes k! C(a, k) C(c', k) per mode); they are kept exact as
+(re, im) pairs of Python ints.
+
+Canonical orders (a reading; the paper does not print one): every registry is
+sorted by (total bosonic degree, tau, c_1, a_1, ..., c_M, a_M); records within
+a target by (left input index, right input index).
+"""
+from __future__ import annotations
+
+import itertools
+import math
+from functools import lru_cache
+from typing import Dict, List, Tuple
+
+Label = Tuple[int, Tuple[int, ...], Tuple[int, ...]]      # (tau, c, a)
+GInt = Tuple[int, int]                                     # re, im
+
+# sigma_t sigma_u = phase * sigma_w, phase = i**e; tau 0 = I, 1 = x, 2 = y, 3 = z
+_CYCLIC = {(1, 2), (2, 3), (3, 1)}
+
+
+def pauli_mul(t: int, u: int) -> Tuple[int, int]:
+    """(w, e) with sigma_t sigma_u = i**e sigma_w."""
+    if t == 0:
+        return u, 0
+    if u == 0:
+        return t, 0
+    if t == u:
+        return 0, 0
+    w = 6 - t - u
+    return w, (1 if (t, u) in _CYCLIC else 3)
+
+
+@lru_cache(maxsize=None)
+def mode_product(c1: int, a1: int, c2: int, a2: int) -> Tuple[Tuple[int, int, int], ...]:
+    """Normal ordering of (b^+)^c1 b^a1 (b^+)^c2 b^a2 for one mode:
+    sum_k k! C(a1, k) C(c2, k) (b^+)^(c1+c2-k) b^(a1+a2-k)  (Wick contractions of
+    the a1 annihilators with the c2 creators).  Returns ((c, a, coeff), ...)."""
+    out = []
+    for k in range(min(a1, c2) + 1):
+        out.append((c1 + c2 - k, a1 + a2 - k, math.factorial(k) * math.comb(a1, k) * math.comb(c2, k)))
+    return tuple(out)
+
+
+def boson_product(cA, aA, cB, aB) -> List[Tuple[Tuple[int, ...], Tuple[int, ...], int]]:
+    """Normal-ordered product of two multi-mode monomials (modes commute)."""
+    terms = [((), (), 1)]
+    for m in range(len(cA)):
+        nxt = []
+        for c, a, f in terms:
+            for cc, aa, g in mode_product(cA[m], aA[m], cB[m], aB[m]):
+                nxt.append((c + (cc,), a + (aa,), f * g))
+        terms = nxt
+    return terms
+
+
+_IPOW = [(1, 0), (0, 1), (-1, 0), (0, -1)]
+
+
+def commutator(A: Label, B: Label) -> Dict[Label, GInt]:
+    """[B_A, B_B] as {label: Gaussian-integer coefficient}, zeros dropped."""
+    out: Dict[Label, List[int]] = {}
+    for (X, Y, sign) in ((A, B, 1), (B, A, -1)):
+        w, e = pauli_mul(X[0], Y[0])
+        pr, pi = _IPOW[e]
+        for c, a, f in boson_product(X[1], X[2], Y[1], Y[2]):
+            acc = out.setdefault((w, c, a), [0, 0])
+            acc[0] += sign * pr * f
+            acc[1] += sign * pi * f
+    return {k: (v[0], v[1]) for k, v in out.items() if v[0] != 0 or v[1] != 0}
+
+
+def degree(L: Label) -> int:
+    return sum(L[1]) + sum(L[2])
+
+
+def sort_key(L: Label):
+    key = [degree(L), L[0]]
+    for m in range(len(L[1])):
+        key += [L[1][m], L[2][m]]
+    return tuple(key)
+
+
+def registry(M: int, p: int) -> List[Label]:
+    """The complete degree-p registry in canonical order."""
+    out = []
+    for exps in itertools.product(range(p + 1), repeat=2 * M):
+        if sum(exps) > p:
+            continue
+        c, a = tuple(exps[0::2]), tuple(exps[1::2])
+        for tau in range(4):
+            out.append((tau, c, a))
+    return sorted(out, key=sort_key)
+
+
+def registry_size(M: int, p: int) -> int:
+    """Eq. basis-size."""
+    return 4 * math.comb(2 * M + p, p)
+
+
+def is_diagonal(L: Label) -> bool:
+    return L[0] in (0, 3) and L[1] == L[2]
+
+
+class PBGraph:
+    """Registries and record lists (k, i, j, (re, im)) of one (M, p)."""
+
+    def __init__(self, M: int, p: int, outside: bool = False):
+        self.M, self.p = M, p
+        self.labels = registry(M, p)
+        self.index = {L: n for n, L in enumerate(self.labels)}
+        self.N = len(self.labels)
+        self.diag = [is_diagonal(L) for L in self.labels]
+        D = [n for n in range(self.N) if self.diag[n]]
+        OD = [n for n in range(self.N) if not self.diag[n]]
+        # E_eta: products of a diagonal and an off-diagonal coordinate
+        raw = []
+        for i in D:
+            for j in OD:
+                for L, f in commutator(self.labels[i], self.labels[j]).items():
+                    raw.append((L, i, j, f))
+        self.gen_labels = sorted({r[0] for r in raw}, key=sort_key)
+        self.gen_index = {L: n for n, L in enumerate(self.gen_labels)}
+        self.NG = len(self.gen_labels)
+        self.eta = sorted((self.gen_index[L], i, j, f) for L, i, j, f in raw)
+        # E_L and E_C: generator coordinate x registry coordinate
+        rec_l, rec_c = [], []
+        for a, A in enumerate(self.gen_labels):
+            for j, B in enumerate(self.labels):
+                for L, f in commutator(A, B).items():
+                    k = self.index.get(L)
+                    if k is not None:
+                        rec_l.append((k, a, j, f))
+                    elif outside:
+                        rec_c.append((L, a, j, f))
+        self.flow = sorted(rec_l)
+        if outside:
+            self.out_labels = sorted({r[0] for r in rec_c}, key=sort_key)
+            oi = {L: n for n, L in enumerate(self.out_labels)}
+            self.outside = sorted((oi[L], a, j, f) for L, a, j, f in rec_c)
+
+    # ---------------------------------------------------------------- actions
+    def generator(self, h):
+        """xi = sum alpha (Dh)_i ((I-D)h)_j over E_eta (complex h of length N)."""
+        import numpy as np
+        xi = np.zeros(self.NG, dtype=complex)
+        for a, i, j, f in self.eta:
+            xi[a] += complex(*f) * h[i] * h[j]
+        return xi
+
+    def action(self, xi, x):
+        """F_k = sum beta xi_a x_j over E_L (complex vectors)."""
+        import numpy as np
+        y = np.zeros(self.N, dtype=complex)
+        for k, a, j, f in self.flow:
+            y[k] += complex(*f) * xi[a] * x[j]
+        return y
+
+
+def flow(g: "PBGraph", z0, ds: float, steps: int):
+    """Classic RK4 of the coflow (Eq. coflow): z[:, 0] = H, z[:, 1:] = operators,
+    dz/ds = P[eta(H), z] with eta = [H_d, H_od] from E_eta and P[.,.] from E_L
+    (complex coefficients; the integrator reading of the Majorana flow)."""
+    import numpy as np
+    z = np.array(z0, dtype=complex)
+
+    def rhs(u):
+        xi = g.generator(u[:, 0])
+        return np.stack([g.action(xi, u[:, o]) for o in range(u.shape[1])], axis=1)
+
+    for _ in range(steps):
+        k1 = rhs(z)
+        k2 = rhs(z + 0.5 * ds * k1)
+        k3 = rhs(z + 0.5 * ds * k2)
+        k4 = rhs(z + ds * k3)
+        z = z + (ds / 6.0) * (k1 + 2 * k2 + 2 * k3 + k4)
+    return z

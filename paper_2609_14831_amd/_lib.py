@@ -28,7 +28,7 @@ _L = C.CDLL(LIB_PATH)
 # status codes / enums (mirror include/cutgraph.h)
 CUT_OK, CUT_E_INVAL, CUT_E_IO, CUT_E_FORMAT, CUT_E_CHECKSUM = 0, 1, 2, 3, 4
 CUT_E_NOMEM, CUT_E_DEVICE, CUT_E_NUMERIC, CUT_E_UNSUPPORTED = 5, 6, 7, 8
-CUT_ALG_EPQ, CUT_ALG_MAJORANA = 1, 2
+CUT_ALG_EPQ, CUT_ALG_MAJORANA, CUT_ALG_PAULI_BOSON = 1, 2, 3
 CUT_GRAPH_FLOW, CUT_GRAPH_GEN, CUT_GRAPH_OUTSIDE = 0, 1, 2
 CUT_BUILD_OUTSIDE = 1
 CUT_F64, CUT_F32C, CUT_F32X, CUT_F32 = 0, 1, 2, 3
@@ -47,7 +47,7 @@ STATUS_NAMES = {0: "CUT_OK", 1: "CUT_E_INVAL", 2: "CUT_E_IO", 3: "CUT_E_FORMAT",
 # symbols declared in include/cutgraph.h
 EXPORTS = ["cut_graph_build", "cut_graph_load", "cut_graph_info", "cut_graph_free",
            "cut_graph_apply", "cut_graph_apply_adjoint", "cut_generator", "cut_generator_vjp",
-           "cut_generator_jvp", "cut_graph_jvp", "cut_graph_vjp",
+           "cut_generator_jvp", "cut_graph_jvp", "cut_graph_vjp", "cut_assemble", "cut_graph_labels",
            "cut_flow_integrate", "cut_flow_adjoint", "cut_graph_set_tiling", "cut_graph_autotune",
            "cut_flow_last_timing", "cut_last_error", "cut_version"]
 
@@ -61,7 +61,7 @@ class CutError(RuntimeError):
 class cut_graph_desc(C.Structure):
     _fields_ = [("algebra", C.c_int32), ("size", C.c_int32), ("n_ops", C.c_int64),
                 ("n_records", C.c_int64), ("n_gen_records", C.c_int64), ("n_pairs", C.c_int64),
-                ("n_out_ops", C.c_int64), ("n_out_records", C.c_int64), ("checksum", C.c_uint64), ("file_bytes", C.c_int64), ("build_seconds", C.c_double),
+                ("n_out_ops", C.c_int64), ("n_out_records", C.c_int64), ("n_gen_ops", C.c_int64), ("checksum", C.c_uint64), ("file_bytes", C.c_int64), ("build_seconds", C.c_double),
                 ("identifier", C.c_char * 96)]
 
     def as_dict(self):
@@ -87,6 +87,8 @@ _L.cut_graph_apply_adjoint.argtypes = [_vp, _i32, _i32, _i64, _i64, _vp, _i64, _
                                        _vp, _i64, _vp, _i64, _u32, _vp]
 _L.cut_generator.argtypes = [_vp, _i32, _dbl, _i64, _vp, _i64, _vp, _i64, _vp]
 _L.cut_generator_vjp.argtypes = [_vp, _i32, _dbl, _i64, _vp, _i64, _vp, _i64, _vp, _i64, _vp]
+_L.cut_graph_labels.argtypes = [_vp, _i32, C.POINTER(C.c_uint64), _i64]
+_L.cut_assemble.argtypes = [_vp, _i64, _i64, _i64, _vp, _i64, _i64, _vp, _i64, _u32, _vp]
 _L.cut_generator_jvp.argtypes = [_vp, _i32, _dbl, _i64, _vp, _i64, _vp, _i64, _vp, _i64, _vp]
 _L.cut_graph_jvp.argtypes = [_vp, _i32, _dbl, _i32, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _i64, _vp, _i64,
                              _vp, _i64, _vp, _i64, _vp]
@@ -179,6 +181,16 @@ def cut_graph_info(g: int) -> dict:
     return d.as_dict()
 
 
+def cut_graph_labels(g: int, which: int = 0):
+    """Registry labels as a numpy uint64 array (which: CUT_GRAPH_FLOW / _GEN / _OUTSIDE)."""
+    import numpy as np
+    d = cut_graph_info(g)
+    n = {0: d["n_ops"], 1: d["n_gen_ops"] or d["n_ops"], 2: d["n_out_ops"]}[which]
+    out = np.zeros(n, dtype=np.uint64)
+    _check(_L.cut_graph_labels(g, which, out.ctypes.data_as(C.POINTER(C.c_uint64)), n))
+    return out
+
+
 def cut_graph_free(g: int) -> None:
     _L.cut_graph_free(g)
 
@@ -239,6 +251,15 @@ def cut_graph_vjp(g: int, kind: int, delta: float, precision: int, nsets: int, n
     _check(_L.cut_graph_vjp(g, kind, delta, precision, nsets, nops, _ptr(h), _ld(h, nsets), _ptr(x),
                             _ld(x, cols), _ptr(w), _ld(w, cols), _ptr(g_h), _ld(g_h, nsets), _ptr(g_x),
                             _ld(g_x, cols), flags, _stream(stream)))
+
+
+# --------------------------------------------------------------- assembly --
+def cut_assemble(X, W, Y, flags: int = 0, stream=None) -> None:
+    """Y (=|+=) X @ W for 2-D float64 device tensors X [N, S], W [S, K], Y [N, K]."""
+    N, S = X.shape
+    K = W.shape[1]
+    _check(_L.cut_assemble(_ptr(X), _ld(X, S), N, S, _ptr(W), _ld(W, K), K, _ptr(Y), _ld(Y, K), flags,
+                           _stream(stream)))
 
 
 # ------------------------------------------------------------------- flow --

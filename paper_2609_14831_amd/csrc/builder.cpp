@@ -26,6 +26,7 @@
 #include <cstring>
 #include <functional>
 #include <thread>
+#include <unordered_map>
 
 #include "internal.h"
 
@@ -315,6 +316,471 @@ static void parallel_for(int64_t n, int threads, const std::function<void(int64_
     for (auto& t : th) t.join();
 }
 
+
+// ------------------------------------------------------------ Pauli-boson --
+// Labels B_{tau,c,a} = sigma_tau prod_m (b_m^+)^{c_m} b_m^{a_m} (Eq. monomial),
+// each packed into one 64-bit key whose numeric order is the canonical order
+// (total bosonic degree, tau, c_1, a_1, ..., c_M, a_M): W bits per field, the
+// degree on top, then tau (2 bits), then the exponents, c_1 most significant.
+// W holds 3p, the largest exponent or degree a commutator of a generator label
+// (degree <= 2p) with a registry label (degree <= p) can reach.
+struct PBCodec {
+    int M = 0, W = 0;
+    uint64_t key(int tau, const int* c, const int* a) const {
+        uint64_t d = 0, v = 0;
+        for (int m = 0; m < M; ++m) {
+            d += (uint64_t)(c[m] + a[m]);
+            v = (v << W) | (uint64_t)c[m];
+            v = (v << W) | (uint64_t)a[m];
+        }
+        return (((d << 2) | (uint64_t)tau) << (2 * M * W)) | v;
+    }
+    void unpack(uint64_t k, int& tau, int* c, int* a) const {
+        const uint64_t mask = (1ull << W) - 1;
+        for (int m = M - 1; m >= 0; --m) {
+            a[m] = (int)(k & mask);
+            k >>= W;
+            c[m] = (int)(k & mask);
+            k >>= W;
+        }
+        tau = (int)(k & 3);
+    }
+};
+
+struct PBTerm {
+    uint64_t key;
+    int64_t re, im;
+};
+
+// [B_A, B_B] = B_A B_B - B_B B_A, merged by label, zero sums dropped.  Pauli
+// part: sigma_t sigma_u = i^e sigma_w (x y = i z and cyclic); boson part per
+// mode: (b^+)^c1 b^a1 (b^+)^c2 b^a2 = sum_k k! C(a1,k) C(c2,k) (b^+)^(c1+c2-k)
+// b^(a1+a2-k) (each of k annihilators of the left factor contracted with a
+// creator of the right one).
+struct PBAlgebra {
+    PBCodec cd;
+    int p = 0;
+    int64_t binom[64][64];
+    int64_t fact[32];
+    PBAlgebra(int M_, int p_) : p(p_) {
+        cd.M = M_;
+        int w = 1;
+        while ((1 << w) <= 3 * p_) ++w;
+        cd.W = w;
+        for (int n = 0; n < 64; ++n)
+            for (int k = 0; k < 64; ++k) binom[n][k] = (k == 0) ? 1 : (n == 0 ? 0 : binom[n - 1][k - 1] + binom[n - 1][k]);
+        fact[0] = 1;
+        for (int n = 1; n < 21; ++n) fact[n] = fact[n - 1] * n;   // 20! is the last in int64
+        for (int n = 21; n < 32; ++n) fact[n] = 0;
+    }
+    bool fits() const { return (2 * cd.M + 1) * cd.W + 2 <= 64 && 3 * p < 64; }
+    mutable std::atomic<bool> overflow{false};   // a factor left the int64 range (never cleared)
+
+    static void pauli(int t, int u, int& w, int& e) {
+        if (t == 0 || u == 0) {
+            w = t + u;
+            e = 0;
+        } else if (t == u) {
+            w = 0;
+            e = 0;
+        } else {
+            w = 6 - t - u;
+            e = ((t == 1 && u == 2) || (t == 2 && u == 3) || (t == 3 && u == 1)) ? 1 : 3;
+        }
+    }
+    // appends sign * B_X B_Y
+    void product(uint64_t X, uint64_t Y, int sign, std::vector<PBTerm>& out) const {
+        const int M = cd.M;
+        int tx, ty, cx[8], ax[8], cy[8], ay[8];
+        cd.unpack(X, tx, cx, ax);
+        cd.unpack(Y, ty, cy, ay);
+        int w, e;
+        pauli(tx, ty, w, e);
+        static const int ere[4] = {1, 0, -1, 0}, eim[4] = {0, 1, 0, -1};
+        int k[8] = {0}, kmax[8], c[8], a[8];
+        for (int m = 0; m < M; ++m) kmax[m] = std::min(ax[m], cy[m]);
+        for (;;) {
+            int64_t f = sign;
+            for (int m = 0; m < M; ++m) {
+                int64_t g;
+                if (k[m] >= 21 || __builtin_mul_overflow(fact[k[m]], binom[ax[m]][k[m]], &g) ||
+                    __builtin_mul_overflow(g, binom[cy[m]][k[m]], &g) || __builtin_mul_overflow(f, g, &f))
+                    overflow = true;
+                c[m] = cx[m] + cy[m] - k[m];
+                a[m] = ax[m] + ay[m] - k[m];
+            }
+            out.push_back({cd.key(w, c, a), ere[e] * f, eim[e] * f});
+            int m = 0;
+            while (m < M && k[m] == kmax[m]) k[m++] = 0;
+            if (m == M) break;
+            ++k[m];
+        }
+    }
+    void commutator(uint64_t A, uint64_t B, std::vector<PBTerm>& out) const {
+        out.clear();
+        product(A, B, 1, out);
+        product(B, A, -1, out);
+        std::sort(out.begin(), out.end(), [](const PBTerm& x, const PBTerm& y) { return x.key < y.key; });
+        size_t w = 0;
+        for (size_t r = 0; r < out.size();) {
+            size_t s = r;
+            int64_t re = 0, im = 0;
+            for (; s < out.size() && out[s].key == out[r].key; ++s) {
+                re += out[s].re;
+                im += out[s].im;
+            }
+            if (re != 0 || im != 0) out[w++] = {out[r].key, re, im};
+            r = s;
+        }
+        out.resize(w);
+    }
+    // the complete degree-p registry, canonical order
+    std::vector<uint64_t> registry() const {
+        std::vector<uint64_t> out;
+        const int M = cd.M;
+        std::vector<int> ex(2 * M, 0);
+        std::function<void(int, int)> rec = [&](int pos, int left) {
+            if (pos == 2 * M) {
+                int c[8], a[8];
+                for (int m = 0; m < M; ++m) {
+                    c[m] = ex[2 * m];
+                    a[m] = ex[2 * m + 1];
+                }
+                for (int t = 0; t < 4; ++t) out.push_back(cd.key(t, c, a));
+                return;
+            }
+            for (int v = 0; v <= left; ++v) {
+                ex[pos] = v;
+                rec(pos + 1, left - v);
+            }
+        };
+        rec(0, p);
+        std::sort(out.begin(), out.end());
+        return out;
+    }
+    bool diagonal(uint64_t L) const {
+        int t, c[8], a[8];
+        cd.unpack(L, t, c, a);
+        if (t != 0 && t != 3) return false;
+        for (int m = 0; m < cd.M; ++m)
+            if (c[m] != a[m]) return false;
+        return true;
+    }
+};
+
+struct PBRec {
+    int32_t i, j;
+    int16_t re, im;
+};
+
+// sorts every segment [off[s], off[s+1]) of the arrays (ri, rj, rc) by (ri, rj)
+static void sort_segments(const std::vector<int64_t>& off, int32_t* ri, int32_t* rj, int16_t* rc, int nt) {
+    const int64_t nseg = (int64_t)off.size() - 1;
+    parallel_for(nseg, nt, [&](int64_t b, int64_t e) {
+        std::vector<PBRec> tmp;
+        for (int64_t s = b; s < e; ++s) {
+            const int64_t o = off[s], n = off[s + 1] - off[s];
+            tmp.resize((size_t)n);
+            for (int64_t t = 0; t < n; ++t) tmp[t] = {ri[o + t], rj[o + t], rc[2 * (o + t)], rc[2 * (o + t) + 1]};
+            std::sort(tmp.begin(), tmp.end(),
+                      [](const PBRec& x, const PBRec& y) { return x.i != y.i ? x.i < y.i : x.j < y.j; });
+            for (int64_t t = 0; t < n; ++t) {
+                ri[o + t] = tmp[t].i;
+                rj[o + t] = tmp[t].j;
+                rc[2 * (o + t)] = tmp[t].re;
+                rc[2 * (o + t) + 1] = tmp[t].im;
+            }
+        }
+    });
+}
+
+static int16_t to_i16(int64_t v) {
+    if (v < -32767 || v > 32767) CUT_FAIL(CUT_E_UNSUPPORTED, "cut_graph_build: factor %lld exceeds int16", (long long)v);
+    return (int16_t)v;
+}
+
+// Compiles the Pauli-boson graph (Sec. 2.2-2.3): registry, generator records
+// E_eta and generator registry, retained records E_L and (optionally) the
+// outside-space records E_C, product-major in two traversals over the pairs
+// (generator label, registry label): the first counts the records of every
+// target (and collects the outside labels), the exact-size file is mapped, the
+// second writes each record at a per-target cursor, and every segment is then
+// sorted by (left, right) input so the bytes do not depend on the thread count.
+static cut_status build_pauli_boson(int M, int p, const char* path, int nt, bool outside, cut_graph_desc* desc) {
+    int fd = -1;
+    void* map = MAP_FAILED;
+    size_t map_bytes = 0;
+    try {
+        auto t0 = std::chrono::steady_clock::now();
+        PBAlgebra alg(M, p);
+        if (!alg.fits()) CUT_FAIL(CUT_E_UNSUPPORTED, "cut_graph_build: Pauli-boson M=%d p=%d too large for 64-bit labels", M, p);
+        const std::vector<uint64_t> reg = alg.registry();
+        const int64_t N = (int64_t)reg.size();
+        if (N >= (1ll << 23)) CUT_FAIL(CUT_E_UNSUPPORTED, "cut_graph_build: registry of %lld labels", (long long)N);
+        std::unordered_map<uint64_t, int32_t> ridx;
+        ridx.reserve((size_t)N * 2);
+        for (int64_t r = 0; r < N; ++r) ridx[reg[(size_t)r]] = (int32_t)r;
+        std::vector<uint8_t> diag((size_t)N);
+        std::vector<int32_t> D, OD;
+        for (int64_t r = 0; r < N; ++r) {
+            diag[(size_t)r] = alg.diagonal(reg[(size_t)r]) ? 1 : 0;
+            (diag[(size_t)r] ? D : OD).push_back((int32_t)r);
+        }
+        // generator: [B_i, B_j], i diagonal, j not; its labels form the generator registry
+        struct GRec {
+            uint64_t key;
+            int32_t i, j;
+            int64_t re, im;
+        };
+        std::vector<GRec> graw;
+        {
+            std::vector<PBTerm> t;
+            for (int32_t i : D)
+                for (int32_t j : OD) {
+                    alg.commutator(reg[(size_t)i], reg[(size_t)j], t);
+                    for (auto& x : t) graw.push_back({x.key, i, j, x.re, x.im});
+                }
+        }
+        std::vector<uint64_t> gen;
+        gen.reserve(graw.size());
+        for (auto& r : graw) gen.push_back(r.key);
+        std::sort(gen.begin(), gen.end());
+        gen.erase(std::unique(gen.begin(), gen.end()), gen.end());
+        const int64_t NG = (int64_t)gen.size();
+        if (NG >= (1ll << 23)) CUT_FAIL(CUT_E_UNSUPPORTED, "cut_graph_build: generator registry of %lld labels", (long long)NG);
+        std::unordered_map<uint64_t, int32_t> gidx;
+        gidx.reserve((size_t)NG * 2);
+        for (int64_t r = 0; r < NG; ++r) gidx[gen[(size_t)r]] = (int32_t)r;
+        std::sort(graw.begin(), graw.end(), [&](const GRec& x, const GRec& y) {
+            const int32_t ax = gidx[x.key], ay = gidx[y.key];
+            return ax != ay ? ax < ay : (x.i != y.i ? x.i < y.i : x.j < y.j);
+        });
+        const int64_t Eg = (int64_t)graw.size();
+        std::vector<int64_t> goff((size_t)NG + 1, 0);
+        for (auto& r : graw) goff[(size_t)gidx[r.key] + 1]++;
+        for (int64_t a = 0; a < NG; ++a) goff[a + 1] += goff[a];
+
+        // traversal 1: counts per retained target, outside labels with their counts
+        std::vector<std::vector<int64_t>> tcnt(nt, std::vector<int64_t>((size_t)N, 0));
+        std::vector<std::unordered_map<uint64_t, int64_t>> tout(nt);
+        {
+            std::atomic<int64_t> next{0};
+            auto work = [&](int tid) {
+                std::vector<PBTerm> t;
+                for (int64_t a; (a = next.fetch_add(1)) < NG;)
+                    for (int64_t j = 0; j < N; ++j) {
+                        alg.commutator(gen[(size_t)a], reg[(size_t)j], t);
+                        for (auto& x : t) {
+                            auto it = ridx.find(x.key);
+                            if (it != ridx.end()) tcnt[tid][(size_t)it->second]++;
+                            else if (outside) tout[tid][x.key]++;
+                        }
+                    }
+            };
+            std::vector<std::thread> th;
+            for (int q = 1; q < nt; ++q) th.emplace_back(work, q);
+            work(0);
+            for (auto& x : th) x.join();
+        }
+        std::vector<int64_t> loff((size_t)N + 1, 0);
+        for (int q = 0; q < nt; ++q)
+            for (int64_t k = 0; k < N; ++k) loff[k + 1] += tcnt[q][(size_t)k];
+        tcnt.clear();
+        for (int64_t k = 0; k < N; ++k) loff[k + 1] += loff[k];
+        const int64_t E = loff[(size_t)N];
+        std::vector<uint64_t> olab;
+        std::vector<int64_t> coff(1, 0);
+        std::unordered_map<uint64_t, int64_t> oidx;
+        if (outside) {
+            for (int q = 1; q < nt; ++q) {
+                for (auto& kv : tout[q]) tout[0][kv.first] += kv.second;
+                tout[q].clear();
+            }
+            olab.reserve(tout[0].size());
+            for (auto& kv : tout[0]) olab.push_back(kv.first);
+            std::sort(olab.begin(), olab.end());
+            coff.assign(olab.size() + 1, 0);
+            oidx.reserve(olab.size() * 2);
+            for (size_t q = 0; q < olab.size(); ++q) {
+                oidx[olab[q]] = (int64_t)q;
+                coff[q + 1] = coff[q] + tout[0][olab[q]];
+            }
+            tout.clear();
+        }
+        const int64_t Nc = (int64_t)olab.size(), Ec = coff.back();
+
+        // file layout: base sections, generator labels, outside sections
+        struct Sz {
+            uint32_t id, eb;
+            uint64_t count;
+        };
+        std::vector<Sz> secs = {{SEC_LABELS, 8, (uint64_t)N},       {SEC_DIAG, 1, (uint64_t)N},
+                                {SEC_PAIRS, 4, 0},                   {SEC_FLOW_OFF, 8, (uint64_t)N + 1},
+                                {SEC_FLOW_I, 4, (uint64_t)E},        {SEC_FLOW_J, 4, (uint64_t)E},
+                                {SEC_FLOW_C, 4, (uint64_t)E},        {SEC_GEN_OFF, 8, (uint64_t)NG + 1},
+                                {SEC_GEN_I, 4, (uint64_t)Eg},        {SEC_GEN_J, 4, (uint64_t)Eg},
+                                {SEC_GEN_C, 4, (uint64_t)Eg},        {SEC_GEN_LABELS, 8, (uint64_t)NG}};
+        if (outside) {
+            secs.push_back({SEC_OUT_LABELS, 8, (uint64_t)Nc});
+            secs.push_back({SEC_OUT_OFF, 8, (uint64_t)Nc + 1});
+            secs.push_back({SEC_OUT_I, 4, (uint64_t)Ec});
+            secs.push_back({SEC_OUT_J, 4, (uint64_t)Ec});
+            secs.push_back({SEC_OUT_C, 4, (uint64_t)Ec});
+        }
+        const int nsec = (int)secs.size();
+        SectionEntry tab[kMaxSections];
+        const size_t tab_bytes = nsec * sizeof(SectionEntry);
+        uint64_t pos = align64(sizeof(BundleHeader) + tab_bytes);
+        for (int s = 0; s < nsec; ++s) {
+            tab[s] = {secs[s].id, secs[s].eb, pos, secs[s].count, 0};
+            pos = align64(pos + secs[s].count * secs[s].eb);
+        }
+        const uint64_t file_bytes = pos;
+        std::string tmp = std::string(path) + ".tmp";
+        fd = ::open(tmp.c_str(), O_RDWR | O_CREAT | O_TRUNC, 0644);
+        if (fd < 0) CUT_FAIL(CUT_E_IO, "cannot create %s", tmp.c_str());
+        if (::ftruncate(fd, (off_t)file_bytes) != 0) CUT_FAIL(CUT_E_IO, "cannot size %s", tmp.c_str());
+        map = ::mmap(nullptr, file_bytes, PROT_READ | PROT_WRITE, MAP_SHARED, fd, 0);
+        if (map == MAP_FAILED) CUT_FAIL(CUT_E_IO, "cannot map %s", tmp.c_str());
+        map_bytes = file_bytes;
+        uint8_t* base = (uint8_t*)map;
+        auto sec = [&](int s) { return base + tab[s].offset; };
+        std::memcpy(sec(0), reg.data(), N * 8);
+        std::memcpy(sec(1), diag.data(), N);
+        std::memcpy(sec(3), loff.data(), (N + 1) * 8);
+        std::memcpy(sec(7), goff.data(), (NG + 1) * 8);
+        std::memcpy(sec(11), gen.data(), NG * 8);
+        {
+            int32_t* Gi = (int32_t*)sec(8);
+            int32_t* Gj = (int32_t*)sec(9);
+            int16_t* Gc = (int16_t*)sec(10);
+            for (int64_t e = 0; e < Eg; ++e) {
+                Gi[e] = graw[(size_t)e].i;
+                Gj[e] = graw[(size_t)e].j;
+                Gc[2 * e] = to_i16(graw[(size_t)e].re);
+                Gc[2 * e + 1] = to_i16(graw[(size_t)e].im);
+            }
+        }
+        graw.clear();
+        graw.shrink_to_fit();
+        int32_t* Li = (int32_t*)sec(4);
+        int32_t* Lj = (int32_t*)sec(5);
+        int16_t* Lc = (int16_t*)sec(6);
+        int32_t* Ci = outside ? (int32_t*)sec(14) : nullptr;
+        int32_t* Cj = outside ? (int32_t*)sec(15) : nullptr;
+        int16_t* Cc = outside ? (int16_t*)sec(16) : nullptr;
+        if (outside) {
+            std::memcpy(sec(12), olab.data(), Nc * 8);
+            std::memcpy(sec(13), coff.data(), (Nc + 1) * 8);
+        }
+        // traversal 2: every record at its target's cursor
+        {
+            std::vector<std::atomic<int64_t>> curL((size_t)N), curC((size_t)Nc);
+            for (int64_t k = 0; k < N; ++k) curL[(size_t)k] = loff[(size_t)k];
+            for (int64_t q = 0; q < Nc; ++q) curC[(size_t)q] = coff[(size_t)q];
+            std::atomic<int64_t> next{0};
+            std::atomic<int> overflow{0};
+            auto work = [&]() {
+                std::vector<PBTerm> t;
+                for (int64_t a; (a = next.fetch_add(1)) < NG;)
+                    for (int64_t j = 0; j < N; ++j) {
+                        alg.commutator(gen[(size_t)a], reg[(size_t)j], t);
+                        for (auto& x : t) {
+                            if (x.re < -32767 || x.re > 32767 || x.im < -32767 || x.im > 32767) {
+                                overflow = 1;
+                                continue;
+                            }
+                            auto it = ridx.find(x.key);
+                            if (it != ridx.end()) {
+                                const int64_t q = curL[(size_t)it->second].fetch_add(1);
+                                Li[q] = (int32_t)a;
+                                Lj[q] = (int32_t)j;
+                                Lc[2 * q] = (int16_t)x.re;
+                                Lc[2 * q + 1] = (int16_t)x.im;
+                            } else if (outside) {
+                                const int64_t q = curC[(size_t)oidx.at(x.key)].fetch_add(1);
+                                Ci[q] = (int32_t)a;
+                                Cj[q] = (int32_t)j;
+                                Cc[2 * q] = (int16_t)x.re;
+                                Cc[2 * q + 1] = (int16_t)x.im;
+                            }
+                        }
+                    }
+            };
+            std::vector<std::thread> th;
+            for (int q = 1; q < nt; ++q) th.emplace_back(work);
+            work();
+            for (auto& x : th) x.join();
+            if (overflow) CUT_FAIL(CUT_E_UNSUPPORTED, "cut_graph_build: a factor exceeds int16");
+        }
+        if (alg.overflow) CUT_FAIL(CUT_E_UNSUPPORTED, "cut_graph_build: a factor exceeds the int64 range");
+        sort_segments(loff, Li, Lj, Lc, nt);
+        if (outside) sort_segments(coff, Ci, Cj, Cc, nt);
+
+        for (int s = 0; s < nsec; ++s) tab[s].checksum = checksum64(sec(s), tab[s].count * tab[s].elem_bytes);
+        BundleHeader h{};
+        std::memcpy(h.magic, kMagic, 8);
+        h.version = kVersion;
+        h.header_bytes = sizeof(BundleHeader);
+        h.algebra = CUT_ALG_PAULI_BOSON;
+        h.size = 256 * M + p;
+        h.n_ops = N;
+        h.n_records = E;
+        h.n_gen_records = Eg;
+        h.n_pairs = 0;
+        h.factor_bytes = 4;
+        h.gen_sign = 1;
+        h.n_sections = (uint32_t)nsec;
+        h.section_table_offset = sizeof(BundleHeader);
+        h.file_bytes = file_bytes;
+        h.n_out_ops = Nc;
+        h.n_out_records = Ec;
+        h.n_gen_ops = NG;
+        uint64_t rc = 0;
+        for (int s = 3; s < nsec; ++s) rc = mix64(rc ^ tab[s].checksum);
+        h.records_checksum = rc;
+        snprintf(h.identifier, sizeof h.identifier,
+                 "pauli-boson M=%d p=%d key=deg,tau,c1,a1..:%d bits order=key mask=I|z,c=a factors=int16x2", M, p,
+                 alg.cd.W);
+        h.header_checksum = 0;
+        std::memcpy(base + sizeof(BundleHeader), tab, tab_bytes);
+        h.header_checksum = checksum64(&h, sizeof h) ^ checksum64(tab, tab_bytes);
+        std::memcpy(base, &h, sizeof h);
+        if (::msync(map, map_bytes, MS_SYNC) != 0) CUT_FAIL(CUT_E_IO, "msync failed");
+        ::munmap(map, map_bytes);
+        map = MAP_FAILED;
+        ::close(fd);
+        fd = -1;
+        if (::rename(tmp.c_str(), path) != 0) CUT_FAIL(CUT_E_IO, "cannot rename %s to %s", tmp.c_str(), path);
+        if (desc) {
+            std::memset(desc, 0, sizeof *desc);
+            desc->algebra = CUT_ALG_PAULI_BOSON;
+            desc->size = h.size;
+            desc->n_ops = N;
+            desc->n_records = E;
+            desc->n_gen_records = Eg;
+            desc->n_pairs = 0;
+            desc->n_out_ops = Nc;
+            desc->n_out_records = Ec;
+            desc->n_gen_ops = NG;
+            desc->checksum = rc;
+            desc->file_bytes = (int64_t)file_bytes;
+            desc->build_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+            std::strncpy(desc->identifier, h.identifier, sizeof desc->identifier - 1);
+        }
+        return CUT_OK;
+    } catch (const Fail& f) {
+        if (map != MAP_FAILED) ::munmap(map, map_bytes);
+        if (fd >= 0) ::close(fd);
+        return f.st;
+    } catch (const std::bad_alloc&) {
+        if (map != MAP_FAILED) ::munmap(map, map_bytes);
+        if (fd >= 0) ::close(fd);
+        set_error("cut_graph_build: out of host memory");
+        return CUT_E_NOMEM;
+    }
+}
+
 }  // namespace cut
 
 using namespace cut;
@@ -332,6 +798,13 @@ extern "C" cut_status cut_graph_build(int32_t algebra, int32_t size, const char*
         } else if (algebra == CUT_ALG_MAJORANA) {
             if (size < 4 || size > 64 || (size & 1))
                 CUT_FAIL(CUT_E_INVAL, "cut_graph_build: Majorana size %d must be even in 4..64", size);
+        } else if (algebra == CUT_ALG_PAULI_BOSON) {
+            const int M = size / 256, pdeg = size % 256;
+            if (M < 1 || M > 5 || pdeg < 1)
+                CUT_FAIL(CUT_E_INVAL, "cut_graph_build: Pauli-boson size %d is not 256 M + p, M in 1..5, p >= 1", size);
+            if (flags & ~CUT_BUILD_OUTSIDE) CUT_FAIL(CUT_E_INVAL, "cut_graph_build: unknown flags %#x", flags);
+            const int nt = threads > 0 ? threads : (int)std::max(1u, std::thread::hardware_concurrency());
+            return build_pauli_boson(M, pdeg, path, nt, (flags & CUT_BUILD_OUTSIDE) != 0, desc);
         } else {
             CUT_FAIL(CUT_E_INVAL, "cut_graph_build: unknown algebra %d", algebra);
         }
@@ -561,7 +1034,7 @@ void read_bundle(const char* path, bool verify, HostGraph& g) {
     if (std::memcmp(h.magic, kMagic, 8) != 0) CUT_FAIL(CUT_E_FORMAT, "%s: not a graph bundle", path);
     if (h.version != kVersion || h.header_bytes != sizeof(BundleHeader))
         CUT_FAIL(CUT_E_FORMAT, "%s: unsupported bundle version %u", path, h.version);
-    if ((h.n_sections != SEC_COUNT && h.n_sections != SEC_COUNT_OUT) ||
+    if (h.n_sections < (uint32_t)SEC_COUNT || h.n_sections > (uint32_t)kMaxSections ||
         h.section_table_offset != sizeof(BundleHeader))
         CUT_FAIL(CUT_E_FORMAT, "%s: bad section table", path);
     const int nsec = (int)h.n_sections;
@@ -569,7 +1042,7 @@ void read_bundle(const char* path, bool verify, HostGraph& g) {
     if (fbytes < sizeof(BundleHeader) + tab_bytes) CUT_FAIL(CUT_E_FORMAT, "%s: truncated section table", path);
     if (h.file_bytes != fbytes) CUT_FAIL(CUT_E_FORMAT, "%s: size %llu, header says %llu", path,
                                          (unsigned long long)fbytes, (unsigned long long)h.file_bytes);
-    SectionEntry tab[SEC_COUNT_OUT];
+    SectionEntry tab[kMaxSections];
     std::memcpy(tab, base + sizeof h, tab_bytes);
     {
         BundleHeader hz = h;
@@ -578,27 +1051,42 @@ void read_bundle(const char* path, bool verify, HostGraph& g) {
             CUT_FAIL(CUT_E_CHECKSUM, "%s: header checksum mismatch", path);
     }
     const int64_t N = h.n_ops;
-    if (N <= 0 || h.n_records < 0 || h.n_gen_records < 0 || h.n_pairs < 0 || h.n_pairs > N)
+    if (N <= 0 || h.n_records < 0 || h.n_gen_records < 0 || h.n_pairs < 0 || h.n_pairs > N || h.n_gen_ops < 0)
         CUT_FAIL(CUT_E_FORMAT, "%s: bad sizes", path);
-    const bool outside = nsec == SEC_COUNT_OUT;
+    if ((h.factor_bytes != 1 && h.factor_bytes != 4) || (h.gen_sign != 1 && h.gen_sign != -1))
+        CUT_FAIL(CUT_E_FORMAT, "%s: bad factor format", path);
+    const bool own_gen = h.n_gen_ops > 0;
+    const int64_t NG = own_gen ? h.n_gen_ops : N;
+    // expected section list: the base sections, the generator labels when the
+    // generator has a registry of its own, then the outside-space sections
+    struct Want {
+        uint32_t id, eb;
+        uint64_t count;
+    };
+    const uint32_t fb = (uint32_t)h.factor_bytes;
+    std::vector<Want> want = {{SEC_LABELS, 8, (uint64_t)N},           {SEC_DIAG, 1, (uint64_t)N},
+                              {SEC_PAIRS, 4, (uint64_t)h.n_pairs},     {SEC_FLOW_OFF, 8, (uint64_t)N + 1},
+                              {SEC_FLOW_I, 4, (uint64_t)h.n_records},  {SEC_FLOW_J, 4, (uint64_t)h.n_records},
+                              {SEC_FLOW_C, fb, (uint64_t)h.n_records}, {SEC_GEN_OFF, 8, (uint64_t)NG + 1},
+                              {SEC_GEN_I, 4, (uint64_t)h.n_gen_records}, {SEC_GEN_J, 4, (uint64_t)h.n_gen_records},
+                              {SEC_GEN_C, fb, (uint64_t)h.n_gen_records}};
+    if (own_gen) want.push_back({SEC_GEN_LABELS, 8, (uint64_t)NG});
+    const int out_at = (int)want.size();
+    const bool outside = nsec == out_at + 5;
+    if (!outside && nsec != out_at) CUT_FAIL(CUT_E_FORMAT, "%s: bad section count", path);
     if (outside ? (h.n_out_ops < 0 || h.n_out_records < 0) : (h.n_out_ops != 0 || h.n_out_records != 0))
         CUT_FAIL(CUT_E_FORMAT, "%s: bad outside-space sizes", path);
-    if (h.factor_bytes != 1 || (h.gen_sign != 1 && h.gen_sign != -1))
-        CUT_FAIL(CUT_E_FORMAT, "%s: bad factor format", path);
-    const uint64_t want[SEC_COUNT_OUT][2] = {
-        {SEC_LABELS, (uint64_t)N},          {SEC_DIAG, (uint64_t)N},
-        {SEC_PAIRS, (uint64_t)h.n_pairs},   {SEC_FLOW_OFF, (uint64_t)N + 1},
-        {SEC_FLOW_I, (uint64_t)h.n_records}, {SEC_FLOW_J, (uint64_t)h.n_records},
-        {SEC_FLOW_C, (uint64_t)h.n_records}, {SEC_GEN_OFF, (uint64_t)N + 1},
-        {SEC_GEN_I, (uint64_t)h.n_gen_records}, {SEC_GEN_J, (uint64_t)h.n_gen_records},
-        {SEC_GEN_C, (uint64_t)h.n_gen_records}, {SEC_OUT_LABELS, (uint64_t)h.n_out_ops},
-        {SEC_OUT_OFF, (uint64_t)h.n_out_ops + 1}, {SEC_OUT_I, (uint64_t)h.n_out_records},
-        {SEC_OUT_J, (uint64_t)h.n_out_records}, {SEC_OUT_C, (uint64_t)h.n_out_records}};
-    const uint32_t eb[SEC_COUNT_OUT] = {8, 1, 4, 8, 4, 4, 1, 8, 4, 4, 1, 8, 8, 4, 4, 1};
-    const void* ptr[SEC_COUNT_OUT];
+    if (outside) {
+        want.push_back({SEC_OUT_LABELS, 8, (uint64_t)h.n_out_ops});
+        want.push_back({SEC_OUT_OFF, 8, (uint64_t)h.n_out_ops + 1});
+        want.push_back({SEC_OUT_I, 4, (uint64_t)h.n_out_records});
+        want.push_back({SEC_OUT_J, 4, (uint64_t)h.n_out_records});
+        want.push_back({SEC_OUT_C, fb, (uint64_t)h.n_out_records});
+    }
+    const void* ptr[kMaxSections];
     for (int s = 0; s < nsec; ++s) {
         const SectionEntry& e = tab[s];
-        if (e.id != want[s][0] || e.count != want[s][1] || e.elem_bytes != eb[s] || (e.offset & 63) ||
+        if (e.id != want[s].id || e.count != want[s].count || e.elem_bytes != want[s].eb || (e.offset & 63) ||
             e.offset < sizeof h + tab_bytes || e.offset > fbytes || e.count * e.elem_bytes > fbytes - e.offset)
             CUT_FAIL(CUT_E_FORMAT, "%s: section %d malformed", path, s);
         ptr[s] = base + e.offset;
@@ -609,6 +1097,7 @@ void read_bundle(const char* path, bool verify, HostGraph& g) {
                 CUT_FAIL(CUT_E_CHECKSUM, "%s: section %d checksum mismatch", path, s);
     }
     g.hdr = h;
+    g.n_gen = NG;
     g.labels = (const uint64_t*)ptr[0];
     g.diag = (const uint8_t*)ptr[1];
     g.pairs = (const int32_t*)ptr[2];
@@ -618,17 +1107,21 @@ void read_bundle(const char* path, bool verify, HostGraph& g) {
         g.rj[w] = (const int32_t*)ptr[5 + 4 * w];
         g.rc[w] = (const int8_t*)ptr[6 + 4 * w];
     }
+    if (own_gen) g.gen_labels = (const uint64_t*)ptr[11];
     if (outside) {
-        g.out_labels = (const uint64_t*)ptr[11];
-        g.off[2] = (const int64_t*)ptr[12];
-        g.ri[2] = (const int32_t*)ptr[13];
-        g.rj[2] = (const int32_t*)ptr[14];
-        g.rc[2] = (const int8_t*)ptr[15];
+        g.out_labels = (const uint64_t*)ptr[out_at];
+        g.off[2] = (const int64_t*)ptr[out_at + 1];
+        g.ri[2] = (const int32_t*)ptr[out_at + 2];
+        g.rj[2] = (const int32_t*)ptr[out_at + 3];
+        g.rc[2] = (const int8_t*)ptr[out_at + 4];
     }
     // structural validation: offsets monotone and complete, indices in range
+    // (left inputs of E_L and E_C are generator rows, everything else operator
+    // rows), factors nonzero
     for (int w = 0; w < (outside ? 3 : 2); ++w) {
         const int64_t E = w == 0 ? h.n_records : w == 1 ? h.n_gen_records : h.n_out_records;
-        const int64_t nseg = w == 2 ? h.n_out_ops : N;
+        const int64_t nseg = w == 2 ? h.n_out_ops : w == 1 ? NG : N;
+        const uint64_t ilim = (uint64_t)(w == 1 ? N : NG);
         const int64_t* off = g.off[w];
         if (off[0] != 0 || off[nseg] != E) CUT_FAIL(CUT_E_FORMAT, "%s: offsets incomplete", path);
         for (int64_t k = 0; k < nseg; ++k)
@@ -638,8 +1131,18 @@ void read_bundle(const char* path, bool verify, HostGraph& g) {
         const int8_t* rc = g.rc[w];
         std::atomic<int> bad{0};
         parallel_for(E, 16, [&](int64_t b, int64_t e) {
-            for (int64_t t = b; t < e; ++t)
-                if ((uint32_t)ri[t] >= (uint64_t)N || (uint32_t)rj[t] >= (uint64_t)N || rc[t] == 0) bad = 1;
+            for (int64_t t = b; t < e; ++t) {
+                bool zero;
+                if (fb == 1) {
+                    zero = rc[t] == 0;
+                } else {
+                    int16_t re, im;
+                    std::memcpy(&re, rc + 4 * t, 2);
+                    std::memcpy(&im, rc + 4 * t + 2, 2);
+                    zero = re == 0 && im == 0;
+                }
+                if ((uint32_t)ri[t] >= ilim || (uint32_t)rj[t] >= (uint64_t)N || zero) bad = 1;
+            }
         });
         if (bad) CUT_FAIL(CUT_E_FORMAT, "%s: record index out of range or zero factor", path);
     }

@@ -102,9 +102,10 @@ extern "C" cut_status cut_graph_jvp(cut_graph_t hd, int32_t kind, double delta, 
     const int64_t N = g.N;
     const bool need_x = dh || y;
     Carve cv;
-    const size_t i_eta = cv.add(N * nsets * tb);
-    const size_t i_deta = cv.add(dh ? N * nsets * 8 : 0);
-    const size_t i_deta32 = cv.add(dh && f32 ? N * nsets * 4 : 0);
+    const int64_t NG = g.NG;
+    const size_t i_eta = cv.add(NG * nsets * tb);
+    const size_t i_deta = cv.add(dh ? NG * nsets * 8 : 0);
+    const size_t i_deta32 = cv.add(dh && f32 ? NG * nsets * 4 : 0);
     const size_t i_x32 = cv.add(need_x && f32 ? N * cols * 4 : 0);
     const size_t i_dx32 = cv.add(dx && f32 ? N * cols * 4 : 0);
     char* base = (char*)g.ws_deriv.get(cv.total);
@@ -122,7 +123,7 @@ extern "C" cut_status cut_graph_jvp(cut_graph_t hd, int32_t kind, double delta, 
         eval_generator_jvp(g, kind, delta, (int32_t)nsets, h, ldh, dh, lddh, d64, nsets, s);
         deta = d64;
         if (f32) {
-            launch_round_f32(d64, nsets, N, nsets, (float*)at(i_deta32), nsets, s);
+            launch_round_f32(d64, nsets, NG, nsets, (float*)at(i_deta32), nsets, s);
             deta = at(i_deta32);
         }
     }
@@ -201,10 +202,11 @@ extern "C" cut_status cut_graph_vjp(cut_graph_t hd, int32_t kind, double delta, 
     const bool acc = (flags & CUT_ACCUMULATE) != 0;
     const int64_t N = g.N;
     Carve cv;
-    const size_t i_eta = cv.add(g_x ? N * nsets * (f32 ? 4 : 8) : 0);
+    const int64_t NG = g.NG;
+    const size_t i_eta = cv.add(g_x ? NG * nsets * (f32 ? 4 : 8) : 0);
     const size_t i_w32 = cv.add(f32 ? N * cols * 4 : 0);
     const size_t i_x32 = cv.add(g_h && f32 ? N * cols * 4 : 0);
-    const size_t i_geta = cv.add(g_h ? N * nsets * 8 : 0);
+    const size_t i_geta = cv.add(g_h ? NG * nsets * 8 : 0);
     const size_t i_tmp = cv.add(g_h && kind == CUT_GEN_G2 ? 2 * N * nsets * 8 : 0);
     char* base = (char*)g.ws_deriv.get(cv.total);
     auto at = [&](size_t i) { return (void*)(base + cv.offs[i]); };

@@ -68,7 +68,7 @@ static FlowBufs flow_bufs(Graph& g, int64_t nsets, int64_t nops, int prec, size_
     size_t ohst = o;
     o += al(N * nsets * 8);
     size_t oeta = o;
-    o += al(N * nsets * tb);
+    o += al(g.NG * nsets * tb);
     size_t ons = o;
     o += al(nsets * 4);
     size_t ost = o;
@@ -361,7 +361,7 @@ extern "C" cut_status cut_flow_adjoint(cut_graph_t h, const cut_flow_params* p, 
         const int C = p->ckpt_every;
         const int64_t nslot = (int64_t)C * 4 + 1;
         // extra: stage storage, zr, lam_new, mu, u, eta, geta, vjp scratch
-        const size_t extra = al(nslot * M * 8) + 4 * al(M * 8) + 2 * al(g.N * nsets * 8) + al(2 * g.N * nsets * 8);
+        const size_t extra = al(nslot * M * 8) + 4 * al(M * 8) + 2 * al(g.NG * nsets * 8) + al(2 * g.N * nsets * 8);
         char* ex = nullptr;
         FlowBufs fb = flow_bufs(g, nsets, nops, CUT_F64, extra, &ex);
         double* St = (double*)ex;
@@ -375,9 +375,9 @@ extern "C" cut_status cut_flow_adjoint(cut_graph_t h, const cut_flow_params* p, 
         double* u = (double*)ex;
         ex += al(M * 8);
         double* eta = (double*)ex;
-        ex += al(g.N * nsets * 8);
+        ex += al(g.NG * nsets * 8);
         double* geta = (double*)ex;
-        ex += al(g.N * nsets * 8);
+        ex += al(g.NG * nsets * 8);
         double* tmp = (double*)ex;
         HIP_CHECK(hipMemcpyAsync(fb.nsteps, n_steps, nsets * 4, hipMemcpyHostToDevice, s));
         const int64_t nblk = (T + C - 1) / C;

@@ -741,6 +741,116 @@ static void build_copies(Graph& g, const HostGraph& hg, int w, bool adjoint) {
     }
 }
 
+// Device record with an integer factor v: the factor rides as the bf16 bit
+// pattern of (float)v, which must be exact (the low 16 bits of the float zero).
+static uint2 pack_record_int(int32_t v, uint32_t a, uint32_t b) {
+    const float f = (float)v;
+    uint32_t bits;
+    std::memcpy(&bits, &f, 4);
+    if ((bits & 0xFFFFu) != 0 || (float)v != f || v == 0)
+        CUT_FAIL(CUT_E_UNSUPPORTED, "factor %d is not exactly representable in the device records", v);
+    const uint32_t h = bits >> 16;
+    return make_uint2(((h >> 8) << 24) | a, ((h & 0xFFu) << 24) | b);
+}
+
+// Uploads a target-grouped stream as orientation 0 of record set w and, with
+// `adjoint`, the copies grouped by the right input (orientation 1: a kept,
+// b := target; nb segments) and by the left input (orientation 2: a := target,
+// b kept; na segments), each by a stable counting sort.
+static void upload_set(Graph& g, int w, std::vector<int64_t>&& off, std::vector<uint2>&& rec, bool adjoint,
+                       int64_t na, int64_t nb) {
+    const int64_t nseg = (int64_t)off.size() - 1, E = (int64_t)rec.size();
+    if (adjoint) {
+        for (int o = 1; o <= 2; ++o) {
+            const int64_t ns = o == 1 ? nb : na;
+            std::vector<int64_t> noff(ns + 1, 0);
+            for (int64_t e = 0; e < E; ++e) noff[(o == 1 ? (rec[e].y & 0xFFFFFFu) : (rec[e].x & 0xFFFFFFu)) + 1]++;
+            for (int64_t k = 0; k < ns; ++k) noff[k + 1] += noff[k];
+            std::vector<int64_t> cur(noff.begin(), noff.end() - 1);
+            std::vector<uint2> r2((size_t)E);
+            for (int64_t k = 0; k < nseg; ++k)
+                for (int64_t e = off[k]; e < off[k + 1]; ++e) {
+                    const uint2 r = rec[e];
+                    if (o == 1) r2[cur[r.y & 0xFFFFFFu]++] = make_uint2(r.x, (r.y & 0xFF000000u) | (uint32_t)k);
+                    else r2[cur[r.x & 0xFFFFFFu]++] = make_uint2((r.x & 0xFF000000u) | (uint32_t)k, r.y);
+                }
+            upload_csr(g, g.csr[w][o], ns, std::move(noff), r2);
+        }
+    }
+    upload_csr(g, g.csr[w][0], nseg, std::move(off), rec);
+}
+
+// Real-split form of a set of complex records (Pauli-boson graphs): a complex
+// coefficient vector v of n entries is stored as 2n real rows, row r = Re v_r,
+// row n + r = Im v_r.  A record y_k += c xi_a x_j with c = re + i im becomes
+//   Re y_k += re (xi_a^r x_j^r - xi_a^i x_j^i) - im (xi_a^r x_j^i + xi_a^i x_j^r)
+//   Im y_k += re (xi_a^r x_j^i + xi_a^i x_j^r) + im (xi_a^r x_j^r - xi_a^i x_j^i)
+// i.e. up to four real records per target row, kept in the stored order.
+static void real_split(const HostGraph& hg, int w, int64_t nk, int64_t na, int64_t nj, std::vector<int64_t>& off2,
+                       std::vector<uint2>& rec2) {
+    const int64_t* off = hg.off[w];
+    const int32_t* ri = hg.ri[w];
+    const int32_t* rj = hg.rj[w];
+    const int8_t* rc = hg.rc[w];
+    auto factor = [&](int64_t e, int16_t& re, int16_t& im) {
+        std::memcpy(&re, rc + 4 * e, 2);
+        std::memcpy(&im, rc + 4 * e + 2, 2);
+    };
+    off2.assign(2 * nk + 1, 0);
+    for (int64_t k = 0; k < nk; ++k) {
+        int64_t n = 0;
+        for (int64_t e = off[k]; e < off[k + 1]; ++e) {
+            int16_t re, im;
+            factor(e, re, im);
+            n += 2 * (re != 0) + 2 * (im != 0);
+        }
+        off2[k + 1] = n;        // real rows
+        off2[nk + k + 1] = n;   // imaginary rows (same count)
+    }
+    for (int64_t r = 0; r < 2 * nk; ++r) off2[r + 1] += off2[r];
+    rec2.resize((size_t)off2[2 * nk]);
+    for (int64_t k = 0; k < nk; ++k) {
+        int64_t pr = off2[k], pi = off2[nk + k];
+        for (int64_t e = off[k]; e < off[k + 1]; ++e) {
+            int16_t re, im;
+            factor(e, re, im);
+            const uint32_t ar = (uint32_t)ri[e], ai = (uint32_t)(ri[e] + na);
+            const uint32_t jr = (uint32_t)rj[e], ji = (uint32_t)(rj[e] + nj);
+            if (re != 0) {
+                rec2[pr++] = pack_record_int(re, ar, jr);
+                rec2[pr++] = pack_record_int(-re, ai, ji);
+                rec2[pi++] = pack_record_int(re, ar, ji);
+                rec2[pi++] = pack_record_int(re, ai, jr);
+            }
+            if (im != 0) {
+                rec2[pr++] = pack_record_int(-im, ar, ji);
+                rec2[pr++] = pack_record_int(-im, ai, jr);
+                rec2[pi++] = pack_record_int(im, ar, jr);
+                rec2[pi++] = pack_record_int(-im, ai, ji);
+            }
+        }
+    }
+}
+
+// Pauli-boson graph: every record set in real-split form; operator rows 2N,
+// generator rows 2NG, outside rows 2Nc.
+static void load_pauli_boson(Graph& g, const HostGraph& hg, bool adjoint) {
+    const int64_t N = hg.hdr.n_ops, NG = hg.n_gen;
+    std::vector<int64_t> off;
+    std::vector<uint2> rec;
+    real_split(hg, 0, N, NG, N, off, rec);                 // E_L: target k, left a (generator), right j
+    upload_set(g, 0, std::move(off), std::move(rec), adjoint, 2 * NG, 2 * N);
+    real_split(hg, 1, NG, N, N, off, rec);                 // E_eta: target a, left i, right j (operators)
+    upload_set(g, 1, std::move(off), std::move(rec), adjoint, 2 * N, 2 * N);
+    if (hg.off[2]) {
+        const int64_t Nc = hg.hdr.n_out_ops;
+        real_split(hg, 2, Nc, NG, N, off, rec);
+        upload_set(g, 2, std::move(off), std::move(rec), false, 2 * NG, 2 * N);
+        g.have_outside = true;
+        g.n_out = 2 * Nc;
+    }
+}
+
 // G2 stencil: the E_L records of target S whose left input is a pair coordinate
 // P_a (the Wegner terms of the quadratic diagonal part), at most 4 per target.
 static void build_stencil(Graph& g, const HostGraph& hg, const uint8_t* code) {
@@ -806,12 +916,17 @@ extern "C" cut_status cut_graph_load(const char* path, int32_t dev, uint32_t fla
         HostGraph hg;
         read_bundle(path, (flags & CUT_LOAD_NO_CHECKSUM) == 0, hg);
         const int64_t N = hg.hdr.n_ops;
-        if (N >= (1ll << 24)) CUT_FAIL(CUT_E_UNSUPPORTED, "registry of %lld exceeds 2^24 rows", (long long)N);
-        // factor dictionary over both record sets
+        const bool pb = hg.hdr.algebra == CUT_ALG_PAULI_BOSON;
+        if (pb != (hg.hdr.factor_bytes == 4) || pb != (hg.hdr.n_gen_ops > 0))
+            CUT_FAIL(CUT_E_FORMAT, "%s: factor format does not match the algebra", path);
+        const int64_t rows = pb ? 2 * N : N, grows = pb ? 2 * hg.n_gen : N;
+        if (rows >= (1ll << 24) || grows >= (1ll << 24) || (pb && 2 * hg.hdr.n_out_ops >= (1ll << 31)))
+            CUT_FAIL(CUT_E_UNSUPPORTED, "registry of %lld rows exceeds 2^24", (long long)std::max(rows, grows));
+        // factor dictionary over the int8 record sets (G2 stencil tables)
         uint8_t code[256];
         std::memset(code, 0, sizeof code);
         std::vector<double> ftab;
-        {
+        if (!pb) {
             bool seen[256] = {false};
             for (int w = 0; w < 3; ++w) {
                 const int64_t E = w == 0 ? hg.hdr.n_records : w == 1 ? hg.hdr.n_gen_records : hg.hdr.n_out_records;
@@ -829,7 +944,8 @@ extern "C" cut_status cut_graph_load(const char* path, int32_t dev, uint32_t fla
         g = new Graph();
         g->device = dev;
         g->hdr = hg.hdr;
-        g->N = N;
+        g->N = rows;
+        g->NG = grows;
         g->gen_sign = hg.hdr.gen_sign;
         g->nfactors = (int)ftab.size();
         // factor dictionary of the G2 stencil tables (the record streams carry
@@ -839,31 +955,37 @@ extern "C" cut_status cut_graph_load(const char* path, int32_t dev, uint32_t fla
         HIP_CHECK(hipMemcpy(g->ftab, ftab.data(), 256 * sizeof(double), hipMemcpyHostToDevice));
         const bool adj = (flags & CUT_LOAD_ADJOINT) != 0;
         g->labels_h.assign(hg.labels, hg.labels + N);
-        build_copies(*g, hg, 0, adj);
-        build_copies(*g, hg, 1, adj);
+        if (hg.gen_labels) g->gen_labels_h.assign(hg.gen_labels, hg.gen_labels + hg.n_gen);
+        if (hg.out_labels) g->out_labels_h.assign(hg.out_labels, hg.out_labels + hg.hdr.n_out_ops);
         g->have_adjoint = adj;
-        if (hg.hdr.n_sections == SEC_COUNT_OUT) {
-            // outside-space records: target order only, segments = outside rows
-            const int64_t Nc = hg.hdr.n_out_ops, Ec = hg.hdr.n_out_records;
-            std::vector<uint2> rec((size_t)Ec);
-            for (int64_t e = 0; e < Ec; ++e)
-                rec[e] = pack_record(hg.rc[2][e], (uint32_t)hg.ri[2][e], (uint32_t)hg.rj[2][e]);
-            upload_csr(*g, g->csr[2][0], Nc, std::vector<int64_t>(hg.off[2], hg.off[2] + Nc + 1), rec);
-            g->have_outside = true;
-            g->n_out = Nc;
+        if (pb) {
+            load_pauli_boson(*g, hg, adj);
+        } else {
+            build_copies(*g, hg, 0, adj);
+            build_copies(*g, hg, 1, adj);
+            if (hg.off[2]) {
+                // outside-space records: target order only, segments = outside rows
+                const int64_t Nc = hg.hdr.n_out_ops, Ec = hg.hdr.n_out_records;
+                std::vector<uint2> rec((size_t)Ec);
+                for (int64_t e = 0; e < Ec; ++e)
+                    rec[e] = pack_record(hg.rc[2][e], (uint32_t)hg.ri[2][e], (uint32_t)hg.rj[2][e]);
+                upload_csr(*g, g->csr[2][0], Nc, std::vector<int64_t>(hg.off[2], hg.off[2] + Nc + 1), rec);
+                g->have_outside = true;
+                g->n_out = Nc;
+            }
+            g->diag = dev_alloc<uint8_t>(N);
+            HIP_CHECK(hipMemcpy(g->diag, hg.diag, N, hipMemcpyHostToDevice));
+            g->npairs = hg.hdr.n_pairs;
+            g->pairs = dev_alloc<int32_t>(g->npairs);
+            if (g->npairs) HIP_CHECK(hipMemcpy(g->pairs, hg.pairs, g->npairs * 4, hipMemcpyHostToDevice));
+            build_stencil(*g, hg, code);
         }
-        g->diag = dev_alloc<uint8_t>(N);
-        HIP_CHECK(hipMemcpy(g->diag, hg.diag, N, hipMemcpyHostToDevice));
-        g->npairs = hg.hdr.n_pairs;
-        g->pairs = dev_alloc<int32_t>(g->npairs);
-        if (g->npairs) HIP_CHECK(hipMemcpy(g->pairs, hg.pairs, g->npairs * 4, hipMemcpyHostToDevice));
-        build_stencil(*g, hg, code);
         {
             int lds = 0;
             if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && lds > 0)
                 g->max_lds = lds;
         }
-        build_tiles(*g, hg, code);
+        if (!pb) build_tiles(*g, hg, code);
         HIP_CHECK(hipDeviceSynchronize());
         HIP_CHECK(hipSetDevice(prev));
         *out = (cut_graph_t)g;
@@ -891,15 +1013,38 @@ extern "C" cut_status cut_graph_info(cut_graph_t h, cut_graph_desc* d) {
     std::memset(d, 0, sizeof *d);
     d->algebra = g.hdr.algebra;
     d->size = g.hdr.size;
-    d->n_ops = g.N;
+    d->n_ops = g.hdr.n_ops;
     d->n_records = g.hdr.n_records;
     d->n_gen_records = g.hdr.n_gen_records;
     d->n_pairs = g.hdr.n_pairs;
     d->n_out_ops = g.hdr.n_out_ops;
     d->n_out_records = g.hdr.n_out_records;
+    d->n_gen_ops = g.hdr.n_gen_ops;
     d->checksum = g.hdr.records_checksum;
     d->file_bytes = (int64_t)g.hdr.file_bytes;
     std::strncpy(d->identifier, g.hdr.identifier, sizeof d->identifier - 1);
+    return CUT_OK;
+}
+
+extern "C" cut_status cut_graph_labels(cut_graph_t h, int32_t which, uint64_t* out, int64_t n) {
+    if (!h || !out) {
+        set_error("cut_graph_labels: null argument");
+        return CUT_E_INVAL;
+    }
+    const Graph& g = *(const Graph*)h;
+    const std::vector<uint64_t>* v = which == CUT_GRAPH_FLOW ? &g.labels_h
+                                     : which == CUT_GRAPH_GEN ? (g.gen_labels_h.empty() ? &g.labels_h : &g.gen_labels_h)
+                                     : which == CUT_GRAPH_OUTSIDE ? &g.out_labels_h : nullptr;
+    if (!v || (which == CUT_GRAPH_OUTSIDE && !g.have_outside)) {
+        set_error("cut_graph_labels: unknown or absent registry %d", which);
+        return CUT_E_INVAL;
+    }
+    if (n != (int64_t)v->size()) {
+        set_error("cut_graph_labels: registry %d has %lld labels, %lld requested", which, (long long)v->size(),
+                  (long long)n);
+        return CUT_E_INVAL;
+    }
+    std::memcpy(out, v->data(), v->size() * sizeof(uint64_t));
     return CUT_OK;
 }
 

@@ -67,8 +67,12 @@ enum SectionId : uint32_t {
     SEC_OUT_I = 14,       // int32[Ec]
     SEC_OUT_J = 15,       // int32[Ec]
     SEC_OUT_C = 16,       // int8[Ec]
-    SEC_COUNT_OUT = 16    // sections of a bundle with E_C
+    SEC_COUNT_OUT = 16,   // sections of a bundle with E_C
+    // generator registry labels, present when the generator has a registry of
+    // its own (Pauli-boson graphs); placed after the base sections
+    SEC_GEN_LABELS = 17   // uint64[NG]
 };
+constexpr int kMaxSections = 17;
 
 struct SectionEntry {
     uint32_t id;
@@ -99,7 +103,8 @@ struct BundleHeader {
     uint64_t header_checksum;  // of the header and section table with this field zero
     int64_t n_out_ops;         // outside registry size (0: no E_C)
     int64_t n_out_records;     // |E_C|
-    uint8_t pad[256 - 8 - 4 - 4 - 4 - 4 - 8 * 4 - 4 - 4 - 4 - 4 - 8 * 3 - 96 - 8 - 8 * 2];
+    int64_t n_gen_ops;         // generator registry size (0: the operator registry)
+    uint8_t pad[256 - 8 - 4 - 4 - 4 - 4 - 8 * 4 - 4 - 4 - 4 - 4 - 8 * 3 - 96 - 8 - 8 * 3];
 };
 static_assert(sizeof(BundleHeader) == 256, "header must be 256 bytes");
 
@@ -111,12 +116,16 @@ struct HostGraph {
     const uint64_t* labels = nullptr;
     const uint8_t* diag = nullptr;
     const int32_t* pairs = nullptr;
-    // record sets: 0 = E_L, 1 = E_eta, 2 = E_C (absent: null, size 0)
+    // record sets: 0 = E_L, 1 = E_eta, 2 = E_C (absent: null, size 0).  Factors
+    // are int8 (factor_bytes 1) or int16 (re, im) pairs (factor_bytes 4,
+    // Pauli-boson graphs); rc points at the raw bytes.
     const int64_t* off[3] = {nullptr, nullptr, nullptr};
     const int32_t* ri[3] = {nullptr, nullptr, nullptr};
     const int32_t* rj[3] = {nullptr, nullptr, nullptr};
     const int8_t* rc[3] = {nullptr, nullptr, nullptr};
     const uint64_t* out_labels = nullptr;
+    const uint64_t* gen_labels = nullptr;
+    int64_t n_gen = 0;               // generator rows (the operator registry size when shared)
     void* map = nullptr;
     size_t map_bytes = 0;
     ~HostGraph();
@@ -246,7 +255,8 @@ struct StepGraphCache;
 struct Graph {
     int device = 0;
     BundleHeader hdr{};
-    int64_t N = 0;
+    int64_t N = 0;                   // operator rows (Pauli-boson: 2 x labels, real-split)
+    int64_t NG = 0;                  // generator rows (= N unless the generator has its own registry)
     double gen_sign = 1.0;
     int nfactors = 0;
     double* ftab = nullptr;          // device [256]: factor dictionary of the stencil tables
@@ -257,7 +267,8 @@ struct Graph {
     DevCSR csr[3][3];
     bool have_adjoint = false;
     bool have_outside = false;
-    int64_t n_out = 0;               // outside registry size
+    int64_t n_out = 0;               // outside rows (Pauli-boson: 2 x labels)
+    std::vector<uint64_t> gen_labels_h, out_labels_h;   // host copies (generator registry only when own)
     // block mask and pairs
     uint8_t* diag = nullptr;         // device [N]
     int32_t* pairs = nullptr;        // device [npairs]

@@ -78,7 +78,7 @@ extern "C" cut_status cut_graph_autotune(cut_graph_t h, int64_t nsets, int64_t n
         if (allow_other_float && precision == CUT_F32C) precs.push_back(CUT_F32X);
         if (allow_other_float && precision == CUT_F32X) precs.push_back(CUT_F32C);
         const size_t tb = precision == CUT_F64 ? 8 : 4;
-        DevBuf eta(g.N * nsets * tb), x(g.N * nsets * nops * tb), y(g.N * nsets * nops * 8);
+        DevBuf eta(g.NG * nsets * tb), x(g.N * nsets * nops * tb), y(g.N * nsets * nops * 8);
         std::unique_ptr<DevBuf> part;
         size_t part_bytes = 0;
         auto partials = [&](int pr) -> double* {

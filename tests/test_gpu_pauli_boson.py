@@ -1,0 +1,173 @@
+"""GPU parity of the Pauli-boson graph (the paper's own algebra; Eq. monomial,
+Eq. graph-actions) through the C ABI against the oracle's exact complex
+expansion.  Device vectors are real-split (rows [0, n) real, [n, 2n) imaginary).
+
+Bounds per element, with S_k = sum over the target's records of
+|f| (|Re u| + |Im u|) (|Re v| + |Im v|) (u, v the two inputs of the record):
+FP64 2 gamma_n S with n four times the longest segment (each complex record is
+four real records per output row); float passes add 2 * 2^-24 S and use the
+compensated bound.
+"""
+import numpy as np
+import pytest
+
+import gpu_util as U
+import workloads
+from oracle import pauli_boson as PB
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+_og = {}
+_g = {}
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2609_14831_amd import _lib
+    return _lib
+
+
+def _graphs(L, M, p, outside=True):
+    key = (M, p, outside)
+    if key not in _og:
+        _og[key] = PB.PBGraph(M, p, outside=outside)
+    if key not in _g:
+        import os
+        path = os.path.join(U._tmp, f"pb_{M}_{p}_{int(outside)}.cgb")
+        L.cut_graph_build(L.CUT_ALG_PAULI_BOSON, 256 * M + p, path, 0, L.CUT_BUILD_OUTSIDE if outside else 0)
+        _g[key] = L.cut_graph_load(path, 0, L.CUT_LOAD_ADJOINT)
+    return _g[key], _og[key]
+
+
+def _rs(v):
+    """complex [n, ...] -> real-split device tensor [2n, cols]"""
+    a = workloads.real_split(np.asarray(v))
+    return torch.tensor(a.reshape(a.shape[0], -1), device=DEV).contiguous()
+
+
+def _cplx(t, n):
+    a = t.cpu().numpy()
+    return a[:n] + 1j * a[n:]
+
+
+def _abs_sum(recs, n, u, v):
+    """S_k over (k, a, j, f) records with inputs u[a], v[j] (complex [.., cols])."""
+    S = np.zeros((n,) + np.broadcast_shapes(u.shape[1:], v.shape[1:]))
+    au, av = np.abs(u.real) + np.abs(u.imag), np.abs(v.real) + np.abs(v.imag)
+    for k, a, j, f in recs:
+        S[k] += abs(complex(*f)) * au[a] * av[j]
+    return S
+
+
+def _bound(L, P, seg):
+    n = 4 * seg
+    if P == L.CUT_F64:
+        return U.sum_bound(n)
+    return 2 * U.U32 + (U.sum_bound(n) if P == L.CUT_F32X else U.dot2_bound(n))
+
+
+@pytest.mark.parametrize("M,p", [(1, 4), (2, 4), (3, 2)])
+def test_labels_and_sizes(L, M, p):
+    g, og = _graphs(L, M, p)
+    d = L.cut_graph_info(g)
+    assert d["n_ops"] == og.N == PB.registry_size(M, p) and d["n_gen_ops"] == og.NG
+    assert d["n_out_ops"] == len(og.out_labels)
+    W = (3 * p).bit_length()
+    for which, labs in ((0, og.labels), (1, og.gen_labels), (2, og.out_labels)):
+        keys = L.cut_graph_labels(g, which)
+        assert [workloads.pb_label(int(k), M, W) for k in keys] == labs
+
+
+@pytest.mark.parametrize("M,p", [(1, 4), (2, 4)])
+@pytest.mark.parametrize("prec", ["F64", "F32C", "F32X"])
+def test_generator_action_and_outside(L, M, p, prec):
+    U.say(f"[pauli-boson] M={M} p={p} {prec}")
+    P = getattr(L, "CUT_" + prec)
+    g, og = _graphs(L, M, p)
+    N, NG, NC = og.N, og.NG, len(og.out_labels)
+    nsets, nops = 3, 2
+    rng = np.random.default_rng(10 * M + p)
+    h = np.stack([workloads.pb_hermitian(og.labels, rng) for _ in range(nsets)], axis=1)    # [N, sets]
+    xi = np.stack([og.generator(h[:, s]) for s in range(nsets)], axis=1)                      # [NG, sets]
+    x = rng.normal(size=(N, nops, nsets)) + 1j * rng.normal(size=(N, nops, nsets))
+    # generator (Wegner graph pass over E_eta; FP64)
+    eta = torch.zeros((2 * NG, nsets), dtype=torch.float64, device=DEV)
+    L.cut_generator(g, L.CUT_GEN_WEGNER_GRAPH, 0.0, nsets, _rs(h), eta)
+    S = _abs_sum(og.eta, NG, h, h)
+    seg_g = int(np.max(np.bincount([r[0] for r in og.eta], minlength=NG)))
+    U.assert_within(np.abs(_cplx(eta, NG) - xi), 0 * xi.real, U.sum_bound(4 * seg_g) * S * 2 + 1e-300, "generator")
+    # retained action
+    dt = torch.float64 if P == L.CUT_F64 else torch.float32
+    y = torch.zeros((2 * N, nops * nsets), dtype=torch.float64, device=DEV)
+    L.cut_graph_apply(g, L.CUT_GRAPH_FLOW, P, nsets, nops, _rs(xi).to(dt), _rs(x).to(dt), y)
+    ref = np.stack([np.stack([og.action(xi[:, s], x[:, o, s]) for s in range(nsets)], 1) for o in range(nops)], 1)
+    S = _abs_sum(og.flow, N, xi[:, None, :], x)
+    seg = int(np.max(np.bincount([r[0] for r in og.flow], minlength=N)))
+    got = _cplx(y, N).reshape(N, nops, nsets)
+    U.assert_within(np.abs(got - ref), 0 * ref.real, _bound(L, P, seg) * S * 2 + 1e-300, "action")
+    # outside-space action
+    yc = torch.zeros((2 * NC, nops * nsets), dtype=torch.float64, device=DEV)
+    L.cut_graph_apply(g, L.CUT_GRAPH_OUTSIDE, P, nsets, nops, _rs(xi).to(dt), _rs(x).to(dt), yc)
+    refc = np.zeros((NC, nops, nsets), dtype=complex)
+    for q, a, j, f in og.outside:
+        refc[q] += complex(*f) * xi[a][None, :] * x[j]
+    S = _abs_sum(og.outside, NC, xi[:, None, :], x)
+    segc = int(np.max(np.bincount([r[0] for r in og.outside], minlength=NC)))
+    gotc = _cplx(yc, NC).reshape(NC, nops, nsets)
+    U.assert_within(np.abs(gotc - refc), 0 * refc.real, _bound(L, P, segc) * S * 2 + 1e-300, "outside")
+
+
+@pytest.mark.parametrize("prec,tol", [("F64", 1e-11), ("F32C", 2e-6)])
+def test_flow_matches_oracle(L, prec, tol):
+    """RK4 coflow of two Hermitian Hamiltonians with one operator each on the
+    M = 1, p = 4 registry (Wegner block generator), 20 steps, against the
+    oracle's complex RK4; the flowed H stays Hermitian.  The projected flow of
+    a complete boson registry is stiff (high-degree labels carry large
+    normal-ordering factors), so H has small off-diagonal parts."""
+    M, p, nsets, nops, ds, steps = 1, 4, 2, 2, 1e-3, 20
+    g, og = _graphs(L, M, p)
+    N = og.N
+    rng = np.random.default_rng(77)
+    z0 = np.zeros((N, nops, nsets), dtype=complex)
+    for s in range(nsets):
+        z0[:, 0, s] = workloads.pb_hermitian(og.labels, rng, 1.0, 0.02)   # a stable flow over s = 0.02
+        z0[:, 1, s] = workloads.pb_hermitian(og.labels, rng, 1.0, 1.0)
+    ref = np.stack([PB.flow(og, z0[:, :, s], ds, steps) for s in range(nsets)], axis=2)
+    z = _rs(z0).reshape(2 * N, nops, nsets).contiguous()
+    prm = L.flow_params(L.CUT_GEN_WEGNER_GRAPH, getattr(L, "CUT_" + prec), ds, 0.0, 0)
+    L.cut_flow_integrate(g, prm, nsets, nops, [steps] * nsets, z)
+    torch.cuda.synchronize()
+    got = _cplx(z.reshape(2 * N, -1), N).reshape(N, nops, nsets)
+    rel = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+    U.say(f"[pauli-boson flow] {prec}: relative error {rel:.3e}")
+    assert rel < tol
+    dag = [og.index[(Lb[0], Lb[2], Lb[1])] for Lb in og.labels]
+    assert np.abs(got[dag, 0, :] - np.conj(got[:, 0, :])).max() < 10 * tol * np.abs(got).max()
+
+
+def test_jvp_matches_exact_polarisation(L):
+    """cut_graph_jvp with the Wegner generator on M = 2, p = 3 (FP64): the
+    generator is quadratic, so d xi = (xi(h + dh) - xi(h - dh)) / 2 exactly, and
+    dF = F(d xi, x) + F(xi, dx)."""
+    M, p, nsets, nops = 2, 3, 2, 2
+    g, og = _graphs(L, M, p, outside=False)
+    N = og.N
+    rng = np.random.default_rng(5)
+    h = np.stack([workloads.pb_hermitian(og.labels, rng) for _ in range(nsets)], 1)
+    dh = np.stack([workloads.pb_hermitian(og.labels, rng) for _ in range(nsets)], 1)
+    x = rng.normal(size=(N, nops, nsets)) + 1j * rng.normal(size=(N, nops, nsets))
+    dx = rng.normal(size=(N, nops, nsets)) + 1j * rng.normal(size=(N, nops, nsets))
+    ref = np.zeros((N, nops, nsets), dtype=complex)
+    for s in range(nsets):
+        xi = og.generator(h[:, s])
+        dxi = 0.5 * (og.generator(h[:, s] + dh[:, s]) - og.generator(h[:, s] - dh[:, s]))
+        for o in range(nops):
+            ref[:, o, s] = og.action(dxi, x[:, o, s]) + og.action(xi, dx[:, o, s])
+    dy = torch.zeros((2 * N, nops * nsets), dtype=torch.float64, device=DEV)
+    L.cut_graph_jvp(g, L.CUT_GEN_WEGNER_GRAPH, 0.0, L.CUT_F64, nsets, nops, _rs(h), _rs(dh), _rs(x), _rs(dx),
+                    None, dy)
+    torch.cuda.synchronize()
+    got = _cplx(dy, N).reshape(N, nops, nsets)
+    assert np.abs(got - ref).max() < 1e-11 * np.abs(ref).max()

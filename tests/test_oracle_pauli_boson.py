@@ -1,0 +1,141 @@
+"""Pins of the oracle's Pauli-boson algebra (Eq. monomial, Eq. basis-size,
+Eq. projected-flow, Eq. graph-actions).
+
+* registry sizes against Eq. basis-size;
+* commutators against dense matrices on a truncated Fock space: sigma_tau (x)
+  prod_m (b^+)^c b^a with b|n> = sqrt(n)|n-1>, compared on the input states whose
+  occupations keep every intermediate state below the cutoff, where the
+  truncated products are exact;
+* the adjoint symmetry [A, B]^+ = [B^+, A^+] of the exact coefficients;
+* record counts of the five-mode degree-4 graph against the numbers the paper
+  prints (Sec. 3.2: 7,017,036 generator + retained-flow contributions and
+  345,388,180 outside-space contributions), through the oracle's plain-C
+  counter;
+* the generator and action against dense commutators on a random Hamiltonian.
+"""
+import itertools
+import json
+import math
+import os
+from functools import reduce
+
+import numpy as np
+import pytest
+
+from oracle import pauli_boson as PB
+
+GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+_SIG = [np.eye(2), np.array([[0, 1], [1, 0]]), np.array([[0, -1j], [1j, 0]]), np.diag([1.0, -1.0])]
+
+
+def _dense(L, nmax):
+    tau, c, a = L
+    b = np.diag(np.sqrt(np.arange(1, nmax + 1)), 1)
+    mats = [np.linalg.matrix_power(b.T, c[m]) @ np.linalg.matrix_power(b, a[m]) for m in range(len(c))]
+    return np.kron(_SIG[tau], reduce(np.kron, mats))
+
+
+def _safe_columns(M, nmax, cmax):
+    cols = []
+    for occ in itertools.product(range(nmax + 1), repeat=M):
+        if all(occ[m] <= nmax - cmax[m] for m in range(M)):
+            idx = 0
+            for m in range(M):
+                idx = idx * (nmax + 1) + occ[m]
+            cols.append(idx)
+    dimb = (nmax + 1) ** M
+    return [s * dimb + q for s in range(2) for q in cols]
+
+
+@pytest.mark.parametrize("M,p", [(1, 1), (1, 4), (2, 3), (3, 2), (5, 4)])
+def test_registry_size(M, p):
+    assert len(PB.registry(M, p)) == PB.registry_size(M, p)
+    assert PB.registry_size(5, 4) == 4004 and PB.registry_size(2, 4) == 280 and PB.registry_size(1, 24) == 1300
+
+
+@pytest.mark.parametrize("M,p,nmax", [(1, 4, 14), (2, 3, 7)])
+def test_commutators_match_dense_matrices(M, p, nmax):
+    labels = PB.registry(M, p)
+    rng = np.random.default_rng(M * 10 + p)
+    pairs = [(labels[i], labels[j]) for i, j in rng.integers(0, len(labels), size=(60, 2))]
+    # generator-registry products too (degree up to 2p on the left)
+    g = PB.PBGraph(M, min(p, 2))
+    pairs += [(g.gen_labels[i], labels[j]) for i, j in
+              zip(rng.integers(0, g.NG, 20), rng.integers(0, len(labels), 20))]
+    checked = 0
+    for A, B in pairs:
+        cmax = [A[1][m] + B[1][m] for m in range(M)]
+        if any(x > nmax - 1 for x in cmax):
+            continue
+        cols = _safe_columns(M, nmax, cmax)
+        DA, DB = _dense(A, nmax), _dense(B, nmax)
+        ref = (DA @ DB - DB @ DA)[:, cols]
+        got = np.zeros(ref.shape, dtype=complex)
+        for L, f in PB.commutator(A, B).items():
+            got += complex(*f) * _dense(L, nmax)[:, cols]
+        assert np.allclose(got, ref, atol=1e-9 * max(1.0, np.abs(ref).max())), (A, B)
+        checked += 1
+    assert checked >= 40
+
+
+def test_commutator_adjoint_symmetry():
+    labels = PB.registry(2, 4)
+    dag = lambda L: (L[0], L[2], L[1])
+    rng = np.random.default_rng(1)
+    for i, j in rng.integers(0, len(labels), size=(300, 2)):
+        A, B = labels[i], labels[j]
+        lhs = {dag(L): (f[0], -f[1]) for L, f in PB.commutator(A, B).items()}
+        assert lhs == PB.commutator(dag(B), dag(A))
+
+
+def test_generator_and_action_match_dense_commutators():
+    """H Hermitian on the M = 1, p = 3 registry: xi = [H_d, H_od] and
+    F = P[eta, X] agree with dense matrices on the safe columns (the outside part
+    is what the projection drops, so only the retained labels are compared by
+    projecting the dense commutator's expansion)."""
+    M, p, nmax = 1, 3, 16
+    g = PB.PBGraph(M, p, outside=True)
+    rng = np.random.default_rng(3)
+    h = np.zeros(g.N, dtype=complex)
+    for n, L in enumerate(g.labels):           # Hermitian: h_{L^+} = conj(h_L)
+        Ld = (L[0], L[2], L[1])
+        m = g.index[Ld]
+        if m == n:
+            h[n] = rng.normal()
+        elif m > n:
+            h[n] = rng.normal() + 1j * rng.normal()
+            h[m] = np.conj(h[n])
+    x = rng.normal(size=g.N) + 1j * rng.normal(size=g.N)
+    xi = g.generator(h)
+    # eta as a dense matrix from the generator registry vs [H_d, H_od] densely
+    dense = lambda coeffs, labs: sum(c * _dense(L, nmax) for c, L in zip(coeffs, labs))
+    # the joint sigma_z / boson-number eigenspaces are single product states, so
+    # the block-diagonal part of H is its diagonal in that basis
+    Hfull = dense(h, g.labels)
+    Hd = np.diag(np.diag(Hfull))
+    Hod = Hfull - Hd
+    cols = _safe_columns(M, nmax, [2 * p])
+    eta_dense = (Hd @ Hod - Hod @ Hd)[:, cols]
+    assert np.allclose(dense(xi, g.gen_labels)[:, cols], eta_dense, atol=1e-8)
+    # retained + outside action equals the full commutator [eta, X]
+    F = g.action(xi, x)
+    C = np.zeros(len(g.out_labels), dtype=complex)
+    for q, a, j, f in g.outside:
+        C[q] += complex(*f) * xi[a] * x[j]
+    cols = _safe_columns(M, nmax, [3 * p])
+    Xd = dense(x, g.labels)
+    E = dense(xi, g.gen_labels)
+    full = (E @ Xd - Xd @ E)[:, cols]
+    got = dense(F, g.labels)[:, cols] + dense(C, g.out_labels)[:, cols]
+    assert np.allclose(got, full, atol=1e-7 * np.abs(full).max())
+
+
+def test_five_mode_counts_match_the_paper():
+    """Sec. 3.2: complete degree-four registry with five boson modes."""
+    from oracle import native
+    ref = json.load(open(os.path.join(GOLD, "pauli_boson_counts.json")))
+    for case in ref["cases"]:
+        got = native.pb_counts(case["M"], case["p"])
+        for key in ("n_ops", "production", "outside"):
+            if key in case:
+                assert got[key] == case[key], (case, got)

@@ -176,3 +176,42 @@ def random_dense(shape, seed: int, scale: float = 1.0) -> np.ndarray:
     """Plain seeded N(0, scale) array for operand / adjoint-seed tests."""
     rng = np.random.default_rng([SEED_BASE, 7, seed])
     return rng.normal(0.0, scale, size=shape)
+
+
+def pb_label(key: int, M: int, W: int):
+    """(tau, c, a) of a Pauli-boson label key: W-bit fields, from the top:
+    degree, tau (2 bits), then c_1, a_1, ..., c_M, a_M (the layout
+    cut_graph_labels documents)."""
+    mask = (1 << W) - 1
+    c, a = [0] * M, [0] * M
+    for m in range(M - 1, -1, -1):
+        a[m] = key & mask
+        key >>= W
+        c[m] = key & mask
+        key >>= W
+    return (key & 3, tuple(c), tuple(a))
+
+
+def pb_hermitian(labels, rng, diag_scale: float = 1.0, off_scale: float = 0.1) -> np.ndarray:
+    """Seeded complex coefficients of a Hermitian operator over Pauli-boson
+    labels (tau, c, a): h_{L^+} = conj(h_L) with B_{tau,c,a}^+ = B_{tau,a,c};
+    block-diagonal labels (tau in {I, z}, c = a) ~ N(0, diag_scale), the others
+    off_scale * (N(0,1) + i N(0,1)), real where a label is its own adjoint."""
+    index = {L: n for n, L in enumerate(labels)}
+    h = np.zeros(len(labels), dtype=complex)
+    for n, L in enumerate(labels):
+        m = index[(L[0], L[2], L[1])]
+        if m < n:
+            continue
+        diag = L[0] in (0, 3) and L[1] == L[2]
+        if m == n:
+            h[n] = rng.normal() * (diag_scale if diag else off_scale)
+        else:
+            h[n] = off_scale * (rng.normal() + 1j * rng.normal())
+            h[m] = np.conj(h[n])
+    return h
+
+
+def real_split(v: np.ndarray) -> np.ndarray:
+    """Rows [0, n) real parts, [n, 2n) imaginary parts (axis 0)."""
+    return np.concatenate([v.real, v.imag], axis=0)
