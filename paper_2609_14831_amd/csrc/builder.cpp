@@ -560,11 +560,27 @@ static cut_status build_pauli_boson(int M, int p, const char* path, int nt, bool
         for (auto& r : graw) goff[(size_t)gidx[r.key] + 1]++;
         for (int64_t a = 0; a < NG; ++a) goff[a + 1] += goff[a];
 
-        // traversal 1: counts per retained target, outside labels with their counts
+        // candidate outside labels: every label of degree p+1 .. 3p (a bracket of a
+        // generator label, degree <= 2p, with a registry label reaches no
+        // further), indexed once; the outside registry is the subset reached
+        std::vector<uint64_t> cand;
+        std::unordered_map<uint64_t, int32_t> cidx;
+        if (outside) {
+            PBAlgebra wide(M, 3 * p);
+            wide.cd = alg.cd;                       // same key layout
+            for (uint64_t key : wide.registry())
+                if (!ridx.count(key)) cand.push_back(key);
+            if ((int64_t)cand.size() >= (1ll << 31)) CUT_FAIL(CUT_E_UNSUPPORTED, "cut_graph_build: outside space too large");
+            cidx.reserve(cand.size() * 2);
+            for (size_t q = 0; q < cand.size(); ++q) cidx[cand[q]] = (int32_t)q;
+        }
+        // traversal 1: counts per retained target and per candidate outside label
         std::vector<std::vector<int64_t>> tcnt(nt, std::vector<int64_t>((size_t)N, 0));
-        std::vector<std::unordered_map<uint64_t, int64_t>> tout(nt);
+        std::vector<std::atomic<int64_t>> ccnt(cand.size());
+        for (auto& c : ccnt) c.store(0, std::memory_order_relaxed);
         {
             std::atomic<int64_t> next{0};
+            std::atomic<int> stray{0};
             auto work = [&](int tid) {
                 std::vector<PBTerm> t;
                 for (int64_t a; (a = next.fetch_add(1)) < NG;)
@@ -572,8 +588,13 @@ static cut_status build_pauli_boson(int M, int p, const char* path, int nt, bool
                         alg.commutator(gen[(size_t)a], reg[(size_t)j], t);
                         for (auto& x : t) {
                             auto it = ridx.find(x.key);
-                            if (it != ridx.end()) tcnt[tid][(size_t)it->second]++;
-                            else if (outside) tout[tid][x.key]++;
+                            if (it != ridx.end()) {
+                                tcnt[tid][(size_t)it->second]++;
+                            } else if (outside) {
+                                auto ic = cidx.find(x.key);
+                                if (ic == cidx.end()) stray = 1;
+                                else ccnt[(size_t)ic->second].fetch_add(1, std::memory_order_relaxed);
+                            }
                         }
                     }
             };
@@ -581,6 +602,7 @@ static cut_status build_pauli_boson(int M, int p, const char* path, int nt, bool
             for (int q = 1; q < nt; ++q) th.emplace_back(work, q);
             work(0);
             for (auto& x : th) x.join();
+            if (stray) CUT_FAIL(CUT_E_UNSUPPORTED, "cut_graph_build: a bracket left the degree-3p label space");
         }
         std::vector<int64_t> loff((size_t)N + 1, 0);
         for (int q = 0; q < nt; ++q)
@@ -590,23 +612,15 @@ static cut_status build_pauli_boson(int M, int p, const char* path, int nt, bool
         const int64_t E = loff[(size_t)N];
         std::vector<uint64_t> olab;
         std::vector<int64_t> coff(1, 0);
-        std::unordered_map<uint64_t, int64_t> oidx;
-        if (outside) {
-            for (int q = 1; q < nt; ++q) {
-                for (auto& kv : tout[q]) tout[0][kv.first] += kv.second;
-                tout[q].clear();
-            }
-            olab.reserve(tout[0].size());
-            for (auto& kv : tout[0]) olab.push_back(kv.first);
-            std::sort(olab.begin(), olab.end());
-            coff.assign(olab.size() + 1, 0);
-            oidx.reserve(olab.size() * 2);
-            for (size_t q = 0; q < olab.size(); ++q) {
-                oidx[olab[q]] = (int64_t)q;
-                coff[q + 1] = coff[q] + tout[0][olab[q]];
-            }
-            tout.clear();
+        std::vector<int32_t> cand2out(cand.size(), -1);   // candidate -> outside registry index
+        for (size_t q = 0; q < cand.size(); ++q) {
+            const int64_t n = ccnt[q].load(std::memory_order_relaxed);
+            if (n == 0) continue;
+            cand2out[q] = (int32_t)olab.size();
+            olab.push_back(cand[q]);
+            coff.push_back(coff.back() + n);
         }
+        ccnt = std::vector<std::atomic<int64_t>>();
         const int64_t Nc = (int64_t)olab.size(), Ec = coff.back();
 
         // file layout: base sections, generator labels, outside sections
@@ -698,7 +712,7 @@ static cut_status build_pauli_boson(int M, int p, const char* path, int nt, bool
                                 Lc[2 * q] = (int16_t)x.re;
                                 Lc[2 * q + 1] = (int16_t)x.im;
                             } else if (outside) {
-                                const int64_t q = curC[(size_t)oidx.at(x.key)].fetch_add(1);
+                                const int64_t q = curC[(size_t)cand2out[(size_t)cidx.at(x.key)]].fetch_add(1);
                                 Ci[q] = (int32_t)a;
                                 Cj[q] = (int32_t)j;
                                 Cc[2 * q] = (int16_t)x.re;
