@@ -161,8 +161,8 @@ cut_status cut_graph_info(cut_graph_t g, cut_graph_desc* desc);
  * total degree, tau (2 bits: 0 = I, 1 = x, 2 = y, 3 = z), then c_1, a_1, ...,
  * c_M, a_M (their numeric order is the registry order).  Pauli-boson
  * coefficient vectors are complex and stored real-split on the device: a
- * registry of n labels has 2n rows, row r the real and row n + r the imaginary
- * part of coefficient r (operands, generator, outputs alike).
+ * registry of n labels has 2n rows, row 2r the real and row 2r + 1 the
+ * imaginary part of coefficient r (operands, generator, outputs alike).
  * Errors: CUT_E_INVAL (null argument, unknown or absent registry, n mismatch). */
 cut_status cut_graph_labels(cut_graph_t g, int32_t which, uint64_t* out, int64_t n);
 void cut_graph_free(cut_graph_t g);

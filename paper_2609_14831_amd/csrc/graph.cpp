@@ -781,13 +781,14 @@ static void upload_set(Graph& g, int w, std::vector<int64_t>&& off, std::vector<
 }
 
 // Real-split form of a set of complex records (Pauli-boson graphs): a complex
-// coefficient vector v of n entries is stored as 2n real rows, row r = Re v_r,
-// row n + r = Im v_r.  A record y_k += c xi_a x_j with c = re + i im becomes
+// coefficient vector v of n entries is stored as 2n real rows, interleaved:
+// row 2r = Re v_r, row 2r + 1 = Im v_r (the two halves of one coefficient
+// share a cache line, so every gather of a complex record touches one line per
+// operand).  A record y_k += c xi_a x_j with c = re + i im becomes
 //   Re y_k += re (xi_a^r x_j^r - xi_a^i x_j^i) - im (xi_a^r x_j^i + xi_a^i x_j^r)
 //   Im y_k += re (xi_a^r x_j^i + xi_a^i x_j^r) + im (xi_a^r x_j^r - xi_a^i x_j^i)
 // i.e. up to four real records per target row, kept in the stored order.
-static void real_split(const HostGraph& hg, int w, int64_t nk, int64_t na, int64_t nj, std::vector<int64_t>& off2,
-                       std::vector<uint2>& rec2) {
+static void real_split(const HostGraph& hg, int w, int64_t nk, std::vector<int64_t>& off2, std::vector<uint2>& rec2) {
     const int64_t* off = hg.off[w];
     const int32_t* ri = hg.ri[w];
     const int32_t* rj = hg.rj[w];
@@ -804,18 +805,18 @@ static void real_split(const HostGraph& hg, int w, int64_t nk, int64_t na, int64
             factor(e, re, im);
             n += 2 * (re != 0) + 2 * (im != 0);
         }
-        off2[k + 1] = n;        // real rows
-        off2[nk + k + 1] = n;   // imaginary rows (same count)
+        off2[2 * k + 1] = n;    // real row of target k
+        off2[2 * k + 2] = n;    // imaginary row (same count)
     }
     for (int64_t r = 0; r < 2 * nk; ++r) off2[r + 1] += off2[r];
     rec2.resize((size_t)off2[2 * nk]);
     for (int64_t k = 0; k < nk; ++k) {
-        int64_t pr = off2[k], pi = off2[nk + k];
+        int64_t pr = off2[2 * k], pi = off2[2 * k + 1];
         for (int64_t e = off[k]; e < off[k + 1]; ++e) {
             int16_t re, im;
             factor(e, re, im);
-            const uint32_t ar = (uint32_t)ri[e], ai = (uint32_t)(ri[e] + na);
-            const uint32_t jr = (uint32_t)rj[e], ji = (uint32_t)(rj[e] + nj);
+            const uint32_t ar = 2u * (uint32_t)ri[e], ai = ar + 1u;
+            const uint32_t jr = 2u * (uint32_t)rj[e], ji = jr + 1u;
             if (re != 0) {
                 rec2[pr++] = pack_record_int(re, ar, jr);
                 rec2[pr++] = pack_record_int(-re, ai, ji);
@@ -838,13 +839,13 @@ static void load_pauli_boson(Graph& g, const HostGraph& hg, bool adjoint) {
     const int64_t N = hg.hdr.n_ops, NG = hg.n_gen;
     std::vector<int64_t> off;
     std::vector<uint2> rec;
-    real_split(hg, 0, N, NG, N, off, rec);                 // E_L: target k, left a (generator), right j
+    real_split(hg, 0, N, off, rec);                        // E_L: target k, left a (generator), right j
     upload_set(g, 0, std::move(off), std::move(rec), adjoint, 2 * NG, 2 * N);
-    real_split(hg, 1, NG, N, N, off, rec);                 // E_eta: target a, left i, right j (operators)
+    real_split(hg, 1, NG, off, rec);                       // E_eta: target a, left i, right j (operators)
     upload_set(g, 1, std::move(off), std::move(rec), adjoint, 2 * N, 2 * N);
     if (hg.off[2]) {
         const int64_t Nc = hg.hdr.n_out_ops;
-        real_split(hg, 2, Nc, NG, N, off, rec);
+        real_split(hg, 2, Nc, off, rec);
         upload_set(g, 2, std::move(off), std::move(rec), false, 2 * NG, 2 * N);
         g.have_outside = true;
         g.n_out = 2 * Nc;

@@ -1,6 +1,6 @@
 """GPU parity of the Pauli-boson graph (the paper's own algebra; Eq. monomial,
 Eq. graph-actions) through the C ABI against the oracle's exact complex
-expansion.  Device vectors are real-split (rows [0, n) real, [n, 2n) imaginary).
+expansion.  Device vectors are real-split (row 2r real, row 2r + 1 imaginary).
 
 Bounds per element, with S_k = sum over the target's records of
 |f| (|Re u| + |Im u|) (|Re v| + |Im v|) (u, v the two inputs of the record):
@@ -49,7 +49,8 @@ def _rs(v):
 
 def _cplx(t, n):
     a = t.cpu().numpy()
-    return a[:n] + 1j * a[n:]
+    assert a.shape[0] == 2 * n
+    return workloads.from_real_split(a)
 
 
 def _abs_sum(recs, n, u, v):

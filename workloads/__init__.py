@@ -213,5 +213,13 @@ def pb_hermitian(labels, rng, diag_scale: float = 1.0, off_scale: float = 0.1) -
 
 
 def real_split(v: np.ndarray) -> np.ndarray:
-    """Rows [0, n) real parts, [n, 2n) imaginary parts (axis 0)."""
-    return np.concatenate([v.real, v.imag], axis=0)
+    """Interleaved real-split rows (axis 0): row 2r = Re v_r, row 2r + 1 = Im v_r."""
+    out = np.empty((2 * v.shape[0],) + v.shape[1:])
+    out[0::2] = v.real
+    out[1::2] = v.imag
+    return out
+
+
+def from_real_split(a: np.ndarray) -> np.ndarray:
+    """Inverse of real_split."""
+    return a[0::2] + 1j * a[1::2]
