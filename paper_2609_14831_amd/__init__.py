@@ -5,7 +5,9 @@ include/cutgraph.h).  This package only marshals arguments:
 
 * ``_lib``  -- ctypes binding, one function per C entry point, same names
 * ``flow``  -- torch.autograd.Function running the RK4 coflow forward and its
-               checkpointed discrete adjoint backward through the C ABI
+               checkpointed discrete adjoint backward through the C ABI; and
+               one for a single action with reverse (cut_graph_vjp) and
+               forward-mode (cut_graph_jvp) derivatives
 
 Importing raises if libcutgraph.so has not been built; nothing falls back to a
 CPU implementation.

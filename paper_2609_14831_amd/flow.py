@@ -43,3 +43,65 @@ class FlowFn(torch.autograd.Function):
 def flow(z0, graph, n_steps, generator=L.CUT_GEN_G2, ds=5e-3, delta=0.5, ckpt_every=16,
          precision=L.CUT_F64):
     return FlowFn.apply(z0, graph, n_steps, generator, ds, delta, ckpt_every, precision)
+
+
+def _gen_rows(graph: int) -> int:
+    """Generator rows of a loaded graph (Pauli-boson graphs are real-split)."""
+    d = L.cut_graph_info(graph)
+    return (2 if d["algebra"] == L.CUT_ALG_PAULI_BOSON else 1) * (d["n_gen_ops"] or d["n_ops"])
+
+
+class ActionFn(torch.autograd.Function):
+    """One projected action F(h, x) = L(eta(h)) x (Sec. 2.4), differentiable in
+    both arguments: backward through cut_graph_vjp (the adjoint traversals and
+    the generator VJP), forward mode through cut_graph_jvp (Eq.
+    directional-derivative).  h [rows, nsets], x [rows, nops, nsets], both
+    float64 contiguous on the device; the result has the layout of x."""
+
+    @staticmethod
+    def forward(h, x, graph: int, generator: int, delta: float, precision: int):
+        assert h.is_cuda and x.is_cuda and h.dtype == x.dtype == torch.float64
+        assert h.dim() == 2 and x.dim() == 3 and h.is_contiguous() and x.is_contiguous()
+        N, nops, nsets = x.shape
+        eta = torch.empty((_gen_rows(graph), nsets), dtype=torch.float64, device=h.device)
+        L.cut_generator(graph, generator, delta, nsets, h, eta)
+        y = torch.empty_like(x)
+        xa = x.view(N, nops * nsets)
+        if precision != L.CUT_F64:
+            eta, xa = eta.float(), xa.float()
+        L.cut_graph_apply(graph, L.CUT_GRAPH_FLOW, precision, nsets, nops, eta, xa, y.view(N, nops * nsets))
+        return y
+
+    @staticmethod
+    def setup_context(ctx, inputs, output):
+        h, x, graph, generator, delta, precision = inputs
+        ctx.save_for_backward(h, x)
+        ctx.save_for_forward(h, x)
+        ctx.cfg = (graph, generator, delta, precision)
+
+    @staticmethod
+    def backward(ctx, gy):
+        h, x = ctx.saved_tensors
+        graph, generator, delta, precision = ctx.cfg
+        N, nops, nsets = x.shape
+        g_h = torch.empty_like(h)
+        g_x = torch.empty_like(x)
+        L.cut_graph_vjp(graph, generator, delta, precision, nsets, nops, h, x.view(N, nops * nsets),
+                        gy.contiguous().view(N, nops * nsets), g_h, g_x.view(N, nops * nsets))
+        return g_h, g_x, None, None, None, None
+
+    @staticmethod
+    def jvp(ctx, dh, dx, *_):
+        h, x = ctx.saved_tensors
+        graph, generator, delta, precision = ctx.cfg
+        N, nops, nsets = x.shape
+        dy = torch.empty_like(x)
+        L.cut_graph_jvp(graph, generator, delta, precision, nsets, nops, h,
+                        None if dh is None else dh.contiguous(), x.view(N, nops * nsets),
+                        None if dx is None else dx.contiguous().view(N, nops * nsets), None,
+                        dy.view(N, nops * nsets))
+        return dy
+
+
+def action(h, x, graph, generator=L.CUT_GEN_G2, delta=0.5, precision=L.CUT_F64):
+    return ActionFn.apply(h, x, graph, generator, delta, precision)

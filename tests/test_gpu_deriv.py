@@ -287,3 +287,36 @@ def test_jvp_argument_errors(L):
     ge = U.graph(L, "epq", 4)
     with pytest.raises(L.CutError, match="CUT_E_UNSUPPORTED"):
         L.cut_generator_jvp(ge, L.CUT_GEN_G2, 0.5, 1, h[:16, :1], h[:16, :1], dy[:16, :1])
+
+
+def test_action_autograd_reverse_and_forward_mode(L):
+    """paper_2609_14831_amd.flow.action: torch reverse mode (cut_graph_vjp) and
+    forward mode (cut_graph_jvp) against the oracle's transpose and directional
+    derivative, m = 12, G2, FP64."""
+    from paper_2609_14831_amd.flow import action
+    alg, size, kind, nsets, nops = "majorana", 12, "g2", 3, 2
+    g = U.graph(L, alg, size)
+    og = oracle_graph(alg, size)
+    N = og.N
+    gen, vjp = OG.make_generator(og, kind, 0.5)
+    jvp = OG.make_generator_jvp(og, kind, 0.5)
+    h = _hamiltonian(alg, size, N, nsets, seed=91)
+    x = workloads.random_dense((N, nops, nsets), seed=92)
+    w = workloads.random_dense((N, nops, nsets), seed=93)
+    dh = workloads.random_dense((N, nsets), seed=94)
+    dx = workloads.random_dense((N, nops, nsets), seed=95)
+    th = _t(h).requires_grad_(True)
+    tx = _t(x).requires_grad_(True)
+    y = action(th, tx, g, L.CUT_GEN_G2, 0.5, L.CUT_F64)
+    (y * _t(w)).sum().backward()
+    gh_ref, gx_ref = OD.action_vjp(og, gen, vjp, h, x, w)
+    np.testing.assert_allclose(th.grad.cpu().numpy(), gh_ref, rtol=1e-11, atol=1e-12 * np.abs(gh_ref).max())
+    np.testing.assert_allclose(tx.grad.cpu().numpy(), gx_ref, rtol=1e-11, atol=1e-12 * np.abs(gx_ref).max())
+    import torch.autograd.forward_ad as fwAD
+    with fwAD.dual_level():
+        y2 = action(fwAD.make_dual(_t(h), _t(dh)), fwAD.make_dual(_t(x), _t(dx)), g, L.CUT_GEN_G2, 0.5, L.CUT_F64)
+        dy = fwAD.unpack_dual(y2).tangent
+    ref = OD.action_jvp(og, gen, jvp, h, x, dh, dx)
+    np.testing.assert_allclose(dy.cpu().numpy(), ref, rtol=1e-11, atol=1e-12 * np.abs(ref).max())
+    np.testing.assert_allclose(y.detach().cpu().numpy(), OD.action(og, gen, h, x), rtol=1e-11,
+                               atol=1e-12 * np.abs(y.detach().cpu().numpy()).max())
