@@ -178,6 +178,37 @@ class PBGraph:
         return y
 
 
+def outside_action(g: "PBGraph", xi, x):
+    """C_q = sum gamma xi_a x_j over E_C (the graph must hold outside records)."""
+    import numpy as np
+    y = np.zeros(len(g.out_labels), dtype=complex)
+    for q, a, j, f in g.outside:
+        y[q] += complex(*f) * xi[a] * x[j]
+    return y
+
+
+def flow_outside(g: "PBGraph", z0, ds: float, steps: int):
+    """The flow of ``flow`` plus the outside-space diagnostic: every stage
+    state Z_s of every step adds b_s ds sum_q |C_q(Z_s)|^2 per operand
+    (b = 1/6, 1/3, 1/3, 1/6), C evaluated with the stage generator."""
+    import numpy as np
+    z = np.array(z0, dtype=complex)
+    leak = np.zeros(z.shape[1])
+    b = (1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0)
+    for _ in range(steps):
+        stage, ks = z, []
+        for s in range(4):
+            xi = g.generator(stage[:, 0])
+            for o in range(z.shape[1]):
+                c = outside_action(g, xi, stage[:, o])
+                leak[o] += b[s] * ds * float(np.sum(np.abs(c) ** 2))
+            ks.append(np.stack([g.action(xi, stage[:, o]) for o in range(z.shape[1])], axis=1))
+            if s < 3:
+                stage = z + (0.5 if s < 2 else 1.0) * ds * ks[-1]
+        z = z + (ds / 6.0) * (ks[0] + 2 * ks[1] + 2 * ks[2] + ks[3])
+    return z, leak
+
+
 def flow(g: "PBGraph", z0, ds: float, steps: int):
     """Classic RK4 of the coflow (Eq. coflow): z[:, 0] = H, z[:, 1:] = operators,
     dz/ds = P[eta(H), z] with eta = [H_d, H_od] from E_eta and P[.,.] from E_L

@@ -139,3 +139,29 @@ def test_five_mode_counts_match_the_paper():
         for key in ("n_ops", "production", "outside"):
             if key in case:
                 assert got[key] == case[key], (case, got)
+
+
+def test_flow_outside_matches_plain_flow_and_dense_outside_norm():
+    """One RK4 step on M = 1, p = 3: the flow with the outside-space diagnostic
+    leaves the state as the plain flow does, and each stage's sum_q |C_q|^2 is
+    the squared norm of the part of the dense [eta, X] outside the registry
+    (orthonormality is not used: the outside part is rebuilt from the C_q and
+    compared with the dense commutator minus the retained part)."""
+    import workloads
+    M, p, nmax = 1, 3, 16
+    g = PB.PBGraph(M, p, outside=True)
+    rng = np.random.default_rng(9)
+    z0 = np.stack([workloads.pb_hermitian(g.labels, rng, 1.0, 0.05),
+                   workloads.pb_hermitian(g.labels, rng, 1.0, 1.0)], axis=1)
+    z1, leak = PB.flow_outside(g, z0, 1e-3, 1)
+    np.testing.assert_array_equal(z1, PB.flow(g, z0, 1e-3, 1))
+    assert np.all(leak > 0)
+    xi = g.generator(z0[:, 0])
+    dense = lambda coeffs, labs: sum(c * _dense(L, nmax) for c, L in zip(coeffs, labs))
+    cols = _safe_columns(M, nmax, [3 * p])
+    for o in range(2):
+        E, X = dense(xi, g.gen_labels), dense(z0[:, o], g.labels)
+        full = (E @ X - X @ E)[:, cols]
+        outside = full - dense(g.action(xi, z0[:, o]), g.labels)[:, cols]
+        C = PB.outside_action(g, xi, z0[:, o])
+        assert np.allclose(dense(C, g.out_labels)[:, cols], outside, atol=1e-9 * np.abs(full).max())
