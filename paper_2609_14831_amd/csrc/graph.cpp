@@ -116,6 +116,7 @@ Graph::~Graph() {
     release_step_graphs(*this);
     for (auto& w : csr)
         for (auto& c : w) c.release();
+    for (auto& c : cxs) c.release();
     dev_free(ftab);
     dev_free(diag);
     dev_free(pairs);
@@ -835,18 +836,65 @@ static void real_split(const HostGraph& hg, int w, int64_t nk, std::vector<int64
 
 // Pauli-boson graph: every record set in real-split form; operator rows 2N,
 // generator rows 2NG, outside rows 2Nc.
+// Complex form of a set of records (Pauli-boson graphs), grouped by complex
+// target in the stored order: x = (f_hi << 24) | (imag << 23) | a,
+// y = (f_lo << 24) | j with (f_hi, f_lo) the bf16 pattern of the nonzero part
+// of the factor (a factor with both parts nonzero, which the commutators of
+// this algebra do not produce, would become two records).  The left index must
+// fit in 23 bits.
+static void complex_records(const HostGraph& hg, int w, int64_t nk, std::vector<int64_t>& off2,
+                            std::vector<uint2>& rec2) {
+    const int64_t* off = hg.off[w];
+    const int32_t* ri = hg.ri[w];
+    const int32_t* rj = hg.rj[w];
+    const int8_t* rc = hg.rc[w];
+    auto factor = [&](int64_t e, int16_t& re, int16_t& im) {
+        std::memcpy(&re, rc + 4 * e, 2);
+        std::memcpy(&im, rc + 4 * e + 2, 2);
+    };
+    off2.assign(nk + 1, 0);
+    for (int64_t k = 0; k < nk; ++k) {
+        int64_t n = 0;
+        for (int64_t e = off[k]; e < off[k + 1]; ++e) {
+            int16_t re, im;
+            factor(e, re, im);
+            n += (re != 0) + (im != 0);
+        }
+        off2[k + 1] = off2[k] + n;
+    }
+    rec2.resize((size_t)off2[nk]);
+    int64_t q = 0;
+    for (int64_t e = 0; e < off[nk]; ++e) {
+        int16_t re, im;
+        factor(e, re, im);
+        if ((uint32_t)ri[e] >= (1u << 23))
+            CUT_FAIL(CUT_E_UNSUPPORTED, "generator registry of %d labels exceeds 2^23", ri[e] + 1);
+        if (re != 0) rec2[q++] = pack_record_int(re, (uint32_t)ri[e], (uint32_t)rj[e]);
+        if (im != 0) {
+            const uint2 r = pack_record_int(im, (uint32_t)ri[e], (uint32_t)rj[e]);
+            rec2[q++] = make_uint2(r.x | (1u << 23), r.y);
+        }
+    }
+}
+
 static void load_pauli_boson(Graph& g, const HostGraph& hg, bool adjoint) {
     const int64_t N = hg.hdr.n_ops, NG = hg.n_gen;
     std::vector<int64_t> off;
     std::vector<uint2> rec;
     real_split(hg, 0, N, off, rec);                        // E_L: target k, left a (generator), right j
     upload_set(g, 0, std::move(off), std::move(rec), adjoint, 2 * NG, 2 * N);
+    complex_records(hg, 0, N, off, rec);
+    upload_csr(g, g.cxs[0], N, std::move(off), rec);
+    g.csr[0][0].cx = &g.cxs[0];
     real_split(hg, 1, NG, off, rec);                       // E_eta: target a, left i, right j (operators)
     upload_set(g, 1, std::move(off), std::move(rec), adjoint, 2 * N, 2 * N);
     if (hg.off[2]) {
         const int64_t Nc = hg.hdr.n_out_ops;
         real_split(hg, 2, Nc, off, rec);
         upload_set(g, 2, std::move(off), std::move(rec), false, 2 * NG, 2 * N);
+        complex_records(hg, 2, Nc, off, rec);
+        upload_csr(g, g.cxs[2], Nc, std::move(off), rec);
+        g.csr[2][0].cx = &g.cxs[2];
         g.have_outside = true;
         g.n_out = 2 * Nc;
     }

@@ -182,6 +182,9 @@ struct DevCSR {
     // chunks sweep the same operand region
     ChunkPlan cp;
     std::vector<int64_t> off_h; // host copy of the offsets (tiling plan input)
+    // Pauli-boson E_L / E_C: the same records in complex form, grouped by
+    // complex target (FP64 forward passes run over these; see k_cpass)
+    const DevCSR* cx = nullptr;
     void release();
 };
 
@@ -265,6 +268,7 @@ struct Graph {
     // orientation 0 = by target k (a=i, b=j), 1 = by right input j (a=i, b=k),
     // 2 = by left input i (a=k, b=j)
     DevCSR csr[3][3];
+    DevCSR cxs[3];                   // complex twins of sets 0 and 2 (Pauli-boson only)
     bool have_adjoint = false;
     bool have_outside = false;
     int64_t n_out = 0;               // outside rows (Pauli-boson: 2 x labels)

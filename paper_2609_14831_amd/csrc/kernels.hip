@@ -158,29 +158,35 @@ __device__ inline bool set_active(const KArgs& a, int s) {
 // the next stage operand is written (float or double shadow) together with the
 // FP64 Hamiltonian column.  z and the accumulator are touched once per stage:
 // streamed with non-temporal hints so they do not displace gathered rows.
+// One state element idx with right-hand side f at stage a.stage: updates the
+// accumulator (and, at the last stage, z) and returns the next stage state.
+__device__ inline double rk_combine(const KArgs& a, int64_t idx, double f) {
+    const double ds = a.ds;
+    const double zk = __builtin_nontemporal_load(a.z + idx);
+    double nxt;
+    if (a.stage == 0) {
+        __builtin_nontemporal_store(zk + (ds / 6.0) * f, a.acc + idx);
+        nxt = zk + 0.5 * ds * f;
+    } else if (a.stage == 1) {
+        __builtin_nontemporal_store(__builtin_nontemporal_load(a.acc + idx) + (ds / 3.0) * f, a.acc + idx);
+        nxt = zk + 0.5 * ds * f;
+    } else if (a.stage == 2) {
+        __builtin_nontemporal_store(__builtin_nontemporal_load(a.acc + idx) + (ds / 3.0) * f, a.acc + idx);
+        nxt = zk + ds * f;
+    } else {
+        nxt = __builtin_nontemporal_load(a.acc + idx) + (ds / 6.0) * f;
+        __builtin_nontemporal_store(nxt, a.z + idx);
+    }
+    return nxt;
+}
+
 template <int NOPS, class T>
 __device__ inline void rk_epilogue(const KArgs& a, int64_t seg, int s, const double* v) {
-    const double ds = a.ds;
     T* xo = (T*)a.xout;
 #pragma unroll
     for (int op = 0; op < NOPS; ++op) {
         const int64_t idx = seg * a.ldb + (int64_t)op * a.nsets + s;
-        const double zk = __builtin_nontemporal_load(a.z + idx);
-        const double f = v[op];
-        double nxt;
-        if (a.stage == 0) {
-            __builtin_nontemporal_store(zk + (ds / 6.0) * f, a.acc + idx);
-            nxt = zk + 0.5 * ds * f;
-        } else if (a.stage == 1) {
-            __builtin_nontemporal_store(__builtin_nontemporal_load(a.acc + idx) + (ds / 3.0) * f, a.acc + idx);
-            nxt = zk + 0.5 * ds * f;
-        } else if (a.stage == 2) {
-            __builtin_nontemporal_store(__builtin_nontemporal_load(a.acc + idx) + (ds / 3.0) * f, a.acc + idx);
-            nxt = zk + ds * f;
-        } else {
-            nxt = __builtin_nontemporal_load(a.acc + idx) + (ds / 6.0) * f;
-            __builtin_nontemporal_store(nxt, a.z + idx);
-        }
+        const double nxt = rk_combine(a, idx, v[op]);
         xo[idx] = (T)nxt;
         if (op == 0) a.hst[seg * a.ldh + s] = nxt;
     }
@@ -306,6 +312,14 @@ __global__ __launch_bounds__(256) void k_pass(KArgs a) {
                 for (int q = 0; q < NA; ++q) av[u][q] = buf_load<T>(ra, boff[q], 0);
 #pragma unroll
                 for (int op = 0; op < NOPS; ++op) bv[u][op] = buf_load<T>(rb, boff[op], 0);
+            } else if constexpr (G == 1) {
+                // one set: a row's columns are contiguous at offsets known at
+                // compile time, so the compiler fuses them into 16-byte loads
+                // (half the per-lane gather instructions of separate loads)
+#pragma unroll
+                for (int q = 0; q < NA; ++q) av[u][q] = arow[q];
+#pragma unroll
+                for (int op = 0; op < NOPS; ++op) bv[u][op] = brow[op];
             } else {
                 const char* ac = reinterpret_cast<const char*>(arow);
                 const char* bc = reinterpret_cast<const char*>(brow);
@@ -416,9 +430,14 @@ __global__ __launch_bounds__(256) void k_pass(KArgs a) {
                 for (int u = 0; u < U; ++u) {
                     const int t = t0 + u;
                     const int c = t / G;
-                    const int src = (t % G) * R + sub;
-                    rx[u] = (uint32_t)__shfl((int)mine[c].x, src);
-                    ry[u] = (uint32_t)__shfl((int)mine[c].y, src);
+                    if constexpr (G == 1) {  // every lane takes its own record
+                        rx[u] = mine[c].x;
+                        ry[u] = mine[c].y;
+                    } else {
+                        const int src = (t % G) * R + sub;
+                        rx[u] = (uint32_t)__shfl((int)mine[c].x, src);
+                        ry[u] = (uint32_t)__shfl((int)mine[c].y, src);
+                    }
                     okm[u] = t * R + sub < cnt ? 0xFFFFFFFFu : 0u;
                 }
                 consume(rx, ry, okm);
@@ -471,6 +490,130 @@ __global__ __launch_bounds__(256) void k_pass(KArgs a) {
         else ((double*)a.y)[seg * a.ldy + s] = a.scale * v[0];
     } else {  // EPI_RK: stage combination of classic RK4
         rk_epilogue<NOPS, T>(a, seg, s, v);
+    }
+}
+
+// ------------------------------------------------ complex-record pass ----
+// Pauli-boson graphs, FP64 forward passes straight over the complex records
+// (Sec. 2.2, Eq. graph-actions, with Gaussian-integer factors that are purely
+// real or purely imaginary).  Record: x = (f_hi << 24) | (imag << 23) | a,
+// y = (f_lo << 24) | j, (f_hi, f_lo) the bf16 pattern of the nonzero part of
+// the factor; a is a complex generator row (real-split rows 2a, 2a + 1 of A),
+// j a complex operand row (rows 2j, 2j + 1 of B).  One record occupies NCP
+// lanes, lane = (slot q, column c), NCP the column count nops * nsets rounded
+// up to a power of two; each lane gathers the generator entry (both parts) and
+// both rows of its column of x_j and sums the real and the imaginary part of
+// the target:  g x = (g_r x_r - g_i x_i) + i (g_r x_i + g_i x_r), times f for
+// a real factor, times i f for an imaginary one.  One complex record is read
+// once for its four real products, from a record stream a quarter the size of
+// the real-split one.  Targets are the segments of the complex CSR; tasks are
+// planned like the real-split ones (short targets one per wavefront, long ones
+// split over the 4 wavefronts of a workgroup and combined in LDS in fixed
+// order).
+template <int NCP, int EPI>
+__global__ __launch_bounds__(256) void k_cpass(KArgs a) {
+    constexpr int RS = 64 / NCP, U = 4;
+    __shared__ double red[4][2][64];
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int lane = threadIdx.x & 63;
+    const int q = lane / NCP, c = lane % NCP;
+    const int nsets = a.nsets, ncol = a.nops * nsets;
+    const int cc = c < ncol ? c : ncol - 1;  // lanes past the last column compute on a valid one
+    const int s = nsets == 1 ? 0 : cc % nsets;
+    const int64_t b = blockIdx.x;
+    int64_t t = b;
+    if (a.per_xcd > 0) {
+        t = (b & 7) * a.per_xcd + (b >> 3);
+        if ((b >> 3) >= a.per_xcd) return;
+    }
+    if (t >= a.ntasks) return;
+    const Task task = a.tasks[t];
+    const bool split = task.nseg < 0;
+    int64_t seg, e0, e1;
+    if (split) {
+        seg = task.seg;
+        const int64_t b0 = a.off[seg], n = a.off[seg + 1] - b0;
+        e0 = b0 + (n * wave) / 4;
+        e1 = b0 + (n * (wave + 1)) / 4;
+    } else {
+        if (wave >= task.nseg) return;  // block-uniform task kind: no barrier below
+        seg = task.seg + wave;
+        e0 = a.off[seg];
+        e1 = a.off[seg + 1];
+    }
+    e0 = uniform64(e0);
+    e1 = uniform64(e1);
+    const double* __restrict__ A = (const double*)a.A;
+    const double* __restrict__ B = (const double*)a.B;
+    const int64_t lda = a.lda, ldb = a.ldb;
+    // rows 2a and 2a + 1 of a one-column generator are adjacent (and 16-byte
+    // aligned when A is)
+    const bool gpair = lda == 1 && (reinterpret_cast<uintptr_t>(A) & 15) == 0;
+    double are = 0.0, aim = 0.0;
+    for (int64_t base = e0; base < e1; base += RS * U) {
+        uint2 r[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t e = base + u * RS + q;
+            r[u] = a.rec[e < e1 ? e : e1 - 1];  // clamped: always a valid record
+        }
+        double gr[U], gi[U], xr[U], xi[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t ar = 2 * (int64_t)(r[u].x & 0x7FFFFFu), jr = 2 * (int64_t)(r[u].y & 0xFFFFFFu);
+            if (gpair) {  // both parts of the generator entry: one 16-byte load
+                const double2 gv = *reinterpret_cast<const double2*>(A + ar * lda);
+                gr[u] = gv.x;
+                gi[u] = gv.y;
+            } else {
+                gr[u] = A[ar * lda + s];
+                gi[u] = A[(ar + 1) * lda + s];
+            }
+            const double* xrow = B + jr * ldb + cc;
+            xr[u] = xrow[0];
+            xi[u] = xrow[ldb];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint32_t imag = (r[u].x >> 23) & 1u;
+            const uint32_t fb = base + u * RS + q < e1 ? record_factor_bits(r[u].x, r[u].y) : 0u;
+            const double f = (double)__builtin_bit_cast(float, fb);
+            const double pr = __builtin_fma(-gi[u], xi[u], gr[u] * xr[u]);
+            const double pi = __builtin_fma(gi[u], xr[u], gr[u] * xi[u]);
+            are = __builtin_fma(f, imag ? -pi : pr, are);
+            aim = __builtin_fma(f, imag ? pr : pi, aim);
+        }
+    }
+#pragma unroll
+    for (int o = NCP; o < 64; o <<= 1) {
+        are += __shfl_xor(are, o);
+        aim += __shfl_xor(aim, o);
+    }
+    if (split) {
+        if (q == 0) {
+            red[wave][0][lane] = are;
+            red[wave][1][lane] = aim;
+        }
+        __syncthreads();
+        if (wave != 0) return;
+        if (q == 0) {
+            are = ((red[0][0][lane] + red[1][0][lane]) + red[2][0][lane]) + red[3][0][lane];
+            aim = ((red[0][1][lane] + red[1][1][lane]) + red[2][1][lane]) + red[3][1][lane];
+        }
+    }
+    if (q != 0 || c >= ncol || !set_active(a, s)) return;
+#pragma unroll
+    for (int part = 0; part < 2; ++part) {
+        const int64_t row = 2 * seg + part;
+        const double v = part ? aim : are;
+        if constexpr (EPI == EPI_Y) {
+            double* y = (double*)a.y + row * a.ldy + c;
+            *y = a.accumulate ? *y + a.scale * v : a.scale * v;
+        } else {
+            const double nxt = rk_combine(a, row * ldb + c, v);
+            ((double*)a.xout)[row * ldb + c] = nxt;
+            if (c < nsets) a.hst[row * a.ldh + s] = nxt;  // operand 0 = the Hamiltonian
+        }
     }
 }
 
@@ -552,7 +695,46 @@ static KArgs make_kargs(const PassArgs& p) {
     return k;
 }
 
+static int cpass_columns(int ncol) {
+    return ncol <= 1 ? 1 : ncol <= 2 ? 2 : ncol <= 4 ? 4 : ncol <= 8 ? 8 : ncol <= 16 ? 16 : 32;
+}
+
+// FP64 forward passes of a record set with a complex twin (Pauli-boson E_L
+// and E_C) up to 32 columns run k_cpass; everything else the real-split form
+static bool cpass_usable(int mode, int epi, const PassArgs& p) {
+    return mode == MODE_BCAST && (epi == EPI_Y || epi == EPI_RK) && p.csr->cx != nullptr &&
+           p.precision == CUT_F64 && p.tasks == nullptr && (int64_t)p.nops * p.nsets <= 32;
+}
+
+template <int EPI>
+static void launch_cpass_e(const KArgs& k, int ncp, dim3 grid, hipStream_t s) {
+    switch (ncp) {
+        case 1: hipLaunchKernelGGL((k_cpass<1, EPI>), grid, dim3(256), 0, s, k); break;
+        case 2: hipLaunchKernelGGL((k_cpass<2, EPI>), grid, dim3(256), 0, s, k); break;
+        case 4: hipLaunchKernelGGL((k_cpass<4, EPI>), grid, dim3(256), 0, s, k); break;
+        case 8: hipLaunchKernelGGL((k_cpass<8, EPI>), grid, dim3(256), 0, s, k); break;
+        case 16: hipLaunchKernelGGL((k_cpass<16, EPI>), grid, dim3(256), 0, s, k); break;
+        default: hipLaunchKernelGGL((k_cpass<32, EPI>), grid, dim3(256), 0, s, k); break;
+    }
+}
+
+static void launch_cpass(int epi, const PassArgs& p, hipStream_t s) {
+    PassArgs r = p;
+    r.csr = p.csr->cx;
+    if (r.csr->nseg == 0) return;
+    const KArgs k = make_kargs(r);
+    if (k.ntasks == 0) return;
+    const dim3 grid((unsigned)(k.per_xcd > 0 ? 8 * k.per_xcd : k.ntasks));
+    const int ncp = cpass_columns(p.nops * p.nsets);
+    if (epi == EPI_Y) launch_cpass_e<EPI_Y>(k, ncp, grid, s);
+    else launch_cpass_e<EPI_RK>(k, ncp, grid, s);
+}
+
 void launch_pass(int mode, int epi, const PassArgs& p, hipStream_t s) {
+    if (cpass_usable(mode, epi, p)) {
+        launch_cpass(epi, p, s);
+        return;
+    }
     if (p.csr->nseg == 0) return;
     const KArgs k = make_kargs(p);
     if (k.ntasks == 0) return;
@@ -1206,7 +1388,7 @@ static void launch_tiles_nops(const TileKArgs& t, const KArgs& k, int epi, int p
 }
 
 void launch_forward(const Graph& g, int epi, const PassArgs& a, double* partials, hipStream_t s) {
-    if (epi == EPI_ETA || a.csr != &g.csr[0][0] || partials == nullptr) {
+    if (epi == EPI_ETA || a.csr != &g.csr[0][0] || partials == nullptr || cpass_usable(MODE_BCAST, epi, a)) {
         launch_pass(MODE_BCAST, epi, a, s);
         return;
     }

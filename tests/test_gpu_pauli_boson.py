@@ -172,3 +172,63 @@ def test_jvp_matches_exact_polarisation(L):
     torch.cuda.synchronize()
     got = _cplx(dy, N).reshape(N, nops, nsets)
     assert np.abs(got - ref).max() < 1e-11 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("prec,tol", [("F64", 1e-12), ("F32C", 1e-6)])
+def test_flow_outside_diagnostic_matches_oracle(L, prec, tol):
+    """cut_flow_integrate with outside_norm2 on the M = 1, p = 3 graph (all
+    outside-space records), 5 RK4 steps: per operand column the accumulated
+    sum_s b_s ds sum_q |C_q(Z_s)|^2 (real-split rows 2q, 2q + 1 summed) agrees
+    with the oracle's complex flow_outside, and the flowed z is bitwise the z of
+    the same flow without the diagnostic."""
+    M, p, nsets, nops, ds, steps = 1, 3, 2, 2, 1e-3, 5
+    g, og = _graphs(L, M, p)
+    N = og.N
+    rng = np.random.default_rng(31)
+    z0 = np.zeros((N, nops, nsets), dtype=complex)
+    for s in range(nsets):
+        z0[:, 0, s] = workloads.pb_hermitian(og.labels, rng, 1.0, 0.05)
+        z0[:, 1, s] = workloads.pb_hermitian(og.labels, rng, 1.0, 1.0)
+    ref_leak = np.zeros((nops, nsets))
+    for s in range(nsets):
+        _, ref_leak[:, s] = PB.flow_outside(og, z0[:, :, s], ds, steps)
+    P = getattr(L, "CUT_" + prec)
+    z = _rs(z0).reshape(2 * N, nops, nsets).contiguous()
+    zp = z.clone()
+    leak = torch.zeros(nops * nsets, dtype=torch.float64, device=DEV)
+    L.cut_flow_integrate(g, L.flow_params(L.CUT_GEN_WEGNER_GRAPH, P, ds, 0.0, 0, outside_norm2=leak),
+                         nsets, nops, [steps] * nsets, z)
+    L.cut_flow_integrate(g, L.flow_params(L.CUT_GEN_WEGNER_GRAPH, P, ds, 0.0, 0), nsets, nops,
+                         [steps] * nsets, zp)
+    torch.cuda.synchronize()
+    assert torch.equal(z, zp)
+    got = leak.cpu().numpy().reshape(nops, nsets)
+    rel = np.abs(got - ref_leak).max() / np.abs(ref_leak).max()
+    U.say(f"[pauli-boson outside diagnostic] {prec}: relative error {rel:.3e}")
+    assert np.all(ref_leak > 0) and rel < tol
+
+
+@pytest.mark.parametrize("nsets,nops", [(1, 1), (1, 8), (3, 3), (2, 8), (4, 8), (5, 7)])
+def test_action_column_counts(L, nsets, nops):
+    """FP64 retained and outside-space actions on the M = 1, p = 4 graph for
+    column counts nops * nsets of 1, 8, 9, 16, 32 (the complex-record pass with
+    1 ... 32 lanes per part) and 35 (beyond it: the real-split pass), against
+    the oracle, element by element within the FP64 bound."""
+    M, p = 1, 4
+    g, og = _graphs(L, M, p)
+    N, NC = og.N, len(og.out_labels)
+    rng = np.random.default_rng(100 * nsets + nops)
+    h = np.stack([workloads.pb_hermitian(og.labels, rng) for _ in range(nsets)], axis=1)
+    xi = np.stack([og.generator(h[:, s]) for s in range(nsets)], axis=1)
+    x = rng.normal(size=(N, nops, nsets)) + 1j * rng.normal(size=(N, nops, nsets))
+    for which, recs, n, act in ((L.CUT_GRAPH_FLOW, og.flow, N, og.action),
+                                (L.CUT_GRAPH_OUTSIDE, og.outside, NC, lambda a, b: PB.outside_action(og, a, b))):
+        y = torch.zeros((2 * n, nops * nsets), dtype=torch.float64, device=DEV)
+        L.cut_graph_apply(g, which, L.CUT_F64, nsets, nops, _rs(xi), _rs(x), y)
+        torch.cuda.synchronize()
+        ref = np.stack([np.stack([act(xi[:, s], x[:, o, s]) for s in range(nsets)], 1) for o in range(nops)], 1)
+        S = _abs_sum(recs, n, xi[:, None, :], x)
+        seg = int(np.max(np.bincount([r[0] for r in recs], minlength=n)))
+        got = _cplx(y, n).reshape(n, nops, nsets)
+        U.assert_within(np.abs(got - ref), 0 * ref.real, _bound(L, L.CUT_F64, seg) * S * 2 + 1e-300,
+                        f"which={which} nsets={nsets} nops={nops}")
