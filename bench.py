@@ -237,7 +237,7 @@ def pauli_boson_leg(L, torch, tmp):
                      f"{desc['n_gen_records'] + desc['n_records']} production records, "
                      f"E_C {desc['n_out_records']} outside-space records",
             "compile_s": build_s, "load_s": load_s, "bundle_bytes": desc["file_bytes"],
-            "batch": "8 operators (H + 7), FP64 complex (real-split), Wegner block generator",
+            "batch": "8 operators (H + 7), FP64 complex (real-split vectors, complex-record passes), Wegner block generator",
             "retained_action_ms": t_ret * 1e3, "action_with_outside_ms": t_diag * 1e3,
             "flow_100_steps_s": t_flow, "flow_100_steps_with_outside_s": t_flow_d,
             "trajectory_unchanged_by_diagnostic": same,

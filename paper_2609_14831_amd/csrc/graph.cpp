@@ -885,6 +885,8 @@ static void load_pauli_boson(Graph& g, const HostGraph& hg, bool adjoint) {
     upload_set(g, 0, std::move(off), std::move(rec), adjoint, 2 * NG, 2 * N);
     complex_records(hg, 0, N, off, rec);
     upload_csr(g, g.cxs[0], N, std::move(off), rec);
+    g.cxs[0].na = NG;
+    g.cxs[0].nb = N;
     g.csr[0][0].cx = &g.cxs[0];
     real_split(hg, 1, NG, off, rec);                       // E_eta: target a, left i, right j (operators)
     upload_set(g, 1, std::move(off), std::move(rec), adjoint, 2 * N, 2 * N);
@@ -894,6 +896,8 @@ static void load_pauli_boson(Graph& g, const HostGraph& hg, bool adjoint) {
         upload_set(g, 2, std::move(off), std::move(rec), false, 2 * NG, 2 * N);
         complex_records(hg, 2, Nc, off, rec);
         upload_csr(g, g.cxs[2], Nc, std::move(off), rec);
+        g.cxs[2].na = NG;
+        g.cxs[2].nb = N;
         g.csr[2][0].cx = &g.cxs[2];
         g.have_outside = true;
         g.n_out = 2 * Nc;

@@ -185,6 +185,7 @@ struct DevCSR {
     // Pauli-boson E_L / E_C: the same records in complex form, grouped by
     // complex target (FP64 forward passes run over these; see k_cpass)
     const DevCSR* cx = nullptr;
+    int64_t na = 0, nb = 0;     // complex twins: rows of the left / right input space
     void release();
 };
 
@@ -379,7 +380,7 @@ void launch_round_f32(const double* src, int64_t lds, int64_t rows, int64_t cols
 void launch_zero2d(double* dst, int64_t ld, int64_t rows, int64_t cols, hipStream_t s);
 // out[c] += weight * sum_r y[r][c]^2 for columns of active sets (fixed order;
 // part holds nparts * cols doubles)
-constexpr int32_t kColsqParts = 256;
+constexpr int32_t kColsqParts = 1024;
 void launch_colsq_accumulate(const double* y, int64_t rows, int64_t cols, int32_t nsets, double* part,
                              int32_t nparts, const int32_t* nsteps, const int32_t* step, double weight,
                              double* out, hipStream_t s);

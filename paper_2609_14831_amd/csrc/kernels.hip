@@ -510,7 +510,10 @@ __global__ __launch_bounds__(256) void k_pass(KArgs a) {
 // planned like the real-split ones (short targets one per wavefront, long ones
 // split over the 4 wavefronts of a workgroup and combined in LDS in fixed
 // order).
-template <int NCP, int EPI>
+// GPAIR: the generator has one column at unit stride, so both parts of an
+// entry are one 16-byte load.  Operand offsets are 32-bit byte offsets from
+// the array base (the host checks that both arrays span less than 4 GiB).
+template <int NCP, int EPI, bool GPAIR>
 __global__ __launch_bounds__(256) void k_cpass(KArgs a) {
     constexpr int RS = 64 / NCP, U = 4;
     __shared__ double red[4][2][64];
@@ -543,45 +546,52 @@ __global__ __launch_bounds__(256) void k_cpass(KArgs a) {
     }
     e0 = uniform64(e0);
     e1 = uniform64(e1);
-    const double* __restrict__ A = (const double*)a.A;
-    const double* __restrict__ B = (const double*)a.B;
-    const int64_t lda = a.lda, ldb = a.ldb;
-    // rows 2a and 2a + 1 of a one-column generator are adjacent (and 16-byte
-    // aligned when A is)
-    const bool gpair = lda == 1 && (reinterpret_cast<uintptr_t>(A) & 15) == 0;
-    double are = 0.0, aim = 0.0;
-    for (int64_t base = e0; base < e1; base += RS * U) {
-        uint2 r[U];
+    const char* __restrict__ A = (const char*)a.A;
+    const char* __restrict__ B = (const char*)a.B;
+    const uint32_t lda8 = (uint32_t)a.lda * 8u, ldb8 = (uint32_t)a.ldb * 8u;
+    const uint32_t aoff = (uint32_t)s * 8u, boff = (uint32_t)cc * 8u;
+    const uint2* __restrict__ rec = a.rec;
+    auto fetch = [&](int64_t base, uint2 (&r)[U]) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int64_t e = base + u * RS + q;
-            r[u] = a.rec[e < e1 ? e : e1 - 1];  // clamped: always a valid record
+            r[u] = rec[e < e1 ? e : e1 - 1];  // clamped: always a valid record
         }
+    };
+    double are = 0.0, aim = 0.0;
+    uint2 r[U];
+    if (e0 < e1) fetch(e0, r);
+    for (int64_t base = e0; base < e1; base += RS * U) {
         double gr[U], gi[U], xr[U], xi[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int64_t ar = 2 * (int64_t)(r[u].x & 0x7FFFFFu), jr = 2 * (int64_t)(r[u].y & 0xFFFFFFu);
-            if (gpair) {  // both parts of the generator entry: one 16-byte load
-                const double2 gv = *reinterpret_cast<const double2*>(A + ar * lda);
+            const uint32_t ga = 2u * (r[u].x & 0x7FFFFFu) * lda8 + aoff;
+            if constexpr (GPAIR) {
+                const double2 gv = *reinterpret_cast<const double2*>(A + ga);
                 gr[u] = gv.x;
                 gi[u] = gv.y;
             } else {
-                gr[u] = A[ar * lda + s];
-                gi[u] = A[(ar + 1) * lda + s];
+                gr[u] = *reinterpret_cast<const double*>(A + ga);
+                gi[u] = *reinterpret_cast<const double*>(A + (ga + lda8));
             }
-            const double* xrow = B + jr * ldb + cc;
-            xr[u] = xrow[0];
-            xi[u] = xrow[ldb];
+            const uint32_t xb = 2u * (r[u].y & 0xFFFFFFu) * ldb8 + boff;
+            xr[u] = *reinterpret_cast<const double*>(B + xb);
+            xi[u] = *reinterpret_cast<const double*>(B + (xb + ldb8));
         }
+        uint32_t fb[U], im[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const uint32_t imag = (r[u].x >> 23) & 1u;
-            const uint32_t fb = base + u * RS + q < e1 ? record_factor_bits(r[u].x, r[u].y) : 0u;
-            const double f = (double)__builtin_bit_cast(float, fb);
+            im[u] = (r[u].x >> 23) & 1u;
+            fb[u] = base + u * RS + q < e1 ? record_factor_bits(r[u].x, r[u].y) : 0u;
+        }
+        if (base + RS * U < e1) fetch(base + RS * U, r);  // next group's records in flight
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const double f = (double)__builtin_bit_cast(float, fb[u]);
             const double pr = __builtin_fma(-gi[u], xi[u], gr[u] * xr[u]);
             const double pi = __builtin_fma(gi[u], xr[u], gr[u] * xi[u]);
-            are = __builtin_fma(f, imag ? -pi : pr, are);
-            aim = __builtin_fma(f, imag ? pr : pi, aim);
+            are = __builtin_fma(f, im[u] ? -pi : pr, are);
+            aim = __builtin_fma(f, im[u] ? pr : pi, aim);
         }
     }
 #pragma unroll
@@ -602,6 +612,7 @@ __global__ __launch_bounds__(256) void k_cpass(KArgs a) {
         }
     }
     if (q != 0 || c >= ncol || !set_active(a, s)) return;
+    const int64_t ldb = a.ldb;
 #pragma unroll
     for (int part = 0; part < 2; ++part) {
         const int64_t row = 2 * seg + part;
@@ -702,19 +713,23 @@ static int cpass_columns(int ncol) {
 // FP64 forward passes of a record set with a complex twin (Pauli-boson E_L
 // and E_C) up to 32 columns run k_cpass; everything else the real-split form
 static bool cpass_usable(int mode, int epi, const PassArgs& p) {
-    return mode == MODE_BCAST && (epi == EPI_Y || epi == EPI_RK) && p.csr->cx != nullptr &&
-           p.precision == CUT_F64 && p.tasks == nullptr && (int64_t)p.nops * p.nsets <= 32;
+    if (mode != MODE_BCAST || (epi != EPI_Y && epi != EPI_RK) || p.csr->cx == nullptr ||
+        p.precision != CUT_F64 || p.tasks != nullptr || (int64_t)p.nops * p.nsets > 32)
+        return false;
+    // 32-bit byte offsets into both operand arrays
+    const DevCSR& c = *p.csr->cx;
+    return 2 * c.na * p.lda * 8 < ((int64_t)1 << 32) && 2 * c.nb * p.ldb * 8 < ((int64_t)1 << 32);
 }
 
-template <int EPI>
+template <int EPI, bool GPAIR>
 static void launch_cpass_e(const KArgs& k, int ncp, dim3 grid, hipStream_t s) {
     switch (ncp) {
-        case 1: hipLaunchKernelGGL((k_cpass<1, EPI>), grid, dim3(256), 0, s, k); break;
-        case 2: hipLaunchKernelGGL((k_cpass<2, EPI>), grid, dim3(256), 0, s, k); break;
-        case 4: hipLaunchKernelGGL((k_cpass<4, EPI>), grid, dim3(256), 0, s, k); break;
-        case 8: hipLaunchKernelGGL((k_cpass<8, EPI>), grid, dim3(256), 0, s, k); break;
-        case 16: hipLaunchKernelGGL((k_cpass<16, EPI>), grid, dim3(256), 0, s, k); break;
-        default: hipLaunchKernelGGL((k_cpass<32, EPI>), grid, dim3(256), 0, s, k); break;
+        case 1: hipLaunchKernelGGL((k_cpass<1, EPI, GPAIR>), grid, dim3(256), 0, s, k); break;
+        case 2: hipLaunchKernelGGL((k_cpass<2, EPI, GPAIR>), grid, dim3(256), 0, s, k); break;
+        case 4: hipLaunchKernelGGL((k_cpass<4, EPI, GPAIR>), grid, dim3(256), 0, s, k); break;
+        case 8: hipLaunchKernelGGL((k_cpass<8, EPI, GPAIR>), grid, dim3(256), 0, s, k); break;
+        case 16: hipLaunchKernelGGL((k_cpass<16, EPI, GPAIR>), grid, dim3(256), 0, s, k); break;
+        default: hipLaunchKernelGGL((k_cpass<32, EPI, GPAIR>), grid, dim3(256), 0, s, k); break;
     }
 }
 
@@ -726,8 +741,14 @@ static void launch_cpass(int epi, const PassArgs& p, hipStream_t s) {
     if (k.ntasks == 0) return;
     const dim3 grid((unsigned)(k.per_xcd > 0 ? 8 * k.per_xcd : k.ntasks));
     const int ncp = cpass_columns(p.nops * p.nsets);
-    if (epi == EPI_Y) launch_cpass_e<EPI_Y>(k, ncp, grid, s);
-    else launch_cpass_e<EPI_RK>(k, ncp, grid, s);
+    const bool gpair = p.lda == 1 && (reinterpret_cast<uintptr_t>(p.A) & 15) == 0;
+    if (epi == EPI_Y) {
+        if (gpair) launch_cpass_e<EPI_Y, true>(k, ncp, grid, s);
+        else launch_cpass_e<EPI_Y, false>(k, ncp, grid, s);
+    } else {
+        if (gpair) launch_cpass_e<EPI_RK, true>(k, ncp, grid, s);
+        else launch_cpass_e<EPI_RK, false>(k, ncp, grid, s);
+    }
 }
 
 void launch_pass(int mode, int epi, const PassArgs& p, hipStream_t s) {
@@ -1660,25 +1681,48 @@ void launch_zero2d(double* dst, int64_t ld, int64_t rows, int64_t cols, hipStrea
     hipLaunchKernelGGL(k_zero2d, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, dst, ld, rows, cols);
 }
 
-// Column sums of squares of y [rows][cols], deterministic in two kernels:
-// block (bx, by) covers 64 columns from bx*64 and the rows by*4 + w + q*4*gridDim.y
-// (w = wavefront), summed in that order, then its 4 wavefronts in order ->
-// part[by][c]; k_colsq_finish adds the partial rows in order, scales by
-// `weight` and accumulates into out[c] for the columns of active sets.
+// Column sums of squares of y [rows][cols] (contiguous rows), deterministic in
+// two kernels.  k_colsq_partial: block (bx, by) owns the CB = min(cols, 256)
+// columns from bx*CB; its threads are R = 256 / CB row lanes x CB columns, so
+// every load instruction reads consecutive elements.  Row lane l of block by
+// sums the rows by*R + l + k*R*gridDim.y (k = 0, 1, ...) into four running sums
+// by k mod 4, added as (s0 + s1) + (s2 + s3); the row lanes are then added in
+// order -> part[by][c].  k_colsq_finish adds the partial rows in order, scales
+// by `weight` and accumulates into out[c] for the columns of active sets.
 __global__ __launch_bounds__(256) void k_colsq_partial(const double* __restrict__ y, int64_t rows, int64_t cols,
                                                        double* __restrict__ part) {
-    __shared__ double red[4][64];
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int64_t c = (int64_t)blockIdx.x * 64 + lane;
+    __shared__ double red[256];
+    const int t = threadIdx.x;
+    const int CB = cols < 256 ? (int)cols : 256;
+    const int R = 256 / CB;
+    const int rl = t / CB;
+    const int64_t c = (int64_t)blockIdx.x * CB + t % CB;
     double acc = 0.0;
-    if (c < cols)
-        for (int64_t r = (int64_t)blockIdx.y * 4 + w; r < rows; r += (int64_t)gridDim.y * 4) {
-            const double v = y[r * cols + c];
-            acc = __builtin_fma(v, v, acc);
+    if (rl < R && c < cols) {
+        const int64_t step = (int64_t)R * gridDim.y;
+        int64_t r = (int64_t)blockIdx.y * R + rl;
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+        for (; r + 3 * step < rows; r += 4 * step) {
+            const double v0 = y[r * cols + c], v1 = y[(r + step) * cols + c];
+            const double v2 = y[(r + 2 * step) * cols + c], v3 = y[(r + 3 * step) * cols + c];
+            s0 = __builtin_fma(v0, v0, s0);
+            s1 = __builtin_fma(v1, v1, s1);
+            s2 = __builtin_fma(v2, v2, s2);
+            s3 = __builtin_fma(v3, v3, s3);
         }
-    red[w][lane] = acc;
+        for (; r < rows; r += step) {
+            const double v = y[r * cols + c];
+            s0 = __builtin_fma(v, v, s0);
+        }
+        acc = (s0 + s1) + (s2 + s3);
+    }
+    red[t] = acc;
     __syncthreads();
-    if (w == 0 && c < cols) part[(int64_t)blockIdx.y * cols + c] = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
+    if (t < CB && c < cols) {
+        double sum = 0.0;
+        for (int l = 0; l < R; ++l) sum += red[l * CB + t];
+        part[(int64_t)blockIdx.y * cols + c] = sum;
+    }
 }
 
 __global__ void k_colsq_finish(const double* __restrict__ part, int32_t nparts, int64_t cols, int32_t nsets,
@@ -1694,7 +1738,8 @@ __global__ void k_colsq_finish(const double* __restrict__ part, int32_t nparts, 
 void launch_colsq_accumulate(const double* y, int64_t rows, int64_t cols, int32_t nsets, double* part,
                              int32_t nparts, const int32_t* nsteps, const int32_t* step, double weight,
                              double* out, hipStream_t s) {
-    hipLaunchKernelGGL(k_colsq_partial, dim3((unsigned)((cols + 63) / 64), (unsigned)nparts), dim3(256), 0, s, y,
+    const int64_t cb = cols < 256 ? cols : 256;
+    hipLaunchKernelGGL(k_colsq_partial, dim3((unsigned)((cols + cb - 1) / cb), (unsigned)nparts), dim3(256), 0, s, y,
                        rows, cols, part);
     hipLaunchKernelGGL(k_colsq_finish, dim3((unsigned)((cols + 255) / 256)), dim3(256), 0, s, part, nparts, cols,
                        nsets, nsteps, step, weight, out);
