@@ -1687,8 +1687,9 @@ void launch_zero2d(double* dst, int64_t ld, int64_t rows, int64_t cols, hipStrea
 // every load instruction reads consecutive elements.  Row lane l of block by
 // sums the rows by*R + l + k*R*gridDim.y (k = 0, 1, ...) into four running sums
 // by k mod 4, added as (s0 + s1) + (s2 + s3); the row lanes are then added in
-// order -> part[by][c].  k_colsq_finish adds the partial rows in order, scales
-// by `weight` and accumulates into out[c] for the columns of active sets.
+// order -> part[by][c].  k_colsq_finish adds the partial rows of a column in a
+// fixed tree, scales by `weight` and accumulates into out[c] for the columns
+// of active sets.
 __global__ __launch_bounds__(256) void k_colsq_partial(const double* __restrict__ y, int64_t rows, int64_t cols,
                                                        double* __restrict__ part) {
     __shared__ double red[256];
@@ -1725,14 +1726,26 @@ __global__ __launch_bounds__(256) void k_colsq_partial(const double* __restrict_
     }
 }
 
-__global__ void k_colsq_finish(const double* __restrict__ part, int32_t nparts, int64_t cols, int32_t nsets,
-                               const int32_t* nsteps, const int32_t* step, double weight, double* out) {
-    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= cols) return;
-    if (nsteps && nsteps[c % nsets] <= *step) return;
+__global__ __launch_bounds__(256) void k_colsq_finish(const double* __restrict__ part, int32_t nparts, int64_t cols,
+                                                      int32_t nsets, const int32_t* nsteps, const int32_t* step,
+                                                      double weight, double* out) {
+    // one workgroup per column: thread t adds the partial rows t, t + 256, ...
+    // in order, then a fixed pairwise tree over the 256 threads
+    __shared__ double red[256];
+    const int64_t c = blockIdx.x;
+    const int t = threadIdx.x;
     double acc = 0.0;
-    for (int b = 0; b < nparts; ++b) acc += part[(int64_t)b * cols + c];
-    out[c] += weight * acc;
+    for (int b = t; b < nparts; b += 256) acc += part[(int64_t)b * cols + c];
+    red[t] = acc;
+    __syncthreads();
+#pragma unroll
+    for (int w = 128; w > 0; w >>= 1) {
+        if (t < w) red[t] += red[t + w];
+        __syncthreads();
+    }
+    if (t != 0) return;
+    if (nsteps && nsteps[c % nsets] <= *step) return;
+    out[c] += weight * red[0];
 }
 
 void launch_colsq_accumulate(const double* y, int64_t rows, int64_t cols, int32_t nsets, double* part,
@@ -1741,8 +1754,8 @@ void launch_colsq_accumulate(const double* y, int64_t rows, int64_t cols, int32_
     const int64_t cb = cols < 256 ? cols : 256;
     hipLaunchKernelGGL(k_colsq_partial, dim3((unsigned)((cols + cb - 1) / cb), (unsigned)nparts), dim3(256), 0, s, y,
                        rows, cols, part);
-    hipLaunchKernelGGL(k_colsq_finish, dim3((unsigned)((cols + 255) / 256)), dim3(256), 0, s, part, nparts, cols,
-                       nsets, nsteps, step, weight, out);
+    hipLaunchKernelGGL(k_colsq_finish, dim3((unsigned)cols), dim3(256), 0, s, part, nparts, cols, nsets, nsteps, step,
+                       weight, out);
 }
 
 __global__ void k_bump(int32_t* step) {

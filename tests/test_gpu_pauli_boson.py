@@ -232,3 +232,36 @@ def test_action_column_counts(L, nsets, nops):
         got = _cplx(y, n).reshape(n, nops, nsets)
         U.assert_within(np.abs(got - ref), 0 * ref.real, _bound(L, L.CUT_F64, seg) * S * 2 + 1e-300,
                         f"which={which} nsets={nsets} nops={nops}")
+
+
+@pytest.mark.parametrize("hipgraph", [True, False])
+def test_ragged_flow_with_diagnostic(L, hipgraph):
+    """FP64 flow of three sets with 9, 4 and 0 steps (M = 1, p = 3, two
+    operands each, with the outside-space diagnostic), captured as one hipGraph
+    per step or in stream order: each set matches the oracle's flow and
+    diagnostic over its own number of steps; the set with 0 steps is untouched
+    and accumulates nothing."""
+    M, p, nsets, nops, ds = 1, 3, 3, 2, 1e-3
+    steps = [9, 4, 0]
+    g, og = _graphs(L, M, p)
+    N = og.N
+    rng = np.random.default_rng(44)
+    z0 = np.zeros((N, nops, nsets), dtype=complex)
+    for s in range(nsets):
+        z0[:, 0, s] = workloads.pb_hermitian(og.labels, rng, 1.0, 0.05)
+        z0[:, 1, s] = workloads.pb_hermitian(og.labels, rng, 1.0, 1.0)
+    z = _rs(z0).reshape(2 * N, nops, nsets).contiguous()
+    leak = torch.zeros(nops * nsets, dtype=torch.float64, device=DEV)
+    prm = L.flow_params(L.CUT_GEN_WEGNER_GRAPH, L.CUT_F64, ds, 0.0, 0,
+                        flags=L.CUT_FLOW_HIPGRAPH if hipgraph else 0, outside_norm2=leak)
+    L.cut_flow_integrate(g, prm, nsets, nops, steps, z)
+    torch.cuda.synchronize()
+    got = _cplx(z.reshape(2 * N, -1), N).reshape(N, nops, nsets)
+    got_leak = leak.cpu().numpy().reshape(nops, nsets)
+    for s in range(nsets):
+        ref, ref_leak = PB.flow_outside(og, z0[:, :, s], ds, steps[s])
+        assert np.linalg.norm(got[:, :, s] - ref) <= 1e-12 * np.linalg.norm(ref), s
+        if steps[s] == 0:
+            assert np.array_equal(got[:, :, s], z0[:, :, s]) and np.all(got_leak[:, s] == 0)
+        else:
+            assert np.abs(got_leak[:, s] - ref_leak).max() <= 1e-12 * np.abs(ref_leak).max(), s
