@@ -9,8 +9,9 @@ state, one hipGraph launch per RK step.  A step = one RK4 step of the whole
 batch (4 x {generator, graph pass with the fused stage update}).
 
 Printed (one JSON line): contributions x batch / s over the timed steps; the
-dominant kernel's roofline (HIP-event average of the fused graph pass,
-algorithmic bytes per launch); the plain FP64 one-column flow for the batched /
+dominant kernel's roofline (HIP-event average of the fused graph pass; for the
+compensated float mode against the FP32 VALU issue rate, which binds it, with
+its algorithmic HBM bytes and rate beside); the plain FP64 one-column flow for the batched /
 plain ratio; and the oracle's CPU rate on a bounded sample (cpu_baseline leg).
 """
 from __future__ import annotations
@@ -27,6 +28,13 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# FP32 VALU issue rate without packed instructions (which this library does not
+# emit): 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz, one operation per lane and
+# clock whatever the operation (add, multiply or fused multiply-add)
+VALU_F32_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+# FP32 operations per contribution x column of the compensated dot product
+# (two-product with FMA: 2, two-sum: 6, error accumulation: 2)
+F32C_OPS_PER_TERM = 10
 FP64_VEC_TFLOPS = 78.6
 FP64_MFMA_TFLOPS = 78.6   # dense FP64 matrix peak (the vector FP64 peak is the same figure)
 
@@ -426,13 +434,27 @@ def main():
     log(f"fused pass avg {pass_ms:.4f} ms ({tm['pass_launches']} launches), generator {gen_ms:.4f} ms")
     traffic = measured_traffic(args.precision)
     gathered = E * (nsets + nops * nsets) * pbytes   # one eta row + one operand row per record
-    out["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                       "frac": achieved / HBM_PEAK_GBS,
+    terms = E * nsets * nops                          # contributions x columns of one pass
+    if args.precision == "f32c":
+        # the compensated arithmetic binds this pass: its VALU instructions
+        # fill the SIMDs' issue cycles (counters in profiles/)
+        ops = F32C_OPS_PER_TERM * terms / (pass_ms * 1e-3) / 1e12
+        head = {"bound": "alu", "achieved": ops, "peak": VALU_F32_TOPS, "unit": "TFLOP/s",
+                "frac": ops / VALU_F32_TOPS,
+                "flop_unit": "FP32 operations (add, subtract, multiply and fused multiply-add count one "
+                             "each), 10 per contribution x column; peak = the non-packed FP32 issue rate",
+                "algorithmic_ops_per_launch": F32C_OPS_PER_TERM * terms}
+    else:
+        head = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS}
+    out["roofline"] = {**head,
                        "traffic": traffic["bytes_per_launch"] if traffic else None,
                        "traffic_unit": "bytes per fused pass (FETCH_SIZE x copy factor + WRITE_SIZE)",
                        "kernel": "fused graph pass with RK4 stage epilogue: k_pass<64,5,prec,0,2> "
                                  "(chunks of the quadratic targets + quartic targets) and k_chunk_combine<5,prec,2>",
                        "avg_launch_ms": pass_ms, "algorithmic_bytes_per_launch": bytes_per,
+                       "hbm_achieved_GBs": achieved, "hbm_peak_GBs": HBM_PEAK_GBS,
+                       "hbm_frac": achieved / HBM_PEAK_GBS,
                        "gathered_row_bytes_per_launch": gathered,
                        "gathered_row_rate_GBs": gathered / (pass_ms * 1e-3) / 1e9,
                        "fp64_equiv_tflops": flops_per / (pass_ms * 1e-3) / 1e12,
