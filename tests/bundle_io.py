@@ -18,15 +18,16 @@ FACTOR_SECTIONS = (7, 11, 16)
 
 
 def read(path: str) -> dict:
-    raw = np.fromfile(path, dtype=np.uint8)
-    b = raw.tobytes()
-    assert b[:8] == b"CUTGRPH1"
+    """Header fields and every section as a read-only array over a memory map of
+    the file (nothing is copied, so multi-GB bundles read in place)."""
+    b = np.memmap(path, dtype=np.uint8, mode="r")
+    assert b[:8].tobytes() == b"CUTGRPH1"
     n_sections = struct.unpack_from("<I", b, 64)[0]
     table = struct.unpack_from("<Q", b, 72)[0]
     out = {"n_ops": struct.unpack_from("<q", b, 24)[0],
            "n_records": struct.unpack_from("<q", b, 32)[0],
            "gen_sign": struct.unpack_from("<i", b, 60)[0],
-           "identifier": b[96:192].split(b"\0")[0].decode(),
+           "identifier": b[96:192].tobytes().split(b"\0")[0].decode(),
            "n_out_ops": struct.unpack_from("<q", b, 200)[0],
            "n_out_records": struct.unpack_from("<q", b, 208)[0],
            "n_gen_ops": struct.unpack_from("<q", b, 216)[0]}

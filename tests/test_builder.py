@@ -249,7 +249,36 @@ def test_pauli_boson_deterministic_and_five_mode_counts(tmpdir_mod):
     path, desc = _pb_build(tmpdir_mod, 5, 4, False, name="pb5.cgb")
     assert desc["n_ops"] == five["n_ops"]
     assert desc["n_gen_records"] + desc["n_records"] == five["production"]
+    _five_mode_records_valid(path, desc)
     os.remove(path)
+
+
+def _five_mode_records_valid(path, desc):
+    """Records of the five-mode graph at full size: within every target the
+    (left, right) inputs strictly increase (no record twice), every E_eta
+    record pairs a block-diagonal with an off-diagonal coordinate, and sampled
+    records of E_L and E_eta carry exactly the oracle's bracket coefficient of
+    their target.  With the exact record counts above this pins the record
+    set (the small registries are compared whole in the test before)."""
+    from oracle import pauli_boson as PB
+    M = 5
+    d = bundle_io.read(path)
+    W = int(re.search(r":(\d+) bits", desc["identifier"]).group(1))
+    lab = lambda keys, r: bundle_io.pb_label(int(keys[r]), M, W)
+    diag = d["diag"].astype(bool)
+    rng = np.random.default_rng(20260914)
+    for which, tgt, left in (("flow", d["labels"], d["gen_labels"]), ("gen", d["gen_labels"], d["labels"])):
+        off, I, J, Cf = d[f"{which}_off"], d[f"{which}_i"], d[f"{which}_j"], d[f"{which}_c"]
+        key = I.astype(np.int64) * (1 << 32) + J.astype(np.int64)
+        first = np.zeros(key.size, dtype=bool)
+        first[off[:-1][np.diff(off) > 0]] = True
+        assert np.all((np.diff(key) > 0) | first[1:]), which
+        if which == "gen":
+            assert diag[I].all() and not diag[J].any()
+        sample = rng.choice(key.size, 300, replace=False)
+        for e, k in zip(sample, np.searchsorted(off, sample, side="right") - 1):
+            br = PB.commutator(lab(left, I[e]), lab(d["labels"], J[e]))
+            assert br.get(lab(tgt, k)) == (int(Cf[e, 0]), int(Cf[e, 1])), (which, int(e))
 
 
 def test_pauli_boson_build_memory_near_stored_size(tmp_path):

@@ -265,3 +265,56 @@ def test_ragged_flow_with_diagnostic(L, hipgraph):
             assert np.array_equal(got[:, :, s], z0[:, :, s]) and np.all(got_leak[:, s] == 0)
         else:
             assert np.abs(got_leak[:, s] - ref_leak).max() <= 1e-12 * np.abs(ref_leak).max(), s
+
+
+def test_five_mode_graph_sampled_targets(L):
+    """The paper's benchmark graph at full size (M = 5, p = 4: 7,017,036
+    production and 345,388,180 outside-space records) in the benchmark's launch
+    configuration (FP64, one set, 8 operators: the complex-record passes).
+    Sampled retained and outside targets, the longest of each included, are
+    compared element by element with an oracle-side FP64 evaluation of their
+    stored records; the factors of sampled records among them are checked
+    against the oracle's bracket (the record set as a whole is pinned by the
+    CPU tests: exact counts, sampled brackets, no duplicates)."""
+    import os
+    import bundle_io
+    M, p, nops = 5, 4, 8
+    path = os.path.join(U._tmp, "pb_5_4_full.cgb")
+    U.say("[pauli-boson five-mode] build")
+    L.cut_graph_build(L.CUT_ALG_PAULI_BOSON, 256 * M + p, path, 0, L.CUT_BUILD_OUTSIDE)
+    g = L.cut_graph_load(path, 0, 0)
+    try:
+        d = bundle_io.read(path)
+        N, NG, NC = int(d["n_ops"]), int(d["n_gen_ops"]), int(d["n_out_ops"])
+        W = (3 * p).bit_length()
+        rng = np.random.default_rng(2609)
+        xi = 0.3 * (rng.normal(size=NG) + 1j * rng.normal(size=NG))
+        x = rng.normal(size=(N, nops)) + 1j * rng.normal(size=(N, nops))
+        y = torch.zeros((2 * N, nops), dtype=torch.float64, device=DEV)
+        yc = torch.zeros((2 * NC, nops), dtype=torch.float64, device=DEV)
+        U.say("[pauli-boson five-mode] apply retained and outside")
+        L.cut_graph_apply(g, L.CUT_GRAPH_FLOW, L.CUT_F64, 1, nops, _rs(xi[:, None]), _rs(x), y)
+        L.cut_graph_apply(g, L.CUT_GRAPH_OUTSIDE, L.CUT_F64, 1, nops, _rs(xi[:, None]), _rs(x), yc)
+        torch.cuda.synchronize()
+        lab = lambda keys, r: bundle_io.pb_label(int(keys[r]), M, W)
+        for which, n, got, tgt in (("flow", N, _cplx(y, N), d["labels"]), ("out", NC, _cplx(yc, NC), d["out_labels"])):
+            off, I, J, Cf = d[f"{which}_off"], d[f"{which}_i"], d[f"{which}_j"], d[f"{which}_c"]
+            lens = np.diff(off)
+            ks = np.unique(np.concatenate([rng.choice(n, 300, replace=False), [int(np.argmax(lens))]]))
+            for k in ks:
+                sl = slice(int(off[k]), int(off[k + 1]))
+                f = Cf[sl, 0].astype(np.float64) + 1j * Cf[sl, 1].astype(np.float64)
+                u, v = xi[I[sl]], x[J[sl]]
+                ref = (f * u)[:, None] * v
+                S = ((np.abs(f) * (np.abs(u.real) + np.abs(u.imag)))[:, None]
+                     * (np.abs(v.real) + np.abs(v.imag))).sum(0)
+                err = np.abs(got[k] - ref.sum(0))
+                assert np.all(err <= _bound(L, L.CUT_F64, int(lens[k])) * S * 2 + 1e-300), (which, int(k))
+            for k in ks[:60]:
+                e = int(off[k]) + int(rng.integers(lens[k]))
+                br = PB.commutator(lab(d["gen_labels"], I[e]), lab(d["labels"], J[e]))
+                assert br.get(lab(tgt, k)) == (int(Cf[e, 0]), int(Cf[e, 1])), (which, e)
+            U.say(f"[pauli-boson five-mode] {which}: {ks.size} targets, longest {int(lens.max())} records")
+    finally:
+        L.cut_graph_free(g)
+        os.remove(path)
