@@ -890,6 +890,11 @@ static void load_pauli_boson(Graph& g, const HostGraph& hg, bool adjoint) {
     g.csr[0][0].cx = &g.cxs[0];
     real_split(hg, 1, NG, off, rec);                       // E_eta: target a, left i, right j (operators)
     upload_set(g, 1, std::move(off), std::move(rec), adjoint, 2 * N, 2 * N);
+    complex_records(hg, 1, NG, off, rec);
+    upload_csr(g, g.cxs[1], NG, std::move(off), rec);
+    g.cxs[1].na = N;
+    g.cxs[1].nb = N;
+    g.csr[1][0].cx = &g.cxs[1];
     if (hg.off[2]) {
         const int64_t Nc = hg.hdr.n_out_ops;
         real_split(hg, 2, Nc, off, rec);

@@ -269,7 +269,7 @@ struct Graph {
     // orientation 0 = by target k (a=i, b=j), 1 = by right input j (a=i, b=k),
     // 2 = by left input i (a=k, b=j)
     DevCSR csr[3][3];
-    DevCSR cxs[3];                   // complex twins of sets 0 and 2 (Pauli-boson only)
+    DevCSR cxs[3];                   // complex twins of the record sets (Pauli-boson only)
     bool have_adjoint = false;
     bool have_outside = false;
     int64_t n_out = 0;               // outside rows (Pauli-boson: 2 x labels)

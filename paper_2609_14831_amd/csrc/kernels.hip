@@ -628,6 +628,78 @@ __global__ __launch_bounds__(256) void k_cpass(KArgs a) {
     }
 }
 
+// Short complex targets (at most kShortMax records each, the generator set
+// E_eta of a Pauli-boson graph: about 4 per target), several per wavefront:
+// lane = (target slot, record slot q of 8, column c of NCP), so a wavefront
+// takes 8 / NCP consecutive targets and a workgroup 4 times as many; no task
+// list.  The arithmetic is that of k_cpass; the loop runs to the longest
+// target of the wavefront, shorter ones with factor zero on a valid record.
+constexpr int64_t kShortMax = 64;
+
+template <int NCP, int EPI, bool GPAIR>
+__global__ __launch_bounds__(256) void k_cshort(KArgs a, int64_t ntargets) {
+    constexpr int RS = 8, LT = RS * NCP, TPW = 64 / LT;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int slot = lane / LT, q = (lane % LT) / NCP, c = lane % NCP;
+    const int64_t k = ((int64_t)blockIdx.x * 4 + wave) * TPW + slot;
+    const bool live = k < ntargets;
+    const int64_t kk = live ? k : ntargets - 1;
+    const int nsets = a.nsets, ncol = a.nops * nsets;
+    const int cc = c < ncol ? c : ncol - 1;
+    const int s = nsets == 1 ? 0 : cc % nsets;
+    const int64_t e0 = a.off[kk], e1 = a.off[kk + 1];
+    int n = (int)(e1 - e0);
+#pragma unroll
+    for (int o = LT; o < 64; o <<= 1) n = max(n, __shfl_xor(n, o));
+    const char* __restrict__ A = (const char*)a.A;
+    const char* __restrict__ B = (const char*)a.B;
+    const uint32_t lda8 = (uint32_t)a.lda * 8u, ldb8 = (uint32_t)a.ldb * 8u;
+    const uint32_t aoff = (uint32_t)s * 8u, boff = (uint32_t)cc * 8u;
+    double are = 0.0, aim = 0.0;
+    for (int base = 0; base < n; base += RS) {
+        const int64_t e = e0 + base + q;
+        const bool ok = e < e1;
+        const uint2 r = a.rec[ok ? e : (e1 > e0 ? e1 - 1 : 0)];  // the host launches only when E > 0
+        const uint32_t ga = 2u * (r.x & 0x7FFFFFu) * lda8 + aoff;
+        double gr, gi;
+        if constexpr (GPAIR) {
+            const double2 gv = *reinterpret_cast<const double2*>(A + ga);
+            gr = gv.x;
+            gi = gv.y;
+        } else {
+            gr = *reinterpret_cast<const double*>(A + ga);
+            gi = *reinterpret_cast<const double*>(A + (ga + lda8));
+        }
+        const uint32_t xb = 2u * (r.y & 0xFFFFFFu) * ldb8 + boff;
+        const double xr = *reinterpret_cast<const double*>(B + xb);
+        const double xi = *reinterpret_cast<const double*>(B + (xb + ldb8));
+        const uint32_t im = (r.x >> 23) & 1u;
+        const double f = ok ? (double)__builtin_bit_cast(float, record_factor_bits(r.x, r.y)) : 0.0;
+        const double pr = __builtin_fma(-gi, xi, gr * xr);
+        const double pi = __builtin_fma(gi, xr, gr * xi);
+        are = __builtin_fma(f, im ? -pi : pr, are);
+        aim = __builtin_fma(f, im ? pr : pi, aim);
+    }
+#pragma unroll
+    for (int o = NCP; o < LT; o <<= 1) {
+        are += __shfl_xor(are, o);
+        aim += __shfl_xor(aim, o);
+    }
+    if (q != 0 || !live || c >= ncol || !set_active(a, s)) return;
+#pragma unroll
+    for (int part = 0; part < 2; ++part) {
+        const int64_t row = 2 * k + part;
+        const double v = a.scale * (part ? aim : are);
+        if constexpr (EPI == EPI_ETA) {
+            if (a.out_f32) ((float*)a.y)[row * a.ldy + s] = (float)v;
+            else ((double*)a.y)[row * a.ldy + s] = v;
+        } else {
+            double* y = (double*)a.y + row * a.ldy + c;
+            *y = a.accumulate ? *y + v : v;
+        }
+    }
+}
+
 // ------------------------------------------------------------- dispatch ----
 template <int G, int NOPS, int MODE, int EPI>
 static void launch_prec(const KArgs& k, int prec, dim3 grid, hipStream_t s) {
@@ -706,6 +778,47 @@ static KArgs make_kargs(const PassArgs& p) {
     return k;
 }
 
+// FP64 passes (and the generator pass, FP64 arithmetic) over a complex twin
+// whose targets are all short: k_cshort
+static bool cshort_usable(int mode, int epi, const PassArgs& p) {
+    if (mode != MODE_BCAST || (epi != EPI_ETA && epi != EPI_Y) || p.csr->cx == nullptr || p.tasks != nullptr)
+        return false;
+    const DevCSR& c = *p.csr->cx;
+    if (c.max_len > kShortMax || c.nrec == 0 || (int64_t)p.nops * p.nsets > 8) return false;
+    if (epi == EPI_Y && p.precision != CUT_F64) return false;
+    return 2 * c.na * p.lda * 8 < ((int64_t)1 << 32) && 2 * c.nb * p.ldb * 8 < ((int64_t)1 << 32);
+}
+
+template <int EPI, bool GPAIR>
+static void launch_cshort_e(const KArgs& k, int ncp, int64_t nt, hipStream_t s) {
+    const int tpw = 64 / (8 * ncp);
+    const dim3 grid((unsigned)((nt + 4 * tpw - 1) / (4 * tpw)));
+    switch (ncp) {
+        case 1: hipLaunchKernelGGL((k_cshort<1, EPI, GPAIR>), grid, dim3(256), 0, s, k, nt); break;
+        case 2: hipLaunchKernelGGL((k_cshort<2, EPI, GPAIR>), grid, dim3(256), 0, s, k, nt); break;
+        case 4: hipLaunchKernelGGL((k_cshort<4, EPI, GPAIR>), grid, dim3(256), 0, s, k, nt); break;
+        default: hipLaunchKernelGGL((k_cshort<8, EPI, GPAIR>), grid, dim3(256), 0, s, k, nt); break;
+    }
+}
+
+static void launch_cshort(int epi, const PassArgs& p, hipStream_t s) {
+    PassArgs r = p;
+    r.csr = p.csr->cx;
+    const int64_t nt = r.csr->nseg;
+    if (nt == 0) return;
+    const KArgs k = make_kargs(r);
+    const int ncol = p.nops * p.nsets;
+    const int ncp = ncol <= 1 ? 1 : ncol <= 2 ? 2 : ncol <= 4 ? 4 : 8;
+    const bool gpair = p.lda == 1 && (reinterpret_cast<uintptr_t>(p.A) & 15) == 0;
+    if (epi == EPI_ETA) {
+        if (gpair) launch_cshort_e<EPI_ETA, true>(k, ncp, nt, s);
+        else launch_cshort_e<EPI_ETA, false>(k, ncp, nt, s);
+    } else {
+        if (gpair) launch_cshort_e<EPI_Y, true>(k, ncp, nt, s);
+        else launch_cshort_e<EPI_Y, false>(k, ncp, nt, s);
+    }
+}
+
 static int cpass_columns(int ncol) {
     return ncol <= 1 ? 1 : ncol <= 2 ? 2 : ncol <= 4 ? 4 : ncol <= 8 ? 8 : ncol <= 16 ? 16 : 32;
 }
@@ -752,6 +865,10 @@ static void launch_cpass(int epi, const PassArgs& p, hipStream_t s) {
 }
 
 void launch_pass(int mode, int epi, const PassArgs& p, hipStream_t s) {
+    if (cshort_usable(mode, epi, p)) {
+        launch_cshort(epi, p, s);
+        return;
+    }
     if (cpass_usable(mode, epi, p)) {
         launch_cpass(epi, p, s);
         return;
@@ -1409,7 +1526,8 @@ static void launch_tiles_nops(const TileKArgs& t, const KArgs& k, int epi, int p
 }
 
 void launch_forward(const Graph& g, int epi, const PassArgs& a, double* partials, hipStream_t s) {
-    if (epi == EPI_ETA || a.csr != &g.csr[0][0] || partials == nullptr || cpass_usable(MODE_BCAST, epi, a)) {
+    if (epi == EPI_ETA || a.csr != &g.csr[0][0] || partials == nullptr || cpass_usable(MODE_BCAST, epi, a) ||
+        cshort_usable(MODE_BCAST, epi, a)) {
         launch_pass(MODE_BCAST, epi, a, s);
         return;
     }
