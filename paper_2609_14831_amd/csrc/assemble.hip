@@ -5,11 +5,13 @@
 //
 // Tiling: a workgroup of 4 wavefronts owns a 64 x 64 block of Y; wavefront w
 // owns the 32 x 32 quarter (w / 2, w % 2) as 2 x 2 MFMA tiles of 16 x 16.  The
-// source dimension is walked in chunks of 16: the 64 x 16 slice of X and the
-// 16 x 64 slice of W are staged in LDS (zero-filled past the edges), and every
-// wavefront issues 4 k-steps x 4 tiles of MFMA per chunk.  The next chunk's
-// global loads are issued before the current chunk's MFMAs (register double
-// buffering).
+// source dimension is walked in chunks of 8: the 64 x 8 slice of X (k-major)
+// and the 8 x 64 slice of W are staged in LDS (zero-filled past the edges), and
+// every wavefront issues 2 k-steps x 4 tiles of MFMA per chunk.  The next
+// chunk's global loads are issued before the current chunk's MFMAs and stored
+// to the other of two LDS buffers after them (one barrier per chunk).  Interior
+// blocks take unchecked vector loads and stores; the output is written with
+// non-temporal stores.
 //
 // MFMA 16x16x4 FP64 operand layout (per lane l of the wavefront): A element
 // (row l % 16, k = l / 16), B element (k = l / 16, column l % 16); element r of
@@ -25,15 +27,17 @@ typedef double double4_t __attribute__((ext_vector_type(4)));
 // BM x BN block of Y per workgroup of 4 wavefronts (2 x 2), each wavefront a
 // (BM/2) x (BN/2) quarter as TI x TJ MFMA tiles of 16 x 16; sources in chunks
 // of BK staged in LDS.
-template <int BM, int BN, int BK>
+template <int BM, int BN, int BK, bool ACC>
 __global__ __launch_bounds__(256) void k_assemble(const double* __restrict__ X, int64_t ldx, int64_t N, int64_t S,
                                                   const double* __restrict__ W, int64_t ldw, int64_t K,
-                                                  double* __restrict__ Y, int64_t ldy, int accumulate) {
+                                                  double* __restrict__ Y, int64_t ldy) {
     constexpr int TI = BM / 32, TJ = BN / 32;
     constexpr int XPT = BM * BK / 256, WPT = BK * BN / 256;   // staged elements per thread
     static_assert(BK % 4 == 0 && XPT >= 1 && WPT >= 1, "tile shape");
-    __shared__ double xs[BM][BK + 1];   // X slice, row-major, padded
-    __shared__ double ws[BK][BN + 2];   // W slice, row-major, padded
+    // two buffers of the X slice (k-major: a fragment reads 16 consecutive
+    // rows) and of the W slice, unpadded: 32 KB per workgroup
+    __shared__ double xs[2][BK][BM];
+    __shared__ double ws[2][BK][BN];
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const int64_t row0 = (int64_t)blockIdx.x * BM, col0 = (int64_t)blockIdx.y * BN;
     const int wr = (wave >> 1) * (BM / 2), wc = (wave & 1) * (BN / 2);
@@ -44,14 +48,26 @@ __global__ __launch_bounds__(256) void k_assemble(const double* __restrict__ X, 
     const int xr = t / XTPR, xk = (t % XTPR) * XPT;
     const int wk = t / WTPR, wcol = (t % WTPR) * WPT;
     double xv[XPT], wv[WPT];
+    // interior blocks (every row and column in range) skip the per-element
+    // checks of the staging loads, and of the stores below
+    const bool full = row0 + BM <= N && col0 + BN <= K;
     auto fetch = [&](int64_t k0) {
         const int64_t gr = row0 + xr;
+        const int64_t gk = k0 + wk;
+        if (full && k0 + BK <= S) {
+            const double* xp = X + gr * ldx + k0 + xk;
+            const double* wp = W + gk * ldw + col0 + wcol;
+#pragma unroll
+            for (int e = 0; e < XPT; ++e) xv[e] = xp[e];
+#pragma unroll
+            for (int e = 0; e < WPT; ++e) wv[e] = wp[e];
+            return;
+        }
 #pragma unroll
         for (int e = 0; e < XPT; ++e) {
-            const int64_t gk = k0 + xk + e;
-            xv[e] = (gr < N && gk < S) ? X[gr * ldx + gk] : 0.0;
+            const int64_t k = k0 + xk + e;
+            xv[e] = (gr < N && k < S) ? X[gr * ldx + k] : 0.0;
         }
-        const int64_t gk = k0 + wk;
 #pragma unroll
         for (int e = 0; e < WPT; ++e) {
             const int64_t gc = col0 + wcol + e;
@@ -64,29 +80,38 @@ __global__ __launch_bounds__(256) void k_assemble(const double* __restrict__ X, 
 #pragma unroll
         for (int j = 0; j < TJ; ++j) acc[i][j] = double4_t{0.0, 0.0, 0.0, 0.0};
 
+    // chunk c is read from buffer c % 2 while chunk c + 1 is written to the
+    // other one; one barrier per chunk orders both
+    auto stage = [&](int buf) {
+#pragma unroll
+        for (int e = 0; e < XPT; ++e) xs[buf][xk + e][xr] = xv[e];
+#pragma unroll
+        for (int e = 0; e < WPT; ++e) ws[buf][wk][wcol + e] = wv[e];
+    };
     fetch(0);
+    stage(0);
+    __syncthreads();
+    int buf = 0;
     for (int64_t k0 = 0; k0 < S; k0 += BK) {
-        __syncthreads();   // previous chunk's LDS reads are done
-#pragma unroll
-        for (int e = 0; e < XPT; ++e) xs[xr][xk + e] = xv[e];
-#pragma unroll
-        for (int e = 0; e < WPT; ++e) ws[wk][wcol + e] = wv[e];
-        __syncthreads();
-        if (k0 + BK < S) fetch(k0 + BK);
+        const bool more = k0 + BK < S;
+        if (more) fetch(k0 + BK);
         const int ar = lane & 15, ak = lane >> 4;
 #pragma unroll
         for (int kk = 0; kk < BK; kk += 4) {
             double a[TI], b[TJ];
 #pragma unroll
-            for (int i = 0; i < TI; ++i) a[i] = xs[wr + i * 16 + ar][kk + ak];
+            for (int i = 0; i < TI; ++i) a[i] = xs[buf][kk + ak][wr + i * 16 + ar];
 #pragma unroll
-            for (int j = 0; j < TJ; ++j) b[j] = ws[kk + ak][wc + j * 16 + ar];
+            for (int j = 0; j < TJ; ++j) b[j] = ws[buf][kk + ak][wc + j * 16 + ar];
 #pragma unroll
             for (int i = 0; i < TI; ++i)
 #pragma unroll
                 for (int j = 0; j < TJ; ++j)
                     acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
         }
+        if (more) stage(buf ^ 1);
+        __syncthreads();
+        buf ^= 1;
     }
     // epilogue: element r of a lane is row lane / 16 + 4 r of column lane % 16
     const int oc = lane & 15, orow = lane >> 4;
@@ -95,13 +120,13 @@ __global__ __launch_bounds__(256) void k_assemble(const double* __restrict__ X, 
 #pragma unroll
         for (int j = 0; j < TJ; ++j) {
             const int64_t c = col0 + wc + j * 16 + oc;
-            if (c >= K) continue;
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int64_t n = row0 + wr + i * 16 + orow + 4 * r;
-                if (n >= N) continue;
+                if (!full && (c >= K || n >= N)) continue;
                 double* y = Y + n * ldy + c;
-                *y = accumulate ? *y + acc[i][j][r] : acc[i][j][r];
+                if constexpr (ACC) *y += acc[i][j][r];
+                else __builtin_nontemporal_store(acc[i][j][r], y);  // written once, not re-read here
             }
         }
 }
@@ -120,14 +145,20 @@ extern "C" cut_status cut_assemble(const double* X, int64_t ldx, int64_t N, int6
     if (ldx < S || ldw < K || ldy < K) CUT_FAIL(CUT_E_INVAL, "cut_assemble: leading dimension too small");
     if ((flags & ~CUT_ACCUMULATE) != 0) CUT_FAIL(CUT_E_INVAL, "cut_assemble: unknown flags");
     if (N == 0) return CUT_OK;
-    // 64 x 64 blocks (32 x 32 per wavefront; measured faster than 128 x 128 at
-    // N = 92,170, S = 120, K = 1,024); row blocks along x (up to 2^31 - 1),
-    // column blocks along y (up to 65535)
-    constexpr int BM = 64, BN = 64, BK = 16;
+    // 64 x 64 blocks (32 x 32 per wavefront), chunks of 8 sources: measured at
+    // N = 92,170, S = 120, K = 1,024 against chunks of 4 and 16 and 128-row
+    // blocks; row blocks along x (up to 2^31 - 1), column blocks along y (up
+    // to 65535)
+    constexpr int BM = 64, BN = 64, BK = 8;
     const int64_t gx = (N + BM - 1) / BM, gy = (K + BN - 1) / BN;
     if (gx > 0x7fffffff || gy > 65535) CUT_FAIL(CUT_E_INVAL, "cut_assemble: too large");
-    hipLaunchKernelGGL((k_assemble<BM, BN, BK>), dim3((unsigned)gx, (unsigned)gy), dim3(256), 0, (hipStream_t)stream,
-                       X, ldx, N, S, W, ldw, K, Y, ldy, (flags & CUT_ACCUMULATE) ? 1 : 0);
+    const dim3 grid((unsigned)gx, (unsigned)gy);
+    if (flags & CUT_ACCUMULATE)
+        hipLaunchKernelGGL((k_assemble<BM, BN, BK, true>), grid, dim3(256), 0, (hipStream_t)stream, X, ldx, N, S, W,
+                           ldw, K, Y, ldy);
+    else
+        hipLaunchKernelGGL((k_assemble<BM, BN, BK, false>), grid, dim3(256), 0, (hipStream_t)stream, X, ldx, N, S, W,
+                           ldw, K, Y, ldy);
     HIP_CHECK(hipGetLastError());
     ABI_END
 }
