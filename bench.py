@@ -312,8 +312,8 @@ def main():
     ap.add_argument("--tiling-flags", type=int, default=0, help="CUT_TILE_* flags with --long-records")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the method's batch sharding "
-              "across GPUs is described in DESIGN.md but not built.", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); sharding the coefficient sets "
+              "across GPUs is not built.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

@@ -46,7 +46,7 @@ typedef enum {
     CUT_E_NOMEM = 5,        /* host or device allocation failed */
     CUT_E_DEVICE = 6,       /* HIP runtime error or device fault */
     CUT_E_NUMERIC = 7,      /* non-finite state detected by a flow */
-    CUT_E_UNSUPPORTED = 8   /* valid request outside what this build implements */
+    CUT_E_UNSUPPORTED = 8   /* valid request outside what this library implements */
 } cut_status;
 
 /* Operator algebras the graph compiler knows. */

@@ -30,7 +30,8 @@ Modules:
   native    ctypes wrapper of ``ref_engine.c`` (plain C loops for large graphs)
   ds_select power iteration used to fix the integration step
 
-Readings where the paper is silent are listed in the design doc; every function here
-is pinned by the ``-m "not gpu"`` tests against brute force, closed forms or
-invariants, except where its docstring says "parity unpinned".
+Where the paper is silent, each function's docstring states the reading it
+takes; every function here is pinned by the ``-m "not gpu"`` tests against
+brute force, closed forms or invariants, except where its docstring says
+"parity unpinned".
 """
