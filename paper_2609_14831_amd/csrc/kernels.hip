@@ -628,6 +628,139 @@ __global__ __launch_bounds__(256) void k_cpass(KArgs a) {
     }
 }
 
+// k_cpass for one coefficient set, a column count divisible by CPL (2 or 4), a
+// one-column generator at unit stride and 16-byte aligned operand rows: every
+// lane takes CPL adjacent columns (16-byte loads of both rows of x_j), so a
+// record occupies NCP / CPL lanes and a wavefront step holds CPL times as many
+// records as in k_cpass (fewer load instructions per record).
+template <int NCP, int EPI, int CPL>
+__global__ __launch_bounds__(256) void k_cpassw(KArgs a) {
+    constexpr int LPR = NCP / CPL, RS = 64 / LPR, U = CPL == 2 ? 4 : 2;
+    static_assert(CPL == 2 || CPL == 4, "columns per lane");
+    __shared__ double red[4][2 * CPL][64];
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int lane = threadIdx.x & 63;
+    const int q = lane / LPR, cl = lane % LPR;
+    const int ncol = a.nops;                                   // one set: columns = operands
+    const int c0 = CPL * cl < ncol ? CPL * cl : ncol - CPL;    // lanes past the last group compute on a valid one
+    const int64_t b = blockIdx.x;
+    int64_t t = b;
+    if (a.per_xcd > 0) {
+        t = (b & 7) * a.per_xcd + (b >> 3);
+        if ((b >> 3) >= a.per_xcd) return;
+    }
+    if (t >= a.ntasks) return;
+    const Task task = a.tasks[t];
+    const bool split = task.nseg < 0;
+    int64_t seg, e0, e1;
+    if (split) {
+        seg = task.seg;
+        const int64_t b0 = a.off[seg], n = a.off[seg + 1] - b0;
+        e0 = b0 + (n * wave) / 4;
+        e1 = b0 + (n * (wave + 1)) / 4;
+    } else {
+        if (wave >= task.nseg) return;  // block-uniform task kind: no barrier below
+        seg = task.seg + wave;
+        e0 = a.off[seg];
+        e1 = a.off[seg + 1];
+    }
+    e0 = uniform64(e0);
+    e1 = uniform64(e1);
+    const char* __restrict__ A = (const char*)a.A;
+    const char* __restrict__ B = (const char*)a.B;
+    const uint32_t ldb8 = (uint32_t)a.ldb * 8u, boff = (uint32_t)c0 * 8u;
+    const uint2* __restrict__ rec = a.rec;
+    auto fetch = [&](int64_t base, uint2 (&r)[U]) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t e = base + u * RS + q;
+            r[u] = rec[e < e1 ? e : e1 - 1];  // clamped: always a valid record
+        }
+    };
+    double are[CPL], aim[CPL];
+#pragma unroll
+    for (int h = 0; h < CPL; ++h) are[h] = aim[h] = 0.0;
+    uint2 r[U];
+    if (e0 < e1) fetch(e0, r);
+    for (int64_t base = e0; base < e1; base += RS * U) {
+        double2 gv[U], xr[U][CPL / 2], xi[U][CPL / 2];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            gv[u] = *reinterpret_cast<const double2*>(A + 16u * (r[u].x & 0x7FFFFFu));
+            const uint32_t xb = 2u * (r[u].y & 0xFFFFFFu) * ldb8 + boff;
+#pragma unroll
+            for (int h = 0; h < CPL / 2; ++h) {
+                xr[u][h] = *reinterpret_cast<const double2*>(B + (xb + 16u * h));
+                xi[u][h] = *reinterpret_cast<const double2*>(B + (xb + ldb8 + 16u * h));
+            }
+        }
+        uint32_t fb[U], im[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            im[u] = (r[u].x >> 23) & 1u;
+            fb[u] = base + u * RS + q < e1 ? record_factor_bits(r[u].x, r[u].y) : 0u;
+        }
+        if (base + RS * U < e1) fetch(base + RS * U, r);  // next group's records in flight
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const double f = (double)__builtin_bit_cast(float, fb[u]);
+            const double gr = gv[u].x, gi = gv[u].y;
+#pragma unroll
+            for (int h = 0; h < CPL; ++h) {
+                const double vr = (h & 1) ? xr[u][h / 2].y : xr[u][h / 2].x;
+                const double vi = (h & 1) ? xi[u][h / 2].y : xi[u][h / 2].x;
+                const double pr = __builtin_fma(-gi, vi, gr * vr);
+                const double pi = __builtin_fma(gi, vr, gr * vi);
+                are[h] = __builtin_fma(f, im[u] ? -pi : pr, are[h]);
+                aim[h] = __builtin_fma(f, im[u] ? pr : pi, aim[h]);
+            }
+        }
+    }
+#pragma unroll
+    for (int o = LPR; o < 64; o <<= 1)
+#pragma unroll
+        for (int h = 0; h < CPL; ++h) {
+            are[h] += __shfl_xor(are[h], o);
+            aim[h] += __shfl_xor(aim[h], o);
+        }
+    if (split) {
+        if (q == 0)
+#pragma unroll
+            for (int h = 0; h < CPL; ++h) {
+                red[wave][2 * h][lane] = are[h];
+                red[wave][2 * h + 1][lane] = aim[h];
+            }
+        __syncthreads();
+        if (wave != 0) return;
+        if (q == 0)
+#pragma unroll
+            for (int h = 0; h < CPL; ++h) {
+                are[h] = ((red[0][2 * h][lane] + red[1][2 * h][lane]) + red[2][2 * h][lane]) + red[3][2 * h][lane];
+                aim[h] = ((red[0][2 * h + 1][lane] + red[1][2 * h + 1][lane]) + red[2][2 * h + 1][lane]) +
+                         red[3][2 * h + 1][lane];
+            }
+    }
+    if (q != 0 || CPL * cl >= ncol || !set_active(a, 0)) return;
+    const int64_t ldb = a.ldb;
+#pragma unroll
+    for (int part = 0; part < 2; ++part) {
+        const int64_t row = 2 * seg + part;
+#pragma unroll
+        for (int h = 0; h < CPL; ++h) {
+            const int c = c0 + h;
+            const double v = part ? aim[h] : are[h];
+            if constexpr (EPI == EPI_Y) {
+                double* y = (double*)a.y + row * a.ldy + c;
+                *y = a.accumulate ? *y + a.scale * v : a.scale * v;
+            } else {
+                const double nxt = rk_combine(a, row * ldb + c, v);
+                ((double*)a.xout)[row * ldb + c] = nxt;
+                if (c == 0) a.hst[row * a.ldh] = nxt;  // operand 0 = the Hamiltonian
+            }
+        }
+    }
+}
+
 // Short complex targets (at most kShortMax records each, the generator set
 // E_eta of a Pauli-boson graph: about 4 per target), several per wavefront:
 // lane = (target slot, record slot q of 8, column c of NCP), so a wavefront
@@ -855,6 +988,26 @@ static void launch_cpass(int epi, const PassArgs& p, hipStream_t s) {
     const dim3 grid((unsigned)(k.per_xcd > 0 ? 8 * k.per_xcd : k.ntasks));
     const int ncp = cpass_columns(p.nops * p.nsets);
     const bool gpair = p.lda == 1 && (reinterpret_cast<uintptr_t>(p.A) & 15) == 0;
+    // one set, an even column count and 16-byte aligned operand rows: two
+    // columns per lane (measured on the five-mode benchmark: 4.09 ms for the
+    // action with all outside-space records against 6.07 ms for one column
+    // per lane and 4.46 ms for four)
+    if (gpair && p.nsets == 1 && p.nops % 2 == 0 && ncp >= 2 && ncp <= 8 && p.ldb % 2 == 0 &&
+        (reinterpret_cast<uintptr_t>(p.B) & 15) == 0) {
+        const bool rk = epi == EPI_RK;
+#define CUT_CPASSW(NCP_)                                                                           \
+    if (rk) hipLaunchKernelGGL((k_cpassw<NCP_, EPI_RK, 2>), grid, dim3(256), 0, s, k);            \
+    else hipLaunchKernelGGL((k_cpassw<NCP_, EPI_Y, 2>), grid, dim3(256), 0, s, k);
+        if (ncp == 2) {
+            CUT_CPASSW(2)
+        } else if (ncp == 4) {
+            CUT_CPASSW(4)
+        } else {
+            CUT_CPASSW(8)
+        }
+#undef CUT_CPASSW
+        return;
+    }
     if (epi == EPI_Y) {
         if (gpair) launch_cpass_e<EPI_Y, true>(k, ncp, grid, s);
         else launch_cpass_e<EPI_Y, false>(k, ncp, grid, s);

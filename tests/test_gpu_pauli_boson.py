@@ -318,3 +318,27 @@ def test_five_mode_graph_sampled_targets(L):
     finally:
         L.cut_graph_free(g)
         os.remove(path)
+
+
+@pytest.mark.parametrize("nops", [2, 4, 6])
+def test_one_set_flow_matches_oracle(L, nops):
+    """One coefficient set with an even operand count (two columns per lane in
+    the complex-record pass, RK epilogue included), FP64, 6 steps with the
+    outside-space diagnostic, against the oracle's flow and diagnostic."""
+    M, p, ds, steps = 1, 3, 1e-3, 6
+    g, og = _graphs(L, M, p)
+    N = og.N
+    rng = np.random.default_rng(60 + nops)
+    z0 = np.zeros((N, nops, 1), dtype=complex)
+    z0[:, 0, 0] = workloads.pb_hermitian(og.labels, rng, 1.0, 0.05)
+    for o in range(1, nops):
+        z0[:, o, 0] = workloads.pb_hermitian(og.labels, rng, 1.0, 1.0)
+    z = _rs(z0).reshape(2 * N, nops, 1).contiguous()
+    leak = torch.zeros(nops, dtype=torch.float64, device=DEV)
+    prm = L.flow_params(L.CUT_GEN_WEGNER_GRAPH, L.CUT_F64, ds, 0.0, 0, outside_norm2=leak)
+    L.cut_flow_integrate(g, prm, 1, nops, [steps], z)
+    torch.cuda.synchronize()
+    got = _cplx(z.reshape(2 * N, -1), N)
+    ref, ref_leak = PB.flow_outside(og, z0[:, :, 0], ds, steps)
+    assert np.linalg.norm(got - ref) <= 1e-12 * np.linalg.norm(ref)
+    assert np.abs(leak.cpu().numpy() - ref_leak).max() <= 1e-12 * np.abs(ref_leak).max()
