@@ -39,6 +39,25 @@ FP64_VEC_TFLOPS = 78.6
 FP64_MFMA_TFLOPS = 78.6   # dense FP64 matrix peak (the vector FP64 peak is the same figure)
 
 
+def stream_copy_gbs(torch, dev, nbytes=1 << 30, reps=10):
+    """Measured device copy rate (bytes read + written per second) of a 1 GiB
+    buffer: the practical HBM ceiling the algorithmic and counter rates are
+    also compared with."""
+    src = torch.empty(nbytes // 8, dtype=torch.float64, device=dev).fill_(1.0)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    b.record()
+    b.synchronize()
+    ms = a.elapsed_time(b) / reps
+    del src, dst
+    return 2 * nbytes / (ms * 1e-3) / 1e9
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -460,6 +479,13 @@ def main():
                        "fp64_equiv_tflops": flops_per / (pass_ms * 1e-3) / 1e12,
                        "fp64_vector_peak_tflops": FP64_VEC_TFLOPS}
     out["generator_avg_ms"] = gen_ms
+    copy_gbs = stream_copy_gbs(torch, dev)
+    rl = out["roofline"]
+    rl["stream_copy_GBs"] = copy_gbs
+    rl["hbm_frac_of_copy"] = achieved / copy_gbs
+    if traffic:
+        rl["traffic_GBs"] = traffic["bytes_per_launch"] / (pass_ms * 1e-3) / 1e9
+        rl["traffic_frac_of_copy"] = rl["traffic_GBs"] / copy_gbs
 
     # the other compensated float mode on the same workload (same steps)
     alt = {"f32c": "f32x", "f32x": "f32c"}.get(args.precision)
