@@ -866,6 +866,7 @@ template <int MODE, int EPI>
 static void launch_g(const KArgs& k, int prec, int G, dim3 grid, hipStream_t s) {
     switch (G) {
         case 1: launch_nops<1, MODE, EPI>(k, prec, grid, s); break;
+        case 2: launch_nops<2, MODE, EPI>(k, prec, grid, s); break;
         case 4: launch_nops<4, MODE, EPI>(k, prec, grid, s); break;
         case 8: launch_nops<8, MODE, EPI>(k, prec, grid, s); break;
         case 16: launch_nops<16, MODE, EPI>(k, prec, grid, s); break;
@@ -873,9 +874,9 @@ static void launch_g(const KArgs& k, int prec, int G, dim3 grid, hipStream_t s) 
     }
 }
 
-// lanes per record slot: the smallest of 1, 4, 8, 16, 64 holding nsets
+// lanes per record slot: the smallest of 1, 2, 4, 8, 16, 64 holding nsets
 static int group_width(int nsets) {
-    return nsets <= 1 ? 1 : nsets <= 4 ? 4 : nsets <= 8 ? 8 : nsets <= 16 ? 16 : 64;
+    return nsets <= 1 ? 1 : nsets <= 2 ? 2 : nsets <= 4 ? 4 : nsets <= 8 ? 8 : nsets <= 16 ? 16 : 64;
 }
 
 static KArgs make_kargs(const PassArgs& p) {
