@@ -216,7 +216,7 @@ def _pb_build(tmpdir, M, p, outside, threads=0, name=None):
     return path, desc
 
 
-@pytest.mark.parametrize("M,p,outside", [(1, 4, True), (2, 4, True), (3, 2, True), (2, 3, False)])
+@pytest.mark.parametrize("M,p,outside", [(1, 1, True), (2, 1, True), (1, 4, True), (2, 4, True), (3, 2, True), (2, 3, False)])
 def test_pauli_boson_bit_exact_vs_oracle(tmpdir_mod, M, p, outside):
     """The compiled Pauli-boson graph (registry, generator registry, E_eta, E_L,
     E_C, complex factors) equals the oracle's exact expansion."""

@@ -342,3 +342,46 @@ def test_one_set_flow_matches_oracle(L, nops):
     ref, ref_leak = PB.flow_outside(og, z0[:, :, 0], ds, steps)
     assert np.linalg.norm(got - ref) <= 1e-12 * np.linalg.norm(ref)
     assert np.abs(leak.cpu().numpy() - ref_leak).max() <= 1e-12 * np.abs(ref_leak).max()
+
+
+@pytest.mark.parametrize("M,p", [(1, 1), (2, 1)])
+@pytest.mark.parametrize("nsets", [1, 2])
+def test_smallest_registries(L, M, p, nsets):
+    """Degree-one registries (12 and 20 labels; one record per generator target,
+    a handful per retained or outside target): generator, both actions and a
+    5-step flow with the diagnostic against the oracle, FP64, one and two
+    sets (two operands each)."""
+    nops, ds, steps = 2, 1e-3, 5
+    g, og = _graphs(L, M, p)
+    N, NG, NC = og.N, og.NG, len(og.out_labels)
+    rng = np.random.default_rng(7 * M + nsets)
+    z0 = np.zeros((N, nops, nsets), dtype=complex)
+    for s in range(nsets):
+        z0[:, 0, s] = workloads.pb_hermitian(og.labels, rng, 1.0, 0.1)
+        z0[:, 1, s] = workloads.pb_hermitian(og.labels, rng, 1.0, 1.0)
+    h = z0[:, 0, :]
+    xi = np.stack([og.generator(h[:, s]) for s in range(nsets)], 1)
+    eta = torch.zeros((2 * NG, nsets), dtype=torch.float64, device=DEV)
+    L.cut_generator(g, L.CUT_GEN_WEGNER_GRAPH, 0.0, nsets, _rs(h), eta)
+    y = torch.zeros((2 * N, nops * nsets), dtype=torch.float64, device=DEV)
+    yc = torch.zeros((2 * NC, nops * nsets), dtype=torch.float64, device=DEV)
+    L.cut_graph_apply(g, L.CUT_GRAPH_FLOW, L.CUT_F64, nsets, nops, _rs(xi), _rs(z0), y)
+    L.cut_graph_apply(g, L.CUT_GRAPH_OUTSIDE, L.CUT_F64, nsets, nops, _rs(xi), _rs(z0), yc)
+    z = _rs(z0).reshape(2 * N, nops, nsets).contiguous()
+    leak = torch.zeros(nops * nsets, dtype=torch.float64, device=DEV)
+    L.cut_flow_integrate(g, L.flow_params(L.CUT_GEN_WEGNER_GRAPH, L.CUT_F64, ds, 0.0, 0, outside_norm2=leak),
+                         nsets, nops, [steps] * nsets, z)
+    torch.cuda.synchronize()
+    tol = 1e-13
+    assert np.abs(_cplx(eta, NG) - xi).max() <= tol * max(1.0, np.abs(xi).max())
+    ref = np.stack([np.stack([og.action(xi[:, s], z0[:, o, s]) for s in range(nsets)], 1) for o in range(nops)], 1)
+    assert np.abs(_cplx(y, N).reshape(N, nops, nsets) - ref).max() <= tol * np.abs(ref).max()
+    refc = np.stack([np.stack([PB.outside_action(og, xi[:, s], z0[:, o, s]) for s in range(nsets)], 1)
+                     for o in range(nops)], 1)
+    assert np.abs(_cplx(yc, NC).reshape(NC, nops, nsets) - refc).max() <= tol * np.abs(refc).max()
+    got = _cplx(z.reshape(2 * N, -1), N).reshape(N, nops, nsets)
+    got_leak = leak.cpu().numpy().reshape(nops, nsets)
+    for s in range(nsets):
+        zr, lr = PB.flow_outside(og, z0[:, :, s], ds, steps)
+        assert np.linalg.norm(got[:, :, s] - zr) <= 1e-12 * np.linalg.norm(zr)
+        assert np.abs(got_leak[:, s] - lr).max() <= 1e-12 * np.abs(lr).max()
