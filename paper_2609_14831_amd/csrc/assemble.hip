@@ -3,11 +3,11 @@
 //   Y[n][k] (=|+=) sum_s X[n][s] W[s][k],
 // a dense FP64 product on the matrix cores (v_mfma_f64_16x16x4f64).
 //
-// Tiling: a workgroup of 4 wavefronts owns a 64 x 64 block of Y; wavefront w
-// owns the 32 x 32 quarter (w / 2, w % 2) as 2 x 2 MFMA tiles of 16 x 16.  The
-// source dimension is walked in chunks of 8: the 64 x 8 slice of X (k-major)
-// and the 8 x 64 slice of W are staged in LDS (zero-filled past the edges), and
-// every wavefront issues 2 k-steps x 4 tiles of MFMA per chunk.  The next
+// Tiling: a workgroup of 4 wavefronts owns a 128 x 128 block of Y; wavefront w
+// owns the 64 x 64 quarter (w / 2, w % 2) as 4 x 4 MFMA tiles of 16 x 16.  The
+// source dimension is walked in chunks of 8: the 128 x 8 slice of X (k-major)
+// and the 8 x 128 slice of W are staged in LDS (zero-filled past the edges),
+// and every wavefront issues 2 k-steps x 16 tiles of MFMA per chunk.  The next
 // chunk's global loads are issued before the current chunk's MFMAs and stored
 // to the other of two LDS buffers after them (one barrier per chunk).  Interior
 // blocks take unchecked vector loads and stores; the output is written with
@@ -145,11 +145,11 @@ extern "C" cut_status cut_assemble(const double* X, int64_t ldx, int64_t N, int6
     if (ldx < S || ldw < K || ldy < K) CUT_FAIL(CUT_E_INVAL, "cut_assemble: leading dimension too small");
     if ((flags & ~CUT_ACCUMULATE) != 0) CUT_FAIL(CUT_E_INVAL, "cut_assemble: unknown flags");
     if (N == 0) return CUT_OK;
-    // 64 x 64 blocks (32 x 32 per wavefront), chunks of 8 sources: measured at
-    // N = 92,170, S = 120, K = 1,024 against chunks of 4 and 16 and 128-row
-    // blocks; row blocks along x (up to 2^31 - 1), column blocks along y (up
-    // to 65535)
-    constexpr int BM = 64, BN = 64, BK = 8;
+    // 128 x 128 blocks (64 x 64 per wavefront), chunks of 8 sources: measured
+    // at N = 92,170, S = 120, K = 1,024 against 64 x 64 and 128 x 64 blocks
+    // and chunks of 4 and 16; row blocks along x (up to 2^31 - 1), column
+    // blocks along y (up to 65535)
+    constexpr int BM = 128, BN = 128, BK = 8;
     const int64_t gx = (N + BM - 1) / BM, gy = (K + BN - 1) / BN;
     if (gx > 0x7fffffff || gy > 65535) CUT_FAIL(CUT_E_INVAL, "cut_assemble: too large");
     const dim3 grid((unsigned)gx, (unsigned)gy);
