@@ -1754,18 +1754,27 @@ __global__ void k_g2(int64_t N, int32_t nsets, const int4* __restrict__ st,
     const int s = (int)(gid % nsets);
     if (S >= N) return;
     if (nsteps && nsteps[s] <= *step) return;
+    // all four stencil entries and their loads are issued before any use; an
+    // unused entry (x < 0, always after the used ones; its y and z are 0)
+    // reads row S and pair 0 and weighs zero, which leaves the sums exact
+    int4 e[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) e[t] = st[S * 4 + t];
+    double c[4], eps[4], hp[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const bool ok = e[t].x >= 0;
+        c[t] = ok ? ftab[e[t].z] : 0.0;
+        eps[t] = h[(int64_t)pairs[e[t].y] * ldh + s];
+        hp[t] = h[(ok ? (int64_t)e[t].x : S) * ldh + s];
+    }
     double num = 0.0, q = 0.0;
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
-        const int4 e = st[S * 4 + t];
-        if (e.x < 0) break;
-        const double c = ftab[e.z];
-        const double eps = h[(int64_t)pairs[e.y] * ldh + s];
-        num = __builtin_fma(c * eps, h[(int64_t)e.x * ldh + s], num);
-        q = __builtin_fma(c * eps, c * eps, q);
+        num = __builtin_fma(c[t] * eps[t], hp[t], num);
+        q = __builtin_fma(c[t] * eps[t], c[t] * eps[t], q);
     }
-    const bool has = st[S * 4].x >= 0;
-    const double v = has ? gsign * num / (q + d2) : 0.0;
+    const double v = e[0].x >= 0 ? gsign * num / (q + d2) : 0.0;
     if (eta_f32) ((float*)eta)[S * lde + s] = (float)v;
     else ((double*)eta)[S * lde + s] = v;
 }
