@@ -265,3 +265,35 @@ def test_discrete_adjoint_matches_central_differences(alg, size, kind, nops):
         eps = 1e-5
         fd = (loss(z0 + eps * v) - loss(z0 - eps * v)) / (2 * eps)
         assert np.sum(lam * v) == pytest.approx(fd, rel=2e-8)
+
+
+# ---------------------------------------------------- sampled-row action ----
+
+@pytest.mark.parametrize("m", [10, 12])
+def test_apply_rows_equals_apply_at_those_rows(m):
+    """apply_rows (the reference of every full-size sampled GPU test) on the
+    records of just the sampled targets equals the pinned whole-graph apply at
+    those rows, including the first and last quadratic and quartic targets.
+    A selection by the wrong record field or the wrong operand row fails."""
+    full = A.majorana_graph(m)
+    nq = math.comb(m, 2)
+    rng = np.random.default_rng(m)
+    rows = np.array([0, 1, nq - 1, nq, nq + 1, full.N - 1] + list(rng.integers(0, full.N, 10)))
+    sub = A.majorana_graph(m, targets=rows)
+    eta = workloads.random_dense((full.N, 3), seed=30 + m)
+    x = workloads.random_dense((full.N, 2, 3), seed=40 + m)
+    ref = G.apply(full, eta, x)[rows]
+    scale = np.abs(ref).max()
+    np.testing.assert_allclose(G.apply_rows(sub, eta, x, rows), ref, rtol=0, atol=1e-13 * scale)
+    np.testing.assert_allclose(G.apply_rows(full, eta, x, rows), ref, rtol=0, atol=1e-13 * scale)
+
+    # the same sum with a mistake in the selection must not pass
+    def planted(g, e, xx, rr, key):
+        out = np.zeros((len(rr),) + xx.shape[1:])
+        for t, r in enumerate(rr):
+            sel = key(g) == r
+            out[t] = np.sum(g.c[sel, None, None] * e[g.i[sel]][:, None, :] * xx[g.j[sel]], axis=0)
+        return out
+
+    for key in (lambda g: g.i, lambda g: g.j):
+        assert np.abs(planted(full, eta, x, rows, key) - ref).max() > 1e-3 * scale

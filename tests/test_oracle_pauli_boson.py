@@ -165,3 +165,77 @@ def test_flow_outside_matches_plain_flow_and_dense_outside_norm():
         outside = full - dense(g.action(xi, z0[:, o]), g.labels)[:, cols]
         C = PB.outside_action(g, xi, z0[:, o])
         assert np.allclose(dense(C, g.out_labels)[:, cols], outside, atol=1e-9 * np.abs(full).max())
+
+
+def _pb_small():
+    import workloads
+    g = PB.PBGraph(1, 3, outside=True)
+    rng = np.random.default_rng(21)
+    z0 = np.stack([workloads.pb_hermitian(g.labels, rng, 1.0, 0.05),
+                   workloads.pb_hermitian(g.labels, rng, 1.0, 1.0)], axis=1)
+    return g, z0
+
+
+def _columns(fn, n):
+    """Matrix of a linear map given on unit vectors."""
+    return np.stack([fn(np.eye(n, dtype=complex)[:, j]) for j in range(n)], axis=1)
+
+
+def test_pb_rk4_step_is_fourth_order_taylor_with_fixed_generator():
+    """With the generator held fixed the coflow right-hand side is the linear map
+    L x = P[xi, x], so one classic RK4 step must equal the degree-4 Taylor
+    polynomial sum_p (ds L)^p / p! applied to every column (Eq. coflow under
+    the RK4 reading).  L is taken column by column from the action, which is
+    pinned against dense truncated-Fock commutators above."""
+    g, z0 = _pb_small()
+    xi = g.generator(z0[:, 0])
+    Lm = _columns(lambda e: g.action(xi, e), g.N)
+    g.generator = lambda h: xi        # hold the generator fixed on this instance
+    ds = 0.05
+    z1 = PB.flow(g, z0, ds, 1)
+    taylor = np.zeros_like(z0)
+    term = z0.copy()
+    for p in range(5):
+        taylor += term
+        term = ds * (Lm @ term) / (p + 1)
+    np.testing.assert_allclose(z1, taylor, rtol=0, atol=1e-13 * np.abs(taylor).max())
+    # the exponential differs at fifth order, so the step is not a trivially exact map
+    from scipy.linalg import expm
+    assert np.abs(expm(ds * Lm) @ z0 - z1).max() > 1e-12
+
+
+def test_pb_flow_converges_at_fourth_order():
+    """Self-consistent flow (generator from the stage Hamiltonian): the error
+    at s = 0.1 against a 256-step reference falls by about 2^4 per halving of
+    ds (the spectral radius of the action is about 6.4 here)."""
+    g, z0 = _pb_small()
+    T = 0.1
+    ref = PB.flow(g, z0, T / 256, 256)
+    errs = [np.abs(PB.flow(g, z0, T / n, n) - ref).max() for n in (16, 32)]
+    assert 13.0 < errs[0] / errs[1] < 19.0, errs
+
+
+def test_pb_outside_diagnostic_is_fourth_order_quadrature():
+    """With the generator fixed, Z(s) = exp(sL) z0 and the diagnostic must be
+    the RK4 quadrature of int_0^T sum_q |C_q(Z(s))|^2 ds: against that integral
+    (Gauss-Legendre on the exact trajectory) its error falls by about 2^4 per
+    halving of ds.  A wrong stage weight b_s leaves a first-order error."""
+    from scipy.linalg import expm
+    g, z0 = _pb_small()
+    xi = g.generator(z0[:, 0])
+    Lm = _columns(lambda e: g.action(xi, e), g.N)
+    Cm = _columns(lambda e: PB.outside_action(g, xi, e), g.N)
+    g.generator = lambda h: xi
+    T = 0.2
+    nodes, weights = np.polynomial.legendre.leggauss(40)
+    exact = np.zeros(z0.shape[1])
+    for u, wq in zip(nodes, weights):
+        s = 0.5 * T * (u + 1.0)
+        exact += 0.5 * T * wq * np.sum(np.abs(Cm @ (expm(s * Lm) @ z0)) ** 2, axis=0)
+    errs = []
+    for n in (8, 16):
+        z, leak = PB.flow_outside(g, z0, T / n, n)
+        np.testing.assert_array_equal(z, PB.flow(g, z0, T / n, n))
+        errs.append(np.abs(leak - exact).max() / np.abs(exact).max())
+    assert 13.0 < errs[0] / errs[1] < 19.0, errs
+    assert errs[1] < 1e-6
