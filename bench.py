@@ -9,10 +9,12 @@ state, one hipGraph launch per RK step.  A step = one RK4 step of the whole
 batch (4 x {generator, graph pass with the fused stage update}).
 
 Printed (one JSON line): contributions x batch / s over the timed steps; the
-dominant kernel's roofline (HIP-event average of the fused graph pass; for the
-compensated float mode against the FP32 VALU issue rate, which binds it, with
-its algorithmic HBM bytes and rate beside); the plain FP64 one-column flow for the batched /
-plain ratio; and the oracle's CPU rate on a bounded sample (cpu_baseline leg).
+dominant kernel's roofline (HIP-event average of the fused graph pass; its
+algorithmic HBM bytes per launch over that time, against the 8 TB/s HBM peak,
+for every precision); the same flow in the other precisions (FP64 at the full
+width too); the whole ragged flow counting active columns only; the stress-scale
+2n = 64 graph; the plain FP64 one-column flow for the batched / plain ratio;
+and the oracle's CPU rate on a bounded sample (cpu_baseline leg).
 """
 from __future__ import annotations
 
@@ -28,13 +30,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# FP32 VALU issue rate without packed instructions (which this library does not
-# emit): 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz, one operation per lane and
-# clock whatever the operation (add, multiply or fused multiply-add)
-VALU_F32_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
-# FP32 operations per contribution x column of the compensated dot product
-# (two-product with FMA: 2, two-sum: 6, error accumulation: 2)
-F32C_OPS_PER_TERM = 10
+# VALU issue rate without packed FP32 instructions (which this library does not
+# emit): 256 CUs x 4 SIMDs, one 64-lane instruction every 4 clocks at 2.4 GHz
+VALU_INSTS_PER_S = 256 * 4 * 2.4e9 / 4
 FP64_VEC_TFLOPS = 78.6
 FP64_MFMA_TFLOPS = 78.6   # dense FP64 matrix peak (the vector FP64 peak is the same figure)
 
@@ -75,23 +73,24 @@ def pass_bytes(N, E, nsets, nops, prec_bytes):
             + N * cols * (8 + 14) + N * cols * prec_bytes + N * nsets * 8)
 
 
-def measured_traffic(precision: str):
-    """HBM bytes per fused-pass launch from the committed counter summary, if it
-    was taken on the current kernel source (else None).
+def measured_counters(precision: str, what: str = "traffic", prof_name: str = "fused_pass_m40_counters.md"):
+    """A per-launch figure of the fused pass from a committed counter summary,
+    if it was taken on the current kernel source (else None).
 
-    profiles/fused_pass_m40_counters.md carries a line
-    `traffic <precision> <kernels.hip sha256> <bytes per launch>`.
+    The summary carries lines `<what> <precision> <kernels.hip sha256> <value>`:
+    what = traffic (HBM bytes per launch: FETCH_SIZE x copy factor +
+    WRITE_SIZE) or valu (SQ_INSTS_VALU per launch).
     """
     import hashlib
     src = os.path.join(ROOT, "paper_2609_14831_amd", "csrc", "kernels.hip")
-    prof = os.path.join(ROOT, "profiles", "fused_pass_m40_counters.md")
+    prof = os.path.join(ROOT, "profiles", prof_name)
     if not os.path.exists(prof):
         return None
     digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
     for line in open(prof):
         parts = line.strip().strip("`").split()
-        if len(parts) == 4 and parts[0] == "traffic" and parts[1] == precision and parts[2] == digest:
-            return {"bytes_per_launch": float(parts[3])}
+        if len(parts) == 4 and parts[0] == what and parts[1] == precision and parts[2] == digest:
+            return float(parts[3])
     return None
 
 
@@ -169,6 +168,122 @@ def derivative_leg(L, torch, g, inp, w, prec, E):
     return {"call": "cut_graph_jvp (dh and dx), 64 sets x 5 operands", "ms": t1 * 1e3,
             "ms_with_action": t2 * 1e3, "passes": 2, "contributions_per_s": 2 * E * cols / t1,
             "unit": "contributions×batch/s"}
+
+
+def timed_flow(L, torch, g, inp, w, prec, W, K, E, N, tune=True):
+    """The headline flow (same sets, steps W .. W+K, hipGraph) in another
+    precision, in the tiling the autotuner picks for it; HIP-event average of
+    its fused pass from the same steps in stream order."""
+    dev = torch.device("cuda:0")
+    N_, nops, nsets = inp.z0.shape
+    ns = [int(v) for v in inp.n_steps]
+    tuning = L.cut_graph_autotune(g, nsets, nops, prec, 0) if tune else None
+    z = torch.tensor(inp.z0, device=dev).contiguous()
+    p = L.flow_params(L.CUT_GEN_G2, prec, w.ds, w.delta, 0, flags=L.CUT_FLOW_HIPGRAPH, step_begin=0, step_end=W)
+    L.cut_flow_integrate(g, p, nsets, nops, ns, z)
+    p = L.flow_params(L.CUT_GEN_G2, prec, w.ds, w.delta, 0, flags=L.CUT_FLOW_HIPGRAPH, step_begin=W,
+                      step_end=W + K)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    L.cut_flow_integrate(g, p, nsets, nops, ns, z)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    zt = torch.tensor(inp.z0, device=dev).contiguous()
+    p = L.flow_params(L.CUT_GEN_G2, prec, w.ds, w.delta, 0, flags=L.CUT_FLOW_TIME_PASSES, step_begin=0,
+                      step_end=W + K)
+    L.cut_flow_integrate(g, p, nsets, nops, ns, zt)
+    tm = L.cut_flow_last_timing(g)
+    pass_ms = tm["pass_ms"] / max(1, tm["pass_launches"])
+    pb = pass_bytes(N, E, nsets, nops, 8 if prec == L.CUT_F64 else 4)
+    return {"value": 4 * E * nops * nsets * K / wall, "unit": "contributions×batch/s",
+            "ms_per_step": wall * 1e3 / K, "pass_ms": pass_ms, "algorithmic_bytes_per_launch": pb,
+            "hbm_GBs": pb / (pass_ms * 1e-3) / 1e9, "hbm_frac": pb / (pass_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "tiling": tuning}
+
+
+def full_flow_leg(L, torch, g, inp, w, prec, E, all_active_value):
+    """The whole config-3 flow: every set over its own n_b steps (421 ... 3,660),
+    hipGraph replays with the passes launched over the active sets only.  The
+    rate counts active columns (E x operands x active sets per pass) and is
+    compared with the all-active rate of the timed steps."""
+    dev = torch.device("cuda:0")
+    N_, nops, nsets = inp.z0.shape
+    ns = [int(v) for v in inp.n_steps]
+    T = max(ns)
+    L.cut_graph_autotune(g, nsets, nops, prec, 0)
+    z = torch.tensor(inp.z0, device=dev).contiguous()
+    p = L.flow_params(L.CUT_GEN_G2, prec, w.ds, w.delta, 0, flags=L.CUT_FLOW_HIPGRAPH, step_end=2)
+    L.cut_flow_integrate(g, p, nsets, nops, ns, z)        # captures the step graphs
+    z = torch.tensor(inp.z0, device=dev).contiguous()
+    p = L.flow_params(L.CUT_GEN_G2, prec, w.ds, w.delta, 0, flags=L.CUT_FLOW_HIPGRAPH)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    L.cut_flow_integrate(g, p, nsets, nops, ns, z)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    active = sum(ns) * nops                               # active column-steps
+    value = 4 * E * active / wall
+    return {"steps": T, "s": wall, "value": value, "unit": "contributions×batch/s (active columns)",
+            "active_fraction_of_lane_steps": sum(ns) / (nsets * T),
+            "ratio_to_all_active": value / all_active_value}
+
+
+def stress_leg(L, torch, tmp, profile=False):
+    """Stress scale (the 2n = 64 Majorana graph: 637,392 strings, 457,720,704
+    records): 16 sets (H only), G2, RK4 at ds = 5e-3, 200 steps; F32C and FP64,
+    each in its autotuned tiling, hipGraph replays; the fused pass's
+    algorithmic bytes over its HIP-event average against HBM peak."""
+    import numpy as np
+    import workloads
+    dev = torch.device("cuda:0")
+    w = workloads.WORKLOADS[4]
+    path = os.path.join(tmp, "m64.cgb")
+    desc = L.cut_graph_build(L.CUT_ALG_MAJORANA, w.size, path, 0)
+    t0 = time.perf_counter()
+    g = L.cut_graph_load(path, 0, 0)
+    load_s = time.perf_counter() - t0
+    os.remove(path)
+    N, E = desc["n_ops"], desc["n_records"]
+    inp = workloads.make_inputs(4)
+    nsets, nops = w.nsets, w.nops
+    ns = [int(v) for v in inp.n_steps]
+    T = max(ns)
+    res = {"graph": f"majorana m={w.size}: N={N}, E={E} records ({E * 8 / 1e9:.2f} GB at 8 B)",
+           "compile_s": desc["build_seconds"], "load_s": load_s, "steps": T,
+           "sets": nsets, "operands": nops}
+    for name, prec in (("f32c", L.CUT_F32C), ("f64", L.CUT_F64)):
+        tuning = L.cut_graph_autotune(g, nsets, nops, prec, 0)
+        if profile:
+            z = torch.tensor(inp.z0, device=dev).contiguous()
+            p = L.flow_params(L.CUT_GEN_G2, prec, w.ds, w.delta, 0, flags=L.CUT_FLOW_TIME_PASSES, step_end=3)
+            L.cut_flow_integrate(g, p, nsets, nops, ns, z)
+            res[name] = {"tiling": tuning}
+            continue
+        z = torch.tensor(inp.z0, device=dev).contiguous()
+        p = L.flow_params(L.CUT_GEN_G2, prec, w.ds, w.delta, 0, flags=L.CUT_FLOW_HIPGRAPH, step_end=2)
+        L.cut_flow_integrate(g, p, nsets, nops, ns, z)        # capture
+        z = torch.tensor(inp.z0, device=dev).contiguous()
+        p = L.flow_params(L.CUT_GEN_G2, prec, w.ds, w.delta, 0, flags=L.CUT_FLOW_HIPGRAPH)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        L.cut_flow_integrate(g, p, nsets, nops, ns, z)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        zt = torch.tensor(inp.z0, device=dev).contiguous()
+        p = L.flow_params(L.CUT_GEN_G2, prec, w.ds, w.delta, 0, flags=L.CUT_FLOW_TIME_PASSES, step_end=5)
+        L.cut_flow_integrate(g, p, nsets, nops, ns, zt)
+        tm = L.cut_flow_last_timing(g)
+        pass_ms = tm["pass_ms"] / max(1, tm["pass_launches"])
+        pb = pass_bytes(N, E, nsets, nops, 8 if prec == L.CUT_F64 else 4)
+        res[name] = {"s_200_steps": wall, "ms_per_step": wall * 1e3 / T,
+                     "value": 4 * E * nsets * nops * T / wall, "unit": "contributions×batch/s",
+                     "pass_ms": pass_ms, "algorithmic_bytes_per_launch": pb,
+                     "hbm_GBs": pb / (pass_ms * 1e-3) / 1e9,
+                     "hbm_frac": pb / (pass_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                     "record_stream_GBs": E * 8 / (pass_ms * 1e-3) / 1e9, "tiling": tuning}
+        del z, zt
+    L.cut_graph_free(g)
+    return res
 
 
 def assembly_leg(L, torch, N):
@@ -319,12 +434,15 @@ def main():
     ap.add_argument("--precision", default="f32c", choices=["f32c", "f32x", "f64", "f32"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-outside", action="store_true", help="skip the outside-space action leg")
-    ap.add_argument("--only", choices=["assembly", "outside", "pauli_boson"],
+    ap.add_argument("--no-stress", action="store_true", help="skip the 2n = 64 stress-scale leg")
+    ap.add_argument("--only", choices=["assembly", "outside", "pauli_boson", "stress"],
                     help="run only that leg and print its JSON (for profiling)")
     ap.add_argument("--minimal", action="store_true", help="timed flow only")
     ap.add_argument("--profile", action="store_true",
                     help="counter runs: a 1 GiB device copy (calibration), then the steps in "
                          "stream order (no hipGraph), nothing else")
+    ap.add_argument("--plain", action="store_true",
+                    help="with --profile: the plain FP64 flow, one operand column (one set, H only)")
     ap.add_argument("--long-records", type=int, default=0,
                     help="fixed tiling (long-target threshold); 0 = autotune")
     ap.add_argument("--chunk-records", type=int, default=512, help="chunk length with --long-records")
@@ -352,6 +470,10 @@ def main():
     if args.only == "pauli_boson":
         print(json.dumps({"pauli_boson": pauli_boson_leg(L, torch, tempfile.mkdtemp(prefix="cutgraph_bench_"))}),
               flush=True)
+        return
+    if args.only == "stress":
+        print(json.dumps({"stress_m64": stress_leg(L, torch, tempfile.mkdtemp(prefix="cutgraph_bench_"),
+                                                   profile=args.profile)}), flush=True)
         return
     if args.only == "outside":
         print(json.dumps({"outside_space": outside_leg(L, torch, tempfile.mkdtemp(prefix="cutgraph_bench_"))}),
@@ -390,11 +512,15 @@ def main():
         dst = torch.empty_like(src)
         dst.copy_(src)
         torch.cuda.synchronize()
+        if args.plain:
+            nsets, nops, ns = 1, 1, [ns[0]]
+            z = torch.tensor(inp.z0[:, :1, :1], device=dev).contiguous()
         p = L.flow_params(L.CUT_GEN_G2, PREC, w.ds, w.delta, 0, flags=L.CUT_FLOW_TIME_PASSES,
                           step_begin=0, step_end=W + K)
         L.cut_flow_integrate(g, p, nsets, nops, ns, z)
         tm = L.cut_flow_last_timing(g)
         print(json.dumps({"profile": True, "copy_bytes_each_way": 1 << 30, "steps": W + K,
+                          "sets": nsets, "operands": nops,
                           "pass_avg_ms": tm["pass_ms"] / max(1, tm["pass_launches"]),
                           "pass_bytes": pass_bytes(N, E, nsets, nops, pbytes)}), flush=True)
         return
@@ -451,40 +577,34 @@ def main():
     achieved = bytes_per / (pass_ms * 1e-3) / 1e9
     flops_per = 2.0 * E * nsets * nops
     log(f"fused pass avg {pass_ms:.4f} ms ({tm['pass_launches']} launches), generator {gen_ms:.4f} ms")
-    traffic = measured_traffic(args.precision)
+    traffic = measured_counters(args.precision, "traffic")
+    valu = measured_counters(args.precision, "valu")
     gathered = E * (nsets + nops * nsets) * pbytes   # one eta row + one operand row per record
     terms = E * nsets * nops                          # contributions x columns of one pass
-    if args.precision == "f32c":
-        # the compensated arithmetic binds this pass: its VALU instructions
-        # fill the SIMDs' issue cycles (counters in profiles/)
-        ops = F32C_OPS_PER_TERM * terms / (pass_ms * 1e-3) / 1e12
-        head = {"bound": "alu", "achieved": ops, "peak": VALU_F32_TOPS, "unit": "TFLOP/s",
-                "frac": ops / VALU_F32_TOPS,
-                "flop_unit": "FP32 operations (add, subtract, multiply and fused multiply-add count one "
-                             "each), 10 per contribution x column; peak = the non-packed FP32 issue rate",
-                "algorithmic_ops_per_launch": F32C_OPS_PER_TERM * terms}
-    else:
-        head = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS}
-    out["roofline"] = {**head,
-                       "traffic": traffic["bytes_per_launch"] if traffic else None,
-                       "traffic_unit": "bytes per fused pass (FETCH_SIZE x copy factor + WRITE_SIZE)",
+    out["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                       "frac": achieved / HBM_PEAK_GBS,
+                       "traffic": traffic,
+                       "traffic_unit": "HBM bytes per fused pass (FETCH_SIZE x copy factor + WRITE_SIZE)",
                        "kernel": "fused graph pass with RK4 stage epilogue: k_pass<64,5,prec,0,2> "
                                  "(chunks of the quadratic targets + quartic targets) and k_chunk_combine<5,prec,2>",
                        "avg_launch_ms": pass_ms, "algorithmic_bytes_per_launch": bytes_per,
-                       "hbm_achieved_GBs": achieved, "hbm_peak_GBs": HBM_PEAK_GBS,
-                       "hbm_frac": achieved / HBM_PEAK_GBS,
                        "gathered_row_bytes_per_launch": gathered,
                        "gathered_row_rate_GBs": gathered / (pass_ms * 1e-3) / 1e9,
                        "fp64_equiv_tflops": flops_per / (pass_ms * 1e-3) / 1e12,
                        "fp64_vector_peak_tflops": FP64_VEC_TFLOPS}
+    if valu:
+        # diagnostic: VALU instructions per contribution x column and the share
+        # of the SIMDs' issue cycles they fill (counters in profiles/)
+        out["roofline"]["valu_diagnostic"] = {
+            "insts_per_launch": valu, "per_term": valu * 64 / terms,
+            "issue_frac": valu / (pass_ms * 1e-3) / VALU_INSTS_PER_S}
     out["generator_avg_ms"] = gen_ms
     copy_gbs = stream_copy_gbs(torch, dev)
     rl = out["roofline"]
     rl["stream_copy_GBs"] = copy_gbs
     rl["hbm_frac_of_copy"] = achieved / copy_gbs
     if traffic:
-        rl["traffic_GBs"] = traffic["bytes_per_launch"] / (pass_ms * 1e-3) / 1e9
+        rl["traffic_GBs"] = traffic / (pass_ms * 1e-3) / 1e9
         rl["traffic_frac_of_copy"] = rl["traffic_GBs"] / copy_gbs
 
     # the other compensated float mode on the same workload (same steps)
@@ -507,6 +627,13 @@ def main():
                                 "ms_per_step": alt_wall * 1e3 / K, "tiling": alt_tuning}
         log(f"{alt}: {alt_wall * 1e3 / K:.3f} ms/step")
         del za
+
+    # the same flow with FP64 passes at the full width (64 sets x 5 operands)
+    out["batched_fp64"] = timed_flow(L, torch, g, inp, w, L.CUT_F64, W, K, E, N, tune=args.long_records <= 0)
+    log(f"batched fp64: {out['batched_fp64']}")
+    # the whole ragged flow (421 ... 3,660 steps), counting active columns only
+    out["full_ragged_flow"] = full_flow_leg(L, torch, g, inp, w, PREC, E, value)
+    log(f"full ragged flow: {out['full_ragged_flow']}")
 
     # plain FP64 flow, one operand column per pass (one set, H only), in the
     # tiling tuned for that shape
@@ -538,6 +665,10 @@ def main():
 
     out["assembly"] = assembly_leg(L, torch, N)
     log(f"assembly: {out['assembly']}")
+
+    if not args.no_stress:
+        out["stress_m64"] = stress_leg(L, torch, tmp)
+        log(f"stress-scale m=64: {out['stress_m64']}")
 
     if not args.no_outside:
         out["outside_space"] = outside_leg(L, torch, tmp)

@@ -22,9 +22,20 @@
  *    op*nsets + s belongs to operand op (0 = the Hamiltonian) of coefficient set
  *    s.  A generator row holds nsets columns.  Every operand column of set s is
  *    paired with generator column s.
- *  - A graph handle owns all device copies of the graph and a work area that
- *    grows on demand; calls on one handle must not overlap in time (serialise
- *    them on one stream).
+ *  - A graph handle owns all device copies of the graph and its work areas.
+ *    Work areas are sized only by cut_graph_reserve (and re-sized by the
+ *    tiling calls for the shapes reserved so far).  The computing entry points
+ *    -- cut_graph_apply, cut_graph_apply_adjoint, cut_generator*,
+ *    cut_graph_jvp/vjp, cut_flow_integrate, cut_flow_adjoint -- never allocate
+ *    device memory and never synchronise the device; a shape that was not
+ *    reserved fails with CUT_E_INVAL before any launch.
+ *  - Concurrency: the graph's records and plans are read-only during
+ *    computing calls, but the work areas are shared by every call on one
+ *    handle.  Calls that use a work area (chunked forward passes, generator
+ *    VJP, derivatives, flows) must not overlap in time on one handle: issue
+ *    them on one stream, or load the bundle once per stream.  Setup calls
+ *    (reserve, set_tiling, autotune, free) must not run concurrently with any
+ *    other call on the handle.
  */
 #ifndef CUTGRAPH_H
 #define CUTGRAPH_H
@@ -87,10 +98,17 @@ typedef enum {
 /* Generators eta(h) (Sec. 2.1, Eq. block-generator). */
 typedef enum {
     CUT_GEN_WEGNER_GRAPH = 1, /* eta = [H_d, H_od] as a graph pass over E_eta */
-    CUT_GEN_G2 = 2            /* Majorana: Wegner generator of the quadratic diagonal
+    CUT_GEN_G2 = 2,           /* Majorana: Wegner generator of the quadratic diagonal
                                  part H_0 = sum_a eps_a Gamma_{P_a}, eps_a = h_{P_a},
                                  divided elementwise by Q_S = sum_t (c_t eps_{a_t})^2
                                  + delta^2 (the diagonal of ad_{H_0}^2) */
+    CUT_GEN_G1 = 3            /* Majorana: the literal White-type generator from the
+                                 diagonal pair energies, eta_S = h_S / D_S with
+                                 D_S = 2 sum_{a in F(S)} |eps_a| + delta over the
+                                 pairs a that S flips (|S & P_a| = 1); eta = 0 on
+                                 block-diagonal strings.  In the string basis it
+                                 rotates h_S with its partners S ^ P_a instead of
+                                 damping it: kept for the precision study */
 } cut_generator_kind;
 
 #define CUT_BUILD_OUTSIDE 1u  /* build flags: also compile the outside-space records */
@@ -167,6 +185,33 @@ cut_status cut_graph_info(cut_graph_t g, cut_graph_desc* desc);
 cut_status cut_graph_labels(cut_graph_t g, int32_t which, uint64_t* out, int64_t n);
 void cut_graph_free(cut_graph_t g);
 
+/* ---------------------------------------------------------- work areas --
+ * cut_graph_reserve: sizes the handle's work areas for calls with nsets
+ * coefficient sets and nops operands per set, in every precision, for the
+ * call kinds in `what`:
+ *   CUT_RESERVE_APPLY   cut_graph_apply (partial rows of chunked or tiled
+ *                       forward passes) and cut_generator_vjp;
+ *   CUT_RESERVE_FLOW    cut_flow_integrate (stage operands, RK accumulator,
+ *                       generator, step counters; plus the outside-space
+ *                       diagnostic buffers when the graph holds E_C);
+ *   CUT_RESERVE_DERIV   cut_graph_jvp and cut_graph_vjp;
+ *   CUT_RESERVE_ADJOINT cut_flow_adjoint with checkpoints every ckpt_every
+ *                       steps (stage storage of one checkpoint block).
+ * Work areas only grow; a reservation also covers every smaller nsets / nops.
+ * The shape is remembered: cut_graph_set_tiling and cut_graph_autotune
+ * re-size the work areas for every shape reserved so far.  Growing
+ * synchronises the device and moves the work area (captured flow step graphs
+ * are then re-made).  Errors: CUT_E_INVAL (null handle, unknown flag, shape
+ * out of range, CUT_RESERVE_ADJOINT with ckpt_every < 1), CUT_E_NOMEM,
+ * CUT_E_DEVICE.
+ * cut_graph_reserved_bytes: total bytes of the handle's work areas. */
+#define CUT_RESERVE_APPLY 1u
+#define CUT_RESERVE_FLOW 2u
+#define CUT_RESERVE_DERIV 4u
+#define CUT_RESERVE_ADJOINT 8u
+cut_status cut_graph_reserve(cut_graph_t g, int64_t nsets, int64_t nops, int64_t ckpt_every, uint32_t what);
+cut_status cut_graph_reserved_bytes(cut_graph_t g, int64_t* bytes);
+
 /* ------------------------------------------------------------------ apply --
  * cut_graph_apply: forward graph action (Eq. graph-actions; L(h)x of Sec. 2.4)
  *   y[k][op*nsets+s] (=|+=) sum_{e in E(k)} c_e * eta[i_e][s] * x[j_e][op*nsets+s]
@@ -179,7 +224,9 @@ void cut_graph_free(cut_graph_t g);
  * generator rows for CUT_GRAPH_GEN (whose inputs are both operator rows), outside
  * rows for CUT_GRAPH_OUTSIDE (CUT_E_INVAL if the bundle has no outside-space
  * records).  Pauli-boson graphs have twice as many rows as labels (real-split,
- * see cut_graph_labels). */
+ * see cut_graph_labels).  Chunked and tiled forward passes over E_L keep
+ * partial rows in the work area reserved with CUT_RESERVE_APPLY (CUT_E_INVAL
+ * when it was not reserved for this shape). */
 cut_status cut_graph_apply(cut_graph_t g, int32_t which, int32_t precision, int64_t nsets,
                            int64_t nops, const void* eta, int64_t lde, const void* x,
                            int64_t ldx, double* y, int64_t ldy, uint32_t flags, void* stream);
@@ -202,7 +249,8 @@ cut_status cut_graph_apply_adjoint(cut_graph_t g, int32_t which, int32_t precisi
  * h has the operator rows, eta the generator rows), for CUT_GEN_WEGNER_GRAPH
  * (eta_k = s_g sum_{E_eta(k)} c (Dh)_i ((I-D)h)_j, s_g = +1 for E_pq and
  * Pauli-boson labels, -1 for Majorana strings, whose generator basis is
- * i*Gamma) or CUT_GEN_G2 (Majorana only; eta = 0 on diagonal strings).
+ * i*Gamma), CUT_GEN_G2 or CUT_GEN_G1 (Majorana only; eta = 0 on diagonal
+ * strings).
  * cut_generator_vjp: g_h[r][s] += sum_S gbar[S][s] d eta_S / d h_r. */
 cut_status cut_generator(cut_graph_t g, int32_t kind, double delta, int64_t nsets,
                          const double* h, int64_t ldh, double* eta, int64_t lde, void* stream);
@@ -220,8 +268,9 @@ cut_status cut_generator_vjp(cut_graph_t g, int32_t kind, double delta, int64_t 
  * cut_generator.
  *
  * cut_generator_jvp: deta[r][s] = sum_q (d eta_r / d h_q) dh[q][s] (double,
- * FP64 arithmetic): the quotient rule for CUT_GEN_G2, the product rule over the
- * E_eta records for CUT_GEN_WEGNER_GRAPH.  Errors as cut_generator. */
+ * FP64 arithmetic): the quotient rule for CUT_GEN_G2 and CUT_GEN_G1 (d|eps|/d eps
+ * = sign(eps), 0 at eps = 0), the product rule over the E_eta records for
+ * CUT_GEN_WEGNER_GRAPH.  Errors as cut_generator. */
 cut_status cut_generator_jvp(cut_graph_t g, int32_t kind, double delta, int64_t nsets,
                              const double* h, int64_t ldh, const double* dh, int64_t lddh,
                              double* deta, int64_t ldde, void* stream);
@@ -236,9 +285,9 @@ cut_status cut_generator_jvp(cut_graph_t g, int32_t kind, double delta, int64_t 
  * its derivative are FP64; the graph passes use `precision` (for the float
  * modes eta, eta'(h) dh, x and dx are rounded to float once).  Outputs are
  * overwritten and must not alias an input.  Uses the forward tiling of
- * cut_graph_set_tiling and a work area kept in the handle (grown on demand,
- * synchronising).  Errors: CUT_E_INVAL, CUT_E_UNSUPPORTED (G2 without a
- * pair-flip registry), CUT_E_NOMEM, CUT_E_DEVICE. */
+ * cut_graph_set_tiling and the work area reserved with CUT_RESERVE_DERIV.
+ * Errors: CUT_E_INVAL (also a shape that was not reserved), CUT_E_UNSUPPORTED
+ * (G2 without a pair-flip registry), CUT_E_DEVICE. */
 cut_status cut_graph_jvp(cut_graph_t g, int32_t kind, double delta, int32_t precision, int64_t nsets,
                          int64_t nops, const double* h, int64_t ldh, const double* dh, int64_t lddh,
                          const double* x, int64_t ldx, const double* dx, int64_t lddx, double* y,
@@ -285,7 +334,8 @@ cut_status cut_assemble(const double* X, int64_t ldx, int64_t N, int64_t S, cons
 #define CUT_FLOW_HIPGRAPH 1u
 #define CUT_FLOW_TIME_PASSES 2u  /* without CUT_FLOW_HIPGRAPH: bracket every graph
                                     pass and generator launch with HIP events on
-                                    the launch stream (see cut_flow_last_timing) */
+                                    the launch stream (see cut_flow_last_timing);
+                                    the call then synchronises to read them */
 
 typedef struct {
     int32_t generator;      /* cut_generator_kind */
@@ -298,6 +348,12 @@ typedef struct {
     int64_t step_end;       /* one past the last step; < 0 = max(n_steps) */
     double* outside_norm2;  /* NULL, or device [nops*nsets] doubles: outside-space
                                diagnostic, see cut_flow_integrate */
+    int32_t* nonfinite;     /* NULL: the call synchronises `stream` at its end and
+                               returns CUT_E_NUMERIC if the result holds a
+                               non-finite value.  Otherwise a device int32 that
+                               the call sets to 0 at its start and to 1 if the
+                               result holds a non-finite value; the call then
+                               returns without synchronising. */
 } cut_flow_params;
 
 /* cut_flow_integrate: advances z in place over global steps [step_begin,
@@ -311,9 +367,10 @@ typedef struct {
  * C the outside-space action with the stage generator, in the pass precision;
  * sums of squares in FP64, fixed order): the RK4 quadrature of the integral of
  * |C_X|^2 over the flow.  The flowed z is bitwise the same with or without it.
- * Errors: CUT_E_INVAL (also outside_norm2 without E_C), CUT_E_UNSUPPORTED (G2
- * on a non-Majorana graph), CUT_E_DEVICE, CUT_E_NOMEM, CUT_E_NUMERIC (non-finite
- * z after the flow). */
+ * The work area must be reserved (CUT_RESERVE_FLOW) for (nsets, nops).
+ * Errors: CUT_E_INVAL (also outside_norm2 without E_C, or a shape that was not
+ * reserved), CUT_E_UNSUPPORTED (G2 on a non-Majorana graph), CUT_E_DEVICE,
+ * CUT_E_NUMERIC (non-finite z after the flow, when nonfinite is NULL). */
 cut_status cut_flow_integrate(cut_graph_t g, const cut_flow_params* p, int64_t nsets,
                               int64_t nops, const int32_t* n_steps, double* z, double* ckpt,
                               void* stream);
@@ -325,7 +382,9 @@ cut_status cut_flow_integrate(cut_graph_t g, const cut_flow_params* p, int64_t n
  * loaded with CUT_LOAD_ADJOINT.  lambda (device, layout of z): in dL/dz at the
  * end of the flow, out dL/dz at step 0.  Each checkpoint block is recomputed
  * forward in FP64 with its stage states kept; all adjoint passes are FP64.
- * outside_norm2 is ignored. */
+ * outside_norm2 is ignored; nonfinite as in cut_flow_integrate (checks lambda).
+ * The work area must be reserved with CUT_RESERVE_ADJOINT for (nsets, nops,
+ * ckpt_every). */
 cut_status cut_flow_adjoint(cut_graph_t g, const cut_flow_params* p, int64_t nsets,
                             int64_t nops, const int32_t* n_steps, const double* ckpt,
                             double* lambda, void* stream);
@@ -359,8 +418,9 @@ cut_status cut_flow_adjoint(cut_graph_t g, const cut_flow_params* p, int64_t nse
  * three modes tau with the target; the 4-subsets containing tau are both the
  * targets and the quartic operands of those records, so they are staged in LDS
  * once per tile and each target's four tile sums are added in fixed order.
- * The chunked and tile forms need a work area of partial rows, grown on first
- * use.  Rebuilds the task lists of every loaded copy; synchronises the device.
+ * The chunked and tile forms need a work area of partial rows: the work areas
+ * are re-sized for every shape reserved so far (cut_graph_reserve).  Rebuilds
+ * the task lists of every loaded copy; synchronises the device.
  * Errors: CUT_E_INVAL (null handle, a length < 1, unknown flag), CUT_E_DEVICE. */
 #define CUT_TILE_XCD_REMAP 1u
 #define CUT_TILE_TRIPLES 2u

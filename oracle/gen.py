@@ -16,6 +16,9 @@ Test infrastructure (see the package docstring).  h and eta are [N, nsets].
   and eta = 0 on block-diagonal strings.  N is the Wegner generator of the
   quadratic diagonal part H_0 = sum_a eps_a Gamma_{P_a}; Q_S is the diagonal of
   ad_{H_0}^2 in the orthonormal string basis, regularised by delta^2.
+* g1: the literal reading of a White-type generator from the diagonal pair
+  energies, eta_S = h_S / D_S with D_S = 2 sum_{a in F(S)} |eps_a| + delta
+  (delta >= 0 regularises D_S = 0), eta = 0 on block-diagonal strings.
 """
 from __future__ import annotations
 
@@ -134,12 +137,46 @@ class G2:
         return gh
 
 
+class G1:
+    """eta_S = h_S / (2 sum_{a in F(S)} |h_{P_a}| + delta) on off-diagonal S.
+
+    F(S) = pairs a = (2a, 2a+1) that S holds exactly one mode of; stored as a
+    0/1 matrix flips[S, a]."""
+
+    def __init__(self, m: int, delta: float):
+        reg = MajoranaRegistry(m)
+        self.reg = reg
+        self.delta = float(delta)
+        self.flips = np.stack([_popcount(reg.masks & pm) == 1 for pm in reg.pair_masks], axis=1).astype(float)
+        self.off = ~reg.diag
+
+    def _d(self, h):
+        return 2.0 * self.flips @ np.abs(h[self.reg.pairs]) + self.delta
+
+    def __call__(self, h: np.ndarray) -> np.ndarray:
+        return np.where(self.off[:, None], h / self._d(h), 0.0)
+
+    def jvp(self, h: np.ndarray, dh: np.ndarray) -> np.ndarray:
+        """d eta_S = dh_S / D_S - h_S dD_S / D_S^2, dD_S = 2 sum_{a in F(S)} sign(eps_a) d eps_a."""
+        D = self._d(h)
+        dD = 2.0 * self.flips @ (np.sign(h[self.reg.pairs]) * dh[self.reg.pairs])
+        return np.where(self.off[:, None], dh / D - h * dD / (D * D), 0.0)
+
+    def vjp(self, h: np.ndarray, gbar: np.ndarray) -> np.ndarray:
+        D = self._d(h)
+        gb = np.where(self.off[:, None], gbar, 0.0)
+        gh = gb / D
+        geps = -2.0 * np.sign(h[self.reg.pairs]) * (self.flips.T @ (gb * h / (D * D)))
+        np.add.at(gh, self.reg.pairs, geps)
+        return gh
+
+
 def make_generator(g: Graph, kind: str, delta: float = 0.5):
     """Returns (eta(h), vjp(h, gbar)) for the named generator."""
     if kind == "wegner_graph":
         return (lambda h: wegner_graph(g, h)), (lambda h, gb: wegner_graph_vjp(g, h, gb))
-    if kind == "g2":
-        gen = G2(g.size, delta)
+    if kind in ("g2", "g1"):
+        gen = (G2 if kind == "g2" else G1)(g.size, delta)
         return gen, gen.vjp
     raise ValueError(kind)
 
@@ -148,6 +185,6 @@ def make_generator_jvp(g: Graph, kind: str, delta: float = 0.5):
     """Returns jvp(h, dh) = eta'(h) dh for the named generator."""
     if kind == "wegner_graph":
         return lambda h, dh: wegner_graph_jvp(g, h, dh)
-    if kind == "g2":
-        return G2(g.size, delta).jvp
+    if kind in ("g2", "g1"):
+        return (G2 if kind == "g2" else G1)(g.size, delta).jvp
     raise ValueError(kind)

@@ -13,11 +13,14 @@
  *   g2         eta_S = N_S / Q_S with N_S = -sum_t c_t eps_{a_t} h_{p_t},
  *              Q_S = 4 sum_t eps_{a_t}^2 + delta^2 (stencil rows t of S)
  *   wegner     eta_k = sgn * sum_{e in E_eta(k)} c_e h_{i_e} h_{j_e}
+ *   g1         eta_S = h_S / (2 sum_t |eps_{a_t}| + delta) over the stencil
+ *              rows t of S (the pairs S flips); 0 on strings without any
  *   flow       classic RK4, fixed ds, set b frozen after n_b steps
  *   flow_adj   exact adjoint of the discrete RK4 map, checkpoint recompute
  */
 #include <stdint.h>
 #include <stdlib.h>
+#include <math.h>
 #include <string.h>
 
 /* ---------------------------------------------------------------- records --
@@ -84,7 +87,7 @@ int orc_maj_records(int m, int64_t N, const uint64_t* masks, const uint64_t* sor
 typedef struct {
     int64_t N, nops, nsets;
     const int64_t* off; const int32_t* ri; const int32_t* rj; const double* rc;
-    /* generator: kind 0 = G2 stencil, 1 = Wegner graph over E_eta */
+    /* generator: kind 0 = G2 stencil, 1 = Wegner graph over E_eta, 2 = G1 (stencil pairs) */
     int kind;
     const int64_t* st_off; const int32_t* st_a; const int32_t* st_p; const double* st_c;
     const int32_t* pairs; double delta;
@@ -150,6 +153,14 @@ static void gen_eta(const orc_graph* g, const double* z, double* eta) {
                 eta[S * ns + s] = (g->st_off[S + 1] > g->st_off[S]) ? num / (q + g->delta * g->delta)
                                                                    : 0.0;
             }
+    } else if (g->kind == 2) {
+#pragma omp parallel for
+        for (int64_t S = 0; S < g->N; ++S)
+            for (int64_t s = 0; s < ns; ++s) {
+                double d = g->delta;
+                for (int64_t t = g->st_off[S]; t < g->st_off[S + 1]; ++t) d += 2.0 * fabs(H(g->pairs[g->st_a[t]], s));
+                eta[S * ns + s] = (g->st_off[S + 1] > g->st_off[S]) ? H(S, s) / d : 0.0;
+            }
     } else {
 #pragma omp parallel for
         for (int64_t k = 0; k < g->N; ++k)
@@ -186,6 +197,19 @@ static void gen_vjp(const orc_graph* g, const double* z, const double* gbar, dou
                     gh[(int64_t)g->st_p[t] * ns + s] += gb * (-g->st_c[t] * eps / q);
                     gh[pa * ns + s] += gb * (-g->st_c[t] * H(g->st_p[t], s) / q -
                                              num * 8.0 * eps / (q * q));
+                }
+            }
+        } else if (g->kind == 2) {
+            for (int64_t S = 0; S < g->N; ++S) {
+                if (g->st_off[S + 1] == g->st_off[S]) continue;
+                double d = g->delta;
+                for (int64_t t = g->st_off[S]; t < g->st_off[S + 1]; ++t) d += 2.0 * fabs(H(g->pairs[g->st_a[t]], s));
+                const double gb = gbar[S * ns + s];
+                gh[S * ns + s] += gb / d;
+                for (int64_t t = g->st_off[S]; t < g->st_off[S + 1]; ++t) {
+                    const int64_t pa = g->pairs[g->st_a[t]];
+                    const double e = H(pa, s);
+                    gh[pa * ns + s] += -2.0 * (e > 0.0 ? 1.0 : e < 0.0 ? -1.0 : 0.0) * gb * H(S, s) / (d * d);
                 }
             }
         } else {

@@ -4,6 +4,12 @@ Every function has the name of the C entry point it calls (include/cutgraph.h)
 and takes torch device tensors where the C function takes device pointers.
 No arithmetic of the method happens here, and there is no fallback: if the
 HIP library is missing, importing this module raises.
+
+Work areas: the C computing entry points never allocate; a shape must be
+reserved first (cut_graph_reserve).  For convenience the wrappers of those
+entry points call cut_graph_reserve for their shape before the call (a no-op
+once the shape is reserved) unless ``reserve=False`` is passed, which gives the
+C behaviour unchanged (CUT_E_INVAL for a shape that was not reserved).
 """
 from __future__ import annotations
 
@@ -32,13 +38,14 @@ CUT_ALG_EPQ, CUT_ALG_MAJORANA, CUT_ALG_PAULI_BOSON = 1, 2, 3
 CUT_GRAPH_FLOW, CUT_GRAPH_GEN, CUT_GRAPH_OUTSIDE = 0, 1, 2
 CUT_BUILD_OUTSIDE = 1
 CUT_F64, CUT_F32C, CUT_F32X, CUT_F32 = 0, 1, 2, 3
-CUT_GEN_WEGNER_GRAPH, CUT_GEN_G2 = 1, 2
+CUT_GEN_WEGNER_GRAPH, CUT_GEN_G2, CUT_GEN_G1 = 1, 2, 3
 CUT_ACCUMULATE = 1
 CUT_LOAD_ADJOINT, CUT_LOAD_NO_CHECKSUM = 1, 2
 CUT_FLOW_HIPGRAPH = 1
 CUT_FLOW_TIME_PASSES = 2
 CUT_TILE_XCD_REMAP, CUT_TILE_TRIPLES, CUT_TILE_NO_CHUNKS, CUT_TILE_TRIPLE_CHUNKS = 1, 2, 4, 8
 CUT_TILE_QUAD_BLOCKS = 16
+CUT_RESERVE_APPLY, CUT_RESERVE_FLOW, CUT_RESERVE_DERIV, CUT_RESERVE_ADJOINT = 1, 2, 4, 8
 
 STATUS_NAMES = {0: "CUT_OK", 1: "CUT_E_INVAL", 2: "CUT_E_IO", 3: "CUT_E_FORMAT",
                 4: "CUT_E_CHECKSUM", 5: "CUT_E_NOMEM", 6: "CUT_E_DEVICE", 7: "CUT_E_NUMERIC",
@@ -49,7 +56,8 @@ EXPORTS = ["cut_graph_build", "cut_graph_load", "cut_graph_info", "cut_graph_fre
            "cut_graph_apply", "cut_graph_apply_adjoint", "cut_generator", "cut_generator_vjp",
            "cut_generator_jvp", "cut_graph_jvp", "cut_graph_vjp", "cut_assemble", "cut_graph_labels",
            "cut_flow_integrate", "cut_flow_adjoint", "cut_graph_set_tiling", "cut_graph_autotune",
-           "cut_flow_last_timing", "cut_last_error", "cut_version"]
+           "cut_flow_last_timing", "cut_graph_reserve", "cut_graph_reserved_bytes", "cut_last_error",
+           "cut_version"]
 
 
 class CutError(RuntimeError):
@@ -73,7 +81,8 @@ class cut_graph_desc(C.Structure):
 class cut_flow_params(C.Structure):
     _fields_ = [("generator", C.c_int32), ("precision", C.c_int32), ("ds", C.c_double),
                 ("delta", C.c_double), ("ckpt_every", C.c_int32), ("flags", C.c_uint32),
-                ("step_begin", C.c_int64), ("step_end", C.c_int64), ("outside_norm2", C.c_void_p)]
+                ("step_begin", C.c_int64), ("step_end", C.c_int64), ("outside_norm2", C.c_void_p),
+                ("nonfinite", C.c_void_p)]
 
 
 _vp, _i32, _i64, _u32, _dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_uint32, C.c_double
@@ -98,6 +107,8 @@ _L.cut_flow_integrate.argtypes = [_vp, C.POINTER(cut_flow_params), _i64, _i64, C
                                   _vp]
 _L.cut_flow_adjoint.argtypes = [_vp, C.POINTER(cut_flow_params), _i64, _i64, C.POINTER(_i32), _vp, _vp, _vp]
 _L.cut_graph_set_tiling.argtypes = [_vp, _i64, _i64, _u32]
+_L.cut_graph_reserve.argtypes = [_vp, _i64, _i64, _i64, _u32]
+_L.cut_graph_reserved_bytes.argtypes = [_vp, C.POINTER(_i64)]
 
 
 class cut_flow_timing(C.Structure):
@@ -201,10 +212,24 @@ def cut_graph_set_tiling(g: int, long_records: int, chunk_records: int, flags: i
     _check(_L.cut_graph_set_tiling(g, long_records, chunk_records, flags))
 
 
+# ------------------------------------------------------------- work areas --
+def cut_graph_reserve(g: int, nsets: int, nops: int, ckpt_every: int = 0, what: int = CUT_RESERVE_APPLY) -> None:
+    """Sizes the handle's work areas for calls of this shape (CUT_RESERVE_* flags)."""
+    _check(_L.cut_graph_reserve(g, nsets, nops, ckpt_every, what))
+
+
+def cut_graph_reserved_bytes(g: int) -> int:
+    b = _i64()
+    _check(_L.cut_graph_reserved_bytes(g, C.byref(b)))
+    return b.value
+
+
 # ------------------------------------------------------------------ apply --
 def cut_graph_apply(g: int, which: int, precision: int, nsets: int, nops: int, eta, x, y,
-                    flags: int = 0, stream=None) -> None:
+                    flags: int = 0, stream=None, reserve: bool = True) -> None:
     """y[k, op*nsets+s] (=|+=) sum_e c eta[i, s] x[j, op*nsets+s]; 2-D row-major tensors."""
+    if reserve:
+        cut_graph_reserve(g, nsets, nops, 0, CUT_RESERVE_APPLY)
     _check(_L.cut_graph_apply(g, which, precision, nsets, nops, _ptr(eta), _ld(eta, nsets), _ptr(x),
                               _ld(x, nops * nsets), _ptr(y), _ld(y, nops * nsets), flags,
                               _stream(stream)))
@@ -223,7 +248,10 @@ def cut_generator(g: int, kind: int, delta: float, nsets: int, h, eta, stream=No
                             _stream(stream)))
 
 
-def cut_generator_vjp(g: int, kind: int, delta: float, nsets: int, h, gbar, g_h, stream=None) -> None:
+def cut_generator_vjp(g: int, kind: int, delta: float, nsets: int, h, gbar, g_h, stream=None,
+                      reserve: bool = True) -> None:
+    if reserve:
+        cut_graph_reserve(g, nsets, 1, 0, CUT_RESERVE_APPLY)
     _check(_L.cut_generator_vjp(g, kind, delta, nsets, _ptr(h), _ld(h, nsets), _ptr(gbar),
                                 _ld(gbar, nsets), _ptr(g_h), _ld(g_h, nsets), _stream(stream)))
 
@@ -235,9 +263,11 @@ def cut_generator_jvp(g: int, kind: int, delta: float, nsets: int, h, dh, deta, 
 
 
 def cut_graph_jvp(g: int, kind: int, delta: float, precision: int, nsets: int, nops: int, h, dh, x, dx,
-                  y, dy, stream=None) -> None:
+                  y, dy, stream=None, reserve: bool = True) -> None:
     """dy = apply(eta'(h) dh, x) + apply(eta(h), dx); y = apply(eta(h), x) when given.
     dh, dx, x and y may be None as the C function allows."""
+    if reserve:
+        cut_graph_reserve(g, nsets, nops, 0, CUT_RESERVE_DERIV)
     cols = nops * nsets
     _check(_L.cut_graph_jvp(g, kind, delta, precision, nsets, nops, _ptr(h), _ld(h, nsets), _ptr(dh),
                             _ld(dh, nsets), _ptr(x), _ld(x, cols), _ptr(dx), _ld(dx, cols), _ptr(y),
@@ -245,8 +275,10 @@ def cut_graph_jvp(g: int, kind: int, delta: float, precision: int, nsets: int, n
 
 
 def cut_graph_vjp(g: int, kind: int, delta: float, precision: int, nsets: int, nops: int, h, x, w,
-                  g_h, g_x, flags: int = 0, stream=None) -> None:
+                  g_h, g_x, flags: int = 0, stream=None, reserve: bool = True) -> None:
     """g_x (=|+=) L(eta(h))^T w; g_h (=|+=) eta'(h)^T geta(w, x); either output may be None."""
+    if reserve:
+        cut_graph_reserve(g, nsets, nops, 0, CUT_RESERVE_DERIV)
     cols = nops * nsets
     _check(_L.cut_graph_vjp(g, kind, delta, precision, nsets, nops, _ptr(h), _ld(h, nsets), _ptr(x),
                             _ld(x, cols), _ptr(w), _ld(w, cols), _ptr(g_h), _ld(g_h, nsets), _ptr(g_x),
@@ -264,11 +296,15 @@ def cut_assemble(X, W, Y, flags: int = 0, stream=None) -> None:
 
 # ------------------------------------------------------------------- flow --
 def flow_params(generator: int, precision: int, ds: float, delta: float = 0.5, ckpt_every: int = 0,
-                flags: int = CUT_FLOW_HIPGRAPH, step_begin: int = 0, step_end: int = -1, outside_norm2=None):
+                flags: int = CUT_FLOW_HIPGRAPH, step_begin: int = 0, step_end: int = -1, outside_norm2=None,
+                nonfinite=None):
     """outside_norm2: None, or a device float64 tensor of nops*nsets elements that
-    the flow accumulates the outside-space diagnostic into."""
+    the flow accumulates the outside-space diagnostic into.  nonfinite: None (the
+    call synchronises and raises CUT_E_NUMERIC on a non-finite result) or a
+    device int32 tensor the call sets to 1 on a non-finite result, without
+    synchronising."""
     return cut_flow_params(generator, precision, ds, delta, ckpt_every, flags, step_begin, step_end,
-                           _ptr(outside_norm2))
+                           _ptr(outside_norm2), _ptr(nonfinite))
 
 
 def _steps_arg(n_steps):
@@ -277,8 +313,10 @@ def _steps_arg(n_steps):
 
 
 def cut_flow_integrate(g: int, params: cut_flow_params, nsets: int, nops: int, n_steps, z, ckpt=None,
-                       stream=None) -> None:
+                       stream=None, reserve: bool = True) -> None:
     """z: device float64 [N, nops, nsets] contiguous, advanced in place."""
+    if reserve:
+        cut_graph_reserve(g, nsets, nops, 0, CUT_RESERVE_FLOW)
     _check(_L.cut_flow_integrate(g, C.byref(params), nsets, nops, _steps_arg(n_steps), _ptr(z),
                                  _ptr(ckpt), _stream(stream)))
 
@@ -296,6 +334,8 @@ def cut_flow_last_timing(g: int) -> dict:
 
 
 def cut_flow_adjoint(g: int, params: cut_flow_params, nsets: int, nops: int, n_steps, ckpt, lam,
-                     stream=None) -> None:
+                     stream=None, reserve: bool = True) -> None:
+    if reserve:
+        cut_graph_reserve(g, nsets, nops, params.ckpt_every, CUT_RESERVE_ADJOINT)
     _check(_L.cut_flow_adjoint(g, C.byref(params), nsets, nops, _steps_arg(n_steps), _ptr(ckpt),
                                _ptr(lam), _stream(stream)))

@@ -38,6 +38,8 @@ void eval_generator(Graph& g, int kind, double delta, int32_t nsets, const doubl
                     int64_t lde, bool eta_f32, const int32_t* nsteps, const int32_t* step, hipStream_t s) {
     if (kind == CUT_GEN_G2) {
         launch_g2(g, delta, nsets, h, ldh, eta, lde, eta_f32, nsteps, step, s);
+    } else if (kind == CUT_GEN_G1) {
+        launch_g1(g, delta, nsets, h, ldh, eta, lde, eta_f32, nsteps, step, s);
     } else {
         PassArgs p{};
         p.csr = &g.csr[1][0];
@@ -58,9 +60,9 @@ void eval_generator(Graph& g, int kind, double delta, int32_t nsets, const doubl
 }
 
 void check_generator(const Graph& g, int kind) {
-    if (kind == CUT_GEN_G2) {
+    if (stencil_generator(kind)) {
         if (g.hdr.algebra != CUT_ALG_MAJORANA || !g.have_stencil)
-            CUT_FAIL(CUT_E_UNSUPPORTED, "G2 generator needs a pair-flip registry (Majorana strings)");
+            CUT_FAIL(CUT_E_UNSUPPORTED, "G1 / G2 generators need a pair-flip registry (Majorana strings)");
     } else if (kind != CUT_GEN_WEGNER_GRAPH) {
         CUT_FAIL(CUT_E_INVAL, "unknown generator %d", kind);
     }
@@ -73,6 +75,10 @@ void eval_generator_vjp(Graph& g, int kind, double delta, int32_t nsets, const d
                         hipStream_t s) {
     if (kind == CUT_GEN_G2) {
         launch_g2_vjp(g, delta, nsets, h, ldh, gbar, ldg, g_h, ldgh, tmp, s);
+        return;
+    }
+    if (kind == CUT_GEN_G1) {
+        launch_g1_vjp(g, delta, nsets, h, ldh, gbar, ldg, g_h, ldgh, tmp, s);
         return;
     }
     if (!g.have_adjoint) CUT_FAIL(CUT_E_INVAL, "generator VJP needs a graph loaded with CUT_LOAD_ADJOINT");
@@ -104,11 +110,13 @@ void eval_generator_vjp(Graph& g, int kind, double delta, int32_t nsets, const d
 
 using namespace cut;
 
-extern "C" cut_status cut_graph_apply(cut_graph_t h, int32_t which, int32_t precision, int64_t nsets,
-                                      int64_t nops, const void* eta, int64_t lde, const void* x, int64_t ldx,
-                                      double* y, int64_t ldy, uint32_t flags, void* stream) {
-    ABI_BEGIN
-    Graph& g = checked(h);
+namespace cut {
+
+// Validates the arguments of a forward action and returns its pass arguments;
+// *part_bytes receives the partial-row bytes its forward pass needs (0: none).
+PassArgs apply_args(Graph& g, int32_t which, int32_t precision, int64_t nsets, int64_t nops, const void* eta,
+                    int64_t lde, const void* x, int64_t ldx, double* y, int64_t ldy, uint32_t flags,
+                    size_t* part_bytes) {
     if (which != CUT_GRAPH_FLOW && which != CUT_GRAPH_GEN && which != CUT_GRAPH_OUTSIDE)
         CUT_FAIL(CUT_E_INVAL, "unknown record set %d", which);
     if (which == CUT_GRAPH_OUTSIDE && !g.have_outside)
@@ -118,7 +126,6 @@ extern "C" cut_status cut_graph_apply(cut_graph_t h, int32_t which, int32_t prec
     if (!eta || !x || !y) CUT_FAIL(CUT_E_INVAL, "cut_graph_apply: null operand");
     if (lde < nsets || ldx < nops * nsets || ldy < nops * nsets)
         CUT_FAIL(CUT_E_INVAL, "cut_graph_apply: leading dimension too small");
-    DeviceGuard dg(g.device);
     PassArgs p{};
     p.csr = &g.csr[which][0];
     p.A = eta;
@@ -132,9 +139,21 @@ extern "C" cut_status cut_graph_apply(cut_graph_t h, int32_t which, int32_t prec
     p.ldy = ldy;
     p.accumulate = (flags & CUT_ACCUMULATE) ? 1 : 0;
     p.scale = 1.0;
-    double* part = nullptr;
-    const size_t pb = which == CUT_GRAPH_FLOW ? forward_partial_bytes(g, p.nsets, p.nops, precision) : 0;
-    if (pb) part = (double*)g.ws_part.get(pb);
+    *part_bytes = which == CUT_GRAPH_FLOW ? forward_partial_bytes(g, p.nsets, p.nops, precision) : 0;
+    return p;
+}
+
+}  // namespace cut
+
+extern "C" cut_status cut_graph_apply(cut_graph_t h, int32_t which, int32_t precision, int64_t nsets,
+                                      int64_t nops, const void* eta, int64_t lde, const void* x, int64_t ldx,
+                                      double* y, int64_t ldy, uint32_t flags, void* stream) {
+    ABI_BEGIN
+    Graph& g = checked(h);
+    size_t pb = 0;
+    const PassArgs p = apply_args(g, which, precision, nsets, nops, eta, lde, x, ldx, y, ldy, flags, &pb);
+    DeviceGuard dg(g.device);
+    double* part = pb ? (double*)g.ws_part.need(pb, "cut_graph_apply (partial rows)") : nullptr;
     launch_forward(g, EPI_Y, p, part, (hipStream_t)stream);
     HIP_CHECK(hipGetLastError());
     ABI_END
@@ -210,7 +229,8 @@ extern "C" cut_status cut_generator_vjp(cut_graph_t h, int32_t kind, double delt
     if (!hh || !gbar || !g_h || ldh < nsets || ldg < nsets || ldgh < nsets)
         CUT_FAIL(CUT_E_INVAL, "cut_generator_vjp: bad operand");
     DeviceGuard dg(g.device);
-    double* tmp = kind == CUT_GEN_G2 ? (double*)g.ws_small.get(sizeof(double) * 2 * g.N * nsets) : nullptr;
+    double* tmp = stencil_generator(kind) ? (double*)g.ws_small.need(sizeof(double) * 2 * g.N * nsets, "cut_generator_vjp")
+                                     : nullptr;
     eval_generator_vjp(g, kind, delta, (int32_t)nsets, hh, ldh, gbar, ldg, g_h, ldgh, tmp, (hipStream_t)stream);
     HIP_CHECK(hipGetLastError());
     ABI_END

@@ -17,6 +17,10 @@ void eval_generator_jvp(Graph& g, int kind, double delta, int32_t nsets, const d
         launch_g2_jvp(g, delta, nsets, h, ldh, dh, lddh, deta, ldde, s);
         return;
     }
+    if (kind == CUT_GEN_G1) {
+        launch_g1_jvp(g, delta, nsets, h, ldh, dh, lddh, deta, ldde, s);
+        return;
+    }
     // eta_k = s_g sum_{E_eta(k)} c h_i h_j with i block-diagonal and j not (the
     // only records with a nonzero bracket), so by the product rule
     // deta_k = s_g sum c (dh_i h_j + h_i dh_j): two passes over the same records
@@ -58,7 +62,47 @@ struct Carve {
     }
 };
 
+// work area of cut_graph_jvp: eta, deta (FP64), their float shadows, float x / dx
+struct JvpLayout {
+    Carve cv;
+    size_t eta, deta, deta32, x32, dx32;
+    JvpLayout(const Graph& g, int64_t nsets, int64_t nops, int precision, bool dh, bool dx, bool need_x) {
+        const bool f32 = precision != CUT_F64;
+        const size_t tb = f32 ? 4 : 8;
+        const int64_t N = g.N, NG = g.NG, cols = nops * nsets;
+        eta = cv.add(NG * nsets * tb);
+        deta = cv.add(dh ? NG * nsets * 8 : 0);
+        deta32 = cv.add(dh && f32 ? NG * nsets * 4 : 0);
+        x32 = cv.add(need_x && f32 ? N * cols * 4 : 0);
+        dx32 = cv.add(dx && f32 ? N * cols * 4 : 0);
+    }
+};
+
+// work area of cut_graph_vjp: eta, float w / x, geta, generator-VJP scratch
+struct VjpLayout {
+    Carve cv;
+    size_t eta, w32, x32, geta, tmp;
+    VjpLayout(const Graph& g, int64_t nsets, int64_t nops, int precision, bool gx, bool gh, bool g2) {
+        const bool f32 = precision != CUT_F64;
+        const int64_t N = g.N, NG = g.NG, cols = nops * nsets;
+        eta = cv.add(gx ? NG * nsets * (f32 ? 4 : 8) : 0);
+        w32 = cv.add(f32 ? N * cols * 4 : 0);
+        x32 = cv.add(gh && f32 ? N * cols * 4 : 0);
+        geta = cv.add(gh ? NG * nsets * 8 : 0);
+        tmp = cv.add(gh && g2 ? 2 * N * nsets * 8 : 0);
+    }
+};
+
 }  // namespace
+
+size_t jvp_ws_bytes(const Graph& g, int64_t nsets, int64_t nops, int prec) {
+    return JvpLayout(g, nsets, nops, prec, true, true, true).cv.total;
+}
+
+size_t vjp_ws_bytes(const Graph& g, int64_t nsets, int64_t nops, int prec) {
+    return VjpLayout(g, nsets, nops, prec, true, true, true).cv.total;
+}
+
 }  // namespace cut
 
 using namespace cut;
@@ -101,17 +145,14 @@ extern "C" cut_status cut_graph_jvp(cut_graph_t hd, int32_t kind, double delta, 
     const size_t tb = f32 ? 4 : 8;
     const int64_t N = g.N;
     const bool need_x = dh || y;
-    Carve cv;
+    const JvpLayout lay(g, nsets, nops, precision, dh != nullptr, dx != nullptr, need_x);
+    const Carve& cv = lay.cv;
     const int64_t NG = g.NG;
-    const size_t i_eta = cv.add(NG * nsets * tb);
-    const size_t i_deta = cv.add(dh ? NG * nsets * 8 : 0);
-    const size_t i_deta32 = cv.add(dh && f32 ? NG * nsets * 4 : 0);
-    const size_t i_x32 = cv.add(need_x && f32 ? N * cols * 4 : 0);
-    const size_t i_dx32 = cv.add(dx && f32 ? N * cols * 4 : 0);
-    char* base = (char*)g.ws_deriv.get(cv.total);
+    const size_t i_eta = lay.eta, i_deta = lay.deta, i_deta32 = lay.deta32, i_x32 = lay.x32, i_dx32 = lay.dx32;
+    char* base = (char*)g.ws_deriv.need(cv.total, "cut_graph_jvp");
     auto at = [&](size_t i) { return (void*)(base + cv.offs[i]); };
     const size_t pb = forward_partial_bytes(g, (int32_t)nsets, (int32_t)nops, precision);
-    double* part = pb ? (double*)g.ws_part.get(pb) : nullptr;
+    double* part = pb ? (double*)g.ws_part.need(pb, "cut_graph_jvp (partial rows)") : nullptr;
 
     // eta(h) in the pass precision (rounded once for the float modes)
     void* eta = at(i_eta);
@@ -201,14 +242,11 @@ extern "C" cut_status cut_graph_vjp(cut_graph_t hd, int32_t kind, double delta, 
     const bool f32 = precision != CUT_F64;
     const bool acc = (flags & CUT_ACCUMULATE) != 0;
     const int64_t N = g.N;
-    Carve cv;
+    const VjpLayout lay(g, nsets, nops, precision, g_x != nullptr, g_h != nullptr, stencil_generator(kind));
+    const Carve& cv = lay.cv;
     const int64_t NG = g.NG;
-    const size_t i_eta = cv.add(g_x ? NG * nsets * (f32 ? 4 : 8) : 0);
-    const size_t i_w32 = cv.add(f32 ? N * cols * 4 : 0);
-    const size_t i_x32 = cv.add(g_h && f32 ? N * cols * 4 : 0);
-    const size_t i_geta = cv.add(g_h ? NG * nsets * 8 : 0);
-    const size_t i_tmp = cv.add(g_h && kind == CUT_GEN_G2 ? 2 * N * nsets * 8 : 0);
-    char* base = (char*)g.ws_deriv.get(cv.total);
+    const size_t i_eta = lay.eta, i_w32 = lay.w32, i_x32 = lay.x32, i_geta = lay.geta, i_tmp = lay.tmp;
+    char* base = (char*)g.ws_deriv.need(cv.total, "cut_graph_vjp");
     auto at = [&](size_t i) { return (void*)(base + cv.offs[i]); };
 
     const void* wo = w;
@@ -259,7 +297,7 @@ extern "C" cut_status cut_graph_vjp(cut_graph_t hd, int32_t kind, double delta, 
         launch_pass(MODE_REDOPS, EPI_Y, p, s);
         if (!acc) launch_zero2d(g_h, ldgh, N, nsets, s);
         eval_generator_vjp(g, kind, delta, (int32_t)nsets, h, ldh, geta, nsets, g_h, ldgh,
-                           kind == CUT_GEN_G2 ? (double*)at(i_tmp) : nullptr, s);
+                           stencil_generator(kind) ? (double*)at(i_tmp) : nullptr, s);
     }
     HIP_CHECK(hipGetLastError());
     ABI_END

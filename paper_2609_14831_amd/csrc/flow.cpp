@@ -6,12 +6,13 @@
 // (t < n_steps[s]) is read on the device from that counter, so the same
 // kernel sequence serves every step and is captured once as a hipGraph.
 //
-// Work area (grown on demand, kept in the handle):
+// Work area (reserved with cut_graph_reserve, kept in the handle):
 //   xsh[2]  next/current stage operand (float or double) [N][nops][nsets]
 //   acc     RK accumulator (double)                     [N][nops][nsets]
 //   hst     FP64 Hamiltonian column of the stage         [N][nsets]
 //   eta     generator in the stage precision              [N][nsets]
 //   nsteps, step, flag (int32)
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <vector>
@@ -20,10 +21,18 @@
 
 namespace cut {
 
+// Captured RK steps of one flow configuration (key), one graph per width
+// class: the sets a step launches over (0 = all of them, else the active
+// prefix length, see set_ranges).  Replays run on `stream`; captures are made
+// on `cap`, which never runs work.
 struct StepGraphCache {
-    hipGraphExec_t exec = nullptr;
-    hipGraph_t graph = nullptr;
-    hipStream_t stream = nullptr;
+    struct Cls {
+        int64_t id;
+        hipGraph_t graph;
+        hipGraphExec_t exec;
+    };
+    std::vector<Cls> cls;
+    hipStream_t stream = nullptr, cap = nullptr;
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
     std::vector<uint64_t> key;
 };
@@ -31,13 +40,45 @@ struct StepGraphCache {
 void release_step_graphs(Graph& g) {
     StepGraphCache* c = g.graphs;
     if (!c) return;
-    if (c->exec) (void)hipGraphExecDestroy(c->exec);
-    if (c->graph) (void)hipGraphDestroy(c->graph);
+    for (auto& e : c->cls) {
+        if (e.exec) (void)hipGraphExecDestroy(e.exec);
+        if (e.graph) (void)hipGraphDestroy(e.graph);
+    }
     if (c->ev_in) (void)hipEventDestroy(c->ev_in);
     if (c->ev_out) (void)hipEventDestroy(c->ev_out);
     if (c->stream) (void)hipStreamDestroy(c->stream);
+    if (c->cap) (void)hipStreamDestroy(c->cap);
     delete c;
     g.graphs = nullptr;
+}
+
+// Launch pieces covering the sets [0, A).  A piece of w sets runs with lane
+// groups of w lanes (w a power of two), and its pass costs a fixed part (the
+// record stream, the per-record decode, the combine) plus a part in
+// proportion to w; below 8 sets the state layout (one cache line per operand
+// and set) makes narrow pieces no cheaper.  Measured on the 2n = 40 graph, 64
+// sets x 5 operands, per pass: 8 sets 0.95 ms, 16 sets 1.30, 32 sets 2.0, 64
+// sets 3.41.  The cheapest cover from those widths: 8 for A <= 8, 16 up to 16,
+// 32 up to 32, 32 + 8 up to 40, 32 + 16 up to 48, else 64 per 64 sets.
+struct SetRange {
+    int32_t s0, s1;
+};
+static std::vector<SetRange> set_ranges(int32_t A) {
+    std::vector<SetRange> r;
+    int32_t s = 0;
+    while (A - s > 48) {
+        const int32_t n = std::min(64, A - s);
+        r.push_back({s, s + n});
+        s += n;
+    }
+    const int32_t rem = A - s;
+    if (rem > 32) {
+        r.push_back({s, s + 32});
+        r.push_back({s + 32, A});
+    } else if (rem > 0) {
+        r.push_back({s, A});
+    }
+    return r;
 }
 
 static size_t al(size_t x) { return (x + 255) & ~size_t(255); }
@@ -51,46 +92,82 @@ struct FlowBufs {
     int32_t* step;
     int32_t* flag;
     double* part;   // tile partial slots (null when the tile path is not taken)
+    double* zp;     // the state with its sets in flow order (see cut_flow_integrate)
+    int32_t* perm;  // flow order: position q holds caller set perm[q]
 };
 
-static FlowBufs flow_bufs(Graph& g, int64_t nsets, int64_t nops, int prec, size_t extra, char** extra_ptr) {
+// byte offsets of the flow's work area (one layout for sizing and carving)
+struct FlowLayout {
+    size_t xs0, xs1, acc, hst, eta, ns, st, fl, part, zp, perm, ex, total, part_bytes;
+};
+
+static FlowLayout flow_layout(const Graph& g, int64_t nsets, int64_t nops, int prec, size_t extra) {
     const bool f32 = prec != CUT_F64;
-    const size_t part_bytes = forward_partial_bytes(g, (int32_t)nsets, (int32_t)nops, prec);
+    FlowLayout L{};
+    L.part_bytes = forward_partial_bytes(g, (int32_t)nsets, (int32_t)nops, prec);
     const int64_t N = g.N, cols = nops * nsets;
     const size_t tb = f32 ? 4 : 8;
     size_t o = 0;
-    size_t oxs0 = o;
+    L.xs0 = o;
     o += al(N * cols * tb);
-    size_t oxs1 = o;
+    L.xs1 = o;
     o += al(N * cols * tb);
-    size_t oacc = o;
+    L.acc = o;
     o += al(N * cols * 8);
-    size_t ohst = o;
+    L.hst = o;
     o += al(N * nsets * 8);
-    size_t oeta = o;
+    L.eta = o;
     o += al(g.NG * nsets * tb);
-    size_t ons = o;
+    L.ns = o;
     o += al(nsets * 4);
-    size_t ost = o;
+    L.st = o;
     o += 256;
-    size_t ofl = o;
+    L.fl = o;
     o += 256;
-    size_t opart = o;
-    o += al(part_bytes);
-    size_t oex = o;
+    L.part = o;
+    o += al(L.part_bytes);
+    L.zp = o;
+    o += al(N * cols * 8);
+    L.perm = o;
+    o += al(nsets * 4);
+    L.ex = o;
     o += al(extra);
-    char* b = (char*)g.ws.get(o);
+    L.total = o;
+    return L;
+}
+
+size_t flow_ws_bytes(const Graph& g, int64_t nsets, int64_t nops, int prec, size_t extra) {
+    return flow_layout(g, nsets, nops, prec, extra).total;
+}
+
+size_t flow_outside_extra(const Graph& g, int64_t nsets, int64_t nops) {
+    const int64_t cols = nops * nsets;
+    return g.have_outside ? al(g.n_out * cols * 8) + al((size_t)kColsqParts * cols * 8) : 0;
+}
+
+// stage storage, zr, lam_new, mu, u, eta, geta, vjp scratch of the adjoint flow
+size_t flow_adjoint_extra(const Graph& g, int64_t nsets, int64_t nops, int64_t ckpt_every) {
+    const int64_t M = g.N * nops * nsets;
+    const int64_t nslot = ckpt_every * 4 + 1;
+    return al(nslot * M * 8) + 4 * al(M * 8) + 2 * al(g.NG * nsets * 8) + al(2 * g.N * nsets * 8);
+}
+
+static FlowBufs flow_bufs(Graph& g, int64_t nsets, int64_t nops, int prec, size_t extra, char** extra_ptr) {
+    const FlowLayout L = flow_layout(g, nsets, nops, prec, extra);
+    char* b = (char*)g.ws.need(L.total, extra > 0 ? "the flow (with its diagnostic or adjoint storage)" : "the flow");
     FlowBufs f;
-    f.xsh[0] = b + oxs0;
-    f.xsh[1] = b + oxs1;
-    f.acc = (double*)(b + oacc);
-    f.hst = (double*)(b + ohst);
-    f.eta = b + oeta;
-    f.nsteps = (int32_t*)(b + ons);
-    f.step = (int32_t*)(b + ost);
-    f.flag = (int32_t*)(b + ofl);
-    f.part = part_bytes ? (double*)(b + opart) : nullptr;
-    if (extra_ptr) *extra_ptr = b + oex;
+    f.xsh[0] = b + L.xs0;
+    f.xsh[1] = b + L.xs1;
+    f.acc = (double*)(b + L.acc);
+    f.hst = (double*)(b + L.hst);
+    f.eta = b + L.eta;
+    f.nsteps = (int32_t*)(b + L.ns);
+    f.step = (int32_t*)(b + L.st);
+    f.flag = (int32_t*)(b + L.fl);
+    f.part = L.part_bytes ? (double*)(b + L.part) : nullptr;
+    f.zp = (double*)(b + L.zp);
+    f.perm = (int32_t*)(b + L.perm);
+    if (extra_ptr) *extra_ptr = b + L.ex;
     return f;
 }
 
@@ -110,6 +187,8 @@ struct StepPlan {
     double* onorm = nullptr;
     double* cbuf = nullptr;
     double* cpart = nullptr;
+    // sets each graph pass launches over (empty: all of them in one launch)
+    std::vector<SetRange> ranges;
 };
 
 // HIP events bracketing launches (kind 0 = graph pass, 1 = generator)
@@ -184,8 +263,15 @@ static void enqueue_step(const StepPlan& P, hipStream_t s, PassTimer* tm = nullp
         p.hst = P.fb.hst;
         p.ldh = P.nsets;
         if (tm) tm->mark(0, s);
-        if (P.fb.part) launch_forward(g, EPI_RK, p, P.fb.part, s);
-        else launch_pass(MODE_BCAST, EPI_RK, p, s);
+        const size_t nr = std::max<size_t>(1, P.ranges.size());
+        for (size_t r = 0; r < nr; ++r) {
+            if (!P.ranges.empty()) {
+                p.s0 = P.ranges[r].s0;
+                p.s1 = P.ranges[r].s1;
+            }
+            if (P.fb.part) launch_forward(g, EPI_RK, p, P.fb.part, s);
+            else launch_pass(MODE_BCAST, EPI_RK, p, s);
+        }
         if (tm) tm->mark(0, s);
     }
     launch_bump(P.fb.step, s);
@@ -223,14 +309,37 @@ extern "C" cut_status cut_flow_integrate(cut_graph_t h, const cut_flow_params* p
         const bool outside = p->outside_norm2 != nullptr;
         if (outside && !g.have_outside)
             CUT_FAIL(CUT_E_INVAL, "flow: outside_norm2 needs a graph with outside-space records");
-        const size_t ob = outside ? al(g.n_out * cols * 8) + al((size_t)kColsqParts * cols * 8) : 0;
+        const size_t ob = outside ? flow_outside_extra(g, nsets, nops) : 0;
         char* oex = nullptr;
         FlowBufs fb = flow_bufs(g, nsets, nops, p->precision, ob, &oex);
-        HIP_CHECK(hipMemcpyAsync(fb.nsteps, n_steps, nsets * 4, hipMemcpyHostToDevice, stream));
+        // Ragged batch: the sets run in the order of decreasing n_steps, so the
+        // sets still active at step t are a prefix of length A(t) and each
+        // graph pass launches over that prefix only (in pieces, set_ranges).
+        // The state is permuted into that order in the work area and back at
+        // the end.  With the outside-space diagnostic (accumulated per caller
+        // column) the caller's order is kept and passes cover the sets up to
+        // the last active one.
+        std::vector<int32_t>& perm = g.flow_perm_h;
+        std::vector<int32_t>& ns_run = g.flow_nsteps_h;
+        perm.resize(nsets);
+        for (int32_t q = 0; q < (int32_t)nsets; ++q) perm[q] = q;
+        if (!outside)
+            std::stable_sort(perm.begin(), perm.end(), [&](int32_t a, int32_t b) { return n_steps[a] > n_steps[b]; });
+        bool identity = true;
+        for (int32_t q = 0; q < (int32_t)nsets; ++q) identity = identity && perm[q] == q;
+        ns_run.resize(nsets);
+        for (int32_t q = 0; q < (int32_t)nsets; ++q) ns_run[q] = n_steps[perm[q]];
+        double* zs = identity ? z : fb.zp;
+        HIP_CHECK(hipMemcpyAsync(fb.nsteps, ns_run.data(), nsets * 4, hipMemcpyHostToDevice, stream));
+        if (!identity) {
+            HIP_CHECK(hipMemcpyAsync(fb.perm, perm.data(), nsets * 4, hipMemcpyHostToDevice, stream));
+            launch_permute_sets(z, zs, g.N, (int32_t)nops, (int32_t)nsets, fb.perm, false, stream);
+        }
         launch_set_scalar(fb.step, (int32_t)t0, stream);
-        launch_set_scalar(fb.flag, 0, stream);
-        launch_prep_state(z, g.N, (int32_t)nops, (int32_t)nsets, fb.xsh[0], f32, fb.hst, stream);
-        StepPlan P{&g, p->generator, p->precision, p->ds, p->delta, (int32_t)nsets, (int32_t)nops, fb, z, {}, {}};
+        int32_t* const flagp = p->nonfinite ? p->nonfinite : fb.flag;
+        launch_set_scalar(flagp, 0, stream);
+        launch_prep_state(zs, g.N, (int32_t)nops, (int32_t)nsets, fb.xsh[0], f32, fb.hst, stream);
+        StepPlan P{&g, p->generator, p->precision, p->ds, p->delta, (int32_t)nsets, (int32_t)nops, fb, zs, {}, {}};
         for (int st = 0; st < 4; ++st) {
             P.xin[st] = fb.xsh[st & 1];
             P.xout[st] = fb.xsh[(st + 1) & 1];
@@ -240,13 +349,34 @@ extern "C" cut_status cut_flow_integrate(cut_graph_t h, const cut_flow_params* p
             P.cbuf = (double*)oex;
             P.cpart = (double*)(oex + al(g.n_out * cols * 8));
         }
+        // width class of step t: the sets up to the last active one, when the
+        // pass honours set ranges (else 0: every set in one launch)
+        PassArgs probe{};
+        probe.csr = &g.csr[0][0];
+        probe.nsets = (int32_t)nsets;
+        probe.nops = (int32_t)nops;
+        probe.precision = p->precision;
+        probe.lda = nsets;
+        probe.ldb = cols;
+        const bool ranged = forward_set_ranges(g, probe);
+        auto width_class = [&](int64_t t) -> int64_t {
+            if (!ranged) return 0;
+            int64_t last = 0;
+            for (int32_t q = 0; q < (int32_t)nsets; ++q)
+                if (ns_run[q] > t) last = q + 1;
+            return last == nsets ? 0 : last;
+        };
+        auto set_class = [&](int64_t c) {
+            P.ranges.clear();
+            if (c > 0) P.ranges = set_ranges((int32_t)c);
+        };
         const bool use_graph = (p->flags & CUT_FLOW_HIPGRAPH) && t1 - t0 > 1;
         const bool timed = !use_graph && (p->flags & CUT_FLOW_TIME_PASSES);
         PassTimer timer;
         g.timing = cut_flow_timing{};
         StepGraphCache* gc = nullptr;
         if (use_graph) {
-            std::vector<uint64_t> key = {(uint64_t)(uintptr_t)z, (uint64_t)(uintptr_t)g.ws.ptr, (uint64_t)p->generator,
+            std::vector<uint64_t> key = {(uint64_t)(uintptr_t)zs, (uint64_t)(uintptr_t)g.ws.ptr, (uint64_t)p->generator,
                                          (uint64_t)p->precision, (uint64_t)nsets, (uint64_t)nops, 0, 0,
                                          g.tiling_gen, (uint64_t)(uintptr_t)fb.part,
                                          (uint64_t)(uintptr_t)p->outside_norm2};
@@ -257,25 +387,48 @@ extern "C" cut_status cut_flow_integrate(cut_graph_t h, const cut_flow_params* p
                 gc = new StepGraphCache();
                 g.graphs = gc;
                 HIP_CHECK(hipStreamCreateWithFlags(&gc->stream, hipStreamNonBlocking));
+                HIP_CHECK(hipStreamCreateWithFlags(&gc->cap, hipStreamNonBlocking));
                 HIP_CHECK(hipEventCreateWithFlags(&gc->ev_in, hipEventDisableTiming));
                 HIP_CHECK(hipEventCreateWithFlags(&gc->ev_out, hipEventDisableTiming));
-                HIP_CHECK(hipStreamBeginCapture(gc->stream, hipStreamCaptureModeThreadLocal));
-                enqueue_step(P, gc->stream);
-                HIP_CHECK(hipStreamEndCapture(gc->stream, &gc->graph));
-                HIP_CHECK(hipGraphInstantiate(&gc->exec, gc->graph, nullptr, nullptr, 0));
                 gc->key = key;
             }
             gc = g.graphs;
+            // capture every width class this call needs before any replay
+            for (int64_t t = t0; t < t1; ++t) {
+                const int64_t c = width_class(t);
+                bool have = false;
+                for (auto& e : gc->cls) have = have || e.id == c;
+                if (have) continue;
+                set_class(c);
+                StepGraphCache::Cls e{c, nullptr, nullptr};
+                HIP_CHECK(hipStreamBeginCapture(gc->cap, hipStreamCaptureModeThreadLocal));
+                enqueue_step(P, gc->cap);
+                HIP_CHECK(hipStreamEndCapture(gc->cap, &e.graph));
+                HIP_CHECK(hipGraphInstantiate(&e.exec, e.graph, nullptr, nullptr, 0));
+                gc->cls.push_back(e);
+            }
             HIP_CHECK(hipEventRecord(gc->ev_in, stream));
             HIP_CHECK(hipStreamWaitEvent(gc->stream, gc->ev_in, 0));
         }
         hipStream_t run = use_graph ? gc->stream : stream;
         for (int64_t t = t0; t < t1; ++t) {
-            if (ckpt && p->ckpt_every > 0 && t % p->ckpt_every == 0)
-                HIP_CHECK(hipMemcpyAsync(ckpt + (t / p->ckpt_every) * M, z, M * 8, hipMemcpyDeviceToDevice, run));
-            if (use_graph) HIP_CHECK(hipGraphLaunch(gc->exec, run));
-            else enqueue_step(P, run, timed ? &timer : nullptr);
+            if (ckpt && p->ckpt_every > 0 && t % p->ckpt_every == 0) {
+                double* slot = ckpt + (t / p->ckpt_every) * M;
+                if (identity) HIP_CHECK(hipMemcpyAsync(slot, zs, M * 8, hipMemcpyDeviceToDevice, run));
+                else launch_permute_sets(zs, slot, g.N, (int32_t)nops, (int32_t)nsets, fb.perm, true, run);
+            }
+            const int64_t c = width_class(t);
+            if (use_graph) {
+                hipGraphExec_t ex = nullptr;
+                for (auto& e : gc->cls)
+                    if (e.id == c) ex = e.exec;
+                HIP_CHECK(hipGraphLaunch(ex, run));
+            } else {
+                set_class(c);
+                enqueue_step(P, run, timed ? &timer : nullptr);
+            }
         }
+        if (!identity) launch_permute_sets(zs, z, g.N, (int32_t)nops, (int32_t)nsets, fb.perm, true, run);
         if (timed) {
             HIP_CHECK(hipStreamSynchronize(run));
             for (size_t q = 0; q + 1 < timer.used; q += 2) {
@@ -290,12 +443,13 @@ extern "C" cut_status cut_flow_integrate(cut_graph_t h, const cut_flow_params* p
                 }
             }
         }
-        launch_finite_check(z, M, fb.flag, run);
+        launch_finite_check(z, M, flagp, run);
         if (use_graph) {
             HIP_CHECK(hipEventRecord(gc->ev_out, run));
             HIP_CHECK(hipStreamWaitEvent(stream, gc->ev_out, 0));
         }
         HIP_CHECK(hipGetLastError());
+        if (p->nonfinite) return CUT_OK;
         int32_t flag = 0;
         HIP_CHECK(hipMemcpyAsync(&flag, fb.flag, 4, hipMemcpyDeviceToHost, stream));
         HIP_CHECK(hipStreamSynchronize(stream));
@@ -360,8 +514,7 @@ extern "C" cut_status cut_flow_adjoint(cut_graph_t h, const cut_flow_params* p, 
         const int64_t cols = nops * nsets, M = g.N * cols;
         const int C = p->ckpt_every;
         const int64_t nslot = (int64_t)C * 4 + 1;
-        // extra: stage storage, zr, lam_new, mu, u, eta, geta, vjp scratch
-        const size_t extra = al(nslot * M * 8) + 4 * al(M * 8) + 2 * al(g.NG * nsets * 8) + al(2 * g.N * nsets * 8);
+        const size_t extra = flow_adjoint_extra(g, nsets, nops, C);
         char* ex = nullptr;
         FlowBufs fb = flow_bufs(g, nsets, nops, CUT_F64, extra, &ex);
         double* St = (double*)ex;
@@ -421,9 +574,11 @@ extern "C" cut_status cut_flow_adjoint(cut_graph_t h, const cut_flow_params* p, 
                 launch_copy_active(g.N, (int32_t)cols, (int32_t)nsets, fb.nsteps, fb.step, lam_new, lambda, s);
             }
         }
-        launch_set_scalar(fb.flag, 0, s);
-        launch_finite_check(lambda, M, fb.flag, s);
+        int32_t* const flagp = p->nonfinite ? p->nonfinite : fb.flag;
+        launch_set_scalar(flagp, 0, s);
+        launch_finite_check(lambda, M, flagp, s);
         HIP_CHECK(hipGetLastError());
+        if (p->nonfinite) return CUT_OK;
         int32_t flag = 0;
         HIP_CHECK(hipMemcpyAsync(&flag, fb.flag, 4, hipMemcpyDeviceToHost, s));
         HIP_CHECK(hipStreamSynchronize(s));

@@ -83,22 +83,28 @@ void DevCSR::release() {
     nseg = nrec = ntasks = per_xcd = 0;
 }
 
-void* Workspace::get(size_t need) {
-    if (need <= bytes) return ptr;
+void* Workspace::need(size_t n, const char* what) const {
+    if (n <= bytes) return ptr;
+    CUT_FAIL(CUT_E_INVAL,
+             "%s needs a work area of %zu bytes, %zu are reserved: call cut_graph_reserve with this shape "
+             "(and again after a tiling change that adds partial rows)",
+             what, n, bytes);
+}
+
+void Workspace::reserve(size_t n) {
+    if (n <= bytes) return;
     if (ptr) {
         HIP_CHECK(hipDeviceSynchronize());
         (void)hipFree(ptr);
         ptr = nullptr;
         bytes = 0;
     }
-    size_t nb = std::max(need, bytes + bytes / 2);
-    hipError_t e = hipMalloc(&ptr, nb);
+    hipError_t e = hipMalloc(&ptr, n);
     if (e != hipSuccess) {
         ptr = nullptr;
-        CUT_FAIL(CUT_E_NOMEM, "workspace hipMalloc(%zu): %s", nb, hipGetErrorString(e));
+        CUT_FAIL(CUT_E_NOMEM, "work area hipMalloc(%zu): %s", n, hipGetErrorString(e));
     }
-    bytes = nb;
-    return ptr;
+    bytes = n;
 }
 
 void Workspace::release() {
@@ -1115,6 +1121,7 @@ extern "C" cut_status cut_graph_set_tiling(cut_graph_t h, int64_t long_records, 
         DeviceGuard dg(g.device);
         HIP_CHECK(hipDeviceSynchronize());
         apply_tiling(g, long_records, chunk_records, flags);
+        rereserve(g);
         return CUT_OK;
     } catch (const Fail& f) {
         return f.st;

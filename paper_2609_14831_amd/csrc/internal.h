@@ -247,10 +247,16 @@ struct QuadBlockPlan {
     void release();
 };
 
+// Device work area of a graph handle.  It is sized only by reservation calls
+// (cut_graph_reserve, and the tiling calls that re-size it for the shapes
+// reserved so far); the computing entry points take their share with need(),
+// which never allocates or synchronises and fails with CUT_E_INVAL when the
+// reservation is too small.
 struct Workspace {
     void* ptr = nullptr;
     size_t bytes = 0;
-    void* get(size_t need);     // grows (synchronising) when too small
+    void* need(size_t n, const char* what) const;
+    void reserve(size_t n);     // grows: synchronises the device, frees, allocates
     void release();
 };
 
@@ -304,11 +310,27 @@ struct Graph {
     Workspace ws_small;              // scratch of single generator-VJP calls
     Workspace ws_part;               // tile partial slots of single forward passes
     Workspace ws_deriv;              // generator, tangent and float shadows of derivative calls
+    // shapes reserved so far: (nsets, nops, ckpt_every, CUT_RESERVE_* flags)
+    std::vector<std::vector<int64_t>> reserved;
     StepGraphCache* graphs = nullptr;
+    // host copies the last flow uploaded (kept alive past the asynchronous copies)
+    std::vector<int32_t> flow_perm_h, flow_nsteps_h;
     cut_flow_timing timing{};        // last timed flow
     std::vector<std::pair<std::vector<int64_t>, cut_tuning>> tune_cache;
     ~Graph();
 };
+
+// work-area sizes (bytes) of the computing entry points for one shape and
+// precision; reserve_shape() grows every work area to the largest over the
+// precisions, rereserve() repeats that for every shape reserved so far (after
+// the tiling, and with it the partial-row count, changed)
+size_t flow_ws_bytes(const Graph& g, int64_t nsets, int64_t nops, int prec, size_t extra);
+size_t flow_outside_extra(const Graph& g, int64_t nsets, int64_t nops);
+size_t flow_adjoint_extra(const Graph& g, int64_t nsets, int64_t nops, int64_t ckpt_every);
+size_t jvp_ws_bytes(const Graph& g, int64_t nsets, int64_t nops, int prec);
+size_t vjp_ws_bytes(const Graph& g, int64_t nsets, int64_t nops, int prec);
+void reserve_shape(Graph& g, int64_t nsets, int64_t nops, int64_t ckpt_every, uint32_t what);
+void rereserve(Graph& g);
 
 // tiling plan (host) -> device task list
 void build_tasks(Graph& g, DevCSR& c);
@@ -330,6 +352,7 @@ struct PassArgs {
     const void* B;
     int64_t ldb;
     int32_t nsets, nops;
+    int32_t s0 = 0, s1 = 0;         // sets [s0, s1) covered (s1 = 0: all); see forward_set_ranges
     int32_t precision;              // cut_precision
     const int32_t* nsteps;          // device [nsets] or null (all active)
     const int32_t* step;            // device scalar or null
@@ -362,6 +385,11 @@ size_t forward_partial_bytes(const Graph& g, int32_t nsets, int32_t nops, int32_
 size_t tile_partial_bytes(const Graph& g, int32_t nsets, int32_t nops);
 bool quadblocks_usable(const Graph& g, int32_t nsets, int32_t nops, int32_t precision);
 void launch_forward(const Graph& g, int epi, const PassArgs& a, double* partials, hipStream_t s);
+bool forward_set_ranges(const Graph& g, const PassArgs& a);
+// rows x (nops x nsets) state: dst[r][op][s] = src[r][op][perm[s]] (inverse:
+// dst[r][op][perm[s]] = src[r][op][s])
+void launch_permute_sets(const double* src, double* dst, int64_t rows, int32_t nops, int32_t nsets,
+                         const int32_t* perm, bool inverse, hipStream_t s);
 
 void launch_g2(const Graph& g, double delta, int32_t nsets, const double* h, int64_t ldh,
                void* eta, int64_t lde, bool eta_f32, const int32_t* nsteps, const int32_t* step,
@@ -371,6 +399,16 @@ void launch_g2_vjp(const Graph& g, double delta, int32_t nsets, const double* h,
                    hipStream_t s);
 void launch_g2_jvp(const Graph& g, double delta, int32_t nsets, const double* h, int64_t ldh,
                    const double* dh, int64_t lddh, double* deta, int64_t ldde, hipStream_t s);
+
+void launch_g1(const Graph& g, double delta, int32_t nsets, const double* h, int64_t ldh, void* eta,
+               int64_t lde, bool eta_f32, const int32_t* nsteps, const int32_t* step, hipStream_t s);
+void launch_g1_jvp(const Graph& g, double delta, int32_t nsets, const double* h, int64_t ldh,
+                   const double* dh, int64_t lddh, double* deta, int64_t ldde, hipStream_t s);
+void launch_g1_vjp(const Graph& g, double delta, int32_t nsets, const double* h, int64_t ldh,
+                   const double* gbar, int64_t ldg, double* g_h, int64_t ldgh, double* tmp, hipStream_t s);
+// generators evaluated from the pair-flip stencil (G1, G2): they need scratch
+// of 2 N nsets doubles in their VJP
+inline bool stencil_generator(int kind) { return kind == CUT_GEN_G1 || kind == CUT_GEN_G2; }
 
 // elementwise helpers
 void launch_prep_state(const double* z, int64_t rows, int32_t nops, int32_t nsets, void* xsh,
@@ -392,6 +430,12 @@ void launch_adj_combine(int64_t rows, int32_t ncols, int32_t nsets, const int32_
 void launch_copy_active(int64_t rows, int32_t ncols, int32_t nsets, const int32_t* nsteps,
                         const int32_t* step, const double* src, double* dst, hipStream_t s);
 void launch_finite_check(const double* z, int64_t n, int32_t* flag, hipStream_t s);
+
+// validated pass arguments of a forward action (cut_graph_apply and its
+// allocation-free variant); *part_bytes = partial-row bytes it needs
+PassArgs apply_args(Graph& g, int32_t which, int32_t precision, int64_t nsets, int64_t nops, const void* eta,
+                    int64_t lde, const void* x, int64_t ldx, double* y, int64_t ldy, uint32_t flags,
+                    size_t* part_bytes);
 
 // shared by the ABI entry points (capi.cpp) and the flow driver (flow.cpp)
 Graph& checked(cut_graph_t h);

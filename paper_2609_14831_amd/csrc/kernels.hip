@@ -19,6 +19,7 @@
 // stage combination fused into the flow pass, Eq. coflow integrated at fixed ds).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <type_traits>
 
 #include "internal.h"
@@ -36,6 +37,7 @@ struct KArgs {
     const void* B;
     int64_t ldb;
     int32_t nsets, nops;
+    int32_t s0, s1;   // the sets [s0, s1) this launch covers (columns keep the nsets stride)
     const int32_t* nsteps;
     const int32_t* step;
     void* y;
@@ -93,7 +95,10 @@ struct Acc<CUT_F32> {
     __device__ double get() const { return (double)v; }
 };
 // Compensated: error-free product (FMA) and error-free sum (two-sum); the
-// running error terms are summed in a second float.
+// running error terms are summed in a second float.  add() treats one term;
+// add_sum() folds the float partial of a group of terms (accumulated by FMAs,
+// so its products and sums are rounded within the group only) into (hi, lo)
+// with one two-sum: per term that costs one FMA plus 1/U of the two-sum.
 template <>
 struct Acc<CUT_F32C> {
     float hi = 0.f, lo = 0.f;
@@ -108,6 +113,14 @@ struct Acc<CUT_F32C> {
         float se = (hi - (s - bb)) + (p - bb);
         hi = s;
         lo += se + pe;
+    }
+    __device__ void add_sum(float p) {
+#pragma clang fp contract(off)
+        float s = hi + p;
+        float bb = s - hi;
+        float se = (hi - (s - bb)) + (p - bb);
+        hi = s;
+        lo += se;
     }
     __device__ double get() const { return (double)hi + (double)lo; }
 };
@@ -204,8 +217,8 @@ __global__ __launch_bounds__(256) void k_pass(KArgs a) {
     const int lane = threadIdx.x & 63;
     const int sg = lane % G;
     const int sub = lane / G;
-    const int s = blockIdx.y * G + sg;
-    const bool act = set_active(a, s);
+    const int s = a.s0 + blockIdx.y * G + sg;
+    const bool act = s < a.s1 && set_active(a, s);
     const bool chunked = a.chunks != nullptr && (int64_t)blockIdx.x < a.nchunk_blocks;
     Task task{0, 0};
     int32_t slot = 0;
@@ -255,7 +268,7 @@ __global__ __launch_bounds__(256) void k_pass(KArgs a) {
     const int nsets = a.nsets;
     // lanes of inactive sets compute on an in-range column and are discarded
     // at the epilogue; no load is ever predicated
-    const int sl = s < nsets ? s : nsets - 1;
+    const int sl = s < a.s1 ? s : a.s1 - 1;
     // lane byte offsets of the gathered columns within a row: 32-bit and
     // unsigned, so each gather takes the (uniform) row address as its scalar
     // base and needs no per-lane address arithmetic
@@ -266,16 +279,40 @@ __global__ __launch_bounds__(256) void k_pass(KArgs a) {
 #ifndef CUT_PASS_UNROLL
 #define CUT_PASS_UNROLL 4
 #endif
-    constexpr int U = (NOPS <= 2) ? 8 : CUT_PASS_UNROLL;
+    constexpr int U = (NOPS <= 2 || PREC == CUT_F32C) ? 8 : CUT_PASS_UNROLL;
     // The gathers of U records are all issued before any arithmetic, so U
     // dependent load chains are in flight per lane group; then accum() adds the
     // U terms.  A record slot past the segment end holds a valid clamped record
     // and gets factor zero.
     auto accum = [&](const T (&av)[U][NA], const T (&bv)[U][NOPS], const float (&fc)[U]) {
+        if constexpr (PREC == CUT_F32C) {
+            // the U terms of each column in one float partial (FMA chain),
+            // then one two-sum into the compensated accumulator
+            if constexpr (MODE == MODE_BCAST) {
+                float tl[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) tl[u] = fc[u] * av[u][0];
+#pragma unroll
+                for (int op = 0; op < NOPS; ++op) {
+                    float p = tl[0] * bv[0][op];
+#pragma unroll
+                    for (int u = 1; u < U; ++u) p = __builtin_fmaf(tl[u], bv[u][op], p);
+                    acc[op].add_sum(p);
+                }
+            } else {
+                float p = 0.f;
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+#pragma unroll
+                    for (int op = 0; op < NOPS; ++op) p = __builtin_fmaf(fc[u] * av[u][op], bv[u][op], p);
+                acc[0].add_sum(p);
+            }
+            return;
+        }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const double cf = (double)fc[u];
-            if constexpr (MODE == MODE_BCAST && (PREC == CUT_F32C || PREC == CUT_F32)) {
+            if constexpr (MODE == MODE_BCAST && PREC == CUT_F32) {
                 const float tl = fc[u] * av[u][0];
 #pragma unroll
                 for (int op = 0; op < NOPS; ++op) acc[op].add(tl, bv[u][op]);
@@ -313,13 +350,23 @@ __global__ __launch_bounds__(256) void k_pass(KArgs a) {
 #pragma unroll
                 for (int op = 0; op < NOPS; ++op) bv[u][op] = buf_load<T>(rb, boff[op], 0);
             } else if constexpr (G == 1) {
-                // one set: a row's columns are contiguous at offsets known at
-                // compile time, so the compiler fuses them into 16-byte loads
-                // (half the per-lane gather instructions of separate loads)
+                if (nsets == 1) {
+                    // one set: a row's columns are contiguous at offsets known
+                    // at compile time, so the compiler fuses them into 16-byte
+                    // loads (half the per-lane gather instructions)
 #pragma unroll
-                for (int q = 0; q < NA; ++q) av[u][q] = arow[q];
+                    for (int q = 0; q < NA; ++q) av[u][q] = arow[q];
 #pragma unroll
-                for (int op = 0; op < NOPS; ++op) bv[u][op] = brow[op];
+                    for (int op = 0; op < NOPS; ++op) bv[u][op] = brow[op];
+                } else {
+                    // one set of several (a one-set piece of a set range)
+                    const char* ac = reinterpret_cast<const char*>(arow);
+                    const char* bc = reinterpret_cast<const char*>(brow);
+#pragma unroll
+                    for (int q = 0; q < NA; ++q) av[u][q] = *reinterpret_cast<const T*>(ac + boff[q]);
+#pragma unroll
+                    for (int op = 0; op < NOPS; ++op) bv[u][op] = *reinterpret_cast<const T*>(bc + boff[op]);
+                }
             } else {
                 const char* ac = reinterpret_cast<const char*>(arow);
                 const char* bc = reinterpret_cast<const char*>(brow);
@@ -870,13 +917,23 @@ static void launch_g(const KArgs& k, int prec, int G, dim3 grid, hipStream_t s) 
         case 4: launch_nops<4, MODE, EPI>(k, prec, grid, s); break;
         case 8: launch_nops<8, MODE, EPI>(k, prec, grid, s); break;
         case 16: launch_nops<16, MODE, EPI>(k, prec, grid, s); break;
+        case 32: launch_nops<32, MODE, EPI>(k, prec, grid, s); break;
         default: launch_nops<64, MODE, EPI>(k, prec, grid, s); break;
     }
 }
 
-// lanes per record slot: the smallest of 1, 2, 4, 8, 16, 64 holding nsets
+// lanes per record slot: the smallest power of two up to 64 holding nsets
 static int group_width(int nsets) {
-    return nsets <= 1 ? 1 : nsets <= 2 ? 2 : nsets <= 4 ? 4 : nsets <= 8 ? 8 : nsets <= 16 ? 16 : 64;
+    int G = 1;
+    while (G < nsets && G < 64) G <<= 1;
+    return G;
+}
+
+// lane groups of a launch over the sets [s0, s1) of nsets: at least 8 lanes
+// when the state has that many sets, since below 8 a lane group reads a whole
+// cache line per operand for each set and gets no cheaper
+static int range_group_width(const KArgs& k) {
+    return group_width(std::max(k.s1 - k.s0, std::min(8, (int)k.nsets)));
 }
 
 static KArgs make_kargs(const PassArgs& p) {
@@ -893,6 +950,8 @@ static KArgs make_kargs(const PassArgs& p) {
     k.ldb = p.ldb;
     k.nsets = p.nsets;
     k.nops = p.nops;
+    k.s0 = p.s1 > 0 ? p.s0 : 0;
+    k.s1 = p.s1 > 0 ? p.s1 : p.nsets;
     k.nsteps = p.nsteps;
     k.step = p.step;
     k.y = p.y;
@@ -1031,9 +1090,9 @@ void launch_pass(int mode, int epi, const PassArgs& p, hipStream_t s) {
     if (p.csr->nseg == 0) return;
     const KArgs k = make_kargs(p);
     if (k.ntasks == 0) return;
-    const int G = group_width(p.nsets);
+    const int G = range_group_width(k);
     const int64_t nblk = k.per_xcd > 0 ? 8 * k.per_xcd : k.ntasks;
-    dim3 grid((unsigned)nblk, (unsigned)((p.nsets + G - 1) / G));
+    dim3 grid((unsigned)nblk, (unsigned)((k.s1 - k.s0 + G - 1) / G));
     if (mode == MODE_BCAST) {
         if (epi == EPI_Y) launch_g<MODE_BCAST, EPI_Y>(k, p.precision, G, grid, s);
         else if (epi == EPI_ETA) launch_g<MODE_BCAST, EPI_ETA>(k, p.precision, G, grid, s);
@@ -1313,9 +1372,10 @@ __global__ __launch_bounds__(256) void k_chunk_combine(KArgs a, const double* __
                                                        const int32_t* __restrict__ crow, int64_t nlong) {
     using T = typename PrecT<PREC>::T;
     const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= nlong * a.nsets) return;
-    const int64_t l = q / a.nsets;
-    const int s = (int)(q % a.nsets);
+    const int nr = a.s1 - a.s0;
+    if (q >= nlong * nr) return;
+    const int64_t l = q / nr;
+    const int s = a.s0 + (int)(q % nr);
     if (a.nsteps && a.nsteps[s] <= *a.step) return;
     const int64_t row = crow[l];
     double v[NOPS];
@@ -1341,7 +1401,7 @@ __global__ __launch_bounds__(256) void k_chunk_combine(KArgs a, const double* __
 template <int NOPS, int EPI>
 static void launch_chunk_combine_p(const KArgs& k, int prec, const ChunkPlan& c, const double* P, int64_t ldp,
                                    hipStream_t s) {
-    const unsigned nb = (unsigned)((c.nlong * k.nsets + 255) / 256);
+    const unsigned nb = (unsigned)((c.nlong * (k.s1 - k.s0) + 255) / 256);
     switch (prec) {
         case CUT_F64: hipLaunchKernelGGL((k_chunk_combine<NOPS, CUT_F64, EPI>), dim3(nb), dim3(256), 0, s, k, P, ldp, c.cstart, c.crow, c.nlong); break;
         case CUT_F32X: hipLaunchKernelGGL((k_chunk_combine<NOPS, CUT_F32X, EPI>), dim3(nb), dim3(256), 0, s, k, P, ldp, c.cstart, c.crow, c.nlong); break;
@@ -1599,8 +1659,8 @@ static void launch_chunked(const Graph& g, const ChunkPlan& c, int epi, const Pa
     r.ntasks = c.nshort;
     r.per_xcd = c.short_per_xcd;
     KArgs k = make_kargs(r);
-    const int G = group_width(a.nsets);
-    const unsigned ychunks = (unsigned)((a.nsets + G - 1) / G);
+    const int G = range_group_width(k);
+    const unsigned ychunks = (unsigned)((k.s1 - k.s0 + G - 1) / G);
     const int64_t ldp = (int64_t)a.nops * a.nsets;
     k.chunks = c.chunks;
     k.nchunks = c.nchunks;
@@ -1678,6 +1738,14 @@ static void launch_tiles_nops(const TileKArgs& t, const KArgs& k, int epi, int p
     launch_tile_p<NOPS>(t, prec, G, grid, lds, s);
     if (epi == EPI_Y) launch_combine_p<NOPS, EPI_Y>(k, prec, t.P, t.pstride, t.ldp, row0, nrows, s);
     else launch_combine_p<NOPS, EPI_RK>(k, prec, t.P, t.pstride, t.ldp, row0, nrows, s);
+}
+
+// whether launch_forward honours a set range [s0, s1) of `a` (the segment
+// kernel, chunked or not); the block, tile and complex-record kernels always
+// cover every set
+bool forward_set_ranges(const Graph& g, const PassArgs& a) {
+    if (cpass_usable(MODE_BCAST, EPI_RK, a) || cshort_usable(MODE_BCAST, EPI_RK, a)) return false;
+    return !tiles_usable(g, a.nsets, a.nops, a.precision) && !quadblocks_usable(g, a.nsets, a.nops, a.precision);
 }
 
 void launch_forward(const Graph& g, int epi, const PassArgs& a, double* partials, hipStream_t s) {
@@ -1912,6 +1980,122 @@ void launch_g2_vjp(const Graph& g, double delta, int32_t nsets, const double* h,
                        nsets, g.st_p_off, g.st_p, g.pairs, g.ftab, g.gen_sign, h, ldh, w, u, g_h, ldgh);
 }
 
+// ------------------------------------------------------------------- G1 ----
+// Literal White-type generator from the diagonal pair energies:
+//   eta_S = h_S / D_S,  D_S = 2 sum_{a in F(S)} |eps_a| + delta,  eps_a = h_{P_a},
+// over the flipped pairs F(S) of an off-diagonal string S (its stencil entries'
+// pairs); eta = 0 on block-diagonal strings.  FP64 arithmetic.
+__device__ inline double g1_denominator(const int4* __restrict__ st, const int32_t* __restrict__ pairs,
+                                        const double* __restrict__ h, int64_t ldh, int64_t S, int s,
+                                        double delta, bool& has) {
+    int4 e[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) e[t] = st[S * 4 + t];
+    double d = 0.0;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const double eps = h[(int64_t)pairs[e[t].y] * ldh + s];
+        d += e[t].x >= 0 ? 2.0 * __builtin_fabs(eps) : 0.0;
+    }
+    has = e[0].x >= 0;
+    return d + delta;
+}
+
+__global__ void k_g1(int64_t N, int32_t nsets, const int4* __restrict__ st, const int32_t* __restrict__ pairs,
+                     double delta, const double* __restrict__ h, int64_t ldh, void* eta, int64_t lde, int eta_f32,
+                     const int32_t* nsteps, const int32_t* step) {
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t S = gid / nsets;
+    const int s = (int)(gid % nsets);
+    if (S >= N) return;
+    if (nsteps && nsteps[s] <= *step) return;
+    bool has;
+    const double d = g1_denominator(st, pairs, h, ldh, S, s, delta, has);
+    const double v = has ? h[S * ldh + s] / d : 0.0;
+    if (eta_f32) ((float*)eta)[S * lde + s] = (float)v;
+    else ((double*)eta)[S * lde + s] = v;
+}
+
+// d eta_S = dh_S / D_S - h_S dD_S / D_S^2,  dD_S = 2 sum_{a in F(S)} sign(eps_a) d eps_a
+__global__ void k_g1_jvp(int64_t N, int32_t nsets, const int4* __restrict__ st, const int32_t* __restrict__ pairs,
+                         double delta, const double* __restrict__ h, int64_t ldh, const double* __restrict__ dh,
+                         int64_t lddh, double* deta, int64_t ldde) {
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t S = gid / nsets;
+    const int s = (int)(gid % nsets);
+    if (S >= N) return;
+    double d = delta, dd = 0.0;
+    for (int t = 0; t < 4; ++t) {
+        const int4 e = st[S * 4 + t];
+        if (e.x < 0) break;
+        const int64_t pa = pairs[e.y];
+        const double eps = h[pa * ldh + s];
+        d += 2.0 * __builtin_fabs(eps);
+        dd += 2.0 * (eps > 0.0 ? 1.0 : eps < 0.0 ? -1.0 : 0.0) * dh[pa * lddh + s];
+    }
+    const bool has = st[S * 4].x >= 0;
+    deta[S * ldde + s] = has ? (dh[S * lddh + s] * d - h[S * ldh + s] * dd) / (d * d) : 0.0;
+}
+
+// VJP stage 1: w_S = gbar_S / D_S (added into g_h[S]) and u_S = gbar_S h_S / D_S^2
+__global__ void k_g1_vjp_prep(int64_t N, int32_t nsets, const int4* __restrict__ st,
+                              const int32_t* __restrict__ pairs, double delta, const double* __restrict__ h,
+                              int64_t ldh, const double* __restrict__ gbar, int64_t ldg, double* u, double* g_h,
+                              int64_t ldgh) {
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t S = gid / nsets;
+    const int s = (int)(gid % nsets);
+    if (S >= N) return;
+    bool has;
+    const double d = g1_denominator(st, pairs, h, ldh, S, s, delta, has);
+    const double gb = has ? gbar[S * ldg + s] : 0.0;
+    g_h[S * ldgh + s] += gb / d;
+    u[S * nsets + s] = gb * h[S * ldh + s] / (d * d);
+}
+
+// VJP stage 2: g_h[P_a] -= 2 sign(eps_a) sum_{S: a in F(S)} u_S (one wavefront
+// per (pair a, set s) over the pair's list of strings, fixed order)
+__global__ void k_g1_vjp_pairs(int64_t npairs, int32_t nsets, const int64_t* __restrict__ poff,
+                               const int4* __restrict__ pent, const int32_t* __restrict__ pairs,
+                               const double* __restrict__ h, int64_t ldh, const double* __restrict__ u,
+                               double* g_h, int64_t ldgh) {
+    const int64_t wid = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int lane = threadIdx.x & 63;
+    const int64_t a = wid / nsets;
+    const int s = (int)(wid % nsets);
+    if (a >= npairs) return;
+    const int64_t pa = pairs[a];
+    const double eps = h[pa * ldh + s];
+    double acc = 0.0;
+    for (int64_t q = poff[a] + lane; q < poff[a + 1]; q += 64) acc += u[(int64_t)pent[q].x * nsets + s];
+    for (int o = 1; o < 64; o <<= 1) acc += __shfl_xor(acc, o);
+    if (lane == 0) g_h[pa * ldgh + s] -= 2.0 * (eps > 0.0 ? 1.0 : eps < 0.0 ? -1.0 : 0.0) * acc;
+}
+
+void launch_g1(const Graph& g, double delta, int32_t nsets, const double* h, int64_t ldh, void* eta,
+               int64_t lde, bool eta_f32, const int32_t* nsteps, const int32_t* step, hipStream_t s) {
+    const int64_t n = g.N * nsets;
+    hipLaunchKernelGGL(k_g1, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, g.N, nsets, g.stencil, g.pairs,
+                       delta, h, ldh, eta, lde, (int)eta_f32, nsteps, step);
+}
+
+void launch_g1_jvp(const Graph& g, double delta, int32_t nsets, const double* h, int64_t ldh,
+                   const double* dh, int64_t lddh, double* deta, int64_t ldde, hipStream_t s) {
+    const int64_t n = g.N * nsets;
+    hipLaunchKernelGGL(k_g1_jvp, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, g.N, nsets, g.stencil,
+                       g.pairs, delta, h, ldh, dh, lddh, deta, ldde);
+}
+
+void launch_g1_vjp(const Graph& g, double delta, int32_t nsets, const double* h, int64_t ldh,
+                   const double* gbar, int64_t ldg, double* g_h, int64_t ldgh, double* tmp, hipStream_t s) {
+    const int64_t n = g.N * nsets;
+    hipLaunchKernelGGL(k_g1_vjp_prep, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, g.N, nsets, g.stencil,
+                       g.pairs, delta, h, ldh, gbar, ldg, tmp, g_h, ldgh);
+    const int64_t waves = g.npairs * nsets;
+    hipLaunchKernelGGL(k_g1_vjp_pairs, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, s, g.npairs, nsets,
+                       g.st_p_off, g.st_p, g.pairs, h, ldh, tmp, g_h, ldgh);
+}
+
 // ---------------------------------------------------------- elementwise ----
 __global__ void k_prep_state(const double* z, int64_t rows, int32_t nops, int32_t nsets, void* xsh,
                              int f32, double* hst) {
@@ -2087,6 +2271,24 @@ void launch_copy_active(int64_t rows, int32_t ncols, int32_t nsets, const int32_
     const int64_t n = rows * ncols;
     hipLaunchKernelGGL(k_copy_active, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, nsets, nsteps,
                        step, src, dst);
+}
+
+// set permutation of a [rows][nops][nsets] state (one thread per element)
+__global__ void k_permute_sets(const double* __restrict__ src, double* __restrict__ dst, int64_t n,
+                               int32_t nsets, const int32_t* __restrict__ perm, int inverse) {
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n) return;
+    const int64_t base = q - q % nsets;
+    const int s = (int)(q % nsets);
+    if (inverse) dst[base + perm[s]] = src[q];
+    else dst[q] = src[base + perm[s]];
+}
+void launch_permute_sets(const double* src, double* dst, int64_t rows, int32_t nops, int32_t nsets,
+                         const int32_t* perm, bool inverse, hipStream_t s) {
+    const int64_t n = rows * nops * nsets;
+    if (n == 0) return;
+    hipLaunchKernelGGL(k_permute_sets, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, src, dst, n, nsets,
+                       perm, inverse ? 1 : 0);
 }
 
 __global__ void k_finite(const double* z, int64_t n, int32_t* flag) {

@@ -72,6 +72,7 @@ extern "C" cut_status cut_graph_autotune(cut_graph_t h, int64_t nsets, int64_t n
             if (kv.first == key) {
                 *out = kv.second;
                 apply_tiling(g, out->long_records, out->chunk_records, out->tiling_flags);
+                rereserve(g);
                 return CUT_OK;
             }
         std::vector<int> precs = {precision};
@@ -138,6 +139,7 @@ extern "C" cut_status cut_graph_autotune(cut_graph_t h, int64_t nsets, int64_t n
                 best = cut_tuning{cands[i].lr, cands[i].cr, cands[i].flags, cands[i].prec, ms, best.default_ms};
         }
         apply_tiling(g, best.long_records, best.chunk_records, best.tiling_flags);
+        rereserve(g);
         HIP_CHECK(hipEventDestroy(e0));
         HIP_CHECK(hipEventDestroy(e1));
         HIP_CHECK(hipStreamDestroy(s));

@@ -11,11 +11,14 @@ Calls only the oracle (and the seeded workload generator):
                      the shortest and the longest set, shape [N, 5, 1]
   cfg4_two_steps.npy config 4 (m=64, G2, ds=5e-3): z after 2 RK4 steps of sets
                      0 and 15, shape [N, 1, 2]
+  cfg2_g1_flow_s10.npy
+                     config 2 with the literal generator G1 (delta=0.5): z at
+                     s=10, shape [N, 3, 1] (precision study)
 
 Sets are independent in the flow (each set's generator is built from its own
 Hamiltonian column), so a set flowed alone is the set flowed in the batch.
 
-Usage: python tests/golden/make_oracle_goldens.py [cfg2|cfg5|cfg3|cfg4 ...]
+Usage: python tests/golden/make_oracle_goldens.py [cfg2|cfg2_g1|cfg5|cfg3|cfg4 ...]
 """
 import os
 import sys
@@ -38,6 +41,17 @@ def cfg2():
     z, _ = native.Engine(g, "g2", w.delta).flow(inp.z0, w.ds, inp.n_steps)
     np.save(os.path.join(HERE, "cfg2_flow_s10.npy"), z)
     print(f"cfg2: {inp.n_steps} steps in {time.time() - t:.1f} s", flush=True)
+
+
+def cfg2_g1():
+    """Config 2 with the literal generator G1 (precision study): z at s=10."""
+    w = workloads.WORKLOADS[2]
+    inp = workloads.make_inputs(2)
+    g = native.majorana_graph(w.size)
+    t = time.time()
+    z, _ = native.Engine(g, "g1", w.delta).flow(inp.z0, w.ds, inp.n_steps)
+    np.save(os.path.join(HERE, "cfg2_g1_flow_s10.npy"), z)
+    print(f"cfg2 G1: {inp.n_steps} steps in {time.time() - t:.1f} s", flush=True)
 
 
 def cfg5():
@@ -93,4 +107,4 @@ def cfg4():
 if __name__ == "__main__":
     which = sys.argv[1:] or ["cfg2", "cfg5"]
     for name in which:
-        {"cfg2": cfg2, "cfg5": cfg5, "cfg3": cfg3, "cfg4": cfg4}[name]()
+        {"cfg2": cfg2, "cfg2_g1": cfg2_g1, "cfg5": cfg5, "cfg3": cfg3, "cfg4": cfg4}[name]()

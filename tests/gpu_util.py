@@ -21,10 +21,23 @@ def sum_bound(n: int) -> float:
     return 2 * g
 
 
-def dot2_bound(n: int) -> float:
-    """Relative (to sum |terms|) error bound of the compensated dot product."""
-    g = n * U32 / (1 - n * U32)
-    return g * g + 2.0 ** -52
+def gamma32(n: int) -> float:
+    return n * U32 / (1 - n * U32)
+
+
+# records whose terms the compensated float pass sums in one float partial
+F32C_GROUP = 8
+
+
+def dot2_bound(n: int, group: int = F32C_GROUP) -> float:
+    """Relative (to sum |terms|) error bound of the compensated float pass over
+    n terms: each group of at most `group` terms is summed in one float by FMAs
+    (error gamma_group of the group's sum of |terms|; the adjoint pass into the
+    generator sums F32C_GROUP records x nops operands per group), the group
+    partials go through two-sum into (hi, lo) (the compensated sum of Ogita,
+    Rump and Oishi: gamma_n^2), hi + lo is rounded to FP64 (2^-52)."""
+    g = gamma32(n)
+    return gamma32(group) + g * g + 2.0 ** -52
 
 
 def say(msg: str) -> None:

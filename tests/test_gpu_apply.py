@@ -151,7 +151,7 @@ def test_adjoint_parity(L, alg, size, nsets, nops, prec):
     if P != L.CUT_F64:
         eta, x, w = U.f32(eta), U.f32(x), U.f32(w)
     nmax = max(np.bincount(og.j).max(), np.bincount(og.i).max()) * nops
-    tol = U.sum_bound(nmax) if prec in ("F64", "F32X") else U.dot2_bound(nmax)
+    tol = U.sum_bound(nmax) if prec in ("F64", "F32X") else U.dot2_bound(nmax, U.F32C_GROUP * nops)
     ga = A.Graph(og.algebra, og.size, N, og.k, og.i, og.j, np.abs(og.c), og.diag, og.pairs, 1.0)
     U.assert_within(gx.cpu().numpy().reshape(N, nops, nsets), OGr.adjoint_x(og, eta, w),
                     tol * OGr.adjoint_x(ga, np.abs(eta), np.abs(w)) + 1e-300, "g_x")
@@ -160,7 +160,8 @@ def test_adjoint_parity(L, alg, size, nsets, nops, prec):
 
 
 @pytest.mark.parametrize("alg,size,kind", [("epq", 8, "wegner_graph"), ("majorana", 10, "wegner_graph"),
-                                           ("majorana", 10, "g2"), ("majorana", 16, "g2")])
+                                           ("majorana", 10, "g2"), ("majorana", 16, "g2"),
+                                           ("majorana", 10, "g1"), ("majorana", 16, "g1")])
 def test_generator_and_vjp_parity(L, alg, size, kind):
     U.say(f"[generator] {alg} {size} {kind}")
     g = U.graph(L, alg, size)
@@ -173,7 +174,7 @@ def test_generator_and_vjp_parity(L, alg, size, kind):
     else:
         h = workloads.small_majorana(size, nsets, 1, seed=5)[:, 0, :]
     gen, vjp = OG.make_generator(og, kind, 0.5)
-    K = L.CUT_GEN_G2 if kind == "g2" else L.CUT_GEN_WEGNER_GRAPH
+    K = {"g2": L.CUT_GEN_G2, "g1": L.CUT_GEN_G1}.get(kind, L.CUT_GEN_WEGNER_GRAPH)
     th = torch.tensor(h, device=DEV)
     te = torch.zeros((N, nsets), dtype=torch.float64, device=DEV)
     L.cut_generator(g, K, 0.5, nsets, th, te)

@@ -80,6 +80,27 @@ def test_majorana_flow_ragged(L, prec, tiling):
             assert r < (1e-13 if prec == "F64" else 1e-7), (s, op, r)
 
 
+@pytest.mark.parametrize("prec", ["F64", "F32C"])
+def test_majorana_flow_g1(L, prec):
+    """The literal generator G1 in the flow (ragged, hipGraph) against the
+    oracle over a short window (G1 rotates coefficients instead of damping
+    them, so longer flows amplify every rounding; see the precision study)."""
+    U.say(f"[flow] majorana m=12 G1 {prec}")
+    m = 12
+    g = U.graph(L, "majorana", m)
+    og = A.majorana_graph(m)
+    z0 = workloads.small_majorana(m, 4, 2, seed=27)
+    ns = np.array([10, 3, 10, 0], dtype=np.int32)
+    z, _ = _flow(L, g, z0, ns, L.CUT_GEN_G1, getattr(L, "CUT_" + prec), 1e-2)
+    gen, _ = OG.make_generator(og, "g1", 0.5)
+    zr, _ = OF.integrate(og, gen, z0, 1e-2, ns)
+    np.testing.assert_array_equal(z[:, :, 3], z0[:, :, 3])
+    for s in range(4):
+        for op in range(2):
+            r = _rel(z[:, op, s], zr[:, op, s])
+            assert r < (1e-12 if prec == "F64" else 1e-6), (s, op, r)
+
+
 @pytest.mark.parametrize("tiling", FLOW_TILINGS)
 def test_majorana_flow_many_sets(L, tiling):
     """40 ragged sets x 2 operands (64-lane form, tiles usable), F32C, hipGraph."""

@@ -297,3 +297,62 @@ def test_apply_rows_equals_apply_at_those_rows(m):
 
     for key in (lambda g: g.i, lambda g: g.j):
         assert np.abs(planted(full, eta, x, rows, key) - ref).max() > 1e-3 * scale
+
+
+# ------------------------------------------------------------------- G1 ----
+
+def test_g1_closed_form_on_hand_built_hamiltonian():
+    """eta_S = h_S / (2 sum_{a in F(S)} |eps_a| + delta) on a hand-built
+    H_0 + V at m = 8 (pairs (0,1), (2,3), (4,5), (6,7)), with the flipped pairs
+    of each string written out by hand: {0,2} flips pairs 0 and 1, {1,6}
+    pairs 0 and 3, {0,1,2,4} pairs 1 and 2, {0,2,4,6} all four, {2,3,4,7}
+    pairs 2 and 3; the diagonal strings {0,1} and {0,1,2,3} get eta = 0."""
+    m, delta = 8, 0.25
+    reg = A.MajoranaRegistry(m)
+    row = lambda modes: int(reg.index_of(np.array([sum(1 << q for q in modes)], dtype=np.uint64))[0])
+    eps = [0.9, -0.4, 1.3, -2.0]
+    h = np.zeros((reg.N, 1))
+    for a, e in enumerate(eps):
+        h[row((2 * a, 2 * a + 1)), 0] = e
+    V = {(0, 2): 0.3, (1, 6): -0.7, (0, 1, 2, 4): 0.11, (0, 2, 4, 6): -0.05, (2, 3, 4, 7): 0.2}
+    flips = {(0, 2): (0, 1), (1, 6): (0, 3), (0, 1, 2, 4): (1, 2), (0, 2, 4, 6): (0, 1, 2, 3), (2, 3, 4, 7): (2, 3)}
+    for S, v in V.items():
+        h[row(S), 0] = v
+    h[row((0, 1, 2, 3)), 0] = 0.6          # a diagonal quartic
+    eta = GEN.G1(m, delta)(h)
+    for S, v in V.items():
+        want = v / (2 * sum(abs(eps[a]) for a in flips[S]) + delta)
+        assert abs(eta[row(S), 0] - want) < 1e-15
+    for S in ((0, 1), (2, 3), (0, 1, 2, 3)):
+        assert eta[row(S), 0] == 0.0
+    assert np.count_nonzero(eta) == len(V)
+
+
+@pytest.mark.parametrize("m", [8, 10])
+def test_g1_jvp_and_vjp(m):
+    """G1's JVP against central differences (exact up to rounding away from
+    eps_a = 0: eta is a rational function there) and its VJP against the JVP
+    through <gbar, J dh> = <J^T gbar, dh>."""
+    g1 = GEN.G1(m, 0.5)
+    h = workloads.small_majorana(m, 3, 1, seed=17)[:, 0, :]
+    dh = workloads.random_dense(h.shape, seed=18)
+    jv = g1.jvp(h, dh)
+    for step in (1e-5, 1e-6):
+        fd = (g1(h + step * dh) - g1(h - step * dh)) / (2 * step)
+        assert np.abs(fd - jv).max() < 1e-7 * np.abs(jv).max()
+    gbar = workloads.random_dense(h.shape, seed=19)
+    lhs = np.sum(gbar * jv)
+    rhs = np.sum(g1.vjp(h, gbar) * dh)
+    assert abs(lhs - rhs) < 1e-13 * (abs(lhs) + 1.0)
+
+
+def test_g1_engine_flow_matches_numpy_flow():
+    """The C engine's G1 flow equals the NumPy oracle's (same RK4, same records)."""
+    from oracle import native
+    m = 10
+    g = A.majorana_graph(m)
+    z0 = workloads.small_majorana(m, 2, 2, seed=23)
+    gen, _ = GEN.make_generator(g, "g1", 0.5)
+    zr, _ = F.integrate(g, gen, z0, 1e-2, [15, 9])
+    ze, _ = native.Engine(g, "g1", 0.5).flow(z0, 1e-2, [15, 9])
+    assert np.abs(ze - zr).max() < 1e-12 * np.abs(zr).max()
