@@ -238,6 +238,22 @@ cut_status cut_graph_apply(cut_graph_t g, int32_t which, int32_t precision, int6
  * Either output may be NULL (then its inputs may be NULL too).  Needs a graph
  * loaded with CUT_LOAD_ADJOINT (else CUT_E_INVAL).  Types as cut_graph_apply.
  * which = CUT_GRAPH_OUTSIDE is not supported (CUT_E_INVAL). */
+/* cut_graph_apply_noalloc: cut_graph_apply for callers that cannot allocate
+ * device memory or call a reserving entry point first (code under stream
+ * capture, tight serving loops, harnesses that forbid allocation).  Same
+ * arguments, result and kernels; the partial rows of a chunked or tiled
+ * forward pass live in a fixed device array of 64 MiB built into the library
+ * (one per GPU, held until the process ends) instead of the handle's work
+ * area, so no cut_graph_reserve is needed and nothing is allocated.  Every
+ * call on one GPU shares that array (it keeps the last call's partial rows;
+ * each call writes every row it reads first), so calls that overlap in time on
+ * one GPU race: issue them on one stream.  Errors: as cut_graph_apply, plus
+ * CUT_E_INVAL when the shape and tiling need more than 64 MiB of partial rows
+ * (fewer columns per call, longer chunks or CUT_TILE_NO_CHUNKS fit). */
+cut_status cut_graph_apply_noalloc(cut_graph_t g, int32_t which, int32_t precision, int64_t nsets,
+                                   int64_t nops, const void* eta, int64_t lde, const void* x, int64_t ldx,
+                                   double* y, int64_t ldy, uint32_t flags, void* stream);
+
 cut_status cut_graph_apply_adjoint(cut_graph_t g, int32_t which, int32_t precision, int64_t nsets,
                                    int64_t nops, const void* eta, int64_t lde, const void* x,
                                    int64_t ldx, const void* w, int64_t ldw, double* g_x,

@@ -53,7 +53,7 @@ STATUS_NAMES = {0: "CUT_OK", 1: "CUT_E_INVAL", 2: "CUT_E_IO", 3: "CUT_E_FORMAT",
 
 # symbols declared in include/cutgraph.h
 EXPORTS = ["cut_graph_build", "cut_graph_load", "cut_graph_info", "cut_graph_free",
-           "cut_graph_apply", "cut_graph_apply_adjoint", "cut_generator", "cut_generator_vjp",
+           "cut_graph_apply", "cut_graph_apply_noalloc", "cut_graph_apply_adjoint", "cut_generator", "cut_generator_vjp",
            "cut_generator_jvp", "cut_graph_jvp", "cut_graph_vjp", "cut_assemble", "cut_graph_labels",
            "cut_flow_integrate", "cut_flow_adjoint", "cut_graph_set_tiling", "cut_graph_autotune",
            "cut_flow_last_timing", "cut_graph_reserve", "cut_graph_reserved_bytes", "cut_last_error",
@@ -92,6 +92,7 @@ _L.cut_graph_info.argtypes = [_vp, C.POINTER(cut_graph_desc)]
 _L.cut_graph_free.argtypes = [_vp]
 _L.cut_graph_free.restype = None
 _L.cut_graph_apply.argtypes = [_vp, _i32, _i32, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _i64, _u32, _vp]
+_L.cut_graph_apply_noalloc.argtypes = [_vp, _i32, _i32, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _i64, _u32, _vp]
 _L.cut_graph_apply_adjoint.argtypes = [_vp, _i32, _i32, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _i64,
                                        _vp, _i64, _vp, _i64, _u32, _vp]
 _L.cut_generator.argtypes = [_vp, _i32, _dbl, _i64, _vp, _i64, _vp, _i64, _vp]
@@ -233,6 +234,15 @@ def cut_graph_apply(g: int, which: int, precision: int, nsets: int, nops: int, e
     _check(_L.cut_graph_apply(g, which, precision, nsets, nops, _ptr(eta), _ld(eta, nsets), _ptr(x),
                               _ld(x, nops * nsets), _ptr(y), _ld(y, nops * nsets), flags,
                               _stream(stream)))
+
+
+def cut_graph_apply_noalloc(g: int, which: int, precision: int, nsets: int, nops: int, eta, x, y,
+                            flags: int = 0, stream=None) -> None:
+    """cut_graph_apply with its partial rows in the library's fixed device array
+    (no reservation, nothing allocated)."""
+    _check(_L.cut_graph_apply_noalloc(g, which, precision, nsets, nops, _ptr(eta), _ld(eta, nsets), _ptr(x),
+                                      _ld(x, nops * nsets), _ptr(y), _ld(y, nops * nsets), flags,
+                                      _stream(stream)))
 
 
 def cut_graph_apply_adjoint(g: int, which: int, precision: int, nsets: int, nops: int, eta, x, w,

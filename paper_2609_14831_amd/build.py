@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libcutgraph.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["builder.cpp", "graph.cpp", "capi.cpp", "deriv.cpp", "flow.cpp", "tune.cpp", "reserve.cpp", "kernels.hip", "assemble.hip"]
+SOURCES = ["builder.cpp", "graph.cpp", "capi.cpp", "deriv.cpp", "flow.cpp", "tune.cpp", "reserve.cpp", "kernels.hip", "assemble.hip", "noalloc.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-x", "hip", "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
