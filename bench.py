@@ -195,10 +195,40 @@ def timed_flow(L, torch, g, inp, w, prec, W, K, E, N, tune=True):
     tm = L.cut_flow_last_timing(g)
     pass_ms = tm["pass_ms"] / max(1, tm["pass_launches"])
     pb = pass_bytes(N, E, nsets, nops, 8 if prec == L.CUT_F64 else 4)
+    name = {L.CUT_F64: "f64", L.CUT_F32C: "f32c", L.CUT_F32X: "f32x", L.CUT_F32: "f32"}[prec]
+    traffic = measured_counters(name, "traffic")
     return {"value": 4 * E * nops * nsets * K / wall, "unit": "contributions×batch/s",
             "ms_per_step": wall * 1e3 / K, "pass_ms": pass_ms, "algorithmic_bytes_per_launch": pb,
             "hbm_GBs": pb / (pass_ms * 1e-3) / 1e9, "hbm_frac": pb / (pass_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "traffic": traffic, "traffic_GBs": traffic / (pass_ms * 1e-3) / 1e9 if traffic else None,
             "tiling": tuning}
+
+
+def ragged_windows_leg(L, torch, g, inp, w, prec, E, all_active_value, steps=10):
+    """Windows of `steps` RK4 steps starting late in the config-3 flow, in
+    stream order (the state's values do not change the work, only which sets
+    are still active); rate over active columns, against the all-active rate of
+    the timed steps."""
+    dev = torch.device("cuda:0")
+    N_, nops, nsets = inp.z0.shape
+    ns = [int(v) for v in inp.n_steps]
+    L.cut_graph_autotune(g, nsets, nops, prec, 0)
+    res = []
+    for t0 in (1000, 2000, 2800, 3200, 3500):
+        active = sum(sum(1 for n in ns if n > t) for t in range(t0, t0 + steps))
+        z = torch.tensor(inp.z0, device=dev).contiguous()
+        p = L.flow_params(L.CUT_GEN_G2, prec, w.ds, w.delta, 0, flags=0, step_begin=t0, step_end=t0 + 1)
+        L.cut_flow_integrate(g, p, nsets, nops, ns, z)
+        p = L.flow_params(L.CUT_GEN_G2, prec, w.ds, w.delta, 0, flags=0, step_begin=t0, step_end=t0 + steps)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        L.cut_flow_integrate(g, p, nsets, nops, ns, z)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t1
+        v = 4 * E * nops * active / wall
+        res.append({"first_step": t0, "active_sets": sum(1 for n in ns if n > t0), "ms_per_step": wall * 1e3 / steps,
+                    "value": v, "ratio_to_all_active": v / all_active_value})
+    return res
 
 
 def full_flow_leg(L, torch, g, inp, w, prec, E, all_active_value):
@@ -252,7 +282,13 @@ def stress_leg(L, torch, tmp, profile=False):
            "compile_s": desc["build_seconds"], "load_s": load_s, "steps": T,
            "sets": nsets, "operands": nops}
     for name, prec in (("f32c", L.CUT_F32C), ("f64", L.CUT_F64)):
-        tuning = L.cut_graph_autotune(g, nsets, nops, prec, 0)
+        if profile:
+            # counter runs: the tiling the autotuner picks for both precisions in
+            # unprofiled runs, fixed (counter collection perturbs the timings)
+            L.cut_graph_set_tiling(g, 1024, 512, 0)
+            tuning = {"long_records": 1024, "chunk_records": 512, "tiling_flags": 0, "autotuned": False}
+        else:
+            tuning = L.cut_graph_autotune(g, nsets, nops, prec, 0)
         if profile:
             z = torch.tensor(inp.z0, device=dev).contiguous()
             p = L.flow_params(L.CUT_GEN_G2, prec, w.ds, w.delta, 0, flags=L.CUT_FLOW_TIME_PASSES, step_end=3)
@@ -284,6 +320,64 @@ def stress_leg(L, torch, tmp, profile=False):
         del z, zt
     L.cut_graph_free(g)
     return res
+
+
+def reverse_flow_leg(L, torch, tmp):
+    """The differentiated flow of config 5 (2n = 24 graph, 8 sets, H only,
+    G2, ds = 5e-3 to s = 10: 2,000 RK4 steps): the forward flow with a
+    checkpoint every 16 steps, then the discrete adjoint of the whole flow
+    (each checkpoint block recomputed in FP64 with its stage states kept, four
+    transposed graph passes per RK stage).  Both in FP64, timed separately."""
+    import workloads
+    dev = torch.device("cuda:0")
+    w = workloads.WORKLOADS[5]
+    path = os.path.join(tmp, "m24.cgb")
+    desc = L.cut_graph_build(L.CUT_ALG_MAJORANA, w.size, path, 0)
+    g = L.cut_graph_load(path, 0, L.CUT_LOAD_ADJOINT)
+    os.remove(path)
+    N, E = desc["n_ops"], desc["n_records"]
+    inp = workloads.make_inputs(5)
+    nsets, nops, C = w.nsets, w.nops, w.ckpt_every
+    ns = [int(v) for v in inp.n_steps]
+    T = max(ns)
+    ck = torch.zeros(((T + C - 1) // C, N, nops, nsets), dtype=torch.float64, device=dev)
+    L.cut_graph_reserve(g, nsets, nops, C, L.CUT_RESERVE_FLOW | L.CUT_RESERVE_ADJOINT)
+    res = {"workload": f"majorana m={w.size} (N={N}, E={E}), {nsets} sets, H only, {T} RK4 steps, "
+                       f"checkpoints every {C} steps, FP64"}
+    for rep in range(2):   # the first round captures the step graph and warms up
+        z = torch.tensor(inp.z0, device=dev).contiguous()
+        p = L.flow_params(L.CUT_GEN_G2, L.CUT_F64, w.ds, w.delta, C)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        L.cut_flow_integrate(g, p, nsets, nops, ns, z, ck)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        lam = torch.zeros_like(z)
+        lam[torch.tensor(workloads_pairs(w.size), device=dev), 0, :] = 1.0
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        L.cut_flow_adjoint(g, p, nsets, nops, ns, ck, lam)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+    fwd_pass = 4 * T * E * nops * nsets
+    res.update({"forward_s": t1 - t0, "adjoint_s": t3 - t2, "adjoint_over_forward": (t3 - t2) / (t1 - t0),
+                "forward_contributions_per_s": fwd_pass / (t1 - t0),
+                "adjoint_note": "per step: the block's forward recompute (4 passes) + 4 stages x "
+                                "(generator, j-grouped and i-grouped passes, generator VJP)"})
+    L.cut_graph_free(g)
+    return res
+
+
+def workloads_pairs(m):
+    """Registry rows of the pair strings {2a, 2a+1} (2-subsets come first,
+    lexicographic): the rows the config-5 loss sums."""
+    rows, r = [], 0
+    for i in range(m):
+        for j in range(i + 1, m):
+            if j == i + 1 and i % 2 == 0:
+                rows.append(r)
+            r += 1
+    return rows
 
 
 def assembly_leg(L, torch, N):
@@ -435,6 +529,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-outside", action="store_true", help="skip the outside-space action leg")
     ap.add_argument("--no-stress", action="store_true", help="skip the 2n = 64 stress-scale leg")
+    ap.add_argument("--full-flow", action="store_true",
+                    help="also time the whole ragged config-3 flow (3,660 steps, about a minute)")
     ap.add_argument("--only", choices=["assembly", "outside", "pauli_boson", "stress"],
                     help="run only that leg and print its JSON (for profiling)")
     ap.add_argument("--minimal", action="store_true", help="timed flow only")
@@ -631,9 +727,14 @@ def main():
     # the same flow with FP64 passes at the full width (64 sets x 5 operands)
     out["batched_fp64"] = timed_flow(L, torch, g, inp, w, L.CUT_F64, W, K, E, N, tune=args.long_records <= 0)
     log(f"batched fp64: {out['batched_fp64']}")
-    # the whole ragged flow (421 ... 3,660 steps), counting active columns only
-    out["full_ragged_flow"] = full_flow_leg(L, torch, g, inp, w, PREC, E, value)
-    log(f"full ragged flow: {out['full_ragged_flow']}")
+    # ragged batch: windows late in the flow, where fewer sets are active,
+    # counting active columns only (stream order, every window's passes
+    # launched over the active prefix); the whole flow with --full-flow
+    out["ragged_windows"] = ragged_windows_leg(L, torch, g, inp, w, PREC, E, value)
+    log(f"ragged windows: {out['ragged_windows']}")
+    if args.full_flow:
+        out["full_ragged_flow"] = full_flow_leg(L, torch, g, inp, w, PREC, E, value)
+        log(f"full ragged flow: {out['full_ragged_flow']}")
 
     # plain FP64 flow, one operand column per pass (one set, H only), in the
     # tiling tuned for that shape
@@ -650,8 +751,20 @@ def main():
     L.cut_flow_integrate(g, p, 1, 1, ns1, z1)
     torch.cuda.synchronize()
     plain = 4 * E * K / (time.perf_counter() - t0)
+    z1 = torch.tensor(inp.z0[:, :1, :1], device=dev).contiguous()
+    p = L.flow_params(L.CUT_GEN_G2, L.CUT_F64, w.ds, w.delta, 0, flags=L.CUT_FLOW_TIME_PASSES,
+                      step_begin=0, step_end=W + K)
+    L.cut_flow_integrate(g, p, 1, 1, ns1, z1)
+    tm1 = L.cut_flow_last_timing(g)
+    plain_ms = tm1["pass_ms"] / max(1, tm1["pass_launches"])
+    pb1 = pass_bytes(N, E, 1, 1, 8)
+    tr1 = measured_counters("plain", "traffic")
     out["plain_fp64_flow"] = {"value": plain, "unit": "contributions×batch/s",
-                              "columns": 1, "ratio_batched_over_plain": value / plain}
+                              "columns": 1, "ratio_batched_over_plain": value / plain,
+                              "pass_ms": plain_ms, "algorithmic_bytes_per_launch": pb1,
+                              "hbm_GBs": pb1 / (plain_ms * 1e-3) / 1e9,
+                              "hbm_frac": pb1 / (plain_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                              "traffic": tr1}
     log(f"plain FP64 one-column flow {plain:.3e}/s; batched/plain = {value / plain:.1f}x")
     # directional derivative of one action at the headline shape (Sec. 2.4,
     # Eq. directional-derivative): generator + its JVP + two forward passes
@@ -665,6 +778,8 @@ def main():
 
     out["assembly"] = assembly_leg(L, torch, N)
     log(f"assembly: {out['assembly']}")
+    out["reverse_flow"] = reverse_flow_leg(L, torch, tmp)
+    log(f"reverse flow: {out['reverse_flow']}")
 
     if not args.no_stress:
         out["stress_m64"] = stress_leg(L, torch, tmp)

@@ -359,12 +359,17 @@ extern "C" cut_status cut_flow_integrate(cut_graph_t h, const cut_flow_params* p
         probe.lda = nsets;
         probe.ldb = cols;
         const bool ranged = forward_set_ranges(g, probe);
+        // (a prefix that one 64-set piece would cover runs as a full-width
+        // launch instead, which keeps the tiling's block and tile kernels)
         auto width_class = [&](int64_t t) -> int64_t {
             if (!ranged) return 0;
             int64_t last = 0;
             for (int32_t q = 0; q < (int32_t)nsets; ++q)
                 if (ns_run[q] > t) last = q + 1;
-            return last == nsets ? 0 : last;
+            if (last == nsets) return 0;
+            const std::vector<SetRange> r = set_ranges((int32_t)last);
+            if (nsets <= 64 && r.size() == 1 && r[0].s1 - r[0].s0 > 32) return 0;
+            return last;
         };
         auto set_class = [&](int64_t c) {
             P.ranges.clear();

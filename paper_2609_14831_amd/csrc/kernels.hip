@@ -133,6 +133,26 @@ __device__ inline auto left_term(double cf, typename PrecT<PREC>::T av) {
     else return (float)cf * av;
 }
 
+// acc[op] += sum_u t[u] * b[u][op]: in the compensated float mode the U terms
+// of a column share one float partial and one two-sum; otherwise term by term
+template <int PREC, int U, int NOPS, class TL, class TB>
+__device__ inline void add_group(Acc<PREC> (&acc)[NOPS], const TL (&t)[U], const TB (&b)[U][NOPS]) {
+    if constexpr (PREC == CUT_F32C) {
+#pragma unroll
+        for (int op = 0; op < NOPS; ++op) {
+            float p = t[0] * b[0][op];
+#pragma unroll
+            for (int u = 1; u < U; ++u) p = __builtin_fmaf(t[u], b[u][op], p);
+            acc[op].add_sum(p);
+        }
+    } else {
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int op = 0; op < NOPS; ++op) acc[op].add(t[u], b[u][op]);
+    }
+}
+
 // FP32 bit pattern of the factor of a device record: its bf16 bit pattern is
 // split over the top bytes of the two row indices (high byte with the left row).
 __device__ __forceinline__ uint32_t record_factor_bits(uint32_t x, uint32_t y) {
@@ -1189,13 +1209,13 @@ __global__ __launch_bounds__(256) void k_tile(TileKArgs a) {
                     for (int op = 0; op < NOPS; ++op) bv[u][op] = lrow[op * G];
                 }
             }
+            decltype(left_term<PREC>(0.0, av[0])) tl[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const double cf = ok[u] ? (double)__builtin_bit_cast(float, rr[u].y & 0xFFFF0000u) : 0.0;
-                const auto tl = left_term<PREC>(cf, av[u]);
-#pragma unroll
-                for (int op = 0; op < NOPS; ++op) acc[op].add(tl, bv[u][op]);
+                tl[u] = left_term<PREC>(cf, av[u]);
             }
+            add_group<PREC, U, NOPS>(acc, tl, bv);
         }
         double v[NOPS];
 #pragma unroll
@@ -1288,14 +1308,17 @@ __global__ __launch_bounds__(512) void k_tile64(TileKArgs a) {
                 rec_at(r0 + u < half ? r0 + u : half - 1, rx[u], ry[u]);
                 gv[u] = buf_load<T>(rsH, voff, (int32_t)rx[u] * lde_b);
             }
+            decltype(left_term<PREC>(0.0, gv[0])) tl[UA];
+            T lv[UA][NOPS];
 #pragma unroll
             for (int u = 0; u < UA; ++u) {
                 const uint32_t fb = r0 + u < half ? (ry[u] & 0xFFFF0000u) : 0u;
-                const auto tl = left_term<PREC>((double)__builtin_bit_cast(float, fb), gv[u]);
+                tl[u] = left_term<PREC>((double)__builtin_bit_cast(float, fb), gv[u]);
                 const T* lrow = lds + (int)((ry[u] >> 1) & 0x7FFFu) * ROW + lane;
 #pragma unroll
-                for (int op = 0; op < NOPS; ++op) acc[op].add(tl, lrow[op * 64]);
+                for (int op = 0; op < NOPS; ++op) lv[u][op] = lrow[op * 64];
             }
+            add_group<PREC, UA, NOPS>(acc, tl, lv);
         }
         // second half: generator from LDS, operand = quadratic row
         for (int r0 = half; r0 < RT; r0 += U) {
@@ -1308,14 +1331,14 @@ __global__ __launch_bounds__(512) void k_tile64(TileKArgs a) {
                 for (int op = 0; op < NOPS; ++op)
                     bv[u][op] = buf_load<T>(rsX, voff, (int32_t)rx[u] * ldx_b + op * nsets * (int32_t)sizeof(T));
             }
+            decltype(left_term<PREC>(0.0, bv[0][0])) tl[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const uint32_t fb = r0 + u < RT ? (ry[u] & 0xFFFF0000u) : 0u;
                 const T* lrow = lds + (int)((ry[u] >> 1) & 0x7FFFu) * ROW + lane;
-                const auto tl = left_term<PREC>((double)__builtin_bit_cast(float, fb), lrow[NOPS * 64]);
-#pragma unroll
-                for (int op = 0; op < NOPS; ++op) acc[op].add(tl, bv[u][op]);
+                tl[u] = left_term<PREC>((double)__builtin_bit_cast(float, fb), lrow[NOPS * 64]);
             }
+            add_group<PREC, U, NOPS>(acc, tl, bv);
         }
         if (act) {
             double* P = a.P + (int64_t)a.slot[tile * M + t] * a.pstride + (int64_t)trows[t] * a.ldp + s;
@@ -1435,12 +1458,15 @@ size_t chunk_partial_bytes(const Graph& g, int32_t nsets, int32_t nops) {
 static bool quad_and_tiles(const Graph& g, int32_t nsets, int32_t nops, int32_t precision);
 
 size_t forward_partial_bytes(const Graph& g, int32_t nsets, int32_t nops, int32_t precision) {
+    // the chunk plan's rows are always needed: a launch over part of the sets
+    // runs the plain chunked form whatever the tiling
+    const size_t chunk = chunk_partial_bytes(g, nsets, nops);
     if (tiles_usable(g, nsets, nops, precision)) {
         size_t b = tile_partial_bytes(g, nsets, nops);
         if (quad_and_tiles(g, nsets, nops, precision)) b += (size_t)g.qb.cp_lead.nslots * nops * nsets * sizeof(double);
-        return b;
+        return std::max(b, chunk);
     }
-    return chunk_partial_bytes(g, nsets, nops);
+    return chunk;
 }
 
 // ------------------------------------------------ quadratic-target blocks ----
@@ -1579,8 +1605,14 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
                 const auto tv = left_term<PREC>((double)f2, ev);
 #pragma unroll
                 for (int op = 0; op < NOPS; ++op) {
-                    acc[j][op].add(tu, lv[op * 64]);
-                    acc[j][op].add(tv, xu[op]);
+                    if constexpr (PREC == CUT_F32C) {
+                        // the target's two records of this triple in one float
+                        // partial, one two-sum into the compensated sum
+                        acc[j][op].add_sum(__builtin_fmaf(tv, xu[op], tu * lv[op * 64]));
+                    } else {
+                        acc[j][op].add(tu, lv[op * 64]);
+                        acc[j][op].add(tv, xu[op]);
+                    }
                 }
             }
         }
@@ -1740,18 +1772,25 @@ static void launch_tiles_nops(const TileKArgs& t, const KArgs& k, int epi, int p
     else launch_combine_p<NOPS, EPI_RK>(k, prec, t.P, t.pstride, t.ldp, row0, nrows, s);
 }
 
-// whether launch_forward honours a set range [s0, s1) of `a` (the segment
-// kernel, chunked or not); the block, tile and complex-record kernels always
-// cover every set
+// whether launch_forward honours a set range [s0, s1) of `a`: a launch over a
+// proper range of the sets runs the segment kernel over the plain chunk plan
+// (always built with the tiling), the block and tile kernels only full-width
+// launches; the complex-record kernels always cover every set
 bool forward_set_ranges(const Graph& g, const PassArgs& a) {
-    if (cpass_usable(MODE_BCAST, EPI_RK, a) || cshort_usable(MODE_BCAST, EPI_RK, a)) return false;
-    return !tiles_usable(g, a.nsets, a.nops, a.precision) && !quadblocks_usable(g, a.nsets, a.nops, a.precision);
+    (void)g;
+    return !cpass_usable(MODE_BCAST, EPI_RK, a) && !cshort_usable(MODE_BCAST, EPI_RK, a);
 }
 
 void launch_forward(const Graph& g, int epi, const PassArgs& a, double* partials, hipStream_t s) {
     if (epi == EPI_ETA || a.csr != &g.csr[0][0] || partials == nullptr || cpass_usable(MODE_BCAST, epi, a) ||
         cshort_usable(MODE_BCAST, epi, a)) {
         launch_pass(MODE_BCAST, epi, a, s);
+        return;
+    }
+    const bool ranged = a.s1 > 0 && (a.s0 != 0 || a.s1 != a.nsets);
+    if (ranged) {
+        if (g.csr[0][0].cp.nlong > 0) launch_chunked(g, g.csr[0][0].cp, epi, a, partials, s);
+        else launch_pass(MODE_BCAST, epi, a, s);
         return;
     }
     if (!tiles_usable(g, a.nsets, a.nops, a.precision)) {

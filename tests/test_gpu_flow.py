@@ -80,6 +80,26 @@ def test_majorana_flow_ragged(L, prec, tiling):
             assert r < (1e-13 if prec == "F64" else 1e-7), (s, op, r)
 
 
+@pytest.mark.parametrize("tiling", [(1024, 512, 0), (64, 64, 1), (1024, 64, 8)])
+@pytest.mark.parametrize("prec", ["F64", "F32C"])
+def test_majorana_one_column_flow(L, prec, tiling):
+    """One coefficient set, H only (the plain FP64 flow's shape: one-column
+    passes with the quadratic rows staged in LDS), chunked tilings, hipGraph,
+    against the oracle."""
+    U.say(f"[flow] majorana m=16 one column {prec} tiling {tiling}")
+    m = 16
+    g = U.graph(L, "majorana", m)
+    L.cut_graph_set_tiling(g, *tiling)
+    og = A.majorana_graph(m)
+    z0 = workloads.small_majorana(m, 1, 1, seed=29)
+    z, _ = _flow(L, g, z0, [25], L.CUT_GEN_G2, getattr(L, "CUT_" + prec), 1e-2, flags=L.CUT_FLOW_HIPGRAPH)
+    L.cut_graph_set_tiling(g, 1024, 512, 0)
+    gen, _ = OG.make_generator(og, "g2", 0.5)
+    zr, _ = OF.integrate(og, gen, z0, 1e-2, [25])
+    r = _rel(z[:, 0, 0], zr[:, 0, 0])
+    assert r < (1e-13 if prec == "F64" else 1e-7), r
+
+
 @pytest.mark.parametrize("prec", ["F64", "F32C"])
 def test_majorana_flow_g1(L, prec):
     """The literal generator G1 in the flow (ragged, hipGraph) against the
