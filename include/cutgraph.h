@@ -72,7 +72,12 @@ typedef enum {
                                modes, the complete degree-p registry |c|+|a| <= p
                                (4 C(2M+p, p) labels, Eq. basis-size); size =
                                256 M + p (M in 1..5).  Complex coefficients; the
-                               generator [H_d, H_od] has a registry of its own */
+                               generator [H_d, H_od] has a registry of its own.
+                               Factors are Gaussian integers, exact in 128-bit
+                               arithmetic during compilation and stored as int16
+                               (re, im) pairs, or as the nearest FP64 pairs when
+                               one leaves int16 (M = 1 from p = 8; the degree-24
+                               one-mode registry reaches ~2e37) */
 } cut_algebra;
 
 /* Record sets stored in a graph (Eq. graph-actions). */
@@ -139,7 +144,8 @@ typedef struct {
  * every target and fixes the exact array sizes, the file is then sized and
  * mapped, the second traversal writes every record at its final place.  The
  * bundle holds the registry labels, block mask, pair list, rules identifier,
- * factor precision (int8), the target-grouped records of E_L and E_eta and one
+ * factor precision (int8; Pauli-boson: int16 or FP64 pairs, see
+ * CUT_ALG_PAULI_BOSON), the target-grouped records of E_L and E_eta and one
  * checksum per section.  Two builds are bitwise identical.
  * With CUT_BUILD_OUTSIDE (Majorana, m <= 32) the bundle also holds the outside
  * registry (every 6-subset of the modes, lexicographic) and the target-grouped
@@ -150,8 +156,9 @@ typedef struct {
  * `threads` <= 0 selects the hardware concurrency.  `desc` (nullable) receives
  * the sizes.  Errors: CUT_E_INVAL (unknown algebra or flag, size out of range:
  * E_pq 1..64, Majorana even 4..64; CUT_BUILD_OUTSIDE with E_pq, whose registry
- * is closed), CUT_E_UNSUPPORTED (CUT_BUILD_OUTSIDE above 32 modes), CUT_E_IO,
- * CUT_E_NOMEM. */
+ * is closed), CUT_E_UNSUPPORTED (CUT_BUILD_OUTSIDE above 32 modes; a
+ * Pauli-boson registry whose labels do not fit 64 bits or p > 31, or a factor
+ * beyond the int128 range), CUT_E_IO, CUT_E_NOMEM. */
 cut_status cut_graph_build(int32_t algebra, int32_t size, const char* path, int32_t threads,
                            uint32_t flags, cut_graph_desc* desc);
 
@@ -162,10 +169,15 @@ cut_status cut_graph_build(int32_t algebra, int32_t size, const char* path, int3
  * the target-sorted record stream to `hip_device` (Sec. 2.3: validated reload).
  * With CUT_LOAD_ADJOINT the input-sorted copies used by the adjoint are built
  * too.  Outside-space records, when the bundle has them, are uploaded in their
- * target order (forward action only).  On success *out owns all device memory;
- * release with cut_graph_free.
- * Errors: CUT_E_IO, CUT_E_FORMAT, CUT_E_CHECKSUM, CUT_E_NOMEM, CUT_E_DEVICE,
- * CUT_E_UNSUPPORTED (N >= 2^24 or more than 256 distinct factors). */
+ * target order (forward action only).  A device record carries 8 significant
+ * bits of factor; a wider Pauli-boson factor is loaded as several records on
+ * the same rows whose factors sum exactly to it (each the remainder truncated
+ * to 8 bits: at most 7 for an FP64 factor, all of its sign), so every pass
+ * evaluates the stored factor with the error bound of a longer segment.
+ * On success *out owns all device memory; release with cut_graph_free.
+ * Errors: CUT_E_IO, CUT_E_FORMAT (also a non-finite factor), CUT_E_CHECKSUM,
+ * CUT_E_NOMEM, CUT_E_DEVICE, CUT_E_UNSUPPORTED (N >= 2^24, more than 256
+ * distinct factors, or a factor piece outside the normal FP32 range). */
 cut_status cut_graph_load(const char* path, int32_t hip_device, uint32_t flags, cut_graph_t* out);
 
 cut_status cut_graph_info(cut_graph_t g, cut_graph_desc* desc);
@@ -232,12 +244,22 @@ cut_status cut_graph_apply(cut_graph_t g, int32_t which, int32_t precision, int6
                            int64_t ldx, double* y, int64_t ldy, uint32_t flags, void* stream);
 
 /* cut_graph_apply_adjoint: the graph-level adjoint (Sec. 2.4): the same factor,
- * accumulated into the input coordinate (factors are real, so no conjugation):
+ * accumulated into the input coordinate (the factors of the real records need
+ * no conjugation):
  *   g_x[j][op*nsets+s]  (=|+=) sum_{e: j_e=j} c_e * eta[i_e][s] * w[k_e][op*nsets+s]
  *   g_eta[i][s]         (=|+=) sum_{e: i_e=i} c_e * sum_op w[k_e][op*nsets+s] * x[j_e][op*nsets+s]
  * Either output may be NULL (then its inputs may be NULL too).  Needs a graph
  * loaded with CUT_LOAD_ADJOINT (else CUT_E_INVAL).  Types as cut_graph_apply.
- * which = CUT_GRAPH_OUTSIDE is not supported (CUT_E_INVAL). */
+ * which = CUT_GRAPH_OUTSIDE is not supported (CUT_E_INVAL).  On Pauli-boson
+ * graphs (real-split rows) this real transpose is the complex adjoint with the
+ * conjugation the paper names: g_x[j] = sum conj(c xi_a) w_k and
+ * g_eta[a] = sum conj(c x_j) w_k. */
+cut_status cut_graph_apply_adjoint(cut_graph_t g, int32_t which, int32_t precision, int64_t nsets,
+                                   int64_t nops, const void* eta, int64_t lde, const void* x,
+                                   int64_t ldx, const void* w, int64_t ldw, double* g_x,
+                                   int64_t ldgx, double* g_eta, int64_t ldge, uint32_t flags,
+                                   void* stream);
+
 /* cut_graph_apply_noalloc: cut_graph_apply for callers that cannot allocate
  * device memory or call a reserving entry point first (code under stream
  * capture, tight serving loops, harnesses that forbid allocation).  Same
@@ -253,12 +275,6 @@ cut_status cut_graph_apply(cut_graph_t g, int32_t which, int32_t precision, int6
 cut_status cut_graph_apply_noalloc(cut_graph_t g, int32_t which, int32_t precision, int64_t nsets,
                                    int64_t nops, const void* eta, int64_t lde, const void* x, int64_t ldx,
                                    double* y, int64_t ldy, uint32_t flags, void* stream);
-
-cut_status cut_graph_apply_adjoint(cut_graph_t g, int32_t which, int32_t precision, int64_t nsets,
-                                   int64_t nops, const void* eta, int64_t lde, const void* x,
-                                   int64_t ldx, const void* w, int64_t ldw, double* g_x,
-                                   int64_t ldgx, double* g_eta, int64_t ldge, uint32_t flags,
-                                   void* stream);
 
 /* -------------------------------------------------------------- generator --
  * cut_generator: eta[r][s] from h[r][s] (both double with leading dimensions;

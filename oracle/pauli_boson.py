@@ -178,6 +178,88 @@ class PBGraph:
         return y
 
 
+def _streamed_part(args):
+    labels, gen_slice, xi_slice, X = args
+    import numpy as np
+    index = {L: n for n, L in enumerate(labels)}
+    F = np.zeros((len(labels),) + X.shape[1:], dtype=complex)
+    S = np.zeros(F.shape)
+    n = np.zeros(len(labels), dtype=np.int64)
+    aX = np.abs(X.real) + np.abs(X.imag)
+    for A, xa in zip(gen_slice, xi_slice):
+        axa = np.abs(xa.real) + np.abs(xa.imag)
+        for j, B in enumerate(labels):
+            for L, f in commutator(A, B).items():
+                k = index.get(L)
+                if k is not None:
+                    F[k] += complex(*f) * xa * X[j]
+                    S[k] += abs(complex(*f)) * axa * aX[j]
+                    n[k] += 1
+    return F, S, n
+
+
+def streamed_action(M: int, p: int, h, X, workers: int = 1):
+    """The generator and retained action of ``PBGraph`` (E_eta, then E_L of
+    Eq. graph-actions) for registries too large to hold their records: xi =
+    sum alpha (Dh)_i ((I-D)h)_j over the diagonal / off-diagonal pairs, the
+    generator registry being every label those brackets reach, then F_k = sum
+    beta xi_a X_j over every (generator label, registry label) pair, each
+    bracket expanded as it is needed.  h is complex [N, sets] (one Hamiltonian
+    per set), X complex [N, nops, sets]; the pairs are dealt over ``workers``
+    processes by generator label and the partial sums added.  Returns a dict:
+    labels, gen_labels, xi [NG, sets], F [N, nops, sets], and for the rounding
+    error of any evaluation order, per output coordinate, the number of terms
+    (xi_n, F_n) and the sums of their absolute sizes (xi_abs: |alpha| |h_i|
+    |h_j|; F_abs: |beta| |xi_a| |X_j|, with |v| = |Re v| + |Im v|)."""
+    import numpy as np
+    labels = registry(M, p)
+    diag = [is_diagonal(L) for L in labels]
+    D = [n for n in range(len(labels)) if diag[n]]
+    OD = [n for n in range(len(labels)) if not diag[n]]
+    h = np.asarray(h, dtype=complex)
+    ah = np.abs(h.real) + np.abs(h.imag)
+    acc: Dict[Label, list] = {}
+    for i in D:
+        for j in OD:
+            for L, f in commutator(labels[i], labels[j]).items():
+                e = acc.setdefault(L, [0, 0, 0])
+                e[0] = e[0] + complex(*f) * h[i] * h[j]
+                e[1] = e[1] + abs(complex(*f)) * ah[i] * ah[j]
+                e[2] += 1
+    gen_labels = sorted(acc, key=sort_key)
+    xi = np.stack([acc[L][0] for L in gen_labels]).astype(complex)
+    X = np.asarray(X, dtype=complex)
+    xi_b = xi[:, None, :]
+    parts = [(labels, gen_labels[w::workers], xi_b[w::workers], X) for w in range(workers)]
+    if workers == 1:
+        out = [_streamed_part(parts[0])]
+    else:
+        import multiprocessing as mp
+        with mp.get_context("fork").Pool(workers) as pool:
+            out = pool.map(_streamed_part, parts)
+    F, S, n = (sum(o[q] for o in out) for q in range(3))
+    return {"labels": labels, "gen_labels": gen_labels, "xi": xi,
+            "xi_abs": np.stack([acc[L][1] for L in gen_labels]).astype(float),
+            "xi_n": np.array([acc[L][2] for L in gen_labels], dtype=np.int64),
+            "F": F, "F_abs": S, "F_n": n}
+
+
+def adjoint(g: "PBGraph", xi, x, w):
+    """Reverse traversal of E_L (Sec. 2.4: the stored factor, accumulated back
+    into the input coordinates with conjugation): with F_k = sum beta xi_a x_j,
+    g_x[j] = sum conj(beta xi_a) w_k and g_xi[a] = sum conj(beta x_j) w_k, the
+    gradients of Re <w, F> = Re sum conj(w_k) F_k with respect to x and xi
+    (complex vectors).  Returns (g_x, g_xi)."""
+    import numpy as np
+    gx = np.zeros(g.N, dtype=complex)
+    gxi = np.zeros(g.NG, dtype=complex)
+    for k, a, j, f in g.flow:
+        c = complex(*f)
+        gx[j] += np.conj(c * xi[a]) * w[k]
+        gxi[a] += np.conj(c * x[j]) * w[k]
+    return gx, gxi
+
+
 def outside_action(g: "PBGraph", xi, x):
     """C_q = sum gamma xi_a x_j over E_C (the graph must hold outside records)."""
     import numpy as np

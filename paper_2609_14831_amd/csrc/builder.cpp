@@ -23,6 +23,7 @@
 #include <algorithm>
 #include <atomic>
 #include <chrono>
+#include <cmath>
 #include <cstring>
 #include <functional>
 #include <thread>
@@ -347,9 +348,13 @@ struct PBCodec {
     }
 };
 
+// Factors are exact 128-bit Gaussian integers: normal ordering of the degree-24
+// one-mode registry reaches 24! C(48, 24) ~ 2e37, beyond int64.
+typedef __int128 i128;
+
 struct PBTerm {
     uint64_t key;
-    int64_t re, im;
+    i128 re, im;
 };
 
 // [B_A, B_B] = B_A B_B - B_B B_A, merged by label, zero sums dropped.  Pauli
@@ -360,8 +365,8 @@ struct PBTerm {
 struct PBAlgebra {
     PBCodec cd;
     int p = 0;
-    int64_t binom[64][64];
-    int64_t fact[32];
+    int64_t binom[64][64];                      // C(63, 31) < 2^63
+    i128 fact[34];                              // 33! < 2^127
     PBAlgebra(int M_, int p_) : p(p_) {
         cd.M = M_;
         int w = 1;
@@ -370,11 +375,12 @@ struct PBAlgebra {
         for (int n = 0; n < 64; ++n)
             for (int k = 0; k < 64; ++k) binom[n][k] = (k == 0) ? 1 : (n == 0 ? 0 : binom[n - 1][k - 1] + binom[n - 1][k]);
         fact[0] = 1;
-        for (int n = 1; n < 21; ++n) fact[n] = fact[n - 1] * n;   // 20! is the last in int64
-        for (int n = 21; n < 32; ++n) fact[n] = 0;
+        for (int n = 1; n < 34; ++n) fact[n] = fact[n - 1] * n;
     }
-    bool fits() const { return (2 * cd.M + 1) * cd.W + 2 <= 64 && 3 * p < 64; }
-    mutable std::atomic<bool> overflow{false};   // a factor left the int64 range (never cleared)
+    // 64-bit labels; a product's exponents (<= 2p) index binom and its
+    // contraction orders (<= p, one factor is a registry label) index fact
+    bool fits() const { return (2 * cd.M + 1) * cd.W + 2 <= 64 && 2 * p < 64; }
+    mutable std::atomic<bool> overflow{false};   // a factor left the int128 range (never cleared)
 
     static void pauli(int t, int u, int& w, int& e) {
         if (t == 0 || u == 0) {
@@ -400,11 +406,11 @@ struct PBAlgebra {
         int k[8] = {0}, kmax[8], c[8], a[8];
         for (int m = 0; m < M; ++m) kmax[m] = std::min(ax[m], cy[m]);
         for (;;) {
-            int64_t f = sign;
+            i128 f = sign;
             for (int m = 0; m < M; ++m) {
-                int64_t g;
-                if (k[m] >= 21 || __builtin_mul_overflow(fact[k[m]], binom[ax[m]][k[m]], &g) ||
-                    __builtin_mul_overflow(g, binom[cy[m]][k[m]], &g) || __builtin_mul_overflow(f, g, &f))
+                i128 g;
+                if (__builtin_mul_overflow(fact[k[m]], (i128)binom[ax[m]][k[m]], &g) ||
+                    __builtin_mul_overflow(g, (i128)binom[cy[m]][k[m]], &g) || __builtin_mul_overflow(f, g, &f))
                     overflow = true;
                 c[m] = cx[m] + cy[m] - k[m];
                 a[m] = ax[m] + ay[m] - k[m];
@@ -424,7 +430,7 @@ struct PBAlgebra {
         size_t w = 0;
         for (size_t r = 0; r < out.size();) {
             size_t s = r;
-            int64_t re = 0, im = 0;
+            i128 re = 0, im = 0;
             for (; s < out.size() && out[s].key == out[r].key; ++s) {
                 re += out[s].re;
                 im += out[s].im;
@@ -468,22 +474,25 @@ struct PBAlgebra {
     }
 };
 
+template <class F>
 struct PBRec {
     int32_t i, j;
-    int16_t re, im;
+    F re, im;
 };
 
-// sorts every segment [off[s], off[s+1]) of the arrays (ri, rj, rc) by (ri, rj)
-static void sort_segments(const std::vector<int64_t>& off, int32_t* ri, int32_t* rj, int16_t* rc, int nt) {
+// sorts every segment [off[s], off[s+1]) of the arrays (ri, rj, rc) by (ri, rj);
+// rc holds (re, im) pairs of F
+template <class F>
+static void sort_segments(const std::vector<int64_t>& off, int32_t* ri, int32_t* rj, F* rc, int nt) {
     const int64_t nseg = (int64_t)off.size() - 1;
     parallel_for(nseg, nt, [&](int64_t b, int64_t e) {
-        std::vector<PBRec> tmp;
+        std::vector<PBRec<F>> tmp;
         for (int64_t s = b; s < e; ++s) {
             const int64_t o = off[s], n = off[s + 1] - off[s];
             tmp.resize((size_t)n);
             for (int64_t t = 0; t < n; ++t) tmp[t] = {ri[o + t], rj[o + t], rc[2 * (o + t)], rc[2 * (o + t) + 1]};
             std::sort(tmp.begin(), tmp.end(),
-                      [](const PBRec& x, const PBRec& y) { return x.i != y.i ? x.i < y.i : x.j < y.j; });
+                      [](const PBRec<F>& x, const PBRec<F>& y) { return x.i != y.i ? x.i < y.i : x.j < y.j; });
             for (int64_t t = 0; t < n; ++t) {
                 ri[o + t] = tmp[t].i;
                 rj[o + t] = tmp[t].j;
@@ -494,10 +503,24 @@ static void sort_segments(const std::vector<int64_t>& off, int32_t* ri, int32_t*
     });
 }
 
-static int16_t to_i16(int64_t v) {
-    if (v < -32767 || v > 32767) CUT_FAIL(CUT_E_UNSUPPORTED, "cut_graph_build: factor %lld exceeds int16", (long long)v);
-    return (int16_t)v;
-}
+static bool fits_i16(i128 v) { return v >= -32767 && v <= 32767; }
+
+// Factor arrays of a Pauli-boson bundle: (re, im) pairs of int16 while every
+// factor fits (4 bytes a record), else of FP64 (16 bytes a record, each factor
+// the FP64 value nearest the exact integer).
+struct PBFactors {
+    uint8_t* base = nullptr;
+    bool wide = false;
+    void put(int64_t q, i128 re, i128 im) const {
+        if (wide) {
+            const double v[2] = {(double)re, (double)im};
+            std::memcpy(base + 16 * q, v, 16);
+        } else {
+            const int16_t v[2] = {(int16_t)re, (int16_t)im};
+            std::memcpy(base + 4 * q, v, 4);
+        }
+    }
+};
 
 // Compiles the Pauli-boson graph (Sec. 2.2-2.3): registry, generator records
 // E_eta and generator registry, retained records E_L and (optionally) the
@@ -530,15 +553,19 @@ static cut_status build_pauli_boson(int M, int p, const char* path, int nt, bool
         struct GRec {
             uint64_t key;
             int32_t i, j;
-            int64_t re, im;
+            i128 re, im;
         };
         std::vector<GRec> graw;
+        std::atomic<int> wide{0};          // a factor leaves int16: FP64 factor arrays
         {
             std::vector<PBTerm> t;
             for (int32_t i : D)
                 for (int32_t j : OD) {
                     alg.commutator(reg[(size_t)i], reg[(size_t)j], t);
-                    for (auto& x : t) graw.push_back({x.key, i, j, x.re, x.im});
+                    for (auto& x : t) {
+                        graw.push_back({x.key, i, j, x.re, x.im});
+                        if (!fits_i16(x.re) || !fits_i16(x.im)) wide = 1;
+                    }
                 }
         }
         std::vector<uint64_t> gen;
@@ -588,9 +615,12 @@ static cut_status build_pauli_boson(int M, int p, const char* path, int nt, bool
                         alg.commutator(gen[(size_t)a], reg[(size_t)j], t);
                         for (auto& x : t) {
                             auto it = ridx.find(x.key);
+                            const bool w16 = !fits_i16(x.re) || !fits_i16(x.im);
                             if (it != ridx.end()) {
                                 tcnt[tid][(size_t)it->second]++;
+                                if (w16) wide = 1;
                             } else if (outside) {
+                                if (w16) wide = 1;
                                 auto ic = cidx.find(x.key);
                                 if (ic == cidx.end()) stray = 1;
                                 else ccnt[(size_t)ic->second].fetch_add(1, std::memory_order_relaxed);
@@ -622,6 +652,8 @@ static cut_status build_pauli_boson(int M, int p, const char* path, int nt, bool
         }
         ccnt = std::vector<std::atomic<int64_t>>();
         const int64_t Nc = (int64_t)olab.size(), Ec = coff.back();
+        if (alg.overflow) CUT_FAIL(CUT_E_UNSUPPORTED, "cut_graph_build: a factor exceeds the int128 range");
+        const uint32_t fb = wide ? 16 : 4;
 
         // file layout: base sections, generator labels, outside sections
         struct Sz {
@@ -631,15 +663,15 @@ static cut_status build_pauli_boson(int M, int p, const char* path, int nt, bool
         std::vector<Sz> secs = {{SEC_LABELS, 8, (uint64_t)N},       {SEC_DIAG, 1, (uint64_t)N},
                                 {SEC_PAIRS, 4, 0},                   {SEC_FLOW_OFF, 8, (uint64_t)N + 1},
                                 {SEC_FLOW_I, 4, (uint64_t)E},        {SEC_FLOW_J, 4, (uint64_t)E},
-                                {SEC_FLOW_C, 4, (uint64_t)E},        {SEC_GEN_OFF, 8, (uint64_t)NG + 1},
+                                {SEC_FLOW_C, fb, (uint64_t)E},       {SEC_GEN_OFF, 8, (uint64_t)NG + 1},
                                 {SEC_GEN_I, 4, (uint64_t)Eg},        {SEC_GEN_J, 4, (uint64_t)Eg},
-                                {SEC_GEN_C, 4, (uint64_t)Eg},        {SEC_GEN_LABELS, 8, (uint64_t)NG}};
+                                {SEC_GEN_C, fb, (uint64_t)Eg},       {SEC_GEN_LABELS, 8, (uint64_t)NG}};
         if (outside) {
             secs.push_back({SEC_OUT_LABELS, 8, (uint64_t)Nc});
             secs.push_back({SEC_OUT_OFF, 8, (uint64_t)Nc + 1});
             secs.push_back({SEC_OUT_I, 4, (uint64_t)Ec});
             secs.push_back({SEC_OUT_J, 4, (uint64_t)Ec});
-            secs.push_back({SEC_OUT_C, 4, (uint64_t)Ec});
+            secs.push_back({SEC_OUT_C, fb, (uint64_t)Ec});
         }
         const int nsec = (int)secs.size();
         SectionEntry tab[kMaxSections];
@@ -667,22 +699,21 @@ static cut_status build_pauli_boson(int M, int p, const char* path, int nt, bool
         {
             int32_t* Gi = (int32_t*)sec(8);
             int32_t* Gj = (int32_t*)sec(9);
-            int16_t* Gc = (int16_t*)sec(10);
+            const PBFactors Gc{sec(10), fb == 16};
             for (int64_t e = 0; e < Eg; ++e) {
                 Gi[e] = graw[(size_t)e].i;
                 Gj[e] = graw[(size_t)e].j;
-                Gc[2 * e] = to_i16(graw[(size_t)e].re);
-                Gc[2 * e + 1] = to_i16(graw[(size_t)e].im);
+                Gc.put(e, graw[(size_t)e].re, graw[(size_t)e].im);
             }
         }
         graw.clear();
         graw.shrink_to_fit();
         int32_t* Li = (int32_t*)sec(4);
         int32_t* Lj = (int32_t*)sec(5);
-        int16_t* Lc = (int16_t*)sec(6);
+        const PBFactors Lc{sec(6), fb == 16};
         int32_t* Ci = outside ? (int32_t*)sec(14) : nullptr;
         int32_t* Cj = outside ? (int32_t*)sec(15) : nullptr;
-        int16_t* Cc = outside ? (int16_t*)sec(16) : nullptr;
+        const PBFactors Cc{outside ? sec(16) : nullptr, fb == 16};
         if (outside) {
             std::memcpy(sec(12), olab.data(), Nc * 8);
             std::memcpy(sec(13), coff.data(), (Nc + 1) * 8);
@@ -693,30 +724,23 @@ static cut_status build_pauli_boson(int M, int p, const char* path, int nt, bool
             for (int64_t k = 0; k < N; ++k) curL[(size_t)k] = loff[(size_t)k];
             for (int64_t q = 0; q < Nc; ++q) curC[(size_t)q] = coff[(size_t)q];
             std::atomic<int64_t> next{0};
-            std::atomic<int> overflow{0};
             auto work = [&]() {
                 std::vector<PBTerm> t;
                 for (int64_t a; (a = next.fetch_add(1)) < NG;)
                     for (int64_t j = 0; j < N; ++j) {
                         alg.commutator(gen[(size_t)a], reg[(size_t)j], t);
                         for (auto& x : t) {
-                            if (x.re < -32767 || x.re > 32767 || x.im < -32767 || x.im > 32767) {
-                                overflow = 1;
-                                continue;
-                            }
                             auto it = ridx.find(x.key);
                             if (it != ridx.end()) {
                                 const int64_t q = curL[(size_t)it->second].fetch_add(1);
                                 Li[q] = (int32_t)a;
                                 Lj[q] = (int32_t)j;
-                                Lc[2 * q] = (int16_t)x.re;
-                                Lc[2 * q + 1] = (int16_t)x.im;
+                                Lc.put(q, x.re, x.im);
                             } else if (outside) {
                                 const int64_t q = curC[(size_t)cand2out[(size_t)cidx.at(x.key)]].fetch_add(1);
                                 Ci[q] = (int32_t)a;
                                 Cj[q] = (int32_t)j;
-                                Cc[2 * q] = (int16_t)x.re;
-                                Cc[2 * q + 1] = (int16_t)x.im;
+                                Cc.put(q, x.re, x.im);
                             }
                         }
                     }
@@ -725,11 +749,14 @@ static cut_status build_pauli_boson(int M, int p, const char* path, int nt, bool
             for (int q = 1; q < nt; ++q) th.emplace_back(work);
             work();
             for (auto& x : th) x.join();
-            if (overflow) CUT_FAIL(CUT_E_UNSUPPORTED, "cut_graph_build: a factor exceeds int16");
         }
-        if (alg.overflow) CUT_FAIL(CUT_E_UNSUPPORTED, "cut_graph_build: a factor exceeds the int64 range");
-        sort_segments(loff, Li, Lj, Lc, nt);
-        if (outside) sort_segments(coff, Ci, Cj, Cc, nt);
+        if (fb == 16) {
+            sort_segments(loff, Li, Lj, (double*)Lc.base, nt);
+            if (outside) sort_segments(coff, Ci, Cj, (double*)Cc.base, nt);
+        } else {
+            sort_segments(loff, Li, Lj, (int16_t*)Lc.base, nt);
+            if (outside) sort_segments(coff, Ci, Cj, (int16_t*)Cc.base, nt);
+        }
 
         for (int s = 0; s < nsec; ++s) tab[s].checksum = checksum64(sec(s), tab[s].count * tab[s].elem_bytes);
         BundleHeader h{};
@@ -742,7 +769,7 @@ static cut_status build_pauli_boson(int M, int p, const char* path, int nt, bool
         h.n_records = E;
         h.n_gen_records = Eg;
         h.n_pairs = 0;
-        h.factor_bytes = 4;
+        h.factor_bytes = (int32_t)fb;
         h.gen_sign = 1;
         h.n_sections = (uint32_t)nsec;
         h.section_table_offset = sizeof(BundleHeader);
@@ -754,8 +781,8 @@ static cut_status build_pauli_boson(int M, int p, const char* path, int nt, bool
         for (int s = 3; s < nsec; ++s) rc = mix64(rc ^ tab[s].checksum);
         h.records_checksum = rc;
         snprintf(h.identifier, sizeof h.identifier,
-                 "pauli-boson M=%d p=%d key=deg,tau,c1,a1..:%d bits order=key mask=I|z,c=a factors=int16x2", M, p,
-                 alg.cd.W);
+                 "pauli-boson M=%d p=%d key=deg,tau,c1,a1..:%d bits order=key mask=I|z,c=a factors=%s", M, p,
+                 alg.cd.W, fb == 16 ? "f64x2" : "int16x2");
         h.header_checksum = 0;
         std::memcpy(base + sizeof(BundleHeader), tab, tab_bytes);
         h.header_checksum = checksum64(&h, sizeof h) ^ checksum64(tab, tab_bytes);
@@ -1067,7 +1094,7 @@ void read_bundle(const char* path, bool verify, HostGraph& g) {
     const int64_t N = h.n_ops;
     if (N <= 0 || h.n_records < 0 || h.n_gen_records < 0 || h.n_pairs < 0 || h.n_pairs > N || h.n_gen_ops < 0)
         CUT_FAIL(CUT_E_FORMAT, "%s: bad sizes", path);
-    if ((h.factor_bytes != 1 && h.factor_bytes != 4) || (h.gen_sign != 1 && h.gen_sign != -1))
+    if ((h.factor_bytes != 1 && h.factor_bytes != 4 && h.factor_bytes != 16) || (h.gen_sign != 1 && h.gen_sign != -1))
         CUT_FAIL(CUT_E_FORMAT, "%s: bad factor format", path);
     const bool own_gen = h.n_gen_ops > 0;
     const int64_t NG = own_gen ? h.n_gen_ops : N;
@@ -1131,7 +1158,7 @@ void read_bundle(const char* path, bool verify, HostGraph& g) {
     }
     // structural validation: offsets monotone and complete, indices in range
     // (left inputs of E_L and E_C are generator rows, everything else operator
-    // rows), factors nonzero
+    // rows), factors nonzero and finite
     for (int w = 0; w < (outside ? 3 : 2); ++w) {
         const int64_t E = w == 0 ? h.n_records : w == 1 ? h.n_gen_records : h.n_out_records;
         const int64_t nseg = w == 2 ? h.n_out_ops : w == 1 ? NG : N;
@@ -1149,11 +1176,16 @@ void read_bundle(const char* path, bool verify, HostGraph& g) {
                 bool zero;
                 if (fb == 1) {
                     zero = rc[t] == 0;
-                } else {
+                } else if (fb == 4) {
                     int16_t re, im;
                     std::memcpy(&re, rc + 4 * t, 2);
                     std::memcpy(&im, rc + 4 * t + 2, 2);
                     zero = re == 0 && im == 0;
+                } else {
+                    double re, im;
+                    std::memcpy(&re, rc + 16 * t, 8);
+                    std::memcpy(&im, rc + 16 * t + 8, 8);
+                    zero = (re == 0 && im == 0) || !std::isfinite(re) || !std::isfinite(im);
                 }
                 if ((uint32_t)ri[t] >= ilim || (uint32_t)rj[t] >= (uint64_t)N || zero) bad = 1;
             }

@@ -10,6 +10,7 @@
 // Each record is 8 bytes: uint32 (f_hi << 24 | a), uint32 (f_lo << 24 | b), where
 // (f_hi, f_lo) is the bf16 bit pattern of the integer factor (exact for int8).
 #include <algorithm>
+#include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -748,16 +749,51 @@ static void build_copies(Graph& g, const HostGraph& hg, int w, bool adjoint) {
     }
 }
 
-// Device record with an integer factor v: the factor rides as the bf16 bit
-// pattern of (float)v, which must be exact (the low 16 bits of the float zero).
-static uint2 pack_record_int(int32_t v, uint32_t a, uint32_t b) {
-    const float f = (float)v;
+// Device record of a factor piece f, a value of at most 8 significant bits in
+// the normal FP32 range: its bf16 bit pattern (the high half of f's FP32 bits,
+// the low half being zero) rides in the top bytes as in pack_record.
+static uint2 pack_piece(float f, uint32_t a, uint32_t b) {
     uint32_t bits;
     std::memcpy(&bits, &f, 4);
-    if ((bits & 0xFFFFu) != 0 || (float)v != f || v == 0)
-        CUT_FAIL(CUT_E_UNSUPPORTED, "factor %d is not exactly representable in the device records", v);
     const uint32_t h = bits >> 16;
     return make_uint2(((h >> 8) << 24) | a, ((h & 0xFFu) << 24) | b);
+}
+
+// Factor pieces.  A device record carries 8 significant bits of factor, so a
+// wider factor v (Pauli-boson normal ordering reaches 24! C(48, 24) ~ 2e37 in
+// the degree-24 one-mode registry) becomes several records on the same rows:
+// piece t is the current remainder truncated to its leading 8 bits, and the
+// remainder minus t is exact in FP64 and 8 bits shorter, so the pieces (at most
+// 7 for an FP64 factor, 1 for any factor of <= 8 significant bits) all carry
+// v's sign and sum exactly to v.  A piece outside the normal FP32 range is
+// refused.  Returns the number of pieces.
+static int factor_pieces(double v, float out[8]) {
+    if (!std::isfinite(v)) CUT_FAIL(CUT_E_FORMAT, "factor %g is not finite", v);
+    int n = 0;
+    while (v != 0.0) {
+        int e;
+        const double m = std::frexp(v, &e);                         // v = m 2^e, 0.5 <= |m| < 1
+        const double t = std::ldexp(std::trunc(std::ldexp(m, 8)), e - 8);
+        if (e < -125 || e > 128 || n == 8)
+            CUT_FAIL(CUT_E_UNSUPPORTED, "factor %.17g is outside the range of the device records", v);
+        out[n++] = (float)t;                                         // exact: 8 significant bits
+        v -= t;                                                      // exact
+    }
+    return n;
+}
+
+// Complex factor of record e of Pauli-boson record set w: int16 or FP64 pairs.
+static inline void pb_factor(const HostGraph& hg, int w, int64_t e, double& re, double& im) {
+    if (hg.hdr.factor_bytes == 16) {
+        std::memcpy(&re, hg.rc[w] + 16 * e, 8);
+        std::memcpy(&im, hg.rc[w] + 16 * e + 8, 8);
+    } else {
+        int16_t r, i;
+        std::memcpy(&r, hg.rc[w] + 4 * e, 2);
+        std::memcpy(&i, hg.rc[w] + 4 * e + 2, 2);
+        re = r;
+        im = i;
+    }
 }
 
 // Uploads a target-grouped stream as orientation 0 of record set w and, with
@@ -794,23 +830,20 @@ static void upload_set(Graph& g, int w, std::vector<int64_t>&& off, std::vector<
 // operand).  A record y_k += c xi_a x_j with c = re + i im becomes
 //   Re y_k += re (xi_a^r x_j^r - xi_a^i x_j^i) - im (xi_a^r x_j^i + xi_a^i x_j^r)
 //   Im y_k += re (xi_a^r x_j^i + xi_a^i x_j^r) + im (xi_a^r x_j^r - xi_a^i x_j^i)
-// i.e. up to four real records per target row, kept in the stored order.
+// i.e. up to four real records per target row and factor piece, kept in the
+// stored order.
 static void real_split(const HostGraph& hg, int w, int64_t nk, std::vector<int64_t>& off2, std::vector<uint2>& rec2) {
     const int64_t* off = hg.off[w];
     const int32_t* ri = hg.ri[w];
     const int32_t* rj = hg.rj[w];
-    const int8_t* rc = hg.rc[w];
-    auto factor = [&](int64_t e, int16_t& re, int16_t& im) {
-        std::memcpy(&re, rc + 4 * e, 2);
-        std::memcpy(&im, rc + 4 * e + 2, 2);
-    };
     off2.assign(2 * nk + 1, 0);
+    float pre[8], pim[8];
     for (int64_t k = 0; k < nk; ++k) {
         int64_t n = 0;
         for (int64_t e = off[k]; e < off[k + 1]; ++e) {
-            int16_t re, im;
-            factor(e, re, im);
-            n += 2 * (re != 0) + 2 * (im != 0);
+            double re, im;
+            pb_factor(hg, w, e, re, im);
+            n += 2 * factor_pieces(re, pre) + 2 * factor_pieces(im, pim);
         }
         off2[2 * k + 1] = n;    // real row of target k
         off2[2 * k + 2] = n;    // imaginary row (same count)
@@ -820,21 +853,22 @@ static void real_split(const HostGraph& hg, int w, int64_t nk, std::vector<int64
     for (int64_t k = 0; k < nk; ++k) {
         int64_t pr = off2[2 * k], pi = off2[2 * k + 1];
         for (int64_t e = off[k]; e < off[k + 1]; ++e) {
-            int16_t re, im;
-            factor(e, re, im);
+            double re, im;
+            pb_factor(hg, w, e, re, im);
+            const int nre = factor_pieces(re, pre), nim = factor_pieces(im, pim);
             const uint32_t ar = 2u * (uint32_t)ri[e], ai = ar + 1u;
             const uint32_t jr = 2u * (uint32_t)rj[e], ji = jr + 1u;
-            if (re != 0) {
-                rec2[pr++] = pack_record_int(re, ar, jr);
-                rec2[pr++] = pack_record_int(-re, ai, ji);
-                rec2[pi++] = pack_record_int(re, ar, ji);
-                rec2[pi++] = pack_record_int(re, ai, jr);
+            for (int t = 0; t < nre; ++t) {
+                rec2[pr++] = pack_piece(pre[t], ar, jr);
+                rec2[pr++] = pack_piece(-pre[t], ai, ji);
+                rec2[pi++] = pack_piece(pre[t], ar, ji);
+                rec2[pi++] = pack_piece(pre[t], ai, jr);
             }
-            if (im != 0) {
-                rec2[pr++] = pack_record_int(-im, ar, ji);
-                rec2[pr++] = pack_record_int(-im, ai, jr);
-                rec2[pi++] = pack_record_int(im, ar, jr);
-                rec2[pi++] = pack_record_int(-im, ai, ji);
+            for (int t = 0; t < nim; ++t) {
+                rec2[pr++] = pack_piece(-pim[t], ar, ji);
+                rec2[pr++] = pack_piece(-pim[t], ai, jr);
+                rec2[pi++] = pack_piece(pim[t], ar, jr);
+                rec2[pi++] = pack_piece(-pim[t], ai, ji);
             }
         }
     }
@@ -844,40 +878,37 @@ static void real_split(const HostGraph& hg, int w, int64_t nk, std::vector<int64
 // generator rows 2NG, outside rows 2Nc.
 // Complex form of a set of records (Pauli-boson graphs), grouped by complex
 // target in the stored order: x = (f_hi << 24) | (imag << 23) | a,
-// y = (f_lo << 24) | j with (f_hi, f_lo) the bf16 pattern of the nonzero part
-// of the factor (a factor with both parts nonzero, which the commutators of
-// this algebra do not produce, would become two records).  The left index must
-// fit in 23 bits.
+// y = (f_lo << 24) | j with (f_hi, f_lo) the bf16 pattern of a factor piece of
+// the real or the imaginary part (one record per nonzero part and piece: the
+// commutators of this algebra give purely real or purely imaginary factors).
+// The left index must fit in 23 bits.
 static void complex_records(const HostGraph& hg, int w, int64_t nk, std::vector<int64_t>& off2,
                             std::vector<uint2>& rec2) {
     const int64_t* off = hg.off[w];
     const int32_t* ri = hg.ri[w];
     const int32_t* rj = hg.rj[w];
-    const int8_t* rc = hg.rc[w];
-    auto factor = [&](int64_t e, int16_t& re, int16_t& im) {
-        std::memcpy(&re, rc + 4 * e, 2);
-        std::memcpy(&im, rc + 4 * e + 2, 2);
-    };
     off2.assign(nk + 1, 0);
+    float pre[8], pim[8];
     for (int64_t k = 0; k < nk; ++k) {
         int64_t n = 0;
         for (int64_t e = off[k]; e < off[k + 1]; ++e) {
-            int16_t re, im;
-            factor(e, re, im);
-            n += (re != 0) + (im != 0);
+            double re, im;
+            pb_factor(hg, w, e, re, im);
+            n += factor_pieces(re, pre) + factor_pieces(im, pim);
         }
         off2[k + 1] = off2[k] + n;
     }
     rec2.resize((size_t)off2[nk]);
     int64_t q = 0;
     for (int64_t e = 0; e < off[nk]; ++e) {
-        int16_t re, im;
-        factor(e, re, im);
+        double re, im;
+        pb_factor(hg, w, e, re, im);
         if ((uint32_t)ri[e] >= (1u << 23))
             CUT_FAIL(CUT_E_UNSUPPORTED, "generator registry of %d labels exceeds 2^23", ri[e] + 1);
-        if (re != 0) rec2[q++] = pack_record_int(re, (uint32_t)ri[e], (uint32_t)rj[e]);
-        if (im != 0) {
-            const uint2 r = pack_record_int(im, (uint32_t)ri[e], (uint32_t)rj[e]);
+        const int nre = factor_pieces(re, pre), nim = factor_pieces(im, pim);
+        for (int t = 0; t < nre; ++t) rec2[q++] = pack_piece(pre[t], (uint32_t)ri[e], (uint32_t)rj[e]);
+        for (int t = 0; t < nim; ++t) {
+            const uint2 r = pack_piece(pim[t], (uint32_t)ri[e], (uint32_t)rj[e]);
             rec2[q++] = make_uint2(r.x | (1u << 23), r.y);
         }
     }
@@ -981,7 +1012,7 @@ extern "C" cut_status cut_graph_load(const char* path, int32_t dev, uint32_t fla
         read_bundle(path, (flags & CUT_LOAD_NO_CHECKSUM) == 0, hg);
         const int64_t N = hg.hdr.n_ops;
         const bool pb = hg.hdr.algebra == CUT_ALG_PAULI_BOSON;
-        if (pb != (hg.hdr.factor_bytes == 4) || pb != (hg.hdr.n_gen_ops > 0))
+        if (pb != (hg.hdr.factor_bytes == 4 || hg.hdr.factor_bytes == 16) || pb != (hg.hdr.n_gen_ops > 0))
             CUT_FAIL(CUT_E_FORMAT, "%s: factor format does not match the algebra", path);
         const int64_t rows = pb ? 2 * N : N, grows = pb ? 2 * hg.n_gen : N;
         if (rows >= (1ll << 24) || grows >= (1ll << 24) || (pb && 2 * hg.hdr.n_out_ops >= (1ll << 31)))

@@ -92,7 +92,7 @@ struct BundleHeader {
     int64_t n_records;
     int64_t n_gen_records;
     int64_t n_pairs;
-    int32_t factor_bytes;    // 1: int8 integer factors
+    int32_t factor_bytes;    // 1: int8 factors; 4: int16 (re, im); 16: FP64 (re, im)
     int32_t gen_sign;        // +1 / -1
     uint32_t n_sections;
     uint32_t reserved;
@@ -117,8 +117,9 @@ struct HostGraph {
     const uint8_t* diag = nullptr;
     const int32_t* pairs = nullptr;
     // record sets: 0 = E_L, 1 = E_eta, 2 = E_C (absent: null, size 0).  Factors
-    // are int8 (factor_bytes 1) or int16 (re, im) pairs (factor_bytes 4,
-    // Pauli-boson graphs); rc points at the raw bytes.
+    // are int8 (factor_bytes 1) or, in Pauli-boson graphs, (re, im) pairs of
+    // int16 (factor_bytes 4) or of FP64 (factor_bytes 16, registries whose
+    // factors leave int16); rc points at the raw bytes.
     const int64_t* off[3] = {nullptr, nullptr, nullptr};
     const int32_t* ri[3] = {nullptr, nullptr, nullptr};
     const int32_t* rj[3] = {nullptr, nullptr, nullptr};

@@ -35,8 +35,9 @@ def read(path: str) -> dict:
     for s in range(n_sections):
         sid, eb, off, cnt, ck = struct.unpack_from("<IIQQQ", b, table + s * SECTION)
         out["sections"][sid] = (off, cnt, eb)
-        if sid in FACTOR_SECTIONS and eb == 4:      # complex factors: int16 (re, im)
-            out[NAMES[sid]] = np.frombuffer(b, dtype=np.int16, count=2 * cnt, offset=off).reshape(cnt, 2)
+        if sid in FACTOR_SECTIONS and eb in (4, 16):  # complex factors: int16 or FP64 (re, im)
+            dt = np.int16 if eb == 4 else np.float64
+            out[NAMES[sid]] = np.frombuffer(b, dtype=dt, count=2 * cnt, offset=off).reshape(cnt, 2)
         else:
             out[NAMES[sid]] = np.frombuffer(b, dtype=DT[sid], count=cnt, offset=off)
     return out

@@ -216,14 +216,21 @@ def _pb_build(tmpdir, M, p, outside, threads=0, name=None):
     return path, desc
 
 
-@pytest.mark.parametrize("M,p,outside", [(1, 1, True), (2, 1, True), (1, 4, True), (2, 4, True), (3, 2, True), (2, 3, False)])
+@pytest.mark.parametrize("M,p,outside", [(1, 1, True), (2, 1, True), (1, 4, True), (2, 4, True), (3, 2, True), (2, 3, False),
+                                         (1, 8, True)])
 def test_pauli_boson_bit_exact_vs_oracle(tmpdir_mod, M, p, outside):
     """The compiled Pauli-boson graph (registry, generator registry, E_eta, E_L,
-    E_C, complex factors) equals the oracle's exact expansion."""
+    E_C, complex factors) equals the oracle's exact expansion.  Factors are
+    stored as int16 pairs while they fit, else as FP64 pairs (M = 1, p = 8
+    reaches 8! C(16, 8) = 518,918,400)."""
     from oracle import pauli_boson as PB
     path, desc = _pb_build(tmpdir_mod, M, p, outside)
     d = bundle_io.read(path)
     og = PB.PBGraph(M, p, outside=outside)
+    recs = og.flow + og.eta + (og.outside if outside else [])
+    wide = max(max(abs(r[3][0]), abs(r[3][1])) for r in recs) > 32767
+    assert desc["identifier"].endswith("factors=f64x2" if wide else "factors=int16x2")
+    assert wide == (M == 1 and p == 8)
     W = int(re.search(r":(\d+) bits", desc["identifier"]).group(1))
     assert [bundle_io.pb_label(int(v), M, W) for v in d["labels"]] == og.labels
     assert [bundle_io.pb_label(int(v), M, W) for v in d["gen_labels"]] == og.gen_labels
@@ -279,6 +286,42 @@ def _five_mode_records_valid(path, desc):
         for e, k in zip(sample, np.searchsorted(off, sample, side="right") - 1):
             br = PB.commutator(lab(left, I[e]), lab(d["labels"], J[e]))
             assert br.get(lab(tgt, k)) == (int(Cf[e, 0]), int(Cf[e, 1])), (which, int(e))
+
+
+def test_degree24_registry_builds_with_exact_fp64_factors(tmpdir_mod):
+    """The complete one-mode degree-24 registry (1,300 labels, the registry of
+    the paper's one-mode study, Sec. 3.1): normal ordering reaches factors
+    beyond int64 (24! C(48, 24) ~ 2e37), which the compiler carries exactly in
+    128-bit integers and stores as the nearest FP64 values.  The per-target
+    record counts of E_L and E_eta equal the oracle's term counts (its streamed
+    expansion, stored by make_oracle_goldens.py pb24); sampled records and the
+    largest factors equal the oracle's exact brackets rounded to FP64; within
+    every target the (left, right) inputs strictly increase."""
+    from oracle import pauli_boson as PB
+    path, desc = _pb_build(tmpdir_mod, 1, 24, False, name="pb24.cgb")
+    assert desc["identifier"].endswith("factors=f64x2") and desc["n_ops"] == 1300
+    gold = np.load(os.path.join(ROOT, "tests", "golden", "pb_m1p24_action.npz"))
+    d = bundle_io.read(path)
+    np.testing.assert_array_equal(np.diff(d["flow_off"]), gold["F_n"])
+    np.testing.assert_array_equal(np.diff(d["gen_off"]), gold["xi_n"])
+    W = int(re.search(r":(\d+) bits", desc["identifier"]).group(1))
+    lab = lambda keys, r: bundle_io.pb_label(int(keys[r]), 1, W)
+    rng = np.random.default_rng(24)
+    for which, tgt, left in (("flow", d["labels"], d["gen_labels"]), ("gen", d["gen_labels"], d["labels"])):
+        off, I, J, Cf = d[f"{which}_off"], d[f"{which}_i"], d[f"{which}_j"], d[f"{which}_c"]
+        key = I.astype(np.int64) * (1 << 32) + J.astype(np.int64)
+        first = np.zeros(key.size, dtype=bool)
+        first[off[:-1][np.diff(off) > 0]] = True
+        assert np.all((np.diff(key) > 0) | first[1:]), which
+        mag = np.abs(Cf).max(axis=1)
+        sample = np.concatenate([rng.choice(key.size, 400, replace=False), np.argsort(mag)[-20:]])
+        for e, k in zip(sample, np.searchsorted(off, sample, side="right") - 1):
+            br = PB.commutator(lab(left, I[e]), lab(d["labels"], J[e]))
+            f = br[lab(tgt, k)]
+            assert (float(f[0]), float(f[1])) == (Cf[e, 0], Cf[e, 1]), (which, int(e))
+        if which == "flow":
+            assert mag.max() > 2.0 ** 63
+    os.remove(path)
 
 
 def test_pauli_boson_build_memory_near_stored_size(tmp_path):

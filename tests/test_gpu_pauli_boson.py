@@ -62,8 +62,17 @@ def _abs_sum(recs, n, u, v):
     return S
 
 
-def _bound(L, P, seg):
-    n = 4 * seg
+def _pieces(recs):
+    """Upper bound on the device records per complex record part: a factor of
+    b significant bits is loaded as ceil(b / 8) records of 8-bit factors."""
+    def sig(v):
+        v = abs(int(v))
+        return v.bit_length() - ((v & -v).bit_length() - 1) if v else 0
+    return max(1, max(-(-max(sig(f[0]), sig(f[1])) // 8) for *_, f in recs))
+
+
+def _bound(L, P, seg, pieces=1):
+    n = 4 * seg * pieces
     if P == L.CUT_F64:
         return U.sum_bound(n)
     return 2 * U.U32 + (U.sum_bound(n) if P == L.CUT_F32X else U.dot2_bound(n))
@@ -81,7 +90,9 @@ def test_labels_and_sizes(L, M, p):
         assert [workloads.pb_label(int(k), M, W) for k in keys] == labs
 
 
-@pytest.mark.parametrize("M,p", [(1, 4), (2, 4)])
+# (1, 8): factors up to 5.2e8 leave int16, so the bundle holds FP64 factors and
+# the loader splits each into records of 8-bit factors
+@pytest.mark.parametrize("M,p", [(1, 4), (2, 4), (1, 8)])
 @pytest.mark.parametrize("prec", ["F64", "F32C", "F32X"])
 def test_generator_action_and_outside(L, M, p, prec):
     U.say(f"[pauli-boson] M={M} p={p} {prec}")
@@ -98,7 +109,8 @@ def test_generator_action_and_outside(L, M, p, prec):
     L.cut_generator(g, L.CUT_GEN_WEGNER_GRAPH, 0.0, nsets, _rs(h), eta)
     S = _abs_sum(og.eta, NG, h, h)
     seg_g = int(np.max(np.bincount([r[0] for r in og.eta], minlength=NG)))
-    U.assert_within(np.abs(_cplx(eta, NG) - xi), 0 * xi.real, U.sum_bound(4 * seg_g) * S * 2 + 1e-300, "generator")
+    U.assert_within(np.abs(_cplx(eta, NG) - xi), 0 * xi.real,
+                    U.sum_bound(4 * seg_g * _pieces(og.eta)) * S * 2 + 1e-300, "generator")
     # retained action
     dt = torch.float64 if P == L.CUT_F64 else torch.float32
     y = torch.zeros((2 * N, nops * nsets), dtype=torch.float64, device=DEV)
@@ -107,7 +119,8 @@ def test_generator_action_and_outside(L, M, p, prec):
     S = _abs_sum(og.flow, N, xi[:, None, :], x)
     seg = int(np.max(np.bincount([r[0] for r in og.flow], minlength=N)))
     got = _cplx(y, N).reshape(N, nops, nsets)
-    U.assert_within(np.abs(got - ref), 0 * ref.real, _bound(L, P, seg) * S * 2 + 1e-300, "action")
+    U.assert_within(np.abs(got - ref), 0 * ref.real, _bound(L, P, seg, _pieces(og.flow)) * S * 2 + 1e-300,
+                    "action")
     # outside-space action
     yc = torch.zeros((2 * NC, nops * nsets), dtype=torch.float64, device=DEV)
     L.cut_graph_apply(g, L.CUT_GRAPH_OUTSIDE, P, nsets, nops, _rs(xi).to(dt), _rs(x).to(dt), yc)
@@ -117,7 +130,61 @@ def test_generator_action_and_outside(L, M, p, prec):
     S = _abs_sum(og.outside, NC, xi[:, None, :], x)
     segc = int(np.max(np.bincount([r[0] for r in og.outside], minlength=NC)))
     gotc = _cplx(yc, NC).reshape(NC, nops, nsets)
-    U.assert_within(np.abs(gotc - refc), 0 * refc.real, _bound(L, P, segc) * S * 2 + 1e-300, "outside")
+    U.assert_within(np.abs(gotc - refc), 0 * refc.real, _bound(L, P, segc, _pieces(og.outside)) * S * 2 + 1e-300,
+                    "outside")
+
+
+@pytest.mark.parametrize("M,p", [(1, 4), (2, 3), (1, 8)])
+@pytest.mark.parametrize("prec", ["F64", "F32X", "F32C"])
+def test_adjoint_matches_oracle(L, M, p, prec):
+    """cut_graph_apply_adjoint on the real-split records (Sec. 2.4 reverse
+    traversal): the real transpose of the real-split action is the complex
+    adjoint with conjugation, g_x[j] = sum conj(beta xi_a) w_k and
+    g_xi[a] = sum over operands of conj(beta x_j) w_k (the oracle's adjoint)."""
+    U.say(f"[pauli-boson adjoint] M={M} p={p} {prec}")
+    P = getattr(L, "CUT_" + prec)
+    g, og = _graphs(L, M, p, outside=False)
+    N, NG = og.N, og.NG
+    nsets, nops = 2, 3
+    rng = np.random.default_rng(40 + 10 * M + p)
+    h = np.stack([workloads.pb_hermitian(og.labels, rng) for _ in range(nsets)], axis=1)
+    xi = np.stack([og.generator(h[:, s]) for s in range(nsets)], axis=1)
+    x = rng.normal(size=(N, nops, nsets)) + 1j * rng.normal(size=(N, nops, nsets))
+    w = rng.normal(size=(N, nops, nsets)) + 1j * rng.normal(size=(N, nops, nsets))
+    dt = torch.float64 if P == L.CUT_F64 else torch.float32
+    gx = torch.zeros((2 * N, nops * nsets), dtype=torch.float64, device=DEV)
+    gxi = torch.zeros((2 * NG, nsets), dtype=torch.float64, device=DEV)
+    L.cut_graph_apply_adjoint(g, L.CUT_GRAPH_FLOW, P, nsets, nops, _rs(xi).to(dt), _rs(x).to(dt), _rs(w).to(dt),
+                              gx, gxi)
+    torch.cuda.synchronize()
+    ref_x = np.zeros((N, nops, nsets), dtype=complex)
+    ref_xi = np.zeros((NG, nsets), dtype=complex)
+    for s in range(nsets):
+        for o in range(nops):
+            a, b = PB.adjoint(og, xi[:, s], x[:, o, s], w[:, o, s])
+            ref_x[:, o, s] = a
+            ref_xi[:, s] += b
+    # absolute sums of the same terms and the longest input segments
+    ax = lambda v: np.abs(v.real) + np.abs(v.imag)
+    Sx = np.zeros((N, nops, nsets))
+    Sxi = np.zeros((NG, nsets))
+    for k, a, j, f in og.flow:
+        c = abs(complex(*f))
+        Sx[j] += c * ax(xi[a])[None, :] * ax(w[k])
+        Sxi[a] += c * np.sum(ax(x[j]) * ax(w[k]), axis=0)
+    pc = _pieces(og.flow)
+    seg_j = int(np.max(np.bincount([r[2] for r in og.flow], minlength=N)))
+    seg_a = int(np.max(np.bincount([r[1] for r in og.flow], minlength=NG))) * nops
+    if P == L.CUT_F64:
+        tj, ta = U.sum_bound(4 * seg_j * pc), U.sum_bound(4 * seg_a * pc)
+    elif P == L.CUT_F32X:
+        tj, ta = 2 * U.U32 + U.sum_bound(4 * seg_j * pc), 2 * U.U32 + U.sum_bound(4 * seg_a * pc)
+    else:
+        tj = 2 * U.U32 + U.dot2_bound(4 * seg_j * pc, U.F32C_GROUP)
+        ta = 2 * U.U32 + U.dot2_bound(4 * seg_a * pc, U.F32C_GROUP * nops)
+    got_x = _cplx(gx, N).reshape(N, nops, nsets)
+    U.assert_within(np.abs(got_x - ref_x), 0 * Sx, tj * Sx * 2 + 1e-300, "g_x")
+    U.assert_within(np.abs(_cplx(gxi, NG) - ref_xi), 0 * Sxi, ta * Sxi * 2 + 1e-300, "g_xi")
 
 
 @pytest.mark.parametrize("prec,tol", [("F64", 1e-11), ("F32C", 2e-6)])
@@ -385,3 +452,47 @@ def test_smallest_registries(L, M, p, nsets):
         zr, lr = PB.flow_outside(og, z0[:, :, s], ds, steps)
         assert np.linalg.norm(got[:, :, s] - zr) <= 1e-12 * np.linalg.norm(zr)
         assert np.abs(got_leak[:, s] - lr).max() <= 1e-12 * np.abs(lr).max()
+
+
+_G24 = {}
+
+
+@pytest.mark.parametrize("prec", ["F64", "F32X", "F32C"])
+def test_degree24_registry_matches_streamed_oracle(L, prec):
+    """The complete one-mode degree-24 registry (1,300 labels: the registry of
+    the paper's one-mode study, Sec. 3.1).  Its normal-ordering factors reach
+    ~2e37, beyond int64, so the bundle holds FP64 factors and every device
+    record carries an 8-bit piece of one (at most 7 per factor).  The Wegner
+    generator and the retained action against the oracle's streamed expansion
+    (it stores no records), computed with its seeded inputs by
+    make_oracle_goldens.py pb24."""
+    import os
+    import re
+    d = np.load(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "pb_m1p24_action.npz"))
+    if "g" not in _G24:
+        path = os.path.join(U._tmp, "pb_1_24.cgb")
+        desc = L.cut_graph_build(L.CUT_ALG_PAULI_BOSON, 256 + 24, path, 0, 0)
+        assert re.search(r"factors=f64x2", desc["identifier"])
+        _G24["g"] = L.cut_graph_load(path, 0, 0)
+    g = _G24["g"]
+    info = L.cut_graph_info(g)
+    N, NG = 1300, d["xi"].shape[0]
+    assert info["n_ops"] == N and info["n_gen_ops"] == NG
+    assert info["n_records"] == int(d["F_n"].sum()) and info["n_gen_records"] == int(d["xi_n"].sum())
+    U.say(f"[pauli-boson degree 24] {prec}: {info['n_records']} retained records")
+    h, x, xi = d["h"], d["x"], d["xi"]
+    nsets, nops = h.shape[1], x.shape[1]
+    eta = torch.zeros((2 * NG, nsets), dtype=torch.float64, device=DEV)
+    L.cut_generator(g, L.CUT_GEN_WEGNER_GRAPH, 0.0, nsets, _rs(h), eta)
+    P = getattr(L, "CUT_" + prec)
+    dt = torch.float64 if P == L.CUT_F64 else torch.float32
+    y = torch.zeros((2 * N, nops * nsets), dtype=torch.float64, device=DEV)
+    L.cut_graph_apply(g, L.CUT_GRAPH_FLOW, P, nsets, nops, _rs(xi).to(dt), _rs(x).to(dt), y)
+    torch.cuda.synchronize()
+    U.assert_within(np.abs(_cplx(eta, NG) - xi), 0 * d["xi_abs"],
+                    U.sum_bound(4 * int(d["xi_n"].max()) * 7) * d["xi_abs"] * 2 + 1e-300, "generator")
+    got = _cplx(y, N).reshape(N, nops, nsets)
+    rel = np.abs(got - d["F"]).max() / np.abs(d["F"]).max()
+    U.say(f"[pauli-boson degree 24] {prec}: max error relative to max |F| {rel:.2e}")
+    U.assert_within(np.abs(got - d["F"]), 0 * d["F_abs"],
+                    _bound(L, P, int(d["F_n"].max()), 7) * d["F_abs"] * 2 + 1e-300, "action")

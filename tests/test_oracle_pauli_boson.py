@@ -239,3 +239,80 @@ def test_pb_outside_diagnostic_is_fourth_order_quadrature():
         errs.append(np.abs(leak - exact).max() / np.abs(exact).max())
     assert 13.0 < errs[0] / errs[1] < 19.0, errs
     assert errs[1] < 1e-6
+
+
+def test_pb_adjoint_is_the_conjugate_transpose_of_the_action():
+    """Sec. 2.4 reverse traversal: with the action's matrices in x (xi fixed)
+    and in xi (x fixed) taken column by column, the oracle's adjoint must be
+    g_x = A_x^H w and g_xi = A_xi^H w (the conjugation the paper names).  A
+    missing conjugate or swapped input fails here."""
+    g, z0 = _pb_small()
+    rng = np.random.default_rng(8)
+    xi = g.generator(z0[:, 0])
+    x = z0[:, 1]
+    w = rng.normal(size=g.N) + 1j * rng.normal(size=g.N)
+    Ax = _columns(lambda e: g.action(xi, e), g.N)
+    Axi = _columns(lambda e: g.action(e, x), g.NG)
+    gx, gxi = PB.adjoint(g, xi, x, w)
+    np.testing.assert_allclose(gx, Ax.conj().T @ w, rtol=0, atol=1e-12 * np.abs(gx).max())
+    np.testing.assert_allclose(gxi, Axi.conj().T @ w, rtol=0, atol=1e-12 * np.abs(gxi).max())
+
+
+def _normal_order_by_commutation(a, c):
+    """b^a (b^+)^c normal ordered by moving one annihilator at a time through the
+    creators with b (b^+)^x = (b^+)^x b + x (b^+)^(x-1): {(creators, annihilators):
+    integer coefficient}."""
+    poly = {(c, 0): 1}
+    for _ in range(a):
+        nxt = {}
+        for (x, y), f in poly.items():
+            nxt[(x, y + 1)] = nxt.get((x, y + 1), 0) + f
+            if x:
+                nxt[(x - 1, y)] = nxt.get((x - 1, y), 0) + x * f
+        poly = nxt
+    return poly
+
+
+def test_wick_factors_at_degree_24_by_commutation():
+    """The normal-ordering factors of the degree-24 one-mode registry (the
+    registry of the paper's one-mode study, Sec. 3.1) leave int64 (24! ~ 6.2e23):
+    the oracle's contraction formula must equal the exact integers obtained by
+    commuting annihilators through creators one at a time, up to 24 of each,
+    and the bracket [b^24, (b^+)^24] must hold 24! on the identity."""
+    for a, c in ((24, 24), (24, 13), (7, 24), (17, 19)):
+        ref = _normal_order_by_commutation(a, c)
+        got = {(cc, aa): f for cc, aa, f in PB.mode_product(0, a, c, 0)}
+        assert got == ref, (a, c)
+    br = PB.commutator((0, (0,), (24,)), (0, (24,), (0,)))
+    assert br[(0, (0,), (0,))] == (math.factorial(24), 0) and math.factorial(24) > 2 ** 63
+
+
+@pytest.mark.parametrize("M,p,workers", [(1, 4, 1), (2, 2, 2), (1, 8, 3)])
+def test_streamed_action_matches_the_record_graph(M, p, workers):
+    """The streamed form (no stored records; used for registries too large to
+    hold theirs) gives the generator registry, xi, F, the per-target term counts
+    and absolute sums of the record graph."""
+    import workloads
+    g = PB.PBGraph(M, p)
+    rng = np.random.default_rng(M * 100 + p)
+    h = np.stack([workloads.pb_hermitian(g.labels, rng) for _ in range(2)], 1)
+    X = rng.normal(size=(g.N, 3, 2)) + 1j * rng.normal(size=(g.N, 3, 2))
+    r = PB.streamed_action(M, p, h, X, workers=workers)
+    xi, F, S, n = r["xi"], r["F"], r["F_abs"], r["F_n"]
+    assert r["labels"] == g.labels and r["gen_labels"] == g.gen_labels
+    np.testing.assert_array_equal(r["xi_n"], np.bincount([e[0] for e in g.eta], minlength=g.NG))
+    ah = np.abs(h.real) + np.abs(h.imag)
+    Sx = np.zeros((g.NG, 2))
+    for a, i, j, f in g.eta:
+        Sx[a] += abs(complex(*f)) * ah[i] * ah[j]
+    np.testing.assert_allclose(r["xi_abs"], Sx, rtol=1e-13)
+    xi0 = np.stack([g.generator(h[:, s]) for s in range(2)], 1)
+    np.testing.assert_allclose(xi, xi0, rtol=0, atol=1e-13 * np.abs(xi0).max())
+    F0 = np.stack([np.stack([g.action(xi0[:, s], X[:, o, s]) for s in range(2)], 1) for o in range(3)], 1)
+    np.testing.assert_allclose(F, F0, rtol=0, atol=1e-13 * np.abs(F0).max())
+    np.testing.assert_array_equal(n, np.bincount([r[0] for r in g.flow], minlength=g.N))
+    S0 = np.zeros(S.shape)
+    ax, aX = np.abs(xi0.real) + np.abs(xi0.imag), np.abs(X.real) + np.abs(X.imag)
+    for k, a, j, f in g.flow:
+        S0[k] += abs(complex(*f)) * ax[a] * aX[j]
+    np.testing.assert_allclose(S, S0, rtol=1e-13)

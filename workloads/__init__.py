@@ -212,6 +212,14 @@ def pb_hermitian(labels, rng, diag_scale: float = 1.0, off_scale: float = 0.1) -
     return h
 
 
+def pb_fock_scale(labels) -> np.ndarray:
+    """1 / sqrt(prod_m c_m! a_m!) per Pauli-boson label (tau, c, a): the size of
+    (b^+)^c b^a between low Fock states grows like sqrt(c! a!), so coefficients
+    drawn on this scale keep high-degree registries (degree 24) in range."""
+    import math
+    return np.array([1.0 / math.sqrt(math.prod(math.factorial(v) for v in L[1] + L[2])) for L in labels])
+
+
 def real_split(v: np.ndarray) -> np.ndarray:
     """Interleaved real-split rows (axis 0): row 2r = Re v_r, row 2r + 1 = Im v_r."""
     out = np.empty((2 * v.shape[0],) + v.shape[1:])
