@@ -73,6 +73,20 @@ def pass_bytes(N, E, nsets, nops, prec_bytes):
             + N * cols * (8 + 14) + N * cols * prec_bytes + N * nsets * 8)
 
 
+def pass_kernels(flags: int) -> str:
+    """The kernels of one fused flow pass at 64 sets x 5 operands in a tiling."""
+    parts = []
+    if flags & 16:
+        parts.append("k_qblock<5,prec> (quadratic-target blocks)")
+    if flags & 2:
+        parts.append("k_tile64<5,prec> (shared-triple tiles of the quartic targets)")
+    parts.append("k_pass<64,5,prec,0,2> (" + ("remaining targets" if flags & 18 else "every target") +
+                 (", unchunked" if flags & 4 else ", long ones in chunks") + ")")
+    if not flags & 4 or flags & 18:
+        parts.append("k_chunk_combine<5,prec,2> (partial rows + RK4 stage epilogue)")
+    return "fused graph pass with RK4 stage epilogue: " + " + ".join(parts)
+
+
 def measured_counters(precision: str, what: str = "traffic", prof_name: str = "fused_pass_m40_counters.md"):
     """A per-launch figure of the fused pass from a committed counter summary,
     if it was taken on the current kernel source (else None).
@@ -681,8 +695,7 @@ def main():
                        "frac": achieved / HBM_PEAK_GBS,
                        "traffic": traffic,
                        "traffic_unit": "HBM bytes per fused pass (FETCH_SIZE x copy factor + WRITE_SIZE)",
-                       "kernel": "fused graph pass with RK4 stage epilogue: k_pass<64,5,prec,0,2> "
-                                 "(chunks of the quadratic targets + quartic targets) and k_chunk_combine<5,prec,2>",
+                       "kernel": pass_kernels(tuning["tiling_flags"]),
                        "avg_launch_ms": pass_ms, "algorithmic_bytes_per_launch": bytes_per,
                        "gathered_row_bytes_per_launch": gathered,
                        "gathered_row_rate_GBs": gathered / (pass_ms * 1e-3) / 1e9,
