@@ -87,20 +87,30 @@ def pass_kernels(flags: int) -> str:
     return "fused graph pass with RK4 stage epilogue: " + " + ".join(parts)
 
 
+KERNEL_SOURCES = ("kernels.hip",)
+
+
+def kernel_digest() -> str:
+    """sha256 over the sources of the segment-pass kernels, in a fixed order."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, "paper_2609_14831_amd", "csrc", name), "rb").read())
+    return h.hexdigest()
+
+
 def measured_counters(precision: str, what: str = "traffic", prof_name: str = "fused_pass_m40_counters.md"):
     """A per-launch figure of the fused pass from a committed counter summary,
-    if it was taken on the current kernel source (else None).
+    if it was taken on the current kernel sources (else None).
 
-    The summary carries lines `<what> <precision> <kernels.hip sha256> <value>`:
+    The summary carries lines `<what> <precision> <kernel_digest()> <value>`:
     what = traffic (HBM bytes per launch: FETCH_SIZE x copy factor +
     WRITE_SIZE) or valu (SQ_INSTS_VALU per launch).
     """
-    import hashlib
-    src = os.path.join(ROOT, "paper_2609_14831_amd", "csrc", "kernels.hip")
     prof = os.path.join(ROOT, "profiles", prof_name)
     if not os.path.exists(prof):
         return None
-    digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    digest = kernel_digest()
     for line in open(prof):
         parts = line.strip().strip("`").split()
         if len(parts) == 4 and parts[0] == what and parts[1] == precision and parts[2] == digest:

@@ -803,6 +803,7 @@ static inline void pb_factor(const HostGraph& hg, int w, int64_t e, double& re, 
 static void upload_set(Graph& g, int w, std::vector<int64_t>&& off, std::vector<uint2>&& rec, bool adjoint,
                        int64_t na, int64_t nb) {
     const int64_t nseg = (int64_t)off.size() - 1, E = (int64_t)rec.size();
+    const int64_t rows = std::max(nseg, std::max(na, nb));
     if (adjoint) {
         for (int o = 1; o <= 2; ++o) {
             const int64_t ns = o == 1 ? nb : na;
@@ -818,9 +819,11 @@ static void upload_set(Graph& g, int w, std::vector<int64_t>&& off, std::vector<
                     else r2[cur[r.x & 0xFFFFFFu]++] = make_uint2((r.x & 0xFF000000u) | (uint32_t)k, r.y);
                 }
             upload_csr(g, g.csr[w][o], ns, std::move(noff), r2);
+            g.csr[w][o].rows = rows;
         }
     }
     upload_csr(g, g.csr[w][0], nseg, std::move(off), rec);
+    g.csr[w][0].rows = rows;
 }
 
 // Real-split form of a set of complex records (Pauli-boson graphs): a complex

@@ -187,6 +187,9 @@ struct DevCSR {
     // complex target (FP64 forward passes run over these; see k_cpass)
     const DevCSR* cx = nullptr;
     int64_t na = 0, nb = 0;     // complex twins: rows of the left / right input space
+    // rows of the largest array a pass over these records reads (targets, left
+    // or right inputs; 0: the segment count), for the 32-bit offset check
+    int64_t rows = 0;
     void release();
 };
 

@@ -988,7 +988,8 @@ static KArgs make_kargs(const PassArgs& p) {
     k.ldh = p.ldh;
     const int64_t esz = p.precision == CUT_F64 ? 8 : 4;
     const int64_t ld = p.lda > p.ldb ? p.lda : p.ldb;
-    k.buf32 = (c.nseg * ld * esz < (int64_t)0x7FFFFFFF) ? 1 : 0;
+    const int64_t rows = c.rows > c.nseg ? c.rows : c.nseg;
+    k.buf32 = (rows * ld * esz < (int64_t)0x7FFFFFFF) ? 1 : 0;
     return k;
 }
 
