@@ -178,6 +178,59 @@ class PBGraph:
         return y
 
 
+def generator_registry(M: int, p: int) -> List[Label]:
+    """Every label the brackets [B_i, B_j] (i block-diagonal, j not) of the
+    degree-p registry reach (the generator registry of Eq. graph-actions),
+    canonical order."""
+    labels = registry(M, p)
+    D = [L for L in labels if is_diagonal(L)]
+    OD = [L for L in labels if not is_diagonal(L)]
+    out = set()
+    for A in D:
+        for B in OD:
+            out.update(commutator(A, B))
+    return sorted(out, key=sort_key)
+
+
+def target_terms(labels: List[Label], gen_labels: List[Label], T: Label):
+    """The terms of target label T in [B_a, B_j] over generator labels a and
+    registry labels j, as sorted (a, j, (re, im)): the records of T in E_L when
+    T is in the registry, in E_C when it is not, found without enumerating
+    every pair.  Per mode, a product of (b^+)^cA b^aA and (b^+)^cB b^aB in
+    either order reaches (b^+)^cT b^aT only through a contraction of order
+    k >= 0 with cT = cA + cB - k and aT = aA + aB - k, and sigma_A sigma_B is
+    proportional to sigma_T only for one tau_A; so for every registry label B
+    the candidates A are cA = cT - cB + k, aA = aT - aB + k over k >= 0 (degree
+    bounded by the generator registry's), and each candidate's bracket gives
+    the exact factor."""
+    gen_index = {L: n for n, L in enumerate(gen_labels)}
+    dmax = max(degree(L) for L in gen_labels)
+    M = len(T[1])
+    out = []
+    for j, B in enumerate(labels):
+        # sigma_A = sigma_T sigma_B up to phase (the Pauli group is abelian
+        # modulo phases, so one tau serves both orders)
+        tau_a = pauli_mul(T[0], B[0])[0]
+        base_c = [T[1][m] - B[1][m] for m in range(M)]
+        base_a = [T[2][m] - B[2][m] for m in range(M)]
+        kmin = [max(0, -base_c[m], -base_a[m]) for m in range(M)]
+        slack = dmax - sum(base_c[m] + base_a[m] + 2 * kmin[m] for m in range(M))
+        if slack < 0:
+            continue
+        for extra in itertools.product(range(slack // 2 + 1), repeat=M):
+            if 2 * sum(extra) > slack:
+                continue
+            k = [kmin[m] + extra[m] for m in range(M)]
+            A = (tau_a, tuple(base_c[m] + k[m] for m in range(M)), tuple(base_a[m] + k[m] for m in range(M)))
+            a = gen_index.get(A)
+            if a is None:
+                continue
+            f = commutator(A, B).get(T)
+            if f is not None:
+                out.append((a, j, f))
+    return sorted(out)
+
+
 def _streamed_part(args):
     labels, gen_slice, xi_slice, X = args
     import numpy as np

@@ -1506,6 +1506,11 @@ struct QBArgs {
 template <int NOPS, int PREC>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k_qblock(QBArgs a) {
     using T = typename PrecT<PREC>::T;
+    // Compensated-float passes accumulate here the CUT_F32X way (exact
+    // products and sums in FP64): as accurate or more than the compensated
+    // float sum, and 2 VALU operations per term instead of 4.5 (a two-sum for
+    // every two records); the operands and their staging stay float.
+    constexpr int APREC = PREC == CUT_F32C ? CUT_F32X : PREC;
     constexpr int ROW = (NOPS + 1) * 64;   // staged elements per row
     extern __shared__ __align__(16) unsigned char qb_lds[];
     T* lds = reinterpret_cast<T*>(qb_lds);  // [2][16][ROW]
@@ -1538,7 +1543,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
     for (int j = 0; j < 8; ++j) slot[j] = __builtin_amdgcn_readfirstlane(a.tslot[bp * 64 + wave * 8 + j]);
     const float fpos = a.fmag;
     const uint32_t* sgw = a.sgn + ((int64_t)bp * 8 + wave) * a.ntrip;
-    Acc<PREC> acc[8][NOPS];
+    Acc<APREC> acc[8][NOPS];
     // per-window (64 triples) lane data: row of each staging slot, sign word
     int32_t rowv[2] = {-1, -1};
     uint32_t sgv = 0;
@@ -1602,18 +1607,12 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
                 const T ev = lv[NOPS * 64];
                 const float f1 = (sbits >> (2 * j)) & 1u ? -fpos : fpos;      // record (T+u, T+v)
                 const float f2 = (sbits >> (2 * j + 1)) & 1u ? -fpos : fpos;  // record (T+v, T+u)
-                const auto tu = left_term<PREC>((double)f1, eu);
-                const auto tv = left_term<PREC>((double)f2, ev);
+                const auto tu = left_term<APREC>((double)f1, eu);
+                const auto tv = left_term<APREC>((double)f2, ev);
 #pragma unroll
                 for (int op = 0; op < NOPS; ++op) {
-                    if constexpr (PREC == CUT_F32C) {
-                        // the target's two records of this triple in one float
-                        // partial, one two-sum into the compensated sum
-                        acc[j][op].add_sum(__builtin_fmaf(tv, xu[op], tu * lv[op * 64]));
-                    } else {
-                        acc[j][op].add(tu, lv[op * 64]);
-                        acc[j][op].add(tv, xu[op]);
-                    }
+                    acc[j][op].add(tu, lv[op * 64]);
+                    acc[j][op].add(tv, xu[op]);
                 }
             }
         }

@@ -316,3 +316,24 @@ def test_streamed_action_matches_the_record_graph(M, p, workers):
     for k, a, j, f in g.flow:
         S0[k] += abs(complex(*f)) * ax[a] * aX[j]
     np.testing.assert_allclose(S, S0, rtol=1e-13)
+
+
+@pytest.mark.parametrize("M,p", [(1, 4), (2, 3), (3, 2)])
+def test_target_terms_are_the_records_of_each_target(M, p):
+    """The per-target expansion (used for targets of registries too large to
+    expand whole, such as the five-mode graph) gives, for every retained and
+    every outside target, exactly the records the whole-graph expansion files
+    under it, factors included; and the generator registry matches."""
+    from collections import defaultdict
+    g = PB.PBGraph(M, p, outside=True)
+    gl = PB.generator_registry(M, p)
+    assert gl == g.gen_labels
+    by_k, by_q = defaultdict(list), defaultdict(list)
+    for k, a, j, f in g.flow:
+        by_k[k].append((a, j, f))
+    for q, a, j, f in g.outside:
+        by_q[q].append((a, j, f))
+    for k, T in enumerate(g.labels):
+        assert PB.target_terms(g.labels, gl, T) == sorted(by_k[k]), k
+    for q, T in enumerate(g.out_labels):
+        assert PB.target_terms(g.labels, gl, T) == sorted(by_q[q]), q
