@@ -67,7 +67,7 @@ def _run_apply(L, g, prec, eta, x, nsets, nops, which=0, y0=None, flags=0):
 
 CASES = [("epq", 8, 1, 1), ("epq", 8, 4, 2), ("majorana", 8, 1, 1), ("majorana", 8, 3, 2),
          ("majorana", 12, 1, 3), ("majorana", 12, 8, 1), ("majorana", 12, 64, 5),
-         ("majorana", 12, 100, 2), ("majorana", 16, 16, 1), ("majorana", 24, 1, 3)]
+         ("majorana", 12, 100, 2), ("majorana", 16, 16, 1), ("majorana", 24, 1, 3), ("majorana", 24, 1, 1)]
 PRECS = ["F64", "F32X", "F32C", "F32"]
 
 

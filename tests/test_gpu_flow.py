@@ -84,10 +84,11 @@ def test_majorana_flow_ragged(L, prec, tiling):
 @pytest.mark.parametrize("prec", ["F64", "F32C"])
 def test_majorana_one_column_flow(L, prec, tiling):
     """One coefficient set, H only (the plain FP64 flow's shape: one-column
-    passes with the quadratic rows staged in LDS), chunked tilings, hipGraph,
-    against the oracle."""
-    U.say(f"[flow] majorana m=16 one column {prec} tiling {tiling}")
-    m = 16
+    passes, one record per lane), chunked tilings (at m = 24 the quadratic
+    targets, 3,124 records, are the chunked ones in the first tiling; the others
+    also cut quartic targets), hipGraph, against the oracle."""
+    U.say(f"[flow] majorana m=24 one column {prec} tiling {tiling}")
+    m = 24
     g = U.graph(L, "majorana", m)
     L.cut_graph_set_tiling(g, *tiling)
     og = A.majorana_graph(m)
