@@ -450,6 +450,13 @@ cut_status cut_flow_adjoint(cut_graph_t g, const cut_flow_params* p, int64_t nse
  * three modes tau with the target; the 4-subsets containing tau are both the
  * targets and the quartic operands of those records, so they are staged in LDS
  * once per tile and each target's four tile sums are added in fixed order.
+ * CUT_TILE_BCHUNK(b), b = 32, 16 or 8 (the B-chunk): the segment kernel's
+ * forward passes give one record at most b lanes, one per coefficient set, so
+ * a launch over more sets runs ceil(sets / b) workgroup columns, each reading
+ * the record stream for its b sets (default, b = 64: one column for up to 64
+ * sets).  Narrower lane groups hold more records per wavefront step; wider ones
+ * read the records once for more sets.  The block and tile kernels keep their
+ * own set blocking.
  * The chunked and tile forms need a work area of partial rows: the work areas
  * are re-sized for every shape reserved so far (cut_graph_reserve).  Rebuilds
  * the task lists of every loaded copy; synchronises the device.
@@ -459,12 +466,15 @@ cut_status cut_flow_adjoint(cut_graph_t g, const cut_flow_params* p, int64_t nse
 #define CUT_TILE_NO_CHUNKS 4u
 #define CUT_TILE_TRIPLE_CHUNKS 8u
 #define CUT_TILE_QUAD_BLOCKS 16u
+#define CUT_TILE_BCHUNK_SHIFT 5    /* 2-bit field: B-chunk 64 >> field */
+#define CUT_TILE_BCHUNK(b) ((uint32_t)((b) == 32 ? 1u : (b) == 16 ? 2u : (b) == 8 ? 3u : 0u) << CUT_TILE_BCHUNK_SHIFT)
 cut_status cut_graph_set_tiling(cut_graph_t g, int64_t long_records, int64_t chunk_records, uint32_t flags);
 
 /* Autotuner: times the forward graph pass for (nsets, nops) over candidate
  * tilings (chunk length 64/128/256/512 records, XCD remap off/on, triple
  * chunks, no chunks, shared-triple tiles and quadratic-target blocks where
- * available; long-target threshold 1024) and, when `precision` is CUT_F32C or
+ * available; long-target threshold 1024), then the three fastest of those with
+ * the narrower B-chunks that the set count allows, and, when `precision` is CUT_F32C or
  * CUT_F32X and `allow_other_float` != 0, over both compensated float modes;
  * applies the fastest tiling to the graph (a candidate must beat the best so
  * far, starting with the graph's current tiling, by at least 2 %) and returns

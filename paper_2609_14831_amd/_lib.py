@@ -45,6 +45,14 @@ CUT_FLOW_HIPGRAPH = 1
 CUT_FLOW_TIME_PASSES = 2
 CUT_TILE_XCD_REMAP, CUT_TILE_TRIPLES, CUT_TILE_NO_CHUNKS, CUT_TILE_TRIPLE_CHUNKS = 1, 2, 4, 8
 CUT_TILE_QUAD_BLOCKS = 16
+CUT_TILE_BCHUNK_SHIFT = 5
+
+
+def CUT_TILE_BCHUNK(b: int) -> int:
+    """Tiling flag of the B-chunk b (32, 16 or 8 sets per lane group; 64: none)."""
+    return {64: 0, 32: 1, 16: 2, 8: 3}[b] << CUT_TILE_BCHUNK_SHIFT
+
+
 CUT_RESERVE_APPLY, CUT_RESERVE_FLOW, CUT_RESERVE_DERIV, CUT_RESERVE_ADJOINT = 1, 2, 4, 8
 
 STATUS_NAMES = {0: "CUT_OK", 1: "CUT_E_INVAL", 2: "CUT_E_IO", 3: "CUT_E_FORMAT",
@@ -209,7 +217,7 @@ def cut_graph_free(g: int) -> None:
 
 def cut_graph_set_tiling(g: int, long_records: int, chunk_records: int, flags: int) -> None:
     """flags: CUT_TILE_XCD_REMAP | CUT_TILE_TRIPLES | CUT_TILE_NO_CHUNKS | CUT_TILE_TRIPLE_CHUNKS
-    | CUT_TILE_QUAD_BLOCKS."""
+    | CUT_TILE_QUAD_BLOCKS | CUT_TILE_BCHUNK(b)."""
     _check(_L.cut_graph_set_tiling(g, long_records, chunk_records, flags))
 
 

@@ -262,6 +262,7 @@ static void enqueue_step(const StepPlan& P, hipStream_t s, PassTimer* tm = nullp
         p.xout = P.xout[st];
         p.hst = P.fb.hst;
         p.ldh = P.nsets;
+        p.gmax = 64 >> g.bchunk;  // the tiling's B-chunk
         if (tm) tm->mark(0, s);
         const size_t nr = std::max<size_t>(1, P.ranges.size());
         for (size_t r = 0; r < nr; ++r) {

@@ -381,6 +381,7 @@ void apply_tiling(Graph& g, int64_t long_records, int64_t chunk_records, uint32_
     g.use_chunks = (flags & CUT_TILE_NO_CHUNKS) ? 0 : 1;
     g.triple_chunks = (flags & CUT_TILE_TRIPLE_CHUNKS) ? 1 : 0;
     g.use_quadblocks = (flags & CUT_TILE_QUAD_BLOCKS) ? 1 : 0;
+    g.bchunk = (int)((flags >> CUT_TILE_BCHUNK_SHIFT) & 3u);
     for (auto& w : g.csr)
         for (auto& c : w)
             if (c.nseg) build_tasks(g, c);
@@ -389,7 +390,7 @@ void apply_tiling(Graph& g, int64_t long_records, int64_t chunk_records, uint32_
 uint32_t tiling_flags(const Graph& g) {
     return (g.xcd_remap ? CUT_TILE_XCD_REMAP : 0u) | (g.use_tiles ? CUT_TILE_TRIPLES : 0u) |
            (g.use_chunks ? 0u : CUT_TILE_NO_CHUNKS) | (g.triple_chunks ? CUT_TILE_TRIPLE_CHUNKS : 0u) |
-           (g.use_quadblocks ? CUT_TILE_QUAD_BLOCKS : 0u);
+           (g.use_quadblocks ? CUT_TILE_QUAD_BLOCKS : 0u) | ((uint32_t)g.bchunk << CUT_TILE_BCHUNK_SHIFT);
 }
 
 static std::vector<Task> plan_tasks(const Graph& g, const std::vector<int64_t>& off, int64_t nseg, int64_t* per_xcd) {
@@ -1149,7 +1150,7 @@ extern "C" cut_status cut_graph_labels(cut_graph_t h, int32_t which, uint64_t* o
 extern "C" cut_status cut_graph_set_tiling(cut_graph_t h, int64_t long_records, int64_t chunk_records,
                                            uint32_t flags) {
     try {
-        if (!h || long_records < 1 || chunk_records < 1 || (flags & ~31u))
+        if (!h || long_records < 1 || chunk_records < 1 || (flags & ~127u))
             CUT_FAIL(CUT_E_INVAL, "cut_graph_set_tiling: bad argument");
         Graph& g = *(Graph*)h;
         DeviceGuard dg(g.device);

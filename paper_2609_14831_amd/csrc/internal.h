@@ -309,6 +309,7 @@ struct Graph {
     int use_quadblocks = 0;
     uint64_t tiling_gen = 0;         // bumped whenever task lists are rebuilt
     int use_chunks = 1;
+    int bchunk = 0;                  // B-chunk field of the tiling flags: lane groups of <= 64 >> bchunk sets
     int64_t max_lds = 65536;         // LDS bytes one workgroup may allocate
     Workspace ws;                    // flow state and stage storage
     Workspace ws_small;              // scratch of single generator-VJP calls
@@ -357,6 +358,7 @@ struct PassArgs {
     int64_t ldb;
     int32_t nsets, nops;
     int32_t s0 = 0, s1 = 0;         // sets [s0, s1) covered (s1 = 0: all); see forward_set_ranges
+    int32_t gmax = 64;              // widest lane group of the segment kernel (the tiling's B-chunk)
     int32_t precision;              // cut_precision
     const int32_t* nsteps;          // device [nsets] or null (all active)
     const int32_t* step;            // device scalar or null

@@ -1111,7 +1111,7 @@ void launch_pass(int mode, int epi, const PassArgs& p, hipStream_t s) {
     if (p.csr->nseg == 0) return;
     const KArgs k = make_kargs(p);
     if (k.ntasks == 0) return;
-    const int G = range_group_width(k);
+    const int G = std::min(range_group_width(k), (int)p.gmax);
     const int64_t nblk = k.per_xcd > 0 ? 8 * k.per_xcd : k.ntasks;
     dim3 grid((unsigned)nblk, (unsigned)((k.s1 - k.s0 + G - 1) / G));
     if (mode == MODE_BCAST) {
@@ -1691,7 +1691,7 @@ static void launch_chunked(const Graph& g, const ChunkPlan& c, int epi, const Pa
     r.ntasks = c.nshort;
     r.per_xcd = c.short_per_xcd;
     KArgs k = make_kargs(r);
-    const int G = range_group_width(k);
+    const int G = std::min(range_group_width(k), (int)a.gmax);
     const unsigned ychunks = (unsigned)((k.s1 - k.s0 + G - 1) / G);
     const int64_t ldp = (int64_t)a.nops * a.nsets;
     k.chunks = c.chunks;
@@ -1781,7 +1781,9 @@ bool forward_set_ranges(const Graph& g, const PassArgs& a) {
     return !cpass_usable(MODE_BCAST, EPI_RK, a) && !cshort_usable(MODE_BCAST, EPI_RK, a);
 }
 
-void launch_forward(const Graph& g, int epi, const PassArgs& a, double* partials, hipStream_t s) {
+void launch_forward(const Graph& g, int epi, const PassArgs& a_in, double* partials, hipStream_t s) {
+    PassArgs a = a_in;
+    a.gmax = 64 >> g.bchunk;  // the tiling's B-chunk
     if (epi == EPI_ETA || a.csr != &g.csr[0][0] || partials == nullptr || cpass_usable(MODE_BCAST, epi, a) ||
         cshort_usable(MODE_BCAST, epi, a)) {
         launch_pass(MODE_BCAST, epi, a, s);

@@ -1,6 +1,7 @@
 // Autotuner for the forward graph pass: segment-to-wavefront tiling (long-target
-// threshold, XCD remap), shared-triple tiles on/off, and optionally the choice
-// between the two compensated float accumulation modes.  Candidates are timed
+// threshold, XCD remap), shared-triple tiles and quadratic-target blocks
+// on/off, the B-chunk (sets per lane group) of the segment kernel, and
+// optionally the choice between the two compensated float accumulation modes.  Candidates are timed
 // with HIP events on a private stream over zero-filled operands of the shape.
 #include <algorithm>
 #include <cstring>
@@ -133,11 +134,38 @@ extern "C" cut_status cut_graph_autotune(cut_graph_t h, int64_t nsets, int64_t n
         const Cand& c0 = cands[0];
         cut_tuning best{c0.lr, c0.cr, c0.flags, c0.prec, median(c0.ms), median(c0.ms)};
         const double gain = 0.98;
-        for (size_t i = 1; i < cands.size(); ++i) {
-            const double ms = median(cands[i].ms);
-            if (ms < gain * best.pass_ms)
-                best = cut_tuning{cands[i].lr, cands[i].cr, cands[i].flags, cands[i].prec, ms, best.default_ms};
+        auto pick = [&](const std::vector<Cand>& cs, size_t from) {
+            for (size_t i = from; i < cs.size(); ++i) {
+                const double ms = median(cs[i].ms);
+                if (ms < gain * best.pass_ms)
+                    best = cut_tuning{cs[i].lr, cs[i].cr, cs[i].flags, cs[i].prec, ms, best.default_ms};
+            }
+        };
+        pick(cands, 1);
+        // second stage: the B-chunk (lane-group width) of the segment kernel,
+        // on the three fastest tilings of the first stage, for every narrower
+        // width the sets allow
+        std::vector<size_t> order(cands.size());
+        for (size_t i = 0; i < order.size(); ++i) order[i] = i;
+        std::stable_sort(order.begin(), order.end(),
+                         [&](size_t x, size_t y) { return median(cands[x].ms) < median(cands[y].ms); });
+        std::vector<Cand> bc;
+        int gw = 1;
+        while (gw < nsets && gw < 64) gw <<= 1;
+        for (size_t r = 0; r < std::min<size_t>(3, order.size()); ++r) {
+            const Cand& c = cands[order[r]];
+            const uint32_t base = c.flags & ~(3u << CUT_TILE_BCHUNK_SHIFT);
+            for (uint32_t code = 1; code <= 3; ++code)
+                if ((64 >> code) < gw)
+                    bc.push_back({c.lr, c.cr, base | (code << CUT_TILE_BCHUNK_SHIFT), c.prec, {0, 0, 0}});
         }
+        for (int round = 0; round < 3; ++round)
+            for (Cand& c : bc) {
+                apply_tiling(g, c.lr, c.cr, c.flags);
+                c.ms[round] = time_pass(g, c.prec, (int32_t)nsets, (int32_t)nops, eta.p, x.p, (double*)y.p,
+                                        partials(c.prec), s, e0, e1);
+            }
+        pick(bc, 0);
         apply_tiling(g, best.long_records, best.chunk_records, best.tiling_flags);
         rereserve(g);
         HIP_CHECK(hipEventDestroy(e0));

@@ -75,9 +75,11 @@ PRECS = ["F64", "F32X", "F32C", "F32"]
 # 16-record chunks with XCD remap; shared-triple tiles; four-wavefront split (no
 # chunks); shared-triple chunks of quartic targets (one or two triples a chunk,
 # with and without XCD remap); quadratic-target blocks (alone, with remap, with
-# triple chunks, with shared-triple tiles)
+# triple chunks, with shared-triple tiles); B-chunks of 32, 16 and 8 sets
+# (alone, with short chunks and XCD remap, with blocks)
 TILINGS = [(1024, 512, 0), (16, 16, 1), (64, 64, 3), (64, 64, 4), (1024, 8, 9), (16, 32, 9), (1024, 128, 8),
-           (1024, 512, 16), (1024, 512, 17), (1024, 16, 25), (1024, 512, 18), (64, 64, 19)]
+           (1024, 512, 16), (1024, 512, 17), (1024, 16, 25), (1024, 512, 18), (64, 64, 19),
+           (1024, 512, 32), (16, 16, 65), (64, 64, 96 | 16)]
 
 
 @pytest.mark.parametrize("tiling", TILINGS)

@@ -75,6 +75,21 @@ def test_unreserved_shape_is_refused(L, g24):
         L.cut_graph_reserve(g24, nsets, nops, 0, L.CUT_RESERVE_ADJOINT)
 
 
+def test_tiling_flags_round_trip(L, g24):
+    """Tiling flags: unknown bits are refused, every B-chunk field is
+    accepted, and the tuner (which also tries B-chunks) returns known bits
+    only."""
+    U.say("[boundary] tiling flags")
+    with pytest.raises(L.CutError) as e:
+        L.cut_graph_set_tiling(g24, 1024, 512, 128)
+    assert e.value.status == L.CUT_E_INVAL
+    for b in (32, 16, 8):
+        L.cut_graph_set_tiling(g24, 1024, 512, L.CUT_TILE_BCHUNK(b) | L.CUT_TILE_XCD_REMAP)
+    t = L.cut_graph_autotune(g24, 16, 2, L.CUT_F32C, 0)
+    assert t["tiling_flags"] & ~127 == 0
+    L.cut_graph_set_tiling(g24, 1024, 512, 0)
+
+
 def test_work_area_fixed_after_reserve_and_tuning(L, g24):
     nsets, nops = 8, 3
     z0, eta = _inputs(24, nsets, nops, 5)

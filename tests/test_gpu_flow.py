@@ -56,7 +56,8 @@ def test_epq_wegner_flow_full_config(L):
 
 
 # default chunked form; quadratic-target blocks; blocks + shared-triple tiles
-FLOW_TILINGS = [(1024, 512, 0), (1024, 512, 17), (1024, 512, 19)]
+# default; blocks with XCD remap; blocks with tiles; B-chunk 16 with XCD remap
+FLOW_TILINGS = [(1024, 512, 0), (1024, 512, 17), (1024, 512, 19), (1024, 512, 64 | 1)]
 
 
 @pytest.mark.parametrize("tiling", FLOW_TILINGS)
