@@ -80,7 +80,8 @@ def pass_kernels(flags: int) -> str:
         parts.append("k_qblock<5,prec> (quadratic-target blocks)")
     if flags & 2:
         parts.append("k_tile64<5,prec> (shared-triple tiles of the quartic targets)")
-    parts.append("k_pass<64,5,prec,0,2> (" + ("remaining targets" if flags & 18 else "every target") +
+    G = 64 >> ((flags >> 5) & 3)   # the B-chunk: lanes per record of the segment kernel
+    parts.append(f"k_pass<{G},5,prec,0,2> (" + ("remaining targets" if flags & 18 else "every target") +
                  (", unchunked" if flags & 4 else ", long ones in chunks") + ")")
     if not flags & 4 or flags & 18:
         parts.append("k_chunk_combine<5,prec,2> (partial rows + RK4 stage epilogue)")
