@@ -359,8 +359,10 @@ __global__ __launch_bounds__(256) void k_pass(KArgs a) {
         float fc[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const T* arow = A + (int64_t)(rx[u] & 0xFFFFFFu) * a.lda;
-            const T* brow = B + (int64_t)(ry[u] & 0xFFFFFFu) * a.ldb;
+            // 24-bit row index times a 32-bit stride (checked on the host):
+            // one 32 x 32 -> 64-bit multiply-add per row
+            const T* arow = A + (uint64_t)(rx[u] & 0xFFFFFFu) * (uint32_t)a.lda;
+            const T* brow = B + (uint64_t)(ry[u] & 0xFFFFFFu) * (uint32_t)a.ldb;
             fc[u] = __builtin_bit_cast(float, record_factor_bits(rx[u], ry[u]) & okm[u]);
             if constexpr (G == 64) {  // one record per wavefront: uniform rows
                 const auto ra = row_rsrc(arow, a.lda * (int64_t)sizeof(T));
@@ -956,8 +958,15 @@ static int range_group_width(const KArgs& k) {
     return group_width(std::max(k.s1 - k.s0, std::min(8, (int)k.nsets)));
 }
 
+// the kernels multiply row indices by 32-bit strides
+static void check_ld(const PassArgs& p) {
+    if (p.lda >= (int64_t)1 << 31 || p.ldb >= (int64_t)1 << 31 || p.ldy >= (int64_t)1 << 31)
+        CUT_FAIL(CUT_E_INVAL, "leading dimension of 2^31 elements or more");
+}
+
 static KArgs make_kargs(const PassArgs& p) {
     const DevCSR& c = *p.csr;
+    check_ld(p);
     KArgs k{};
     k.tasks = p.tasks ? p.tasks : c.tasks;
     k.ntasks = p.tasks ? p.ntasks : c.ntasks;
@@ -1100,6 +1109,7 @@ static void launch_cpass(int epi, const PassArgs& p, hipStream_t s) {
 }
 
 void launch_pass(int mode, int epi, const PassArgs& p, hipStream_t s) {
+    check_ld(p);
     if (cshort_usable(mode, epi, p)) {
         launch_cshort(epi, p, s);
         return;
@@ -1782,6 +1792,7 @@ bool forward_set_ranges(const Graph& g, const PassArgs& a) {
 }
 
 void launch_forward(const Graph& g, int epi, const PassArgs& a_in, double* partials, hipStream_t s) {
+    check_ld(a_in);
     PassArgs a = a_in;
     a.gmax = 64 >> g.bchunk;  // the tiling's B-chunk
     if (epi == EPI_ETA || a.csr != &g.csr[0][0] || partials == nullptr || cpass_usable(MODE_BCAST, epi, a) ||

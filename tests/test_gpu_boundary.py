@@ -90,6 +90,23 @@ def test_tiling_flags_round_trip(L, g24):
     L.cut_graph_set_tiling(g24, 1024, 512, 0)
 
 
+def test_leading_dimension_beyond_32_bits_refused(L, g24):
+    """The kernels multiply row indices by 32-bit strides: a leading dimension
+    of 2^31 elements or more is refused on the host (before any launch, so the
+    small buffers below are never read), through the raw C entry point."""
+    U.say("[boundary] leading dimension limit")
+    import ctypes as C
+    nsets, nops = 1, 1
+    L.cut_graph_reserve(g24, nsets, nops, 0, L.CUT_RESERVE_APPLY)
+    eta = torch.zeros(16, dtype=torch.float64, device=DEV)
+    x = torch.zeros(16, dtype=torch.float64, device=DEV)
+    y = torch.zeros(16, dtype=torch.float64, device=DEV)
+    st = L.lib().cut_graph_apply(g24, 0, L.CUT_F64, nsets, nops, C.c_void_p(eta.data_ptr()), 1 << 31,
+                                 C.c_void_p(x.data_ptr()), 1, C.c_void_p(y.data_ptr()), 1, 0, None)
+    torch.cuda.synchronize()
+    assert st == L.CUT_E_INVAL and "2^31" in L.cut_last_error()
+
+
 def test_work_area_fixed_after_reserve_and_tuning(L, g24):
     nsets, nops = 8, 3
     z0, eta = _inputs(24, nsets, nops, 5)
