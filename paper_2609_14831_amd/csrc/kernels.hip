@@ -299,11 +299,13 @@ __global__ __launch_bounds__(256) void k_pass(KArgs a) {
 #ifndef CUT_PASS_UNROLL
 #define CUT_PASS_UNROLL 4
 #endif
-    constexpr int U = (NOPS <= 2 || PREC == CUT_F32C) ? 8 : CUT_PASS_UNROLL;
+    constexpr int U = (PREC == CUT_F32C && G == 32) ? 16 : (NOPS <= 2 || PREC == CUT_F32C) ? 8 : CUT_PASS_UNROLL;
     // The gathers of U records are all issued before any arithmetic, so U
     // dependent load chains are in flight per lane group; then accum() adds the
     // U terms.  A record slot past the segment end holds a valid clamped record
-    // and gets factor zero.
+    // and gets factor zero.  Compensated-float passes with 32-lane groups take
+    // U = 16 (measured 3 % faster than 8; the float partial of a group then
+    // carries at most gamma_16 of its terms).
     auto accum = [&](const T (&av)[U][NA], const T (&bv)[U][NOPS], const float (&fc)[U]) {
         if constexpr (PREC == CUT_F32C) {
             // the U terms of each column in one float partial (FMA chain),
@@ -477,8 +479,9 @@ __global__ __launch_bounds__(256) void k_pass(KArgs a) {
     } else {
         // Records are fetched cooperatively, 64 per wavefront load (one per
         // lane), then handed to the lane groups by cross-lane moves.
-        constexpr int CH = (G >= U) ? 1 : U / G;  // 64-record chunks per outer iteration
+        constexpr int CH = (G >= U) ? 2 : U / G;  // 64-record chunks per outer iteration
         constexpr int SLOTS = CH * G;             // record slots of one lane group per iteration
+        __shared__ uint2 recs[4][G > 1 ? 64 * CH : 1];
         for (int64_t base = e0; base < e1; base += 64 * CH) {
             uint2 mine[CH];
 #pragma unroll
@@ -491,6 +494,20 @@ __global__ __launch_bounds__(256) void k_pass(KArgs a) {
                 mine[c] = make_uint2((uint32_t)rv, (uint32_t)(rv >> 32));
             }
             const int cnt = (int)((e1 - base) < 64 * CH ? (e1 - base) : 64 * CH);
+            if constexpr (G > 1) {
+                // the wavefront's records go through its own LDS slice: slot t
+                // of lane group `sub` is record t R + sub, one broadcast read
+                // per slot (LDS operations of one wavefront complete in order;
+                // the fences keep the compiler from moving reads above writes
+                // or the next writes above reads)
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+#pragma unroll
+                for (int c = 0; c < CH; ++c) recs[wave][c * 64 + lane] = mine[c];
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            }
 #pragma unroll
             for (int t0 = 0; t0 < SLOTS; t0 += U) {
                 if (t0 * R >= cnt) break;
@@ -503,9 +520,9 @@ __global__ __launch_bounds__(256) void k_pass(KArgs a) {
                         rx[u] = mine[c].x;
                         ry[u] = mine[c].y;
                     } else {
-                        const int src = (t % G) * R + sub;
-                        rx[u] = (uint32_t)__shfl((int)mine[c].x, src);
-                        ry[u] = (uint32_t)__shfl((int)mine[c].y, src);
+                        const uint2 r = recs[wave][t * R + sub];
+                        rx[u] = r.x;
+                        ry[u] = r.y;
                     }
                     okm[u] = t * R + sub < cnt ? 0xFFFFFFFFu : 0u;
                 }

@@ -26,7 +26,8 @@ def gamma32(n: int) -> float:
 
 
 # records whose terms the compensated float pass sums in one float partial
-F32C_GROUP = 8
+# (16 with 32-lane groups, 8 otherwise: the larger bounds both)
+F32C_GROUP = 16
 
 
 def dot2_bound(n: int, group: int = F32C_GROUP) -> float:
