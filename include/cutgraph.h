@@ -17,7 +17,9 @@
  *    NULL = the null stream).  A device fault surfaces as CUT_E_DEVICE from a
  *    later call that synchronises.
  *  - All coefficient pointers are device memory owned by the caller.  Row r of
- *    an operand starts at base + r*ld (ld counted in elements).
+ *    an operand starts at base + r*ld (ld counted in elements).  Leading
+ *    dimensions are below 2^31 elements (the kernels form row addresses from
+ *    32-bit strides); larger ones fail with CUT_E_INVAL before any launch.
  *  - Coefficient layout: a state row holds nops*nsets columns, column
  *    op*nsets + s belongs to operand op (0 = the Hamiltonian) of coefficient set
  *    s.  A generator row holds nsets columns.  Every operand column of set s is
