@@ -769,6 +769,18 @@ static uint2 pack_piece(float f, uint32_t a, uint32_t b) {
 // v's sign and sum exactly to v.  A piece outside the normal FP32 range is
 // refused.  Returns the number of pieces.
 static int factor_pieces(double v, float out[8]) {
+    if (v == 0.0) return 0;
+    {
+        // the common case: a factor of <= 8 significant bits is its own piece
+        const float f = (float)v;
+        uint32_t bits;
+        std::memcpy(&bits, &f, 4);
+        const uint32_t ex = (bits >> 23) & 0xFFu;
+        if ((double)f == v && (bits & 0xFFFFu) == 0 && ex != 0 && ex != 0xFFu) {
+            out[0] = f;
+            return 1;
+        }
+    }
     if (!std::isfinite(v)) CUT_FAIL(CUT_E_FORMAT, "factor %g is not finite", v);
     int n = 0;
     while (v != 0.0) {
