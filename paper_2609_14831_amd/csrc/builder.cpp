@@ -406,12 +406,26 @@ struct PBAlgebra {
         int k[8] = {0}, kmax[8], c[8], a[8];
         for (int m = 0; m < M; ++m) kmax[m] = std::min(ax[m], cy[m]);
         for (;;) {
-            i128 f = sign;
+            // the factor in 64-bit arithmetic while it fits (every registry
+            // but the highest-degree ones), else again in 128-bit
+            int64_t f64 = sign;
+            bool wide = false;
+            for (int m = 0; m < M && !wide; ++m) {
+                int64_t g;
+                wide = k[m] > 20 || __builtin_mul_overflow((int64_t)fact[k[m]], binom[ax[m]][k[m]], &g) ||
+                       __builtin_mul_overflow(g, binom[cy[m]][k[m]], &g) || __builtin_mul_overflow(f64, g, &f64);
+            }
+            i128 f = f64;
+            if (wide) {
+                f = sign;
+                for (int m = 0; m < M; ++m) {
+                    i128 g;
+                    if (__builtin_mul_overflow(fact[k[m]], (i128)binom[ax[m]][k[m]], &g) ||
+                        __builtin_mul_overflow(g, (i128)binom[cy[m]][k[m]], &g) || __builtin_mul_overflow(f, g, &f))
+                        overflow = true;
+                }
+            }
             for (int m = 0; m < M; ++m) {
-                i128 g;
-                if (__builtin_mul_overflow(fact[k[m]], (i128)binom[ax[m]][k[m]], &g) ||
-                    __builtin_mul_overflow(g, (i128)binom[cy[m]][k[m]], &g) || __builtin_mul_overflow(f, g, &f))
-                    overflow = true;
                 c[m] = cx[m] + cy[m] - k[m];
                 a[m] = ax[m] + ay[m] - k[m];
             }
