@@ -445,10 +445,9 @@ struct PBAlgebra {
         for (size_t r = 0; r < out.size();) {
             size_t s = r;
             i128 re = 0, im = 0;
-            for (; s < out.size() && out[s].key == out[r].key; ++s) {
-                re += out[s].re;
-                im += out[s].im;
-            }
+            for (; s < out.size() && out[s].key == out[r].key; ++s)
+                if (__builtin_add_overflow(re, out[s].re, &re) || __builtin_add_overflow(im, out[s].im, &im))
+                    overflow = true;
             if (re != 0 || im != 0) out[w++] = {out[r].key, re, im};
             r = s;
         }
