@@ -1,8 +1,9 @@
 // Autotuner for the forward graph pass: segment-to-wavefront tiling (long-target
 // threshold, XCD remap), shared-triple tiles and quadratic-target blocks
 // on/off, the B-chunk (sets per lane group) of the segment kernel, and
-// optionally the choice between the two compensated float accumulation modes.  Candidates are timed
-// with HIP events on a private stream over zero-filled operands of the shape.
+// optionally the choice between the two compensated float accumulation modes.
+// Candidates are timed with HIP events on a private stream over zero-filled
+// operands of the shape.
 #include <algorithm>
 #include <cstring>
 #include <memory>
