@@ -54,12 +54,13 @@ void release_step_graphs(Graph& g) {
 
 // Launch pieces covering the sets [0, A).  A piece of w sets runs with lane
 // groups of w lanes (w a power of two), and its pass costs a fixed part (the
-// record stream, the per-record decode, the combine) plus a part in
-// proportion to w; below 8 sets the state layout (one cache line per operand
-// and set) makes narrow pieces no cheaper.  Measured on the 2n = 40 graph, 64
-// sets x 5 operands, per pass: 8 sets 0.95 ms, 16 sets 1.30, 32 sets 2.0, 64
-// sets 3.41.  The cheapest cover from those widths: 8 for A <= 8, 16 up to 16,
-// 32 up to 32, 32 + 8 up to 40, 32 + 16 up to 48, else 64 per 64 sets.
+// record stream, the per-record decode, the combine) plus the cache lines its
+// gathers touch: in the layout of all the sets one per operand and line-sized
+// group of sets, so pieces of 8 to 32 sets cost about the same.  Measured on
+// the 2n = 40 graph, 64 sets x 5 operands, F32C, per pass: one piece of 32 sets
+// 1.25 ms, pieces of 32 + 8 sets 2.46 ms, all 64 sets 2.49 ms.  Cover: one
+// piece up to 32 sets, 32 + the rest up to 48, else 64 per 64 sets.  Narrower
+// prefixes are compacted instead (compact_width).
 struct SetRange {
     int32_t s0, s1;
 };
@@ -79,6 +80,29 @@ static std::vector<SetRange> set_ranges(int32_t A) {
         r.push_back({s, A});
     }
     return r;
+}
+
+// Widest compacted state, and widest phase whose full-width passes take the
+// segment kernel (lane groups of <= 16 sets) instead of the tiling's block and
+// tile kernels.
+static const int32_t kCompactSets = 16;
+static const int32_t kNarrowSets = 16;
+
+// Sets the flow's state carries while A sets are still active.  Once the
+// active prefix fits in 16 sets, the finished sets' columns are written out
+// and the state, stage operands and Hamiltonian column are repacked into the
+// layout of W sets, W the smallest power of two >= A.  In the layout of all
+// the sets every operand's few active sets sit on a cache line of their own,
+// so a pass over 16 sets or fewer reads as many lines per row as one over 32;
+// repacked, a row's active sets are contiguous.  Wider states gain nothing: a
+// 32-set state measured the same as a 32-set piece, and widths that are not
+// powers of two put operand runs across cache lines (a 55-set state took 14.3
+// against 10.3 ms per RK step).
+static int32_t compact_width(int32_t A, int32_t nsets) {
+    if (A > kCompactSets) return nsets;
+    int32_t W = 1;
+    while (W < A) W <<= 1;
+    return std::min(W, nsets);
 }
 
 static size_t al(size_t x) { return (x + 255) & ~size_t(255); }
@@ -189,6 +213,9 @@ struct StepPlan {
     double* cpart = nullptr;
     // sets each graph pass launches over (empty: all of them in one launch)
     std::vector<SetRange> ranges;
+    // the state is a compacted phase of at most kNarrowSets sets: full-width
+    // passes take the segment kernel
+    int32_t narrow = 0;
 };
 
 // HIP events bracketing launches (kind 0 = graph pass, 1 = generator)
@@ -263,6 +290,7 @@ static void enqueue_step(const StepPlan& P, hipStream_t s, PassTimer* tm = nullp
         p.hst = P.fb.hst;
         p.ldh = P.nsets;
         p.gmax = 64 >> g.bchunk;  // the tiling's B-chunk
+        p.narrow = P.narrow;
         if (tm) tm->mark(0, s);
         const size_t nr = std::max<size_t>(1, P.ranges.size());
         for (size_t r = 0; r < nr; ++r) {
@@ -330,16 +358,34 @@ extern "C" cut_status cut_flow_integrate(cut_graph_t h, const cut_flow_params* p
         for (int32_t q = 0; q < (int32_t)nsets; ++q) identity = identity && perm[q] == q;
         ns_run.resize(nsets);
         for (int32_t q = 0; q < (int32_t)nsets; ++q) ns_run[q] = n_steps[perm[q]];
-        double* zs = identity ? z : fb.zp;
+        auto active = [&](int64_t t) {
+            int32_t A = 0;
+            for (int32_t q = 0; q < (int32_t)nsets; ++q) A += ns_run[q] > t;
+            return A;
+        };
+        // Compacted phases (compact_width): the state carries the active
+        // prefix only.  Not with the diagnostic (caller order) or checkpoints
+        // (full states in caller order).
+        const bool compact = !outside && !(ckpt && p->ckpt_every > 0) && t1 > t0 &&
+                             compact_width(active(t1 - 1), (int32_t)nsets) < nsets;
+        auto phase_width = [&](int64_t t) -> int32_t {
+            return compact ? compact_width(active(t), (int32_t)nsets) : (int32_t)nsets;
+        };
+        // the widths the state takes over [t0, t1), in order
+        std::vector<int32_t> phases;
+        for (int64_t t = t0; t < t1 && compact; ++t)
+            if (phases.empty() || phases.back() != phase_width(t)) phases.push_back(phase_width(t));
+        if (phases.empty()) phases.push_back((int32_t)nsets);
+        double* zs = (identity && !compact) ? z : fb.zp;
         HIP_CHECK(hipMemcpyAsync(fb.nsteps, ns_run.data(), nsets * 4, hipMemcpyHostToDevice, stream));
-        if (!identity) {
+        if (zs != z) {
             HIP_CHECK(hipMemcpyAsync(fb.perm, perm.data(), nsets * 4, hipMemcpyHostToDevice, stream));
-            launch_permute_sets(z, zs, g.N, (int32_t)nops, (int32_t)nsets, fb.perm, false, stream);
+            launch_move_sets(z, (int32_t)nsets, zs, phases[0], g.N, (int32_t)nops, 0, phases[0], fb.perm, false,
+                             stream);
         }
         launch_set_scalar(fb.step, (int32_t)t0, stream);
         int32_t* const flagp = p->nonfinite ? p->nonfinite : fb.flag;
         launch_set_scalar(flagp, 0, stream);
-        launch_prep_state(zs, g.N, (int32_t)nops, (int32_t)nsets, fb.xsh[0], f32, fb.hst, stream);
         StepPlan P{&g, p->generator, p->precision, p->ds, p->delta, (int32_t)nsets, (int32_t)nops, fb, zs, {}, {}};
         for (int st = 0; st < 4; ++st) {
             P.xin[st] = fb.xsh[st & 1];
@@ -350,31 +396,53 @@ extern "C" cut_status cut_flow_integrate(cut_graph_t h, const cut_flow_params* p
             P.cbuf = (double*)oex;
             P.cpart = (double*)(oex + al(g.n_out * cols * 8));
         }
+        // phase k of a compacted flow keeps the state in zp (k even) or in
+        // the RK accumulator's buffer (k odd), the accumulator in the other:
+        // stage 0 of every step rewrites the accumulator, so at a step
+        // boundary it holds nothing
+        auto enter = [&](size_t k) {
+            P.nsets = phases[k];
+            P.narrow = (phases[k] < nsets && phases[k] <= kNarrowSets) ? 1 : 0;
+            if (compact) {
+                P.z = (k & 1) ? fb.acc : fb.zp;
+                P.fb.acc = (k & 1) ? fb.zp : fb.acc;
+            }
+        };
+        enter(0);
+        launch_prep_state(P.z, g.N, (int32_t)nops, P.nsets, fb.xsh[0], f32, fb.hst, stream);
         // width class of step t: the sets up to the last active one, when the
-        // pass honours set ranges (else 0: every set in one launch)
-        PassArgs probe{};
-        probe.csr = &g.csr[0][0];
-        probe.nsets = (int32_t)nsets;
-        probe.nops = (int32_t)nops;
-        probe.precision = p->precision;
-        probe.lda = nsets;
-        probe.ldb = cols;
-        const bool ranged = forward_set_ranges(g, probe);
+        // pass honours set ranges (else 0: every set of the phase in one launch)
+        auto ranged_at = [&](int32_t W) {
+            PassArgs probe{};
+            probe.csr = &g.csr[0][0];
+            probe.nsets = W;
+            probe.nops = (int32_t)nops;
+            probe.precision = p->precision;
+            probe.lda = W;
+            probe.ldb = (int64_t)nops * W;
+            return forward_set_ranges(g, probe);
+        };
         // (a prefix that one 64-set piece would cover runs as a full-width
         // launch instead, which keeps the tiling's block and tile kernels)
         auto width_class = [&](int64_t t) -> int64_t {
-            if (!ranged) return 0;
+            const int32_t W = phase_width(t);
+            if (!ranged_at(W)) return 0;
             int64_t last = 0;
-            for (int32_t q = 0; q < (int32_t)nsets; ++q)
+            for (int32_t q = 0; q < W; ++q)
                 if (ns_run[q] > t) last = q + 1;
-            if (last == nsets) return 0;
+            if (last == W) return 0;
             const std::vector<SetRange> r = set_ranges((int32_t)last);
-            if (nsets <= 64 && r.size() == 1 && r[0].s1 - r[0].s0 > 32) return 0;
+            if (W <= 64 && r.size() == 1 && r[0].s1 - r[0].s0 > 32) return 0;
             return last;
         };
         auto set_class = [&](int64_t c) {
             P.ranges.clear();
             if (c > 0) P.ranges = set_ranges((int32_t)c);
+        };
+        // captured step of phase k and class c (the phase's width and parity
+        // fix the state's layout and buffers)
+        auto graph_id = [&](size_t k, int64_t c) {
+            return ((int64_t)phases[k] << 33) | ((int64_t)(k & 1) << 32) | c;
         };
         const bool use_graph = (p->flags & CUT_FLOW_HIPGRAPH) && t1 - t0 > 1;
         const bool timed = !use_graph && (p->flags & CUT_FLOW_TIME_PASSES);
@@ -399,42 +467,61 @@ extern "C" cut_status cut_flow_integrate(cut_graph_t h, const cut_flow_params* p
                 gc->key = key;
             }
             gc = g.graphs;
-            // capture every width class this call needs before any replay
+            // capture every (phase, width class) this call needs before any replay
+            size_t k = 0;
             for (int64_t t = t0; t < t1; ++t) {
-                const int64_t c = width_class(t);
+                if (phase_width(t) != phases[k]) ++k;
+                const int64_t c = width_class(t), id = graph_id(k, c);
                 bool have = false;
-                for (auto& e : gc->cls) have = have || e.id == c;
+                for (auto& e : gc->cls) have = have || e.id == id;
                 if (have) continue;
+                enter(k);
                 set_class(c);
-                StepGraphCache::Cls e{c, nullptr, nullptr};
+                StepGraphCache::Cls e{id, nullptr, nullptr};
                 HIP_CHECK(hipStreamBeginCapture(gc->cap, hipStreamCaptureModeThreadLocal));
                 enqueue_step(P, gc->cap);
                 HIP_CHECK(hipStreamEndCapture(gc->cap, &e.graph));
                 HIP_CHECK(hipGraphInstantiate(&e.exec, e.graph, nullptr, nullptr, 0));
                 gc->cls.push_back(e);
             }
+            enter(0);
             HIP_CHECK(hipEventRecord(gc->ev_in, stream));
             HIP_CHECK(hipStreamWaitEvent(gc->stream, gc->ev_in, 0));
         }
         hipStream_t run = use_graph ? gc->stream : stream;
+        size_t k = 0;
         for (int64_t t = t0; t < t1; ++t) {
             if (ckpt && p->ckpt_every > 0 && t % p->ckpt_every == 0) {
                 double* slot = ckpt + (t / p->ckpt_every) * M;
                 if (identity) HIP_CHECK(hipMemcpyAsync(slot, zs, M * 8, hipMemcpyDeviceToDevice, run));
                 else launch_permute_sets(zs, slot, g.N, (int32_t)nops, (int32_t)nsets, fb.perm, true, run);
             }
+            if (phase_width(t) != P.nsets) {
+                // the sets past the new width have finished: their columns go
+                // to the caller's state, the others are repacked into the
+                // other buffer, and the stage operand and Hamiltonian column
+                // are remade from them (the values the last stage wrote)
+                const int32_t Wo = P.nsets, W = phase_width(t);
+                const double* zo = P.z;
+                launch_move_sets(zo, Wo, z, (int32_t)nsets, g.N, (int32_t)nops, W, Wo, fb.perm, true, run);
+                enter(++k);
+                launch_move_sets(zo, Wo, P.z, W, g.N, (int32_t)nops, 0, W, nullptr, false, run);
+                launch_prep_state(P.z, g.N, (int32_t)nops, W, fb.xsh[0], f32, fb.hst, run);
+            }
             const int64_t c = width_class(t);
             if (use_graph) {
                 hipGraphExec_t ex = nullptr;
+                const int64_t id = graph_id(k, c);
                 for (auto& e : gc->cls)
-                    if (e.id == c) ex = e.exec;
+                    if (e.id == id) ex = e.exec;
                 HIP_CHECK(hipGraphLaunch(ex, run));
             } else {
                 set_class(c);
                 enqueue_step(P, run, timed ? &timer : nullptr);
             }
         }
-        if (!identity) launch_permute_sets(zs, z, g.N, (int32_t)nops, (int32_t)nsets, fb.perm, true, run);
+        if (zs != z)
+            launch_move_sets(P.z, P.nsets, z, (int32_t)nsets, g.N, (int32_t)nops, 0, P.nsets, fb.perm, true, run);
         if (timed) {
             HIP_CHECK(hipStreamSynchronize(run));
             for (size_t q = 0; q + 1 < timer.used; q += 2) {

@@ -359,6 +359,11 @@ struct PassArgs {
     int32_t nsets, nops;
     int32_t s0 = 0, s1 = 0;         // sets [s0, s1) covered (s1 = 0: all); see forward_set_ranges
     int32_t gmax = 64;              // widest lane group of the segment kernel (the tiling's B-chunk)
+    // 1: a full-width forward pass takes the segment kernel over the chunk plan
+    // (the route of a launch over a proper set range) instead of the tiling's
+    // block and tile kernels, whose lanes are sets (a ragged flow's compacted
+    // narrow phase)
+    int32_t narrow = 0;
     int32_t precision;              // cut_precision
     const int32_t* nsteps;          // device [nsets] or null (all active)
     const int32_t* step;            // device scalar or null
@@ -396,6 +401,11 @@ bool forward_set_ranges(const Graph& g, const PassArgs& a);
 // dst[r][op][perm[s]] = src[r][op][s])
 void launch_permute_sets(const double* src, double* dst, int64_t rows, int32_t nops, int32_t nsets,
                          const int32_t* perm, bool inverse, hipStream_t s);
+// set columns [q0, q1) between a rows x (nops x ss) state and a rows x
+// (nops x sd) one, map(q) = perm[q] (q without perm): gather
+// dst[r][op][q] = src[r][op][map(q)], scatter dst[r][op][map(q)] = src[r][op][q]
+void launch_move_sets(const double* src, int32_t ss, double* dst, int32_t sd, int64_t rows, int32_t nops,
+                      int32_t q0, int32_t q1, const int32_t* perm, bool scatter, hipStream_t s);
 
 void launch_g2(const Graph& g, double delta, int32_t nsets, const double* h, int64_t ldh,
                void* eta, int64_t lde, bool eta_f32, const int32_t* nsteps, const int32_t* step,

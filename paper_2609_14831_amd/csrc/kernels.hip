@@ -1801,8 +1801,9 @@ static void launch_tiles_nops(const TileKArgs& t, const KArgs& k, int epi, int p
 
 // whether launch_forward honours a set range [s0, s1) of `a`: a launch over a
 // proper range of the sets runs the segment kernel over the plain chunk plan
-// (always built with the tiling), the block and tile kernels only full-width
-// launches; the complex-record kernels always cover every set
+// (always built with the tiling), as does a full-width launch with `narrow`;
+// the block and tile kernels run only other full-width launches; the
+// complex-record kernels always cover every set
 bool forward_set_ranges(const Graph& g, const PassArgs& a) {
     (void)g;
     return !cpass_usable(MODE_BCAST, EPI_RK, a) && !cshort_usable(MODE_BCAST, EPI_RK, a);
@@ -1817,7 +1818,7 @@ void launch_forward(const Graph& g, int epi, const PassArgs& a_in, double* parti
         launch_pass(MODE_BCAST, epi, a, s);
         return;
     }
-    const bool ranged = a.s1 > 0 && (a.s0 != 0 || a.s1 != a.nsets);
+    const bool ranged = a.narrow || (a.s1 > 0 && (a.s0 != 0 || a.s1 != a.nsets));
     if (ranged) {
         if (g.csr[0][0].cp.nlong > 0) launch_chunked(g, g.csr[0][0].cp, epi, a, partials, s);
         else launch_pass(MODE_BCAST, epi, a, s);
@@ -2358,6 +2359,25 @@ void launch_permute_sets(const double* src, double* dst, int64_t rows, int32_t n
     if (n == 0) return;
     hipLaunchKernelGGL(k_permute_sets, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, src, dst, n, nsets,
                        perm, inverse ? 1 : 0);
+}
+
+// set columns between layouts of ss and sd sets (one thread per moved element)
+__global__ void k_move_sets(const double* __restrict__ src, int32_t ss, double* __restrict__ dst, int32_t sd,
+                            int64_t n, int32_t q0, int32_t w, const int32_t* __restrict__ perm, int scatter) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t ro = i / w;  // row * nops + op
+    const int32_t q = q0 + (int32_t)(i % w);
+    const int32_t mq = perm ? perm[q] : q;
+    if (scatter) dst[ro * sd + mq] = src[ro * ss + q];
+    else dst[ro * sd + q] = src[ro * ss + mq];
+}
+void launch_move_sets(const double* src, int32_t ss, double* dst, int32_t sd, int64_t rows, int32_t nops,
+                      int32_t q0, int32_t q1, const int32_t* perm, bool scatter, hipStream_t s) {
+    const int64_t w = (int64_t)q1 - q0, n = rows * nops * w;
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_move_sets, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, src, ss, dst, sd, n, q0,
+                       (int32_t)w, perm, scatter ? 1 : 0);
 }
 
 __global__ void k_finite(const double* z, int64_t n, int32_t* flag) {

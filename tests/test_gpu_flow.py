@@ -157,6 +157,44 @@ def test_flow_graph_replay_matches_stream_path(L, tiling):
     assert np.array_equal(a, b) and np.array_equal(a, c)
 
 
+@pytest.mark.parametrize("prec", ["F64", "F32C"])
+def test_ragged_flow_compacted_phases(L, prec):
+    """24 sets whose active prefix shrinks through 16, 8, 4, 2 and 1 sets, so the
+    flow repacks its state to ever fewer sets (writing the finished ones out):
+    against the oracle per set and operand; hipGraph replays bitwise the stream
+    path; a flow resumed inside a repacked phase bitwise the uninterrupted one;
+    a set with zero steps untouched."""
+    m = 12
+    g = U.graph(L, "majorana", m)
+    L.cut_graph_set_tiling(g, 1024, 512, 17)
+    og = A.majorana_graph(m)
+    nsets, nops = 24, 2
+    z0 = workloads.small_majorana(m, nsets, nops, seed=31)
+    ns = np.array([(5 * b) % 24 + 6 for b in range(nsets)], dtype=np.int32)
+    ns[7] = 0
+    ns[11] = 30
+    P = getattr(L, "CUT_" + prec)
+    U.say(f"[flow] compacted phases {prec}: hipGraph")
+    a, _ = _flow(L, g, z0, ns, L.CUT_GEN_G2, P, 1e-2, flags=L.CUT_FLOW_HIPGRAPH)
+    U.say(f"[flow] compacted phases {prec}: stream order")
+    b, _ = _flow(L, g, z0, ns, L.CUT_GEN_G2, P, 1e-2, flags=0)
+    U.say(f"[flow] compacted phases {prec}: resumed at step 22")
+    z = torch.tensor(z0, device=DEV).contiguous()
+    L.cut_flow_integrate(g, L.flow_params(L.CUT_GEN_G2, P, 1e-2, 0.5, step_end=22), nsets, nops, list(ns), z)
+    L.cut_flow_integrate(g, L.flow_params(L.CUT_GEN_G2, P, 1e-2, 0.5, step_begin=22), nsets, nops, list(ns), z)
+    torch.cuda.synchronize()
+    c = z.cpu().numpy()
+    L.cut_graph_set_tiling(g, 1024, 512, 0)
+    assert np.array_equal(a, b) and np.array_equal(a, c)
+    np.testing.assert_array_equal(a[:, :, 7], z0[:, :, 7])
+    gen, _ = OG.make_generator(og, "g2", 0.5)
+    zr, _ = OF.integrate(og, gen, z0, 1e-2, ns)
+    for s in range(nsets):
+        for op in range(nops):
+            r = _rel(a[:, op, s], zr[:, op, s])
+            assert r < (1e-13 if prec == "F64" else 1e-7), (s, op, r)
+
+
 def test_config2_short_flow_precision(L):
     """Majorana m=24 (config-2 graph, 2.56M records), H + 2 quadratic observables,
     100 RK4 steps: FP64 vs the oracle's C engine, float passes vs FP64."""
