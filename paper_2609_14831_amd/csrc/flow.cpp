@@ -216,6 +216,9 @@ struct StepPlan {
     // the state is a compacted phase of at most kNarrowSets sets: full-width
     // passes take the segment kernel
     int32_t narrow = 0;
+    // narrowest lane group: that of the layout of all the sets, so that a
+    // compacted phase sums every term in the same order (bitwise the same flow)
+    int32_t gfloor = 1;
 };
 
 // HIP events bracketing launches (kind 0 = graph pass, 1 = generator)
@@ -291,6 +294,7 @@ static void enqueue_step(const StepPlan& P, hipStream_t s, PassTimer* tm = nullp
         p.ldh = P.nsets;
         p.gmax = 64 >> g.bchunk;  // the tiling's B-chunk
         p.narrow = P.narrow;
+        p.gfloor = P.gfloor;
         if (tm) tm->mark(0, s);
         const size_t nr = std::max<size_t>(1, P.ranges.size());
         for (size_t r = 0; r < nr; ++r) {
@@ -363,10 +367,23 @@ extern "C" cut_status cut_flow_integrate(cut_graph_t h, const cut_flow_params* p
             for (int32_t q = 0; q < (int32_t)nsets; ++q) A += ns_run[q] > t;
             return A;
         };
+        // whether the passes over W sets honour set ranges (the segment kernel;
+        // not the complex-record kernels, whose lanes are columns)
+        auto ranged_at = [&](int32_t W) {
+            PassArgs probe{};
+            probe.csr = &g.csr[0][0];
+            probe.nsets = W;
+            probe.nops = (int32_t)nops;
+            probe.precision = p->precision;
+            probe.lda = W;
+            probe.ldb = (int64_t)nops * W;
+            return forward_set_ranges(g, probe);
+        };
         // Compacted phases (compact_width): the state carries the active
-        // prefix only.  Not with the diagnostic (caller order) or checkpoints
-        // (full states in caller order).
-        const bool compact = !outside && !(ckpt && p->ckpt_every > 0) && t1 > t0 &&
+        // prefix only, with the lane groups and so the sums of the full layout.
+        // Not with the diagnostic (caller order), checkpoints (full states in
+        // caller order) or passes that cover every set.
+        const bool compact = !outside && !(ckpt && p->ckpt_every > 0) && t1 > t0 && ranged_at((int32_t)nsets) &&
                              compact_width(active(t1 - 1), (int32_t)nsets) < nsets;
         auto phase_width = [&](int64_t t) -> int32_t {
             return compact ? compact_width(active(t), (int32_t)nsets) : (int32_t)nsets;
@@ -408,20 +425,13 @@ extern "C" cut_status cut_flow_integrate(cut_graph_t h, const cut_flow_params* p
                 P.fb.acc = (k & 1) ? fb.zp : fb.acc;
             }
         };
+        // lane groups of a launch over w sets of the full layout span
+        // max(w, min(8, nsets)) sets rounded up to a power of two
+        while (P.gfloor < std::min<int64_t>(8, nsets)) P.gfloor <<= 1;
         enter(0);
         launch_prep_state(P.z, g.N, (int32_t)nops, P.nsets, fb.xsh[0], f32, fb.hst, stream);
         // width class of step t: the sets up to the last active one, when the
         // pass honours set ranges (else 0: every set of the phase in one launch)
-        auto ranged_at = [&](int32_t W) {
-            PassArgs probe{};
-            probe.csr = &g.csr[0][0];
-            probe.nsets = W;
-            probe.nops = (int32_t)nops;
-            probe.precision = p->precision;
-            probe.lda = W;
-            probe.ldb = (int64_t)nops * W;
-            return forward_set_ranges(g, probe);
-        };
         // (a prefix that one 64-set piece would cover runs as a full-width
         // launch instead, which keeps the tiling's block and tile kernels)
         auto width_class = [&](int64_t t) -> int64_t {

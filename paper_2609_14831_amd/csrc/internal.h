@@ -364,6 +364,9 @@ struct PassArgs {
     // block and tile kernels, whose lanes are sets (a ragged flow's compacted
     // narrow phase)
     int32_t narrow = 0;
+    // lane groups of the segment kernel span at least this many sets (a
+    // compacted flow keeps the widths, hence the sums, of its full layout)
+    int32_t gfloor = 1;
     int32_t precision;              // cut_precision
     const int32_t* nsteps;          // device [nsets] or null (all active)
     const int32_t* step;            // device scalar or null

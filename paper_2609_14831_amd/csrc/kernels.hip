@@ -1138,7 +1138,7 @@ void launch_pass(int mode, int epi, const PassArgs& p, hipStream_t s) {
     if (p.csr->nseg == 0) return;
     const KArgs k = make_kargs(p);
     if (k.ntasks == 0) return;
-    const int G = std::min(range_group_width(k), (int)p.gmax);
+    const int G = std::min(std::max(range_group_width(k), (int)p.gfloor), (int)p.gmax);
     const int64_t nblk = k.per_xcd > 0 ? 8 * k.per_xcd : k.ntasks;
     dim3 grid((unsigned)nblk, (unsigned)((k.s1 - k.s0 + G - 1) / G));
     if (mode == MODE_BCAST) {
@@ -1718,7 +1718,7 @@ static void launch_chunked(const Graph& g, const ChunkPlan& c, int epi, const Pa
     r.ntasks = c.nshort;
     r.per_xcd = c.short_per_xcd;
     KArgs k = make_kargs(r);
-    const int G = std::min(range_group_width(k), (int)a.gmax);
+    const int G = std::min(std::max(range_group_width(k), (int)a.gfloor), (int)a.gmax);
     const unsigned ychunks = (unsigned)((k.s1 - k.s0 + G - 1) / G);
     const int64_t ldp = (int64_t)a.nops * a.nsets;
     k.chunks = c.chunks;

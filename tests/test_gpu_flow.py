@@ -161,9 +161,10 @@ def test_flow_graph_replay_matches_stream_path(L, tiling):
 def test_ragged_flow_compacted_phases(L, prec):
     """24 sets whose active prefix shrinks through 16, 8, 4, 2 and 1 sets, so the
     flow repacks its state to ever fewer sets (writing the finished ones out):
-    against the oracle per set and operand; hipGraph replays bitwise the stream
-    path; a flow resumed inside a repacked phase bitwise the uninterrupted one;
-    a set with zero steps untouched."""
+    against the oracle per set and operand; bitwise the flow that keeps every
+    set in its layout (a checkpointed flow: full states in caller order);
+    hipGraph replays bitwise the stream path; a flow resumed inside a repacked
+    phase bitwise the uninterrupted one; a set with zero steps untouched."""
     m = 12
     g = U.graph(L, "majorana", m)
     L.cut_graph_set_tiling(g, 1024, 512, 17)
@@ -184,8 +185,10 @@ def test_ragged_flow_compacted_phases(L, prec):
     L.cut_flow_integrate(g, L.flow_params(L.CUT_GEN_G2, P, 1e-2, 0.5, step_begin=22), nsets, nops, list(ns), z)
     torch.cuda.synchronize()
     c = z.cpu().numpy()
+    U.say(f"[flow] compacted phases {prec}: checkpointed (uncompacted)")
+    d, _ = _flow(L, g, z0, ns, L.CUT_GEN_G2, P, 1e-2, ckpt_every=4, flags=L.CUT_FLOW_HIPGRAPH)
     L.cut_graph_set_tiling(g, 1024, 512, 0)
-    assert np.array_equal(a, b) and np.array_equal(a, c)
+    assert np.array_equal(a, b) and np.array_equal(a, c) and np.array_equal(a, d)
     np.testing.assert_array_equal(a[:, :, 7], z0[:, :, 7])
     gen, _ = OG.make_generator(og, "g2", 0.5)
     zr, _ = OF.integrate(og, gen, z0, 1e-2, ns)
