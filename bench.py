@@ -554,8 +554,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-outside", action="store_true", help="skip the outside-space action leg")
     ap.add_argument("--no-stress", action="store_true", help="skip the 2n = 64 stress-scale leg")
-    ap.add_argument("--full-flow", action="store_true",
-                    help="also time the whole ragged config-3 flow (3,660 steps, about a minute)")
+    ap.add_argument("--no-full-flow", action="store_true",
+                    help="skip the whole ragged flow (3,660 steps, about 30 s)")
     ap.add_argument("--only", choices=["assembly", "outside", "pauli_boson", "stress"],
                     help="run only that leg and print its JSON (for profiling)")
     ap.add_argument("--minimal", action="store_true", help="timed flow only")
@@ -753,10 +753,10 @@ def main():
     log(f"batched fp64: {out['batched_fp64']}")
     # ragged batch: windows late in the flow, where fewer sets are active,
     # counting active columns only (stream order, every window's passes
-    # launched over the active prefix); the whole flow with --full-flow
+    # launched over the active prefix), then the whole flow
     out["ragged_windows"] = ragged_windows_leg(L, torch, g, inp, w, PREC, E, value)
     log(f"ragged windows: {out['ragged_windows']}")
-    if args.full_flow:
+    if not args.no_full_flow:
         out["full_ragged_flow"] = full_flow_leg(L, torch, g, inp, w, PREC, E, value)
         log(f"full ragged flow: {out['full_ragged_flow']}")
 
