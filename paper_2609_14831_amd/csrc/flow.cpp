@@ -166,7 +166,8 @@ size_t flow_ws_bytes(const Graph& g, int64_t nsets, int64_t nops, int prec, size
 
 size_t flow_outside_extra(const Graph& g, int64_t nsets, int64_t nops) {
     const int64_t cols = nops * nsets;
-    return g.have_outside ? al(g.n_out * cols * 8) + al((size_t)kColsqParts * cols * 8) : 0;
+    // outside action, partial sums of its squares, the accumulated norms in flow order
+    return g.have_outside ? al(g.n_out * cols * 8) + al((size_t)kColsqParts * cols * 8) + al(cols * 8) : 0;
 }
 
 // stage storage, zr, lam_new, mu, u, eta, geta, vjp scratch of the adjoint flow
@@ -349,15 +350,14 @@ extern "C" cut_status cut_flow_integrate(cut_graph_t h, const cut_flow_params* p
         // sets still active at step t are a prefix of length A(t) and each
         // graph pass launches over that prefix only (in pieces, set_ranges).
         // The state is permuted into that order in the work area and back at
-        // the end.  With the outside-space diagnostic (accumulated per caller
-        // column) the caller's order is kept and passes cover the sets up to
-        // the last active one.
+        // the end (so are the outside-space diagnostic's accumulated columns),
+        // and the passes are cut into the same pieces with or without the
+        // diagnostic.
         std::vector<int32_t>& perm = g.flow_perm_h;
         std::vector<int32_t>& ns_run = g.flow_nsteps_h;
         perm.resize(nsets);
         for (int32_t q = 0; q < (int32_t)nsets; ++q) perm[q] = q;
-        if (!outside)
-            std::stable_sort(perm.begin(), perm.end(), [&](int32_t a, int32_t b) { return n_steps[a] > n_steps[b]; });
+        std::stable_sort(perm.begin(), perm.end(), [&](int32_t a, int32_t b) { return n_steps[a] > n_steps[b]; });
         bool identity = true;
         for (int32_t q = 0; q < (int32_t)nsets; ++q) identity = identity && perm[q] == q;
         ns_run.resize(nsets);
@@ -381,8 +381,9 @@ extern "C" cut_status cut_flow_integrate(cut_graph_t h, const cut_flow_params* p
         };
         // Compacted phases (compact_width): the state carries the active
         // prefix only, with the lane groups and so the sums of the full layout.
-        // Not with the diagnostic (caller order), checkpoints (full states in
-        // caller order) or passes that cover every set.
+        // Not with the diagnostic (its columns keep the full layout),
+        // checkpoints (full states in caller order) or passes that cover every
+        // set.
         const bool compact = !outside && !(ckpt && p->ckpt_every > 0) && t1 > t0 && ranged_at((int32_t)nsets) &&
                              compact_width(active(t1 - 1), (int32_t)nsets) < nsets;
         auto phase_width = [&](int64_t t) -> int32_t {
@@ -409,9 +410,15 @@ extern "C" cut_status cut_flow_integrate(cut_graph_t h, const cut_flow_params* p
             P.xout[st] = fb.xsh[(st + 1) & 1];
         }
         if (outside) {
-            P.onorm = p->outside_norm2;
             P.cbuf = (double*)oex;
             P.cpart = (double*)(oex + al(g.n_out * cols * 8));
+            P.onorm = p->outside_norm2;
+            if (zs != z) {
+                // the accumulated norms in flow order (one row of nops x nsets)
+                P.onorm = (double*)(oex + al(g.n_out * cols * 8) + al((size_t)kColsqParts * cols * 8));
+                launch_move_sets(p->outside_norm2, (int32_t)nsets, P.onorm, (int32_t)nsets, 1, (int32_t)nops, 0,
+                                 (int32_t)nsets, fb.perm, false, stream);
+            }
         }
         // phase k of a compacted flow keeps the state in zp (k even) or in
         // the RK accumulator's buffer (k odd), the accumulator in the other:
@@ -530,8 +537,12 @@ extern "C" cut_status cut_flow_integrate(cut_graph_t h, const cut_flow_params* p
                 enqueue_step(P, run, timed ? &timer : nullptr);
             }
         }
-        if (zs != z)
+        if (zs != z) {
             launch_move_sets(P.z, P.nsets, z, (int32_t)nsets, g.N, (int32_t)nops, 0, P.nsets, fb.perm, true, run);
+            if (outside)
+                launch_move_sets(P.onorm, (int32_t)nsets, p->outside_norm2, (int32_t)nsets, 1, (int32_t)nops, 0,
+                                 (int32_t)nsets, fb.perm, true, run);
+        }
         if (timed) {
             HIP_CHECK(hipStreamSynchronize(run));
             for (size_t q = 0; q + 1 < timer.used; q += 2) {

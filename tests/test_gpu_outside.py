@@ -140,6 +140,49 @@ def test_flow_outside_diagnostic_vs_oracle(L, prec, tol):
             assert np.abs(z_on - zr).max() < 1e-11 * np.abs(zr).max()
 
 
+@pytest.mark.parametrize("prec,tol", [("F64", 1e-11), ("F32C", 1e-5)])
+def test_flow_outside_diagnostic_scrambled_sets(L, prec, tol):
+    """12 ragged sets in no particular order (the flow runs them sorted by step
+    count and permutes the diagnostic's columns with them): the diagnostic per
+    column against the oracle, and added to what the array held, column by
+    column; the flowed state bitwise the same with and without it (the passes
+    are cut into the same pieces), with and without the hipGraph; a set with
+    zero steps untouched."""
+    from oracle import flow as OF
+    from oracle import gen as OG
+    m, ds = 16, 0.01
+    U.say(f"[outside flow] m=16 12 scrambled sets {prec}")
+    P = getattr(L, "CUT_" + prec)
+    g = U.outside_graph(L, m)
+    nsets, nops = 12, 2
+    z0 = workloads.small_majorana(m, nsets, nops, seed=97)
+    ns = np.array([3, 9, 0, 6, 9, 4, 7, 1, 9, 2, 8, 5], dtype=np.int32)
+    og_l = A.majorana_graph(m)
+    og = A.majorana_outside_graph(m)
+    gen, _ = OG.make_generator(og_l, "g2", 0.5)
+    zr, leak_r = OF.integrate_outside(og_l, gen, og, z0, ds, ns)
+    base = np.arange(1, nops * nsets + 1, dtype=np.float64).reshape(nops, nsets)
+    for flags in (L.CUT_FLOW_HIPGRAPH, 0):
+        z_off, _ = _flow_outside(L, g, z0, ns, P, ds, False, flags)
+        z_on, leak = _flow_outside(L, g, z0, ns, P, ds, True, flags)
+        np.testing.assert_array_equal(z_on, z_off)
+        np.testing.assert_array_equal(z_on[:, :, 2], z0[:, :, 2])
+        assert np.all(leak[:, 2] == 0.0)
+        live = ns > 0
+        rel = np.abs(leak - leak_r)[:, live] / np.maximum(np.abs(leak_r[:, live]), 1e-300)
+        U.say(f"[outside flow] scrambled {prec} flags {flags}: max rel err {rel.max():.3e}")
+        assert np.all(rel < tol)
+        z = torch.tensor(z0, device=DEV).contiguous()
+        acc = torch.tensor(base.ravel(), device=DEV)
+        L.cut_flow_integrate(g, L.flow_params(L.CUT_GEN_G2, P, ds, 0.5, 0, flags=flags, outside_norm2=acc),
+                             nsets, nops, [int(v) for v in ns], z)
+        torch.cuda.synchronize()
+        added = acc.cpu().numpy().reshape(nops, nsets) - base
+        assert np.all(np.abs(added - leak) <= 1e-12 * base)
+        if prec == "F64":
+            assert np.abs(z_on - zr).max() < 1e-11 * np.abs(zr).max()
+
+
 def test_flow_outside_config2_unchanged_trajectory(L):
     """Config-2 graph (m = 24, 48.45M outside-space records), 8 sets x 3
     operands, 20 steps, F32C: the trajectory is bitwise the same with the
