@@ -57,28 +57,24 @@ void release_step_graphs(Graph& g) {
 // record stream, the per-record decode, the combine) plus the cache lines its
 // gathers touch: in the layout of all the sets one per operand and line-sized
 // group of sets, so pieces of 8 to 32 sets cost about the same.  Measured on
-// the 2n = 40 graph, 64 sets x 5 operands, F32C, per pass: one piece of 32 sets
-// 1.25 ms, pieces of 32 + 8 sets 2.46 ms, all 64 sets 2.49 ms.  Cover: one
-// piece up to 32 sets, 32 + the rest up to 48, else 64 per 64 sets.  Narrower
-// prefixes are compacted instead (compact_width).
+// the 2n = 40 graph, 64 sets x 5 operands, F32C, per RK step, in one session:
+// 21-27 active sets 5.1 ms as one piece of 32 sets; 39-41 active sets 10.3 ms
+// as pieces of 32 + the rest, 10.05 ms as one full-width launch (which keeps
+// the tiling's block kernels).  Cover: pieces of 64 sets while more than 32
+// remain, then one piece of the rest.  Prefixes of 16 sets or fewer are
+// compacted instead (compact_width).
 struct SetRange {
     int32_t s0, s1;
 };
 static std::vector<SetRange> set_ranges(int32_t A) {
     std::vector<SetRange> r;
     int32_t s = 0;
-    while (A - s > 48) {
+    while (A - s > 32) {
         const int32_t n = std::min(64, A - s);
         r.push_back({s, s + n});
         s += n;
     }
-    const int32_t rem = A - s;
-    if (rem > 32) {
-        r.push_back({s, s + 32});
-        r.push_back({s + 32, A});
-    } else if (rem > 0) {
-        r.push_back({s, A});
-    }
+    if (A > s) r.push_back({s, A});
     return r;
 }
 
@@ -94,10 +90,12 @@ static const int32_t kNarrowSets = 16;
 // layout of W sets, W the smallest power of two >= A.  In the layout of all
 // the sets every operand's few active sets sit on a cache line of their own,
 // so a pass over 16 sets or fewer reads as many lines per row as one over 32;
-// repacked, a row's active sets are contiguous.  Wider states gain nothing: a
-// 32-set state measured the same as a 32-set piece, and widths that are not
-// powers of two put operand runs across cache lines (a 55-set state took 14.3
-// against 10.3 ms per RK step).
+// repacked, a row's active sets are contiguous.  Wider states do not pay: a
+// state repacked to 32 sets measured slower than a 32-set piece of the full
+// layout (5.18 against 5.10 ms per RK step at 21-27 active sets, 6.33 against
+// 5.07 at 32, where its full-width passes take the block kernels), and widths
+// that are not powers of two put operand runs across cache lines (a 55-set
+// state took 14.3 against 10.3 ms per RK step).
 static int32_t compact_width(int32_t A, int32_t nsets) {
     if (A > kCompactSets) return nsets;
     int32_t W = 1;
